@@ -1,0 +1,199 @@
+"""Throughput benchmark of the DG elastic-wave hot path on one MI355X.
+
+Workload (default): order N=4 (Np=35) nodal DG on the periodic unit cube cut
+into 48^3 x 6 = 663,552 Kuhn tetrahedra; smooth heterogeneous media sampled
+per quadrature point and node from seeded sums of 16 random Fourier modes
+(rho in [1,3], cp in [2,4], cs = cp/[1.6,2]); Gaussian velocity pulse initial
+condition (L2-projected); upwind flux; LSRK(5,4) at CFL 0.5 with cp_max = 4.
+
+One step = one LSRK(5,4) step = five fused stage kernels (volume + face
+flux + LIFT + weight-adjusted mass inverse + stage update) over all
+elements.  Metric: DOF-updates/s = 9 K Np steps / seconds.  The reduced
+precision run is compared with the plain FP64 GPU path on the same mesh,
+media and initial condition (per-field relative L2 after warmup+steps).
+
+Prints one JSON line.  N > 1 GPUs is not supported (one-GPU build).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic HBM bytes per element per stage (each value read or written
+# once): q and res read + written (4 * 9 * Np), 1/rho, lam, mu at the Nq
+# quadrature points, Zp and Zs at the Np nodes, 9 metric terms, 4 x (normal,
+# Fscale), 4 neighbour ids + 4 pattern bytes
+def alg_bytes_per_elem_stage(N, elem_bytes):
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nq = (N + 1) ** 3
+    reals = 4 * 9 * Np + 3 * Nq + 2 * Np + 9 + 16
+    return reals * elem_bytes + 4 * 4 + 4
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
+    p.add_argument("--n", type=int, default=48, help="hexahedra per cube side")
+    p.add_argument("--order", type=int, default=4)
+    p.add_argument("--no-fp64-reference", action="store_true")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-n", type=int, default=12)
+    return p.parse_args()
+
+
+def setup(args, precision, q0=None):
+    import synth
+    from paper_2008_09441_amd import B, Solver
+    s = Solver(args.order, precision=precision, flux="upwind", device=0)
+    s.upload_mesh(synth.kuhn_cube_vertices(args.n))
+    return s
+
+
+def upload_media_and_state(s, media_cache):
+    import synth
+    from paper_2008_09441_amd import B
+    if "media" not in media_cache:
+        xq = s.quad_coords()
+        xn = s.node_coords()
+        media_cache["media"] = synth.fourier_media(xq) + synth.fourier_media(xn)
+        fq = synth.gaussian_pulse_vx(xq)[None]      # only v_x is nonzero
+        q0x = s.project(fq)[0]
+        K, Np, _, _ = s.sizes()
+        q0 = np.zeros((9, K, Np))
+        q0[0] = q0x
+        media_cache["q0"] = q0
+        del xq, xn, fq
+    B.dg_material_upload(s.ctx, *media_cache["media"])
+    s.set_state(media_cache["q0"])
+
+
+def timed_run(s, dt, steps, warmup):
+    import torch
+    s.run(0.0, dt, warmup)
+    s.synchronize()
+    stream = torch.cuda.current_stream(0)    # the stream libdg launches on
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.run(warmup * dt, dt, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def cpu_baseline(args, N):
+    """The oracle (FP64 NumPy, untuned) on a bounded sample: one LSRK(5,4)
+    step on the n_s^3 x 6 periodic cube with the same order, media and
+    initial condition (per-element work identical to the full workload)."""
+    import synth
+    from oracle.dg import ElasticDG
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    ns = args.cpu_sample_n
+    op = ElasticDG(ns, N, synth.fourier_media)
+    q0 = op.project_function(synth.gaussian_pulse)
+    hmin = (1.0 / ns) / math.sqrt(2.0)
+    dt = 0.5 * hmin / (4.0 * (N + 1) ** 2)
+    t0 = time.perf_counter()
+    op.step(q0, np.zeros_like(q0), dt)
+    sec = time.perf_counter() - t0
+    dofs = 9 * op.K * op.Np
+    return {"value": dofs / sec, "unit": "DOF-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"1 LSRK(5,4) step of the FP64 NumPy oracle on the {ns}^3x6 "
+                      f"= {op.K}-tet periodic cube, N={N}, same media/pulse "
+                      f"({sec:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the multi-GPU element partition is design-only)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2008_09441_amd import Solver  # noqa: F401  (fails loudly if unbuilt)
+    N, n = args.order, args.n
+    K = 6 * n ** 3
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    hmin = (1.0 / n) / math.sqrt(2.0)     # 3 vol / max face area of a Kuhn tet
+    dt = 0.5 * hmin / (4.0 * (N + 1) ** 2)
+    cache = {}
+
+    s = setup(args, args.precision)
+    upload_media_and_state(s, cache)
+    sec, wall = timed_run(s, dt, args.steps, args.warmup)
+    q_lo = s.get_state().astype(np.float64)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+
+    dofs = 9 * K * Np
+    value = dofs * args.steps / sec
+    ms_step = sec / args.steps * 1e3
+    stage_s = sec / (5 * args.steps)
+    eb = 8 if args.precision == "fp64" else 4
+    bytes_launch = alg_bytes_per_elem_stage(N, eb) * K
+    achieved = bytes_launch / stage_s / 1e9
+
+    out = {
+        "metric": "DG DOF-updates/sec (FP32/BF16x3 vs FP64 at stated L2 error); batched p50/p99",
+        "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32acc"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"elastic velocity-stress DG, N={N} (Np={Np}), periodic "
+                               f"{n}^3x6 = {K} Kuhn tets, Fourier-mode media, Gaussian "
+                               f"pulse, upwind, LSRK(5,4) CFL 0.5",
+                   "order": N, "elements": K, "dofs": dofs, "precision": args.precision,
+                   "dt": dt},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None,
+                     "kernel": "dgk::stage (fused RHS + LSRK stage)",
+                     "alg_bytes_per_launch": bytes_launch,
+                     "avg_launch_us": stage_s * 1e6},
+        "wall_s_timed": wall,
+    }
+
+    if not args.no_fp64_reference and args.precision != "fp64":
+        s64 = setup(args, "fp64")
+        upload_media_and_state(s64, cache)
+        sec64, _ = timed_run(s64, dt, args.steps, args.warmup)
+        q64 = s64.get_state()
+        s64.close()
+        del s64
+        torch.cuda.empty_cache()
+        err = (np.linalg.norm((q_lo - q64).reshape(9, -1), axis=1)
+               / np.maximum(np.linalg.norm(q64.reshape(9, -1), axis=1), 1e-300))
+        out["fp64_path"] = {"value": dofs * args.steps / sec64,
+                            "ms_per_step": sec64 / args.steps * 1e3}
+        out["speedup_vs_fp64_path"] = sec64 / sec
+        out["rel_l2_vs_fp64_per_field"] = [float(e) for e in err]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * libdg: nodal discontinuous-Galerkin right-hand side and low-storage
+ * Runge-Kutta stepping for the velocity-stress elastic wave equation on
+ * periodic tetrahedral meshes, on one AMD Instinct MI355X (gfx950).
+ *
+ * The mounted paper (sparse-grid noise reduction for particle-in-cell) does
+ * not define this operation; each call below cites the standard published
+ * formulation it follows:
+ *   [HW08]  Hesthaven & Warburton, Nodal Discontinuous Galerkin Methods
+ *           (2008), Ch. 2-3, 6, 10: nodal basis, strong-form DG, LIFT.
+ *   [WSG10] Wilcox, Stadler, Burstedde & Ghattas, JCP 229 (2010): exact
+ *           Riemann (upwind) flux for isotropic elasticity.
+ *   [CHW17] Chan, Hewett & Warburton, SISC 39 (2017); [C18] Chan, IJNME 113
+ *           (2018): weight-adjusted mass inverse for variable coefficients.
+ *   [CK94]  Carpenter & Kennedy, NASA TM-109112 (1994): LSRK(5,4).
+ *
+ * Conventions shared with callers:
+ *   - fields, in order: v_x, v_y, v_z, s_xx, s_yy, s_zz, s_yz, s_xz, s_xy;
+ *   - state layout [9][K][Np] (structure of arrays; Np = (N+1)(N+2)(N+3)/6),
+ *     element type double for DG_FP64, float for DG_FP32 / DG_FP32_BF16X3;
+ *   - reference nodes: equispaced on the reference tetrahedron with vertices
+ *     (-1,-1,-1), (1,-1,-1), (-1,1,-1), (-1,-1,1), enumerated t-index
+ *     outermost, then s, then r; node p of element k sits at
+ *     x0 + F (r+1, s+1, t+1), F = [x1-x0, x2-x0, x3-x0] / 2;
+ *   - quadrature: collapsed Gauss-Jacobi rule, Nq = (N+1)^3 points, point
+ *     q = ia + (N+1) (ib + (N+1) ic), exact to degree 2N+1.
+ *
+ * Errors: every call returns a dg_status; arguments are validated on the
+ * host before any device work; dg_last_error() gives a message.  Device
+ * work is stream-ordered on the context's stream and asynchronous unless
+ * stated; asynchronous device faults surface on the next synchronising
+ * call.  The library never aborts the process.
+ */
+#ifndef DG_H_
+#define DG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+typedef enum {
+  DG_OK = 0,
+  DG_EINVAL = 1,      /* bad argument, size or mesh/material           */
+  DG_ENOMEM = 2,      /* device allocation failed or over HBM budget   */
+  DG_EDEVICE = 3,     /* HIP error, or compute call on host-only ctx   */
+  DG_ESTATE = 4,      /* call out of order (e.g. rhs before material)  */
+  DG_ENONFINITE = 5   /* non-finite input                              */
+} dg_status;
+
+typedef enum { DG_FP64 = 0, DG_FP32 = 1, DG_FP32_BF16X3 = 2 } dg_precision;
+typedef enum { DG_FLUX_UPWIND = 0, DG_FLUX_CENTRAL = 1 } dg_flux;
+
+typedef struct {
+  int32_t order;             /* N, 1..7                                          */
+  int32_t precision;         /* dg_precision                                     */
+  int32_t flux;              /* dg_flux                                          */
+  int32_t device;            /* HIP device ordinal; -1 = host-only (no GPU work) */
+  void* stream;              /* hipStream_t to order work on; NULL = default     */
+  uint64_t hbm_budget_bytes; /* 0 = unlimited                                    */
+} dg_options;
+
+/* Create a context.  *out receives the handle (NULL on failure).  The
+ * reference element of order N is built here in FP64 on the host [HW08]. */
+dg_status dg_create(dg_ctx** out, const dg_options* opt);
+
+/* Destroy a context and free its device memory.  NULL is allowed. */
+void dg_destroy(dg_ctx* ctx);
+
+/* Message for the last failed call on ctx (never NULL). */
+const char* dg_last_error(const dg_ctx* ctx);
+
+/* Sizes: K (elements; 0 before mesh upload), Np, Nfp, Nq.  Any out pointer
+ * may be NULL. */
+dg_status dg_sizes(const dg_ctx* ctx, int64_t* K, int32_t* Np, int32_t* Nfp,
+                   int32_t* Nq);
+
+/* Upload a periodic conforming tetrahedral mesh.  vxyz: host [K][4][3]
+ * per-element vertex coordinates (unwrapped; positive orientation
+ * required); period: host [3] box lengths > 0 of the periodic domain.
+ * Computes connectivity (faces matched by centroid modulo the period, trace
+ * permutations from the vertex correspondence) and affine geometric factors
+ * in FP64 [HW08, Ch. 10], then copies them to the device (cast to the
+ * working precision).  Host arrays are copied; the caller keeps ownership.
+ * Errors: DG_EINVAL (non-positive orientation, unmatched face), DG_ENOMEM. */
+dg_status dg_mesh_upload(dg_ctx* ctx, int64_t K, const double* vxyz,
+                         const double* period);
+
+/* Physical coordinates of the nodes [K][Np][3] / quadrature points
+ * [K][Nq][3] into host arrays, so callers can sample media and initial
+ * conditions.  Requires a mesh. */
+dg_status dg_node_coords(const dg_ctx* ctx, double* xyz);
+dg_status dg_quad_coords(const dg_ctx* ctx, double* xyz);
+
+/* Upload isotropic media.  rho_q, cp_q, cs_q: host [K][Nq] samples at the
+ * quadrature points (for the weight-adjusted mass inverse [CHW17, C18]);
+ * rho_n, cp_n, cs_n: host [K][Np] samples at the nodes (impedances
+ * Zp = rho cp, Zs = rho cs for the upwind flux [WSG10]).  Stored on the
+ * device as 1/rho, lam = rho (cp^2 - 2 cs^2), mu = rho cs^2 and Zp, Zs.
+ * Errors: DG_EINVAL for rho <= 0, cs <= 0 or cp^2 < 2 cs^2 (lam < 0 is
+ * allowed down to the cp >= sqrt(2) cs bound), DG_ENONFINITE for NaN/Inf. */
+dg_status dg_material_upload(dg_ctx* ctx, const double* rho_q, const double* cp_q,
+                             const double* cs_q, const double* rho_n,
+                             const double* cp_n, const double* cs_n);
+
+/* Host FP64 L2 projection of quadrature samples onto the nodal basis:
+ * q[f][k][:] = P_q fq[f][k][:] for f < nfields.  fq: [nfields][K][Nq],
+ * q: [nfields][K][Np], both host. */
+dg_status dg_project(const dg_ctx* ctx, int32_t nfields, const double* fq, double* q);
+
+/* Set / get the context's state [9][K][Np] (working precision).  on_device
+ * != 0: q is a device pointer (copied stream-ordered); else host (the call
+ * synchronises).  dg_state_set also zeroes the LSRK residual. */
+dg_status dg_state_set(dg_ctx* ctx, const void* q, int32_t on_device);
+dg_status dg_state_get(dg_ctx* ctx, void* q, int32_t on_device);
+
+/* Device pointer of the context's current state [9][K][Np] (valid until the
+ * next dg_step / dg_run, which swap buffers). */
+dg_status dg_state_device_ptr(dg_ctx* ctx, void** ptr);
+
+/* Semi-discrete right-hand side rhs = dq/dt for a caller-owned device state
+ * q_dev [9][K][Np] into caller-owned device rhs_dev [9][K][Np] (working
+ * precision; must not alias): volume terms div(sigma), eps(v) [HW08, Ch.
+ * 10], flux of the selected type at every face node gathered through the
+ * neighbour tables [WSG10], LIFT, then the weight-adjusted mass inverse
+ * [CHW17, C18].  Stream-ordered, asynchronous. */
+dg_status dg_rhs(dg_ctx* ctx, const void* q_dev, void* rhs_dev);
+
+/* One LSRK(5,4) step [CK94] of the context's state from time t with step
+ * dt: five fused stages res <- a_s res + dt rhs(q); q <- q + b_s res.
+ * Stream-ordered, asynchronous. */
+dg_status dg_step(dg_ctx* ctx, double t, double dt);
+
+/* nsteps LSRK(5,4) steps from t0.  Stream-ordered, asynchronous. */
+dg_status dg_run(dg_ctx* ctx, double t0, double dt, int64_t nsteps);
+
+/* Wait for the context's stream; reports asynchronous device errors. */
+dg_status dg_synchronize(dg_ctx* ctx);
+
+/* Host FP64 precompute, exported for cross-checking (no device needed).
+ * which: 0 Dr, 1 Ds, 2 Dt [Np][Np]; 3 LIFT [Np][4 Nfp] (face-major
+ * columns, face node order of dg_face_nodes); 4 Vq [Nq][Np]; 5 Pq [Np][Nq];
+ * 6 nodes [Np][3]; 7 quadrature points and weights [Nq][4]. */
+dg_status dg_ref_operator(const dg_ctx* ctx, int32_t which, double* out);
+
+/* Face node masks [4][Nfp] (volume node index of each face node). */
+dg_status dg_face_nodes(const dg_ctx* ctx, int32_t* fmask);
+
+/* Connectivity after dg_mesh_upload: neighbour element [K][4], neighbour
+ * face [K][4], and neighbour volume node of each own face node
+ * [K][4][Nfp]; geometry: metric terms [K][9] (d rst_i / d x_j), face data
+ * [K][4][4] (outward unit normal, Fscale = sJ/J), J [K].  Any pointer may
+ * be NULL. */
+dg_status dg_connectivity(const dg_ctx* ctx, int32_t* etoe, int32_t* etof,
+                          int32_t* nbnode);
+dg_status dg_geometry(const dg_ctx* ctx, double* geo, double* fgeo, double* J);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H_ */

@@ -1,0 +1,544 @@
+// C-ABI of libdg: context, uploads, right-hand side, LSRK(5,4) stepping.
+// The function contracts are documented in include/dg.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "dg_host.hpp"
+#include "dg_kernels.hpp"
+
+namespace {
+
+// LSRK(5,4) coefficients [CK94]
+const double kRkA[5] = {0.0,
+                        -567301805773.0 / 1357537059087.0,
+                        -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0,
+                        -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
+                        5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0,
+                        3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct dg_ctx {
+  dg_options opt{};
+  std::string err;
+  dgh::RefElement re;
+  dgh::MeshData mesh;
+  bool has_mesh = false, has_mat = false, has_state = false;
+  hipStream_t stream = nullptr;
+  size_t elem = 8;          // bytes of the working precision
+  size_t allocated = 0;     // device bytes held
+  // device arrays
+  DevBuf ops;               // Dr | Ds | Dt | LIFT | Vq | Pq
+  DevBuf fmask, geo, fgeo, etoe, etop, pat;
+  DevBuf irho, lam, mu, zp, zs;
+  DevBuf q[2], res;
+  int cur = 0;
+};
+
+namespace {
+
+dg_status fail(dg_ctx* c, dg_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define DG_HIP(ctx, call)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(ctx, DG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool device_ctx(const dg_ctx* c) { return c->opt.device >= 0; }
+
+dg_status set_device(dg_ctx* c) {
+  if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
+  DG_HIP(c, hipSetDevice(c->opt.device));
+  return DG_OK;
+}
+
+void release(dg_ctx* c, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    c->allocated -= b.bytes;
+  }
+  b = DevBuf();
+}
+
+dg_status alloc(dg_ctx* c, DevBuf& b, size_t bytes) {
+  release(c, b);
+  if (bytes == 0) return DG_OK;
+  if (c->opt.hbm_budget_bytes && c->allocated + bytes > c->opt.hbm_budget_bytes)
+    return fail(c, DG_ENOMEM, "allocation of " + std::to_string(bytes) +
+                                  " bytes exceeds the HBM budget");
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess)
+    return fail(c, DG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  b.p = p;
+  b.bytes = bytes;
+  c->allocated += bytes;
+  return DG_OK;
+}
+
+// upload an FP64 host array cast to the working precision
+dg_status upload_real(dg_ctx* c, DevBuf& b, const double* src, size_t n) {
+  dg_status s = alloc(c, b, n * c->elem);
+  if (s != DG_OK) return s;
+  if (c->elem == 8) {
+    DG_HIP(c, hipMemcpy(b.p, src, n * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = float(src[i]);
+    DG_HIP(c, hipMemcpy(b.p, tmp.data(), n * 4, hipMemcpyHostToDevice));
+  }
+  return DG_OK;
+}
+
+template <typename U>
+dg_status upload_raw(dg_ctx* c, DevBuf& b, const U* src, size_t n) {
+  dg_status s = alloc(c, b, n * sizeof(U));
+  if (s != DG_OK) return s;
+  DG_HIP(c, hipMemcpy(b.p, src, n * sizeof(U), hipMemcpyHostToDevice));
+  return DG_OK;
+}
+
+// ---------------------------------------------------------------- launch --
+template <typename T, int N>
+hipError_t launch_generic(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_out,
+                          double a, double b, double dt, int lsrk) {
+  const dgh::RefElement& re = c->re;
+  dgk::StageArgs<T> A;
+  const T* ops = static_cast<const T*>(c->ops.p);
+  const size_t np2 = size_t(re.Np) * re.Np;
+  A.q_in = q_in;
+  A.q_out = q_out;
+  A.res = res;
+  A.rhs_out = rhs_out;
+  A.geo = static_cast<const T*>(c->geo.p);
+  A.fgeo = static_cast<const T*>(c->fgeo.p);
+  A.etoe = static_cast<const int32_t*>(c->etoe.p);
+  A.etop = static_cast<const uint8_t*>(c->etop.p);
+  A.pat = static_cast<const int32_t*>(c->pat.p);
+  A.fmask = static_cast<const int32_t*>(c->fmask.p);
+  A.irho = static_cast<const T*>(c->irho.p);
+  A.lam = static_cast<const T*>(c->lam.p);
+  A.mu = static_cast<const T*>(c->mu.p);
+  A.zp = static_cast<const T*>(c->zp.p);
+  A.zs = static_cast<const T*>(c->zs.p);
+  A.Dr = ops;
+  A.Ds = ops + np2;
+  A.Dt = ops + 2 * np2;
+  A.LIFT = ops + 3 * np2;
+  A.Vq = A.LIFT + size_t(re.Np) * 4 * re.Nfp;
+  A.Pq = A.Vq + size_t(re.Nq) * re.Np;
+  A.K = c->mesh.K;
+  A.a = T(a);
+  A.b = T(b);
+  A.dt = T(dt);
+  A.lsrk = lsrk;
+  A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+  constexpr int E = dgk::elems_per_block<T, N>();
+  constexpr int lds = dgk::lds_bytes<T, N>();
+  const int64_t nblk = (c->mesh.K + E - 1) / E;
+  dgk::stage_generic<T, N><<<dim3(unsigned(nblk)), dim3(dgk::kBlock), lds, c->stream>>>(A);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stage_t(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_out,
+                          double a, double b, double dt, int lsrk) {
+  switch (c->re.N) {
+    case 1: return launch_generic<T, 1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 2: return launch_generic<T, 2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 3: return launch_generic<T, 3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 4: return launch_generic<T, 4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 5: return launch_generic<T, 5>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 6: return launch_generic<T, 6>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 7: return launch_generic<T, 7>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+dg_status launch_stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void* rhs_out,
+                       double a, double b, double dt, int lsrk) {
+  hipError_t e;
+  if (c->elem == 8)
+    e = launch_stage_t<double>(c, static_cast<const double*>(q_in),
+                               static_cast<double*>(q_out), static_cast<double*>(res),
+                               static_cast<double*>(rhs_out), a, b, dt, lsrk);
+  else
+    e = launch_stage_t<float>(c, static_cast<const float*>(q_in), static_cast<float*>(q_out),
+                              static_cast<float*>(res), static_cast<float*>(rhs_out), a, b,
+                              dt, lsrk);
+  if (e != hipSuccess) return fail(c, DG_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
+  return DG_OK;
+}
+
+dg_status fill_zero(dg_ctx* c, void* p, int64_t n) {
+  const int64_t nb = (n + 255) / 256;
+  if (c->elem == 8)
+    hipLaunchKernelGGL(dgk::fill_kernel<double>, dim3(unsigned(nb)), dim3(256), 0, c->stream,
+                       static_cast<double*>(p), n, 0.0);
+  else
+    hipLaunchKernelGGL(dgk::fill_kernel<float>, dim3(unsigned(nb)), dim3(256), 0, c->stream,
+                       static_cast<float*>(p), n, 0.0f);
+  DG_HIP(c, hipGetLastError());
+  return DG_OK;
+}
+
+dg_status ready(dg_ctx* c, bool need_state) {
+  if (!c) return DG_EINVAL;
+  if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
+  if (!c->has_mesh) return fail(c, DG_ESTATE, "no mesh uploaded");
+  if (!c->has_mat) return fail(c, DG_ESTATE, "no material uploaded");
+  if (need_state && !c->has_state) return fail(c, DG_ESTATE, "no state set");
+  return set_device(c);
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+dg_status dg_create(dg_ctx** out, const dg_options* opt) {
+  if (!out) return DG_EINVAL;
+  *out = nullptr;
+  if (!opt) return DG_EINVAL;
+  if (opt->order < 1 || opt->order > 7) return DG_EINVAL;
+  if (opt->precision != DG_FP64 && opt->precision != DG_FP32 &&
+      opt->precision != DG_FP32_BF16X3)
+    return DG_EINVAL;
+  if (opt->flux != DG_FLUX_UPWIND && opt->flux != DG_FLUX_CENTRAL) return DG_EINVAL;
+  dg_ctx* c = new (std::nothrow) dg_ctx();
+  if (!c) return DG_ENOMEM;
+  c->opt = *opt;
+  c->elem = (opt->precision == DG_FP64) ? 8 : 4;
+  c->stream = static_cast<hipStream_t>(opt->stream);
+  std::string err;
+  if (!dgh::build_ref_element(opt->order, c->re, err)) {
+    delete c;
+    return DG_EINVAL;
+  }
+  if (device_ctx(c)) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device >= ndev) {
+      delete c;
+      return DG_EDEVICE;
+    }
+    if (hipSetDevice(opt->device) != hipSuccess) {
+      delete c;
+      return DG_EDEVICE;
+    }
+    // reference operators and face masks, cast to the working precision
+    std::vector<double> ops;
+    const dgh::RefElement& re = c->re;
+    for (const auto* v : {&re.Dr, &re.Ds, &re.Dt, &re.LIFT, &re.Vq, &re.Pq})
+      ops.insert(ops.end(), v->begin(), v->end());
+    if (upload_real(c, c->ops, ops.data(), ops.size()) != DG_OK ||
+        upload_raw(c, c->fmask, re.Fmask.data(), re.Fmask.size()) != DG_OK) {
+      dg_destroy(c);
+      return DG_ENOMEM;
+    }
+  }
+  *out = c;
+  return DG_OK;
+}
+
+void dg_destroy(dg_ctx* c) {
+  if (!c) return;
+  if (device_ctx(c) && hipSetDevice(c->opt.device) == hipSuccess) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (DevBuf* b : {&c->ops, &c->fmask, &c->geo, &c->fgeo, &c->etoe, &c->etop, &c->pat,
+                      &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
+                      &c->res})
+      release(c, *b);
+  }
+  delete c;
+}
+
+const char* dg_last_error(const dg_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+dg_status dg_sizes(const dg_ctx* c, int64_t* K, int32_t* Np, int32_t* Nfp, int32_t* Nq) {
+  if (!c) return DG_EINVAL;
+  if (K) *K = c->has_mesh ? c->mesh.K : 0;
+  if (Np) *Np = c->re.Np;
+  if (Nfp) *Nfp = c->re.Nfp;
+  if (Nq) *Nq = c->re.Nq;
+  return DG_OK;
+}
+
+dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double* period) {
+  if (!c) return DG_EINVAL;
+  if (!vxyz || !period || K <= 0) return fail(c, DG_EINVAL, "mesh: bad arguments");
+  for (int64_t i = 0; i < K * 12; ++i)
+    if (!std::isfinite(vxyz[i])) return fail(c, DG_ENONFINITE, "mesh: non-finite vertex");
+  std::string err;
+  dgh::MeshData m;
+  if (!dgh::build_mesh(c->re, K, vxyz, period, m, err)) return fail(c, DG_EINVAL, err);
+  c->mesh = std::move(m);
+  c->has_mesh = true;
+  c->has_mat = false;
+  c->has_state = false;
+  if (!device_ctx(c)) return DG_OK;
+  dg_status s = set_device(c);
+  if (s != DG_OK) return s;
+  const dgh::MeshData& md = c->mesh;
+  if ((s = upload_real(c, c->geo, md.geo.data(), md.geo.size())) != DG_OK) return s;
+  if ((s = upload_real(c, c->fgeo, md.fgeo.data(), md.fgeo.size())) != DG_OK) return s;
+  if ((s = upload_raw(c, c->etoe, md.EToE.data(), md.EToE.size())) != DG_OK) return s;
+  if ((s = upload_raw(c, c->etop, md.EToP.data(), md.EToP.size())) != DG_OK) return s;
+  if ((s = upload_raw(c, c->pat, md.pat.data(), md.pat.size())) != DG_OK) return s;
+  const size_t nstate = size_t(9) * K * c->re.Np * c->elem;
+  for (DevBuf* b : {&c->q[0], &c->q[1], &c->res})
+    if ((s = alloc(c, *b, nstate)) != DG_OK) return s;
+  c->cur = 0;
+  return DG_OK;
+}
+
+dg_status dg_node_coords(const dg_ctx* c, double* xyz) {
+  if (!c || !xyz) return DG_EINVAL;
+  if (!c->has_mesh) return DG_ESTATE;
+  dgh::node_coords(c->re, c->mesh, xyz);
+  return DG_OK;
+}
+
+dg_status dg_quad_coords(const dg_ctx* c, double* xyz) {
+  if (!c || !xyz) return DG_EINVAL;
+  if (!c->has_mesh) return DG_ESTATE;
+  dgh::quad_coords(c->re, c->mesh, xyz);
+  return DG_OK;
+}
+
+dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
+                             const double* cs_q, const double* rho_n, const double* cp_n,
+                             const double* cs_n) {
+  if (!c) return DG_EINVAL;
+  if (!c->has_mesh) return fail(c, DG_ESTATE, "material: no mesh uploaded");
+  if (!rho_q || !cp_q || !cs_q || !rho_n || !cp_n || !cs_n)
+    return fail(c, DG_EINVAL, "material: null array");
+  const int64_t K = c->mesh.K;
+  const size_t nq = size_t(K) * c->re.Nq, nn = size_t(K) * c->re.Np;
+  auto check = [&](const double* r, const double* p, const double* s, size_t n) -> dg_status {
+    for (size_t i = 0; i < n; ++i) {
+      if (!std::isfinite(r[i]) || !std::isfinite(p[i]) || !std::isfinite(s[i]))
+        return fail(c, DG_ENONFINITE, "material: non-finite sample");
+      if (!(r[i] > 0.0) || !(s[i] > 0.0) || p[i] * p[i] < 2.0 * s[i] * s[i])
+        return fail(c, DG_EINVAL, "material: need rho > 0, cs > 0, cp >= sqrt(2) cs");
+    }
+    return DG_OK;
+  };
+  dg_status s = check(rho_q, cp_q, cs_q, nq);
+  if (s != DG_OK) return s;
+  if ((s = check(rho_n, cp_n, cs_n, nn)) != DG_OK) return s;
+  c->has_mat = false;
+  if (!device_ctx(c)) {
+    c->has_mat = true;
+    return DG_OK;
+  }
+  if ((s = set_device(c)) != DG_OK) return s;
+  std::vector<double> a(nq), b(nq), d(nq);
+  for (size_t i = 0; i < nq; ++i) {
+    const double r = rho_q[i], p = cp_q[i], v = cs_q[i];
+    a[i] = 1.0 / r;
+    b[i] = r * (p * p - 2.0 * v * v);
+    d[i] = r * v * v;
+  }
+  if ((s = upload_real(c, c->irho, a.data(), nq)) != DG_OK) return s;
+  if ((s = upload_real(c, c->lam, b.data(), nq)) != DG_OK) return s;
+  if ((s = upload_real(c, c->mu, d.data(), nq)) != DG_OK) return s;
+  std::vector<double> zp(nn), zs(nn);
+  for (size_t i = 0; i < nn; ++i) {
+    zp[i] = rho_n[i] * cp_n[i];
+    zs[i] = rho_n[i] * cs_n[i];
+  }
+  if ((s = upload_real(c, c->zp, zp.data(), nn)) != DG_OK) return s;
+  if ((s = upload_real(c, c->zs, zs.data(), nn)) != DG_OK) return s;
+  c->has_mat = true;
+  return DG_OK;
+}
+
+dg_status dg_project(const dg_ctx* c, int32_t nfields, const double* fq, double* q) {
+  if (!c || !fq || !q || nfields < 1) return DG_EINVAL;
+  if (!c->has_mesh) return DG_ESTATE;
+  const int Np = c->re.Np, Nq = c->re.Nq;
+  const int64_t K = c->mesh.K;
+  for (int64_t fk = 0; fk < int64_t(nfields) * K; ++fk) {
+    const double* src = fq + fk * Nq;
+    double* dst = q + fk * Np;
+    for (int n = 0; n < Np; ++n) {
+      double acc = 0.0;
+      const double* P = &c->re.Pq[size_t(n) * Nq];
+      for (int j = 0; j < Nq; ++j) acc += P[j] * src[j];
+      dst[n] = acc;
+    }
+  }
+  return DG_OK;
+}
+
+dg_status dg_state_set(dg_ctx* c, const void* q, int32_t on_device) {
+  if (!c || !q) return DG_EINVAL;
+  dg_status s = ready(c, false);
+  if (s != DG_OK) return s;
+  const size_t n = size_t(9) * c->mesh.K * c->re.Np;
+  if (on_device)
+    DG_HIP(c, hipMemcpyAsync(c->q[c->cur].p, q, n * c->elem, hipMemcpyDeviceToDevice,
+                             c->stream));
+  else {
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    DG_HIP(c, hipMemcpy(c->q[c->cur].p, q, n * c->elem, hipMemcpyHostToDevice));
+  }
+  if ((s = fill_zero(c, c->res.p, int64_t(n))) != DG_OK) return s;
+  c->has_state = true;
+  return DG_OK;
+}
+
+dg_status dg_state_get(dg_ctx* c, void* q, int32_t on_device) {
+  if (!c || !q) return DG_EINVAL;
+  dg_status s = ready(c, true);
+  if (s != DG_OK) return s;
+  const size_t n = size_t(9) * c->mesh.K * c->re.Np * c->elem;
+  if (on_device)
+    DG_HIP(c, hipMemcpyAsync(q, c->q[c->cur].p, n, hipMemcpyDeviceToDevice, c->stream));
+  else {
+    DG_HIP(c, hipMemcpyAsync(q, c->q[c->cur].p, n, hipMemcpyDeviceToHost, c->stream));
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return DG_OK;
+}
+
+dg_status dg_state_device_ptr(dg_ctx* c, void** ptr) {
+  if (!c || !ptr) return DG_EINVAL;
+  dg_status s = ready(c, false);
+  if (s != DG_OK) return s;
+  *ptr = c->q[c->cur].p;
+  return DG_OK;
+}
+
+dg_status dg_rhs(dg_ctx* c, const void* q_dev, void* rhs_dev) {
+  if (!c || !q_dev || !rhs_dev) return DG_EINVAL;
+  if (q_dev == rhs_dev) return fail(c, DG_EINVAL, "rhs: q and rhs must not alias");
+  dg_status s = ready(c, false);
+  if (s != DG_OK) return s;
+  if (c->opt.precision == DG_FP32_BF16X3)
+    return fail(c, DG_EINVAL, "rhs: BF16x3 path not available in this build");
+  return launch_stage(c, q_dev, nullptr, nullptr, rhs_dev, 0.0, 0.0, 0.0, 0);
+}
+
+dg_status dg_step(dg_ctx* c, double t, double dt) {
+  if (!c) return DG_EINVAL;
+  if (!std::isfinite(t) || !std::isfinite(dt)) return fail(c, DG_EINVAL, "step: non-finite t/dt");
+  dg_status s = ready(c, true);
+  if (s != DG_OK) return s;
+  if (c->opt.precision == DG_FP32_BF16X3)
+    return fail(c, DG_EINVAL, "step: BF16x3 path not available in this build");
+  for (int st = 0; st < 5; ++st) {
+    s = launch_stage(c, c->q[c->cur].p, c->q[1 - c->cur].p, c->res.p, nullptr, kRkA[st],
+                     kRkB[st], dt, 1);
+    if (s != DG_OK) return s;
+    c->cur = 1 - c->cur;
+  }
+  (void)t;
+  return DG_OK;
+}
+
+dg_status dg_run(dg_ctx* c, double t0, double dt, int64_t nsteps) {
+  if (!c) return DG_EINVAL;
+  if (nsteps < 0) return fail(c, DG_EINVAL, "run: negative step count");
+  for (int64_t i = 0; i < nsteps; ++i) {
+    dg_status s = dg_step(c, t0 + double(i) * dt, dt);
+    if (s != DG_OK) return s;
+  }
+  return DG_OK;
+}
+
+dg_status dg_synchronize(dg_ctx* c) {
+  if (!c) return DG_EINVAL;
+  dg_status s = set_device(c);
+  if (s != DG_OK) return s;
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  DG_HIP(c, hipGetLastError());
+  return DG_OK;
+}
+
+dg_status dg_ref_operator(const dg_ctx* c, int32_t which, double* out) {
+  if (!c || !out) return DG_EINVAL;
+  const dgh::RefElement& re = c->re;
+  const std::vector<double>* src = nullptr;
+  switch (which) {
+    case 0: src = &re.Dr; break;
+    case 1: src = &re.Ds; break;
+    case 2: src = &re.Dt; break;
+    case 3: src = &re.LIFT; break;
+    case 4: src = &re.Vq; break;
+    case 5: src = &re.Pq; break;
+    case 6:
+      for (int i = 0; i < re.Np; ++i) {
+        out[i * 3 + 0] = re.r[i];
+        out[i * 3 + 1] = re.s[i];
+        out[i * 3 + 2] = re.t[i];
+      }
+      return DG_OK;
+    case 7:
+      for (int i = 0; i < re.Nq; ++i) {
+        out[i * 4 + 0] = re.rq[i];
+        out[i * 4 + 1] = re.sq[i];
+        out[i * 4 + 2] = re.tq[i];
+        out[i * 4 + 3] = re.wq[i];
+      }
+      return DG_OK;
+    default: return DG_EINVAL;
+  }
+  std::memcpy(out, src->data(), src->size() * sizeof(double));
+  return DG_OK;
+}
+
+dg_status dg_face_nodes(const dg_ctx* c, int32_t* fmask) {
+  if (!c || !fmask) return DG_EINVAL;
+  for (size_t i = 0; i < c->re.Fmask.size(); ++i) fmask[i] = c->re.Fmask[i];
+  return DG_OK;
+}
+
+dg_status dg_connectivity(const dg_ctx* c, int32_t* etoe, int32_t* etof, int32_t* nbnode) {
+  if (!c) return DG_EINVAL;
+  if (!c->has_mesh) return DG_ESTATE;
+  const dgh::MeshData& m = c->mesh;
+  const int Nfp = c->re.Nfp;
+  for (int64_t i = 0; i < m.K * 4; ++i) {
+    if (etoe) etoe[i] = m.EToE[i];
+    if (etof) etof[i] = m.EToF[i];
+    if (nbnode)
+      for (int j = 0; j < Nfp; ++j) nbnode[i * Nfp + j] = m.pat[size_t(m.EToP[i]) * Nfp + j];
+  }
+  return DG_OK;
+}
+
+dg_status dg_geometry(const dg_ctx* c, double* geo, double* fgeo, double* J) {
+  if (!c) return DG_EINVAL;
+  if (!c->has_mesh) return DG_ESTATE;
+  const dgh::MeshData& m = c->mesh;
+  if (geo) std::memcpy(geo, m.geo.data(), m.geo.size() * sizeof(double));
+  if (fgeo) std::memcpy(fgeo, m.fgeo.data(), m.fgeo.size() * sizeof(double));
+  if (J) std::memcpy(J, m.J.data(), m.J.size() * sizeof(double));
+  return DG_OK;
+}
+
+}  // extern "C"

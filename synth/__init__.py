@@ -42,9 +42,17 @@ def _fourier_unit(x, seed, n_modes=16, kmax=3):
     a = rng.uniform(0.5, 1.0, size=n_modes)
     phi = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
     x = np.asarray(x, dtype=np.float64)
-    g = np.zeros(x.shape[:-1])
+    shp = x.shape[:-1]
+    # evaluated with torch's multi-threaded CPU kernels (FP64): the largest
+    # workload samples ~1e8 points
+    import torch
+    xt = torch.from_numpy(np.ascontiguousarray(x.reshape(-1, 3)))
+    g = torch.zeros(xt.shape[0], dtype=torch.float64)
     for m in range(n_modes):
-        g += a[m] * np.cos(2.0 * np.pi * (x @ ks[m]) + phi[m])
+        arg = xt @ torch.from_numpy(2.0 * np.pi * ks[m])
+        arg += phi[m]
+        g.add_(torch.cos_(arg), alpha=float(a[m]))
+    g = g.numpy().reshape(shp)
     return 0.5 * (1.0 + g / np.sum(np.abs(a)))
 
 
@@ -95,12 +103,19 @@ def layered_media(x, seed=9443, n_cells=24):
 # initial conditions and exact solutions: each returns fields[9, ...]
 # --------------------------------------------------------------------------
 
+def gaussian_pulse_vx(x, x0=(0.5, 0.5, 0.5), width=0.05):
+    """The only nonzero field of the Gaussian velocity pulse:
+    v_x = exp(-|x - x0|^2 / (2 w^2))."""
+    x = np.asarray(x, dtype=np.float64)
+    d = x - np.asarray(x0, dtype=np.float64)
+    return np.exp(-np.sum(d * d, axis=-1) / (2.0 * width * width))
+
+
 def gaussian_pulse(x, x0=(0.5, 0.5, 0.5), width=0.05):
     """v_x = exp(-|x - x0|^2 / (2 w^2)), every other field zero."""
     x = np.asarray(x, dtype=np.float64)
-    d = x - np.asarray(x0, dtype=np.float64)
     out = np.zeros((NFIELDS,) + x.shape[:-1])
-    out[0] = np.exp(-np.sum(d * d, axis=-1) / (2.0 * width * width))
+    out[0] = gaussian_pulse_vx(x, x0, width)
     return out
 
 
@@ -157,3 +172,34 @@ def random_state(K, Np, seed=0, dtype=np.float64):
     """A seeded random nodal state of shape [9, K, Np] (values in [-1, 1])."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-1.0, 1.0, size=(NFIELDS, K, Np)).astype(dtype)
+
+
+# --------------------------------------------------------------------------
+# meshes: per-element vertex coordinates [K, 4, 3] of a periodic box
+# --------------------------------------------------------------------------
+
+def kuhn_cube_vertices(n, length=1.0):
+    """The periodic cube [0, L]^3 cut into n^3 hexahedra (hexahedron
+    i + n*(j + n*k) with corner (i, j, k) L/n), each split into the six Kuhn
+    tetrahedra that share its main diagonal: for each permutation (a, b, c)
+    of the axes in lexicographic order, the path corner -> +e_a -> +e_b ->
+    +e_c.  Odd permutations list their last two vertices swapped, so that
+    every element is positively oriented.  Element index 6*hex + perm."""
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    odd = [False, True, True, False, False, True]
+    local = np.zeros((6, 4, 3))
+    for p, (a, b, c) in enumerate(perms):
+        path = [np.zeros(3)]
+        for ax in (a, b, c):
+            nxt = path[-1].copy()
+            nxt[ax] += 1.0
+            path.append(nxt)
+        if odd[p]:
+            path[2], path[3] = path[3], path[2]
+        local[p] = np.array(path)
+    out = np.empty((n, n, n, 6, 4, 3))
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                out[k, j, i] = local + np.array([i, j, k], dtype=np.float64)
+    return (out * (length / n)).reshape(-1, 4, 3)
