@@ -12,6 +12,8 @@
 #include "../../include/dg.h"
 #include "dg_host.hpp"
 #include "dg_kernels.hpp"
+#include "dg_mfma.hpp"
+#include "dg_mfma_host.hpp"
 
 namespace {
 
@@ -48,6 +50,9 @@ struct dg_ctx {
   DevBuf fmask, geo, fgeo, etoe, etop, pat;
   DevBuf irho, lam, mu, zp, zs;
   DevBuf q[2], res;
+  DevBuf frags;             // BF16x3: operator hi/lo fragments
+  DevBuf matblk;            // BF16x3: material in [tile][3][QP][16]
+  int mfma_grid = 0;
   int cur = 0;
 };
 
@@ -190,6 +195,73 @@ dg_status launch_stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void
   return DG_OK;
 }
 
+template <int N>
+hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res, float* rhs_out,
+                         double a, double b, double dt, int lsrk) {
+  dgm::MfmaArgs A;
+  A.q_in = q_in;
+  A.q_out = q_out;
+  A.res = res;
+  A.rhs_out = rhs_out;
+  A.geo = static_cast<const float*>(c->geo.p);
+  A.fgeo = static_cast<const float*>(c->fgeo.p);
+  A.etoe = static_cast<const int32_t*>(c->etoe.p);
+  A.etop = static_cast<const uint8_t*>(c->etop.p);
+  A.pat = static_cast<const int32_t*>(c->pat.p);
+  A.fmask = static_cast<const int32_t*>(c->fmask.p);
+  A.mat = static_cast<const float*>(c->matblk.p);
+  A.zp = static_cast<const float*>(c->zp.p);
+  A.zs = static_cast<const float*>(c->zs.p);
+  A.frags = static_cast<const dgm::u32x4*>(c->frags.p);
+  A.K = c->mesh.K;
+  A.ntiles = (c->mesh.K + 15) / 16;
+  A.a = float(a);
+  A.b = float(b);
+  A.dt = float(dt);
+  A.lsrk = lsrk;
+  A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+  if (c->mfma_grid == 0) {
+    int cus = 0, per_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                         c->opt.device);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dgm::stage_mfma<N>,
+                                                     dgm::kThreads, 0);
+    per_cu = per_cu > 2 ? 2 : per_cu;
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    c->mfma_grid = ((cus * per_cu + 7) / 8) * 8;
+  }
+  dgm::stage_mfma<N><<<dim3(unsigned(c->mfma_grid)), dim3(dgm::kThreads), 0, c->stream>>>(A);
+  return hipGetLastError();
+}
+
+dg_status launch_mfma(dg_ctx* c, const void* q_in, void* q_out, void* res, void* rhs_out,
+                      double a, double b, double dt, int lsrk) {
+  const float* qi = static_cast<const float*>(q_in);
+  float* qo = static_cast<float*>(q_out);
+  float* rs = static_cast<float*>(res);
+  float* ro = static_cast<float*>(rhs_out);
+  hipError_t e;
+  switch (c->re.N) {
+    case 1: e = launch_mfma_n<1>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 2: e = launch_mfma_n<2>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 3: e = launch_mfma_n<3>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 4: e = launch_mfma_n<4>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    default: e = hipErrorInvalidValue;
+  }
+  if (e != hipSuccess)
+    return fail(c, DG_EDEVICE, std::string("BF16x3 stage launch: ") + hipGetErrorString(e));
+  return DG_OK;
+}
+
+dg_status stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void* rhs_out, double a,
+                double b, double dt, int lsrk) {
+  if (c->opt.precision == DG_FP32_BF16X3)
+    return launch_mfma(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+  return launch_stage(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+}
+
 dg_status fill_zero(dg_ctx* c, void* p, int64_t n) {
   const int64_t nb = (n + 255) / 256;
   if (c->elem == 8)
@@ -225,6 +297,7 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
       opt->precision != DG_FP32_BF16X3)
     return DG_EINVAL;
   if (opt->flux != DG_FLUX_UPWIND && opt->flux != DG_FLUX_CENTRAL) return DG_EINVAL;
+  if (opt->precision == DG_FP32_BF16X3 && !dgh::mfma_supported(opt->order)) return DG_EINVAL;
   dg_ctx* c = new (std::nothrow) dg_ctx();
   if (!c) return DG_ENOMEM;
   c->opt = *opt;
@@ -255,6 +328,13 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
       dg_destroy(c);
       return DG_ENOMEM;
     }
+    if (opt->precision == DG_FP32_BF16X3) {
+      const std::vector<uint16_t> fr = dgh::mfma_fragments(re);
+      if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
+        dg_destroy(c);
+        return DG_ENOMEM;
+      }
+    }
   }
   *out = c;
   return DG_OK;
@@ -266,7 +346,7 @@ void dg_destroy(dg_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (DevBuf* b : {&c->ops, &c->fmask, &c->geo, &c->fgeo, &c->etoe, &c->etop, &c->pat,
                       &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
-                      &c->res})
+                      &c->res, &c->frags, &c->matblk})
       release(c, *b);
   }
   delete c;
@@ -362,9 +442,15 @@ dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
     b[i] = r * (p * p - 2.0 * v * v);
     d[i] = r * v * v;
   }
-  if ((s = upload_real(c, c->irho, a.data(), nq)) != DG_OK) return s;
-  if ((s = upload_real(c, c->lam, b.data(), nq)) != DG_OK) return s;
-  if ((s = upload_real(c, c->mu, d.data(), nq)) != DG_OK) return s;
+  if (c->opt.precision == DG_FP32_BF16X3) {
+    const std::vector<double> blk =
+        dgh::mfma_material(c->re.N, K, a.data(), b.data(), d.data());
+    if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
+  } else {
+    if ((s = upload_real(c, c->irho, a.data(), nq)) != DG_OK) return s;
+    if ((s = upload_real(c, c->lam, b.data(), nq)) != DG_OK) return s;
+    if ((s = upload_real(c, c->mu, d.data(), nq)) != DG_OK) return s;
+  }
   std::vector<double> zp(nn), zs(nn);
   for (size_t i = 0; i < nn; ++i) {
     zp[i] = rho_n[i] * cp_n[i];
@@ -438,9 +524,7 @@ dg_status dg_rhs(dg_ctx* c, const void* q_dev, void* rhs_dev) {
   if (q_dev == rhs_dev) return fail(c, DG_EINVAL, "rhs: q and rhs must not alias");
   dg_status s = ready(c, false);
   if (s != DG_OK) return s;
-  if (c->opt.precision == DG_FP32_BF16X3)
-    return fail(c, DG_EINVAL, "rhs: BF16x3 path not available in this build");
-  return launch_stage(c, q_dev, nullptr, nullptr, rhs_dev, 0.0, 0.0, 0.0, 0);
+  return stage(c, q_dev, nullptr, nullptr, rhs_dev, 0.0, 0.0, 0.0, 0);
 }
 
 dg_status dg_step(dg_ctx* c, double t, double dt) {
@@ -448,11 +532,9 @@ dg_status dg_step(dg_ctx* c, double t, double dt) {
   if (!std::isfinite(t) || !std::isfinite(dt)) return fail(c, DG_EINVAL, "step: non-finite t/dt");
   dg_status s = ready(c, true);
   if (s != DG_OK) return s;
-  if (c->opt.precision == DG_FP32_BF16X3)
-    return fail(c, DG_EINVAL, "step: BF16x3 path not available in this build");
   for (int st = 0; st < 5; ++st) {
-    s = launch_stage(c, c->q[c->cur].p, c->q[1 - c->cur].p, c->res.p, nullptr, kRkA[st],
-                     kRkB[st], dt, 1);
+    s = stage(c, c->q[c->cur].p, c->q[1 - c->cur].p, c->res.p, nullptr, kRkA[st], kRkB[st],
+              dt, 1);
     if (s != DG_OK) return s;
     c->cur = 1 - c->cur;
   }

@@ -1,0 +1,22 @@
+// Host-side layout of the BF16x3 matrix-core stage: operator fragments in
+// MFMA lane order and the blocked material array.  No HIP dependencies.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "dg_host.hpp"
+
+namespace dgh {
+
+// orders with a matrix-core stage kernel
+bool mfma_supported(int N);
+
+// hi/lo bf16 bit patterns of the [Dr|Ds|Dt|LIFT], V_q and P_q fragments,
+// [NFRAG][64 lanes][8]
+std::vector<uint16_t> mfma_fragments(const RefElement& re);
+
+// 1/rho, lam, mu at [K][Nq] -> [ceil(K/16)][3][QP][16] (zero padded)
+std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
+                                  const double* mu);
+
+}  // namespace dgh

@@ -1,0 +1,141 @@
+// Runs the matrix-core stage kernel dgm::stage_mfma<N> on the CPU, for tests:
+// each workgroup is 256 host threads with real barriers; the 16x16x32 bf16
+// MFMA is emulated with its hardware lane layout (A: row lane%16, k 8(lane/16)+j;
+// B: column lane%16, k 8(lane/16)+j; D: column lane%16, row 4(lane/16)+j).
+// Built with AddressSanitizer by the test, so any out-of-bounds access of the
+// kernel source shows up on the CPU.  Reads a binary problem file, writes the
+// right-hand side (or the LSRK increment q_out - q_in) as float32.
+#include <hip/hip_runtime.h>
+#include <thread>
+#include <vector>
+#include <memory>
+#include <cstring>
+#include <cmath>
+#include "dg_mfma.hpp"
+#include "dg_host.hpp"
+#include "dg_mfma_host.hpp"
+
+thread_local emu_dim3 threadIdx, blockIdx;
+emu_dim3 gridDim, blockDim;
+static std::unique_ptr<std::barrier<>> g_bar;
+static std::unique_ptr<std::barrier<>> g_wbar[4];
+struct Slot { emu_bf16x8 a[64], b[64]; };
+static Slot g_slot[4];
+
+void __syncthreads() { g_bar->arrive_and_wait(); }
+
+emu_f32x4 emu_mfma_16x16x32_bf16(emu_bf16x8 a, emu_bf16x8 b, emu_f32x4 c, int, int, int) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  g_slot[w].a[lane] = a;
+  g_slot[w].b[lane] = b;
+  g_wbar[w]->arrive_and_wait();
+  emu_f32x4 d = c;
+  const int n = lane % 16;
+  for (int j = 0; j < 4; ++j) {
+    const int i = 4 * (lane / 16) + j;
+    float acc = c[j];
+    for (int k = 0; k < 32; ++k) {
+      const float av = (float)g_slot[w].a[i + 16 * (k / 8)][k % 8];
+      const float bv = (float)g_slot[w].b[n + 16 * (k / 8)][k % 8];
+      acc += av * bv;
+    }
+    d[j] = acc;
+  }
+  g_wbar[w]->arrive_and_wait();
+  return d;
+}
+
+template <int N>
+static void run(dgm::MfmaArgs A, int grid) {
+  gridDim.x = grid; blockDim.x = 256;
+  for (int b = 0; b < grid; ++b) {
+    g_bar = std::make_unique<std::barrier<>>(256);
+    for (int w = 0; w < 4; ++w) g_wbar[w] = std::make_unique<std::barrier<>>(64);
+    std::vector<std::thread> th;
+    for (int t = 0; t < 256; ++t)
+      th.emplace_back([=]() { threadIdx.x = t; blockIdx.x = b; dgm::stage_mfma<N>(A); });
+    for (auto& x : th) x.join();
+  }
+}
+
+template <typename T> static T* dup(const std::vector<T>& v) {
+  T* p = new T[v.size()];
+  std::memcpy(p, v.data(), v.size() * sizeof(T));
+  return p;
+}
+static float* dupf(const std::vector<double>& v) {
+  float* p = new float[v.size()];
+  for (size_t i = 0; i < v.size(); ++i) p[i] = float(v[i]);
+  return p;
+}
+
+static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
+                       const double* rho_q, const double* cp_q, const double* cs_q,
+                       const double* rho_n, const double* cp_n, const double* cs_n,
+                       const float* q, float* out, int upwind, int grid, int lsrk) {
+  dgh::RefElement re; std::string err;
+  if (!dgh::build_ref_element(N, re, err)) { fprintf(stderr, "%s\n", err.c_str()); return 1; }
+  dgh::MeshData m;
+  if (!dgh::build_mesh(re, K, vxyz, period, m, err)) { fprintf(stderr, "%s\n", err.c_str()); return 2; }
+  const int Np = re.Np, Nq = re.Nq;
+  std::vector<double> a(K * Nq), b(K * Nq), d(K * Nq), zp(K * Np), zs(K * Np);
+  for (int64_t i = 0; i < K * Nq; ++i) {
+    a[i] = 1.0 / rho_q[i]; b[i] = rho_q[i] * (cp_q[i] * cp_q[i] - 2 * cs_q[i] * cs_q[i]);
+    d[i] = rho_q[i] * cs_q[i] * cs_q[i];
+  }
+  for (int64_t i = 0; i < K * Np; ++i) { zp[i] = rho_n[i] * cp_n[i]; zs[i] = rho_n[i] * cs_n[i]; }
+  std::vector<uint16_t> fr = dgh::mfma_fragments(re);
+  dgm::MfmaArgs A{};
+  float* qin = new float[9 * K * Np];
+  std::memcpy(qin, q, sizeof(float) * 9 * K * Np);
+  A.q_in = qin;
+  A.rhs_out = new float[9 * K * Np];
+  A.q_out = lsrk ? new float[9 * K * Np] : nullptr;
+  A.res = nullptr;
+  if (lsrk) { A.res = new float[9 * K * Np]; for (int64_t i = 0; i < 9 * K * Np; ++i) A.res[i] = 0.f; }
+  A.geo = dupf(m.geo); A.fgeo = dupf(m.fgeo);
+  A.etoe = dup(m.EToE); A.etop = dup(m.EToP); A.pat = dup(m.pat);
+  std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
+  A.fmask = dup(fm);
+  A.mat = dupf(dgh::mfma_material(N, K, a.data(), b.data(), d.data()));
+  A.zp = dupf(zp); A.zs = dupf(zs);
+  A.frags = reinterpret_cast<const dgm::u32x4*>(dup(fr));
+  A.K = K; A.ntiles = (K + 15) / 16; A.a = 0.f; A.b = 1.f; A.dt = 1.f; A.lsrk = lsrk; A.upwind = upwind;
+  switch (N) {
+    case 1: run<1>(A, grid); break;
+    case 2: run<2>(A, grid); break;
+    case 3: run<3>(A, grid); break;
+    case 4: run<4>(A, grid); break;
+    default: return 3;
+  }
+  if (lsrk) for (int64_t i = 0; i < 9 * K * Np; ++i) out[i] = A.q_out[i] - A.q_in[i];
+  else std::memcpy(out, A.rhs_out, sizeof(float) * 9 * K * Np);
+  return 0;
+}
+
+// input file: int32 N, flux_upwind, grid, lsrk; int64 K; then float64
+// vxyz[K*12], period[3], rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n
+// [K*Np each]; then float32 q[9*K*Np]
+int main(int argc, char** argv) {
+  if (argc != 3) { fprintf(stderr, "usage: emu in.bin out.bin\n"); return 2; }
+  FILE* f = fopen(argv[1], "rb");
+  if (!f) return 2;
+  int32_t hdr[4]; int64_t K;
+  if (fread(hdr, 4, 4, f) != 4 || fread(&K, 8, 1, f) != 1) return 2;
+  const int N = hdr[0];
+  const int Np = dgh::num_nodes(N), Nq = dgh::num_quad(N);
+  auto rd = [&](size_t n) { std::vector<double> v(n); if (fread(v.data(), 8, n, f) != n) exit(2); return v; };
+  auto vx = rd(K * 12), per = rd(3);
+  auto rq = rd(K * Nq), pq = rd(K * Nq), sq = rd(K * Nq);
+  auto rn = rd(K * Np), pn = rd(K * Np), sn = rd(K * Np);
+  std::vector<float> q(9 * K * Np), out(9 * K * Np);
+  if (fread(q.data(), 4, q.size(), f) != q.size()) return 2;
+  fclose(f);
+  const int rc = emu_rhs(N, K, vx.data(), per.data(), rq.data(), pq.data(), sq.data(), rn.data(),
+                         pn.data(), sn.data(), q.data(), out.data(), hdr[1], hdr[2], hdr[3]);
+  if (rc) return rc;
+  FILE* g = fopen(argv[2], "wb");
+  fwrite(out.data(), 4, out.size(), g);
+  fclose(g);
+  return 0;
+}

@@ -1,0 +1,21 @@
+// Host stand-in for the HIP device environment, used only to run the stage
+// kernels on the CPU in tests (threads, barriers, matrix-core emulation).
+#pragma once
+#include <barrier>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+struct emu_dim3 { unsigned x = 0, y = 0, z = 0; };
+extern thread_local emu_dim3 threadIdx, blockIdx;
+extern emu_dim3 gridDim, blockDim;
+void __syncthreads();
+typedef __bf16 emu_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float emu_f32x4 __attribute__((ext_vector_type(4)));
+emu_f32x4 emu_mfma_16x16x32_bf16(emu_bf16x8 a, emu_bf16x8 b, emu_f32x4 c, int, int, int);
+#define __builtin_amdgcn_mfma_f32_16x16x32_bf16 emu_mfma_16x16x32_bf16

@@ -98,3 +98,71 @@ def test_plane_wave_order3_workload_fp64():
     e_exact = np.sqrt(op.l2_sq(got - qe).sum() / op.l2_sq(qe).sum())
     print("error vs exact solution:", e_exact)
     assert e_exact < 1e-2
+
+
+# --------------------------------------------------------------------------
+# BF16x3 matrix-core path: per-field relative L2 against the FP64 oracle.
+# Each split product carries ~2^-17 relative error; sums of O(Np) terms with
+# operator entries up to ~10 give ~1e-5 on random states.  Bound: 1e-4
+# for random and smooth projected states alike (smooth data cancels more in
+# the derivative sums, so its relative error is the larger); measured values
+# are printed.
+# --------------------------------------------------------------------------
+
+# The order-4 BF16x3 stage kernel faulted the GPU once (an illegal address in
+# the order-4 right-hand side call) although its CPU emulation under
+# AddressSanitizer finds every access in bounds; the order is switched off
+# in the library until the cause is shown, and its cases are skipped.
+N4_SKIP = pytest.mark.skip(reason="order-4 BF16x3 stage switched off after an "
+                                  "unexplained GPU fault (see DESIGN.md)")
+
+
+@pytest.mark.parametrize("n,N", [(3, 1), (3, 2), (3, 3), (4, 3),
+                                 pytest.param(3, 4, marks=N4_SKIP),
+                                 pytest.param(5, 4, marks=N4_SKIP)])
+@pytest.mark.parametrize("flux", ["upwind", "central"])
+def test_rhs_bf16x3_matches_oracle(n, N, flux):
+    print(f"case rhs bf16x3 n={n} N={N} flux={flux}", flush=True)
+    op, s = make_pair(n, N, synth.fourier_media, flux, "bf16x3")
+    q = synth.random_state(op.K, op.Np, seed=40 + N).astype(np.float32).astype(np.float64)
+    ref = op.rhs(q)
+    got = s.rhs(_dev(q, torch.float32)).cpu().numpy()
+    err = rel_l2_per_field(got, ref)
+    print("per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 1e-4
+
+
+def test_rhs_bf16x3_smooth_state():
+    op, s = make_pair(4, 3, synth.fourier_media, "upwind", "bf16x3")
+    q = op.project_function(lambda x: synth.plane_p_wave(x, 0.1) + synth.plane_s_wave(x, 0.2)
+                            + synth.gaussian_pulse(x, width=0.15))
+    q = q.astype(np.float32).astype(np.float64)
+    ref = op.rhs(q)
+    got = s.rhs(_dev(q, torch.float32)).cpu().numpy()
+    err = rel_l2_per_field(got, ref)
+    print("bf16x3 per-field rel L2:", np.array2string(err, precision=2))
+    _, s32 = make_pair(4, 3, synth.fourier_media, "upwind", "fp32", oracle=False)
+    err32 = rel_l2_per_field(s32.rhs(_dev(q, torch.float32)).cpu().numpy(), ref)
+    print("fp32   per-field rel L2:", np.array2string(err32, precision=2))
+    assert err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("n,N", [pytest.param(3, 4, marks=N4_SKIP), (4, 3), (3, 2)])
+def test_one_lsrk_step_bf16x3_matches_oracle(n, N):
+    op, s = make_pair(n, N, synth.fourier_media, "upwind", "bf16x3")
+    q0 = synth.random_state(op.K, op.Np, seed=50 + N).astype(np.float32).astype(np.float64)
+    dt = 1e-3
+    ref, _ = op.step(q0, np.zeros_like(q0), dt)
+    s.set_state(q0)
+    s.step(0.0, dt)
+    got = s.get_state()
+    err = rel_l2_per_field(got, ref)
+    print("per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 1e-5
+
+
+def test_bf16x3_rejects_unsupported_order():
+    from paper_2008_09441_amd import B
+    for N in (4, 5):
+        with pytest.raises(B.DGError):
+            B.dg_create(N, B.DG_FP32_BF16X3, B.DG_FLUX_UPWIND, 0)
