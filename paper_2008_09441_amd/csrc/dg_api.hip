@@ -47,6 +47,7 @@ struct dg_ctx {
   size_t allocated = 0;     // device bytes held
   // device arrays
   DevBuf ops;               // Dr | Ds | Dt | LIFT | Vq | Pq
+  DevBuf opsT;              // transposed: DrT | DsT | DtT | LIFTT | VqT | PqT
   DevBuf fmask, geo, fgeo, etoe, etop, pat;
   DevBuf irho, lam, mu, zp, zs;
   DevBuf q[2], res;
@@ -159,9 +160,49 @@ hipError_t launch_generic(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* r
   A.lsrk = lsrk;
   A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
   constexpr int E = dgk::elems_per_block<T, N>();
-  constexpr int lds = dgk::lds_bytes<T, N>();
   const int64_t nblk = (c->mesh.K + E - 1) / E;
-  dgk::stage_generic<T, N><<<dim3(unsigned(nblk)), dim3(dgk::kBlock), lds, c->stream>>>(A);
+  dgk::stage_generic<T, N><<<dim3(unsigned(nblk)), dim3(dgk::kBlock), 0, c->stream>>>(A);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t launch_cols(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_out, double a,
+                       double b, double dt, int lsrk) {
+  const dgh::RefElement& re = c->re;
+  dgk::ColArgs<T> A;
+  using CO = dgk::ColOrder<N>;
+  const T* ops = static_cast<const T*>(c->opsT.p);
+  const size_t dsz = size_t(re.Np) * CO::NpP;
+  A.q_in = q_in;
+  A.q_out = q_out;
+  A.res = res;
+  A.rhs_out = rhs_out;
+  A.geo = static_cast<const T*>(c->geo.p);
+  A.fgeo = static_cast<const T*>(c->fgeo.p);
+  A.etoe = static_cast<const int32_t*>(c->etoe.p);
+  A.etop = static_cast<const uint8_t*>(c->etop.p);
+  A.pat = static_cast<const int32_t*>(c->pat.p);
+  A.fmask = static_cast<const int32_t*>(c->fmask.p);
+  A.irho = static_cast<const T*>(c->irho.p);
+  A.lam = static_cast<const T*>(c->lam.p);
+  A.mu = static_cast<const T*>(c->mu.p);
+  A.zp = static_cast<const T*>(c->zp.p);
+  A.zs = static_cast<const T*>(c->zs.p);
+  A.DrT = ops;
+  A.DsT = ops + dsz;
+  A.DtT = ops + 2 * dsz;
+  A.LIFTT = ops + 3 * dsz;
+  A.VqT = A.LIFTT + size_t(4 * re.Nfp) * CO::NpP;
+  A.PqT = A.VqT + size_t(re.Np) * CO::QP;
+  A.K = c->mesh.K;
+  A.a = T(a);
+  A.b = T(b);
+  A.dt = T(dt);
+  A.lsrk = lsrk;
+  A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+  constexpr int E = dgk::ColLayout<T, N>::E;
+  const int64_t nblk = (c->mesh.K + E - 1) / E;
+  dgk::stage_cols<T, N><<<dim3(unsigned(nblk)), dim3(dgk::kBlock), 0, c->stream>>>(A);
   return hipGetLastError();
 }
 
@@ -169,10 +210,10 @@ template <typename T>
 hipError_t launch_stage_t(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_out,
                           double a, double b, double dt, int lsrk) {
   switch (c->re.N) {
-    case 1: return launch_generic<T, 1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 2: return launch_generic<T, 2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 3: return launch_generic<T, 3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 4: return launch_generic<T, 4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 1: return launch_cols<T, 1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 2: return launch_cols<T, 2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 3: return launch_cols<T, 3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 4: return launch_cols<T, 4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 5: return launch_generic<T, 5>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 6: return launch_generic<T, 6>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 7: return launch_generic<T, 7>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
@@ -323,7 +364,10 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
     const dgh::RefElement& re = c->re;
     for (const auto* v : {&re.Dr, &re.Ds, &re.Dt, &re.LIFT, &re.Vq, &re.Pq})
       ops.insert(ops.end(), v->begin(), v->end());
-    if (upload_real(c, c->ops, ops.data(), ops.size()) != DG_OK ||
+    // transposed, padded operators for the column kernel
+    const std::vector<double> opsT = dgh::col_operators(re);
+    if (upload_real(c, c->opsT, opsT.data(), opsT.size()) != DG_OK ||
+        upload_real(c, c->ops, ops.data(), ops.size()) != DG_OK ||
         upload_raw(c, c->fmask, re.Fmask.data(), re.Fmask.size()) != DG_OK) {
       dg_destroy(c);
       return DG_ENOMEM;
@@ -344,7 +388,7 @@ void dg_destroy(dg_ctx* c) {
   if (!c) return;
   if (device_ctx(c) && hipSetDevice(c->opt.device) == hipSuccess) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->ops, &c->fmask, &c->geo, &c->fgeo, &c->etoe, &c->etop, &c->pat,
+    for (DevBuf* b : {&c->ops, &c->opsT, &c->fmask, &c->geo, &c->fgeo, &c->etoe, &c->etop, &c->pat,
                       &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
                       &c->res, &c->frags, &c->matblk})
       release(c, *b);

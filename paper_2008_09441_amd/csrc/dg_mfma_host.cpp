@@ -108,6 +108,25 @@ std::vector<uint16_t> mfma_fragments(const RefElement& re) {
   }
 }
 
+std::vector<double> col_operators(const RefElement& re) {
+  const int Np = re.Np, Nq = re.Nq, NF4 = 4 * re.Nfp;
+  const int NpP = 4 * ((Np + 3) / 4), QP = 32 * ((Nq + 31) / 32);
+  std::vector<double> out;
+  // T[i][j] = M[j][i] for i < cols_in, j < rows_out (zero elsewhere)
+  auto put = [&](const std::vector<double>& M, int mrows, int mcols, int trows, int tcols) {
+    for (int i = 0; i < trows; ++i)
+      for (int j = 0; j < tcols; ++j)
+        out.push_back((i < mcols && j < mrows) ? M[size_t(j) * mcols + i] : 0.0);
+  };
+  put(re.Dr, Np, Np, Np, NpP);
+  put(re.Ds, Np, Np, Np, NpP);
+  put(re.Dt, Np, Np, Np, NpP);
+  put(re.LIFT, Np, NF4, NF4, NpP);
+  put(re.Vq, Nq, Np, Np, QP);
+  put(re.Pq, Np, Nq, QP, NpP);
+  return out;
+}
+
 std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
                                   const double* mu) {
   // [tile][field][QP][16]: the accumulator layout reads 16 elements of one

@@ -15,6 +15,11 @@ bool mfma_supported(int N);
 // [NFRAG][64 lanes][8]
 std::vector<uint16_t> mfma_fragments(const RefElement& re);
 
+// Column-kernel operator pack: DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],
+// VqT [Np][QP], PqT [QP][NpP] (transposed, zero padded; NpP = 4 ceil(Np/4),
+// QP = 32 ceil(Nq/32)).
+std::vector<double> col_operators(const RefElement& re);
+
 // 1/rho, lam, mu at [K][Nq] -> [ceil(K/16)][3][QP][16] (zero padded)
 std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
                                   const double* mu);

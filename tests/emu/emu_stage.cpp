@@ -4,13 +4,14 @@
 // B: column lane%16, k 8(lane/16)+j; D: column lane%16, row 4(lane/16)+j).
 // Built with AddressSanitizer by the test, so any out-of-bounds access of the
 // kernel source shows up on the CPU.  Reads a binary problem file, writes the
-// right-hand side (or the LSRK increment q_out - q_in) as float32.
+// right-hand side (or the LSRK increment q_out - q_in) as float64.
 #include <hip/hip_runtime.h>
 #include <thread>
 #include <vector>
 #include <memory>
 #include <cstring>
 #include <cmath>
+#include "dg_kernels.hpp"
 #include "dg_mfma.hpp"
 #include "dg_host.hpp"
 #include "dg_mfma_host.hpp"
@@ -45,17 +46,22 @@ emu_f32x4 emu_mfma_16x16x32_bf16(emu_bf16x8 a, emu_bf16x8 b, emu_f32x4 c, int, i
   return d;
 }
 
-template <int N>
-static void run(dgm::MfmaArgs A, int grid) {
+template <typename F>
+static void run_grid(int grid, F kern) {
   gridDim.x = grid; blockDim.x = 256;
   for (int b = 0; b < grid; ++b) {
     g_bar = std::make_unique<std::barrier<>>(256);
     for (int w = 0; w < 4; ++w) g_wbar[w] = std::make_unique<std::barrier<>>(64);
     std::vector<std::thread> th;
     for (int t = 0; t < 256; ++t)
-      th.emplace_back([=]() { threadIdx.x = t; blockIdx.x = b; dgm::stage_mfma<N>(A); });
+      th.emplace_back([=]() { threadIdx.x = t; blockIdx.x = b; kern(); });
     for (auto& x : th) x.join();
   }
+}
+
+template <int N>
+static void run(dgm::MfmaArgs A, int grid) {
+  run_grid(grid, [=]() { dgm::stage_mfma<N>(A); });
 }
 
 template <typename T> static T* dup(const std::vector<T>& v) {
@@ -69,10 +75,66 @@ static float* dupf(const std::vector<double>& v) {
   return p;
 }
 
+template <typename T>
+static T* dupT(const std::vector<double>& v) {
+  T* p = new T[v.size()];
+  for (size_t i = 0; i < v.size(); ++i) p[i] = T(v[i]);
+  return p;
+}
+
+template <typename T, int N>
+static void run_cols(const dgh::RefElement& re, const dgh::MeshData& m, int64_t K,
+                     const std::vector<double>& irho, const std::vector<double>& lam,
+                     const std::vector<double>& mu, const std::vector<double>& zp,
+                     const std::vector<double>& zs, const float* q, double* out, int upwind,
+                     int lsrk) {
+  const int Np = re.Np;
+  dgk::ColArgs<T> A{};
+  std::vector<double> qd(q, q + 9 * K * Np);
+  A.q_in = dupT<T>(qd);
+  A.rhs_out = new T[9 * K * Np];
+  A.q_out = lsrk ? new T[9 * K * Np] : nullptr;
+  A.res = nullptr;
+  if (lsrk) { A.res = new T[9 * K * Np]; for (int64_t i = 0; i < 9 * K * Np; ++i) A.res[i] = T(0); }
+  A.geo = dupT<T>(m.geo); A.fgeo = dupT<T>(m.fgeo);
+  A.etoe = dup(m.EToE); A.etop = dup(m.EToP); A.pat = dup(m.pat);
+  std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
+  A.fmask = dup(fm);
+  A.irho = dupT<T>(irho); A.lam = dupT<T>(lam); A.mu = dupT<T>(mu);
+  A.zp = dupT<T>(zp); A.zs = dupT<T>(zs);
+  using CO = dgk::ColOrder<N>;
+  const std::vector<double> ops = dgh::col_operators(re);
+  const T* opsT = dupT<T>(ops);
+  const size_t dsz = size_t(Np) * CO::NpP;
+  A.DrT = opsT; A.DsT = opsT + dsz; A.DtT = opsT + 2 * dsz; A.LIFTT = opsT + 3 * dsz;
+  A.VqT = A.LIFTT + size_t(4 * re.Nfp) * CO::NpP; A.PqT = A.VqT + size_t(Np) * CO::QP;
+  A.K = K; A.a = T(0); A.b = T(1); A.dt = T(1); A.lsrk = lsrk; A.upwind = upwind;
+  constexpr int E = dgk::ColLayout<T, N>::E;
+  const int grid = int((K + E - 1) / E);
+  run_grid(grid, [=]() { dgk::stage_cols<T, N>(A); });
+  for (int64_t i = 0; i < 9 * K * Np; ++i)
+    out[i] = lsrk ? double(A.q_out[i]) - double(A.q_in[i]) : double(A.rhs_out[i]);
+}
+
+template <typename T>
+static int cols_dispatch(int N, const dgh::RefElement& re, const dgh::MeshData& m, int64_t K,
+                         const std::vector<double>& a, const std::vector<double>& b,
+                         const std::vector<double>& d, const std::vector<double>& zp,
+                         const std::vector<double>& zs, const float* q, double* out, int up,
+                         int lsrk) {
+  switch (N) {
+    case 1: run_cols<T, 1>(re, m, K, a, b, d, zp, zs, q, out, up, lsrk); return 0;
+    case 2: run_cols<T, 2>(re, m, K, a, b, d, zp, zs, q, out, up, lsrk); return 0;
+    case 3: run_cols<T, 3>(re, m, K, a, b, d, zp, zs, q, out, up, lsrk); return 0;
+    case 4: run_cols<T, 4>(re, m, K, a, b, d, zp, zs, q, out, up, lsrk); return 0;
+    default: return 3;
+  }
+}
+
 static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
                        const double* rho_q, const double* cp_q, const double* cs_q,
                        const double* rho_n, const double* cp_n, const double* cs_n,
-                       const float* q, float* out, int upwind, int grid, int lsrk) {
+                       const float* q, double* out, int upwind, int grid, int lsrk) {
   dgh::RefElement re; std::string err;
   if (!dgh::build_ref_element(N, re, err)) { fprintf(stderr, "%s\n", err.c_str()); return 1; }
   dgh::MeshData m;
@@ -84,6 +146,9 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
     d[i] = rho_q[i] * cs_q[i] * cs_q[i];
   }
   for (int64_t i = 0; i < K * Np; ++i) { zp[i] = rho_n[i] * cp_n[i]; zs[i] = rho_n[i] * cs_n[i]; }
+  if (grid < 0)
+    return grid == -1 ? cols_dispatch<float>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk)
+                      : cols_dispatch<double>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk);
   std::vector<uint16_t> fr = dgh::mfma_fragments(re);
   dgm::MfmaArgs A{};
   float* qin = new float[9 * K * Np];
@@ -108,12 +173,13 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
     case 4: run<4>(A, grid); break;
     default: return 3;
   }
-  if (lsrk) for (int64_t i = 0; i < 9 * K * Np; ++i) out[i] = A.q_out[i] - A.q_in[i];
-  else std::memcpy(out, A.rhs_out, sizeof(float) * 9 * K * Np);
+  for (int64_t i = 0; i < 9 * K * Np; ++i)
+    out[i] = lsrk ? double(A.q_out[i]) - double(A.q_in[i]) : double(A.rhs_out[i]);
   return 0;
 }
 
-// input file: int32 N, flux_upwind, grid, lsrk; int64 K; then float64
+// input file: int32 N, flux_upwind, grid (>0: matrix-core kernel with that
+// grid; -1 / -2: column kernel in FP32 / FP64), lsrk; int64 K; then float64
 // vxyz[K*12], period[3], rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n
 // [K*Np each]; then float32 q[9*K*Np]
 int main(int argc, char** argv) {
@@ -128,14 +194,15 @@ int main(int argc, char** argv) {
   auto vx = rd(K * 12), per = rd(3);
   auto rq = rd(K * Nq), pq = rd(K * Nq), sq = rd(K * Nq);
   auto rn = rd(K * Np), pn = rd(K * Np), sn = rd(K * Np);
-  std::vector<float> q(9 * K * Np), out(9 * K * Np);
+  std::vector<float> q(9 * K * Np);
+  std::vector<double> out(9 * K * Np);
   if (fread(q.data(), 4, q.size(), f) != q.size()) return 2;
   fclose(f);
   const int rc = emu_rhs(N, K, vx.data(), per.data(), rq.data(), pq.data(), sq.data(), rn.data(),
                          pn.data(), sn.data(), q.data(), out.data(), hdr[1], hdr[2], hdr[3]);
   if (rc) return rc;
   FILE* g = fopen(argv[2], "wb");
-  fwrite(out.data(), 4, out.size(), g);
+  fwrite(out.data(), 8, out.size(), g);
   fclose(g);
   return 0;
 }

@@ -1,7 +1,8 @@
-"""CPU check of the BF16x3 matrix-core stage kernel source: the unchanged
-kernel runs on host threads (tests/emu) built with AddressSanitizer, so any
-out-of-bounds index fails the test, and its result is compared with the FP64
-oracle at the BF16x3 bound (1e-4 per-field relative L2)."""
+"""CPU check of the stage kernel sources: the unchanged kernels (the BF16x3
+matrix-core kernel and the FP32/FP64 column kernel) run on host threads
+(tests/emu) built with AddressSanitizer, so any out-of-bounds index fails the
+test, and their results are compared with the FP64 oracle (BF16x3: 1e-4,
+FP32: 2e-5, FP64: 1e-12 per-field relative L2)."""
 import os
 import shutil
 import subprocess
@@ -50,7 +51,7 @@ def _run(exe, tmp_path, n, N, flux="upwind", grid=16, lsrk=0):
     r = subprocess.run([exe, str(fin), str(fout)], capture_output=True, text=True, env=env,
                        timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
-    got = np.fromfile(fout, np.float32).reshape(9, op.K, op.Np)
+    got = np.fromfile(fout, np.float64).reshape(9, op.K, op.Np)
     ref = op.rhs(q.astype(np.float64))
     return rel_l2_per_field(got, ref)
 
@@ -66,3 +67,17 @@ def test_stage_kernel_lsrk_mode(emu_exe, tmp_path):
     # with a = 0, b = dt = 1 the LSRK increment q_out - q_in equals the rhs
     err = _run(emu_exe, tmp_path, 2, 3, "upwind", grid=8, lsrk=1)
     assert err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("n,N,prec,flux", [(3, 1, "f64", "upwind"), (3, 2, "f32", "central"),
+                                           (3, 3, "f64", "upwind"), (3, 4, "f64", "upwind"),
+                                           (3, 4, "f32", "upwind")])
+def test_column_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, prec, flux):
+    err = _run(emu_exe, tmp_path, n, N, flux, grid=-1 if prec == "f32" else -2)
+    print(prec, "per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= (2e-5 if prec == "f32" else 1e-12)
+
+
+def test_column_kernel_lsrk_mode(emu_exe, tmp_path):
+    err = _run(emu_exe, tmp_path, 2, 4, "upwind", grid=-2, lsrk=1)
+    assert err.max() <= 1e-12
