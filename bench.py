@@ -39,6 +39,28 @@ def alg_bytes_per_elem_stage(N, elem_bytes):
     return reals * elem_bytes + 4 * 4 + 4
 
 
+def measured_traffic(kernel, precision, order, elements):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE record of
+    this kernel and workload, or None when there is none or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_records.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        line = line.strip()
+        if not line:
+            continue
+        r = json.loads(line)
+        if (r["kernel"], r["precision"], r["order"], r["elements"]) != (kernel, precision, order, elements):
+            continue
+        src = open(os.path.join(ROOT, r["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest()[:16] != r["source_sha256_16"]:
+            return None
+        return 1024.0 * (r["fetch_kib"] * r["fetch_factor"] + r["write_kib"] * r["write_factor"])
+    return None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -54,6 +76,15 @@ def parse():
                    help="before timing, copy 256 MiB device to device once so that "
                         "counter runs see a kernel with known read/write bytes")
     return p.parse_args()
+
+
+def stage_kernel_name(precision, N):
+    """The kernel one stage launches for this precision and order."""
+    if precision == "bf16x3":
+        return f"stage_mfma<{N}>"
+    if N <= 4:
+        return f"stage_cols<{'double' if precision == 'fp64' else 'float'},{N}>"
+    return f"stage_generic<{'double' if precision == 'fp64' else 'float'},{N}>"
 
 
 def setup(args, precision, q0=None):
@@ -164,6 +195,7 @@ def main():
     eb = 8 if args.precision == "fp64" else 4
     bytes_launch = alg_bytes_per_elem_stage(N, eb) * K
     achieved = bytes_launch / stage_s / 1e9
+    kernel = stage_kernel_name(args.precision, N)
 
     out = {
         "metric": "DG DOF-updates/sec (FP32/BF16x3 vs FP64 at stated L2 error); batched p50/p99",
@@ -178,8 +210,9 @@ def main():
                    "order": N, "elements": K, "dofs": dofs, "precision": args.precision,
                    "dt": dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                     "frac": achieved / 8000.0, "traffic": None,
-                     "kernel": "dgk::stage (fused RHS + LSRK stage)",
+                     "frac": achieved / 8000.0,
+                     "traffic": measured_traffic(kernel, args.precision, N, K),
+                     "kernel": kernel,
                      "alg_bytes_per_launch": bytes_launch,
                      "avg_launch_us": stage_s * 1e6},
         "wall_s_timed": wall,
