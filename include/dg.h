@@ -55,7 +55,7 @@ typedef enum { DG_FP64 = 0, DG_FP32 = 1, DG_FP32_BF16X3 = 2 } dg_precision;
 typedef enum { DG_FLUX_UPWIND = 0, DG_FLUX_CENTRAL = 1 } dg_flux;
 
 typedef struct {
-  int32_t order;             /* N, 1..7                                          */
+  int32_t order;             /* N, 1..7 (DG_FP32_BF16X3: 1..4, else DG_EINVAL)   */
   int32_t precision;         /* dg_precision                                     */
   int32_t flux;              /* dg_flux                                          */
   int32_t device;            /* HIP device ordinal; -1 = host-only (no GPU work) */

@@ -12,7 +12,7 @@
 #include "../../include/dg.h"
 #include "dg_host.hpp"
 #include "dg_kernels.hpp"
-#include "dg_mfma.hpp"
+#include "dg_bx.hpp"
 #include "dg_mfma_host.hpp"
 
 namespace {
@@ -52,8 +52,7 @@ struct dg_ctx {
   DevBuf irho, lam, mu, zp, zs;
   DevBuf q[2], res;
   DevBuf frags;             // BF16x3: operator hi/lo fragments
-  DevBuf matblk;            // BF16x3: material in [tile][3][QP][16]
-  int mfma_grid = 0;
+  DevBuf matblk;            // BF16x3: material blocked by 16-element tile
   int cur = 0;
 };
 
@@ -239,7 +238,7 @@ dg_status launch_stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void
 template <int N>
 hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res, float* rhs_out,
                          double a, double b, double dt, int lsrk) {
-  dgm::MfmaArgs A;
+  dgb::BxArgs A;
   A.q_in = q_in;
   A.q_out = q_out;
   A.res = res;
@@ -253,27 +252,17 @@ hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res,
   A.mat = static_cast<const float*>(c->matblk.p);
   A.zp = static_cast<const float*>(c->zp.p);
   A.zs = static_cast<const float*>(c->zs.p);
-  A.frags = static_cast<const dgm::u32x4*>(c->frags.p);
+  A.frags = static_cast<const dgb::u32x4*>(c->frags.p);
   A.K = c->mesh.K;
-  A.ntiles = (c->mesh.K + 15) / 16;
   A.a = float(a);
   A.b = float(b);
   A.dt = float(dt);
   A.lsrk = lsrk;
   A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
-  if (c->mfma_grid == 0) {
-    int cus = 0, per_cu = 0;
-    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                         c->opt.device);
-    if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dgm::stage_mfma<N>,
-                                                     dgm::kThreads, 0);
-    per_cu = per_cu > 2 ? 2 : per_cu;
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    c->mfma_grid = ((cus * per_cu + 7) / 8) * 8;
-  }
-  dgm::stage_mfma<N><<<dim3(unsigned(c->mfma_grid)), dim3(dgm::kThreads), 0, c->stream>>>(A);
+  // one workgroup per tile of 16 elements
+  const int64_t tiles = (c->mesh.K + dgb::kTile - 1) / dgb::kTile;
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  dgb::stage_bx<N><<<dim3(unsigned(tiles)), dim3(dgb::kThreads), 0, c->stream>>>(A);
   return hipGetLastError();
 }
 

@@ -1,0 +1,609 @@
+// Fused DG elastic-wave stage with BF16x3 matrix-core contractions (gfx950),
+// component-group design.
+//
+// Every dense contraction of the stage -- reference derivatives plus LIFT,
+// interpolation to the quadrature points (V_q) and projection back (P_q) --
+// runs on v_mfma_f32_16x16x32_bf16 as a split product: each FP32 operand x is
+// written x = hi + lo with hi = bf16(x), lo = bf16(x - hi), and
+// A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi with FP32 accumulation (relative
+// error ~2^-16 per product).  Fluxes, the chain rule, material weights and
+// the LSRK(5,4) update [CK94] are FP32.
+//
+// One workgroup (four waves) owns a tile of 16 consecutive elements; the
+// MFMA column index is the element, so a lane keeps the same element through
+// the whole stage.  Each wave owns a fixed set of output components of the
+// right-hand side and carries them through every contraction without any
+// exchange with the other waves:
+//   wave 0: v_x, v_y          (1/rho weights)
+//   wave 1: v_z, s_yz         (1/rho and 2 mu weights)
+//   wave 2: s_xx, s_yy, s_zz  (lam tr(e) + 2 mu e: the trace couples them)
+//   wave 3: s_xz, s_xy        (2 mu weights)
+// Phases (barriers only between the shared ones):
+//   A  stage q[9][Np][16] and the metric terms in LDS (coalesced reads);
+//   B  face fluxes [9][4 Nfp][16] in LDS, one thread per element face node:
+//      own trace from LDS, neighbour trace gathered through the (neighbour,
+//      trace pattern) tables, exact-Riemann upwind or central flux [WSG10],
+//      scaled by Fscale;
+//   C  per wave: r_c = sum_d D_d U_{c,d} + LIFT f_c as one K loop over the
+//      concatenated [D_r|D_s|D_t|LIFT] operator [HW08, Ch. 10], with
+//      U_{c,d} = sum_j G_dj w_cj q_{f_cj} folding the element's constant
+//      metric terms into the inputs (div sigma rows, eps(v) rows);
+//   D  per wave, for each chunk of 32 quadrature points: V_q r, the pointwise
+//      weight-adjusted material operator [CHW17, C18], accumulation of P_q;
+//      the accumulators of one contraction are the B operand of the next
+//      (K slots permuted on the host), so values never leave their lane;
+//   E  right-hand side store or fused stage update, coalesced over [9][K][Np].
+// Operator fragments (hi/lo, in lane order) are read from global memory and
+// stay in the L2/L1 caches; the material is stored blocked by element tile in
+// the lane order of phase D, so its loads are whole 1 KiB wave transactions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dg_bx_layout.hpp"
+
+namespace dgb {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;   // four waves
+constexpr int kTile = 16;       // elements per workgroup
+constexpr int kES = 17;         // LDS stride of a row of 16 element values (odd)
+
+struct BxArgs {
+  const float* q_in;     // [9][K][Np]
+  float* q_out;          // [9][K][Np] (LSRK mode)
+  float* res;            // [9][K][Np] (LSRK mode)
+  float* rhs_out;        // [9][K][Np] (rhs mode)
+  const float* geo;      // [K][9]: d(r,s,t)_i / d(x,y,z)_j at i*3+j
+  const float* fgeo;     // [K][4][4]: outward unit normal, Fscale
+  const int32_t* etoe;   // [K][4]
+  const uint8_t* etop;   // [K][4]
+  const int32_t* pat;    // [npat][Nfp]
+  const int32_t* fmask;  // [4][Nfp]
+  const float* mat;      // [ceil(K/16)][3][MATS]: 1/rho, lam, mu blocked
+  const float* zp;       // [K][Np]
+  const float* zs;
+  const u32x4* frags;    // [NFRAG][64]
+  int64_t K;
+  float a, b, dt;
+  int lsrk;              // 0: write rhs_out; 1: fused LSRK update
+  int upwind;            // 1 upwind, 0 central
+};
+
+
+// Output component c (vx vy vz sxx syy szz syz sxz sxy) of the volume term
+// is sum_d D_d U_{c,d} with U_{c,d} = sum_j G_dj w(c,j) q_{f(c,j)}: the stress
+// row (sigma_{c x}, sigma_{c y}, sigma_{c z}) for the velocity components,
+// the symmetrised velocity pattern for the strain components.
+__host__ __device__ constexpr int comp_field(int c, int j) {
+  return c == 0 ? (j == 0 ? 3 : j == 1 ? 8 : 7)
+       : c == 1 ? (j == 0 ? 8 : j == 1 ? 4 : 6)
+       : c == 2 ? (j == 0 ? 7 : j == 1 ? 6 : 5)
+       : c == 3 ? 0
+       : c == 4 ? 1
+       : c == 5 ? 2
+       : c == 6 ? (j == 1 ? 2 : 1)
+       : c == 7 ? (j == 0 ? 2 : 0)
+       : (j == 0 ? 1 : 0);
+}
+__host__ __device__ constexpr float comp_weight(int c, int j) {
+  return c < 3 ? 1.f
+       : c < 6 ? (j == c - 3 ? 1.f : 0.f)
+       : (j == c - 6 ? 0.f : 0.5f);
+}
+
+// components owned by wave W
+__host__ __device__ constexpr int wave_ncomp(int W) { return W == 2 ? 3 : 2; }
+__host__ __device__ constexpr int wave_comp(int W, int i) {
+  return W == 0 ? i : W == 1 ? (i == 0 ? 2 : 6) : W == 2 ? 3 + i : 7 + i;
+}
+
+__device__ __forceinline__ f32x4 mma(const u32x4& a, const bf16x8& b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mma3(const u32x4& ah, const u32x4& al, const bf16x8& bh,
+                                      const bf16x8& bl, f32x4 c) {
+  c = mma(ah, bh, c);
+  c = mma(ah, bl, c);
+  c = mma(al, bh, c);
+  return c;
+}
+
+__device__ __forceinline__ void split8(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const __bf16 h = (__bf16)v[j];
+    hi[j] = h;
+    lo[j] = (__bf16)(v[j] - (float)h);
+  }
+}
+
+// LDS use of one workgroup, in floats, and its padded allocation in bytes
+template <int N>
+struct BLds {
+  using O = BOrd<N>;
+  static constexpr int SQ = 9 * O::Np * kES;             // q       [9][Np][17]
+  static constexpr int SG = kTile * 9;                   // metric  [16][9]
+  static constexpr int SF = 9 * O::NF4 * kES;            // fluxes  [9][4 Nfp][17]
+  static constexpr int SR = 9 * O::Np * kES;             // result  [9][Np][17] (over the fluxes)
+  // the three-component wave keeps its V_q B operands (hi/lo, lane order)
+  // in LDS behind the result rows during phase D
+  static constexpr int RO = (SR + 3) & ~3;
+  static constexpr int SRL = 3 * O::SVQ * 2 * 64 * 4;
+  static constexpr int SU = SF > RO + SRL ? SF : RO + SRL;
+  static constexpr int OFF_U = (SQ + SG + 3) & ~3;       // 16-byte aligned union
+  static constexpr int USED = (OFF_U + SU) * 4;
+  // Padded so that the workgroups one CU can hold (160 KiB of LDS) never use
+  // more than 128 KiB together (at most 3 per CU at >40 KiB each, or 2 at
+  // >53.3 KiB each).
+  static constexpr int FLOOR = USED <= 43690 ? 40976 : (USED <= 65536 ? 54630 : 0);
+  static constexpr int BYTES = USED > FLOOR ? USED : FLOOR;
+};
+
+// Phase C for wave W: acc[i][t] = rows 16 t + 4 g + j of r_{comp i}
+template <int N, int W>
+__device__ __forceinline__ void vol_lift(const BxArgs& A, const float* sq, const float* sg,
+                                         const float* sF, int lane, f32x4 (&acc)[3][BOrd<N>::RT]) {
+  using O = BOrd<N>;
+  constexpr int Np = O::Np, NF4 = O::NF4, RT = O::RT, SN = O::SN, SVL = O::SVL;
+  constexpr int NC = wave_ncomp(W);
+  const int e = lane & 15, g = lane >> 4;
+  float G[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) G[i] = sg[e * 9 + i];
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // operator fragments are prefetched one K step ahead (the fragment reads
+  // hit L2; without the prefetch each step waits for its own)
+  u32x4 fc[RT][2], fn[RT][2];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) fc[t][h] = A.frags[(O::OFF_V + t * SVL * 2 + h) * 64 + lane];
+#pragma unroll
+  for (int s = 0; s < SVL; ++s) {
+    if (s + 1 < SVL) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          fn[t][h] = A.frags[(O::OFF_V + (t * SVL + s + 1) * 2 + h) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float bv[NC][8];
+    if (s < SN) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // node slots: entries beyond Np meet zero operator columns, so the
+        // clamped node only has to be a finite value
+        const int m = min(g + 4 * (2 * s + h), Np - 1);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          const int c = wave_comp(W, i);
+          float a[3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            a[j] = comp_weight(c, j) != 0.f
+                       ? comp_weight(c, j) * sq[(comp_field(c, j) * Np + m) * kES + e]
+                       : 0.f;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            float u = 0.f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              if (comp_weight(c, j) != 0.f) u += G[d * 3 + j] * a[j];
+            bv[i][3 * h + d] = u;
+          }
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jf = min(g + 4 * (2 * s + h), NF4 - 1);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) bv[i][6 + h] = sF[(wave_comp(W, i) * NF4 + jf) * kES + e];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int jf = min(g + 4 * (2 * SN + 8 * (s - SN) + j), NF4 - 1);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) bv[i][j] = sF[(wave_comp(W, i) * NF4 + jf) * kES + e];
+      }
+    }
+    bf16x8 bh[NC], bl[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) split8(bv[i], bh[i], bl[i]);
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int i = 0; i < NC; ++i) acc[i][t] = mma3(fc[t][0], fc[t][1], bh[i], bl[i], acc[i][t]);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) fc[t][0] = fn[t][0], fc[t][1] = fn[t][1];
+  }
+}
+
+// Material samples of chunk ch for this lane: m[f][u] holds quadrature
+// points 32 ch + 16 u + 4 g + j (j < 4) of field f (1/rho, lam, mu); only the
+// fields wave W uses are loaded
+template <int N, int W>
+__device__ __forceinline__ void mat_chunk(const BxArgs& A, int64_t tile, int lane, int ch,
+                                          f32x4 (&m)[3][2]) {
+  using O = BOrd<N>;
+  constexpr bool need[3] = {W == 0 || W == 1, W == 2, W != 0};
+  const f32x4* mat = reinterpret_cast<const f32x4*>(A.mat) + tile * 3 * (O::MATS / 4);
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      m[f][u] = need[f] ? mat[f * (O::MATS / 4) + (ch * 2 + u) * 64 + lane]
+                        : f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Phase D for wave W: V_q, material, P_q; the nodal result goes to sr.  m0
+// holds the material of chunk 0 (loaded before phase C).
+template <int N, int W>
+__device__ __forceinline__ void quad_proj(const BxArgs& A, int64_t tile, int lane,
+                                          const f32x4 (&acc)[3][BOrd<N>::RT],
+                                          const f32x4 (&m0)[3][2], float* sr, bf16x8* srl) {
+  using O = BOrd<N>;
+  constexpr int Np = O::Np, RT = O::RT, QT = O::QT, QC = O::QC, SVQ = O::SVQ;
+  constexpr int NC = wave_ncomp(W);
+  const int e = lane & 15, g = lane >> 4;
+
+  // V_q B operands: K slot 8 g + j of step s holds row 4 g + j % 4 of node
+  // tile 2 s + j / 4, which is where this lane's accumulator already has it.
+  // The three-component wave parks them in LDS (register budget).
+  constexpr bool park = (NC == 3);
+  bf16x8 rh[NC][SVQ], rl[NC][SVQ];
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int s = 0; s < SVQ; ++s) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int t = 2 * s + j / 4;
+        v[j] = t < RT ? acc[i][t][j % 4] : 0.f;
+      }
+      split8(v, rh[i][s], rl[i][s]);
+      if constexpr (park) {
+        srl[((i * SVQ + s) * 2 + 0) * 64 + lane] = rh[i][s];
+        srl[((i * SVQ + s) * 2 + 1) * 64 + lane] = rl[i][s];
+      }
+    }
+
+  f32x4 out[NC][RT];
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) out[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // V_q fragments of chunk 0; inside the loop the P_q fragments and the next
+  // chunk's material are issued at the top of a chunk, the next chunk's V_q
+  // fragments after its V_q products, so every fetch is covered by MFMA work
+  u32x4 fv[2][SVQ][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int s = 0; s < SVQ; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        fv[u][s][h] = u < QT ? A.frags[(O::OFF_Q + (u * SVQ + s) * 2 + h) * 64 + lane]
+                             : u32x4{0u, 0u, 0u, 0u};
+  f32x4 m[3][2];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) m[f][0] = m0[f][0], m[f][1] = m0[f][1];
+#pragma unroll
+  for (int ch = 0; ch < QC; ++ch) {
+    u32x4 fp[RT][2];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) fp[t][h] = A.frags[(O::OFF_P + (t * QC + ch) * 2 + h) * 64 + lane];
+    f32x4 mn[3][2];
+    if (ch + 1 < QC) mat_chunk<N, W>(A, tile, lane, ch + 1, mn);
+    __builtin_amdgcn_sched_barrier(0);
+    const f32x4* mi = m[0];
+    const f32x4* ml = m[1];
+    const f32x4* mm = m[2];
+    f32x4 w[NC][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int i = 0; i < NC; ++i) w[i][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (2 * ch + u < QT) {
+#pragma unroll
+        for (int s = 0; s < SVQ; ++s)
+#pragma unroll
+          for (int i = 0; i < NC; ++i) {
+            if constexpr (park)
+              w[i][u] = mma3(fv[u][s][0], fv[u][s][1], srl[((i * SVQ + s) * 2 + 0) * 64 + lane],
+                             srl[((i * SVQ + s) * 2 + 1) * 64 + lane], w[i][u]);
+            else
+              w[i][u] = mma3(fv[u][s][0], fv[u][s][1], rh[i][s], rl[i][s], w[i][u]);
+          }
+      }
+    }
+    if (ch + 1 < QC) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int s = 0; s < SVQ; ++s)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            fv[u][s][h] = 2 * (ch + 1) + u < QT
+                              ? A.frags[(O::OFF_Q + ((2 * (ch + 1) + u) * SVQ + s) * 2 + h) * 64 + lane]
+                              : u32x4{0u, 0u, 0u, 0u};
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // pointwise weight-adjusted material operator
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if constexpr (W == 0) {
+        w[0][u] *= mi[u];
+        w[1][u] *= mi[u];
+      } else if constexpr (W == 1) {
+        w[0][u] *= mi[u];
+        w[1][u] *= 2.f * mm[u];
+      } else if constexpr (W == 2) {
+        const f32x4 tr = w[0][u] + w[1][u] + w[2][u];
+        const f32x4 m2 = 2.f * mm[u];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) w[i][u] = ml[u] * tr + m2 * w[i][u];
+      } else {
+        w[0][u] *= 2.f * mm[u];
+        w[1][u] *= 2.f * mm[u];
+      }
+    }
+    // P_q B operands: K slot 8 g + j of chunk ch is row 4 g + j % 4 of
+    // quadrature tile 2 ch + j / 4
+    bf16x8 ph[NC], pl[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = w[i][j / 4][j % 4];
+      split8(v, ph[i], pl[i]);
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int i = 0; i < NC; ++i) out[i][t] = mma3(fp[t][0], fp[t][1], ph[i], pl[i], out[i][t]);
+    if (ch + 1 < QC) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) m[f][0] = mn[f][0], m[f][1] = mn[f][1];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 16 * t + 4 * g + j;
+        if (n < Np) sr[(wave_comp(W, i) * Np + n) * kES + e] = out[i][t][j];
+      }
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
+  using O = BOrd<N>;
+  using L = BLds<N>;
+  constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, RT = O::RT;
+  __shared__ __align__(16) float smem[L::BYTES / 4];
+  float* sq = smem;               // [9][Np][17]
+  float* sg = sq + L::SQ;         // [16][9]
+  float* sF = smem + L::OFF_U;    // [9][NF4][17]  (phases B, C)
+  float* sr = sF;                 // [9][Np][17]   (phases D, E)
+  bf16x8* srl = reinterpret_cast<bf16x8*>(sF + L::RO);   // wave 2, phase D
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // XCD-aware tile order: consecutive workgroups go round-robin to the eight
+  // XCDs, so give each XCD one contiguous range of tiles (neighbour traces
+  // then mostly hit its own L2)
+  const int64_t G = gridDim.x, bid = blockIdx.x;
+  const int64_t xcd = bid & 7, per = G >> 3, rem8 = G & 7;
+  const int64_t tile = xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3);
+  const int64_t K = A.K;
+  const int64_t KNp = K * Np;
+  const int64_t e0 = tile * kTile;
+  const int ne = int((K - e0) < kTile ? (K - e0) : kTile);
+
+  // A: stage q and the metric terms; every thread issues all its loads
+  // before the first LDS store (the phase is latency bound otherwise)
+  constexpr int TQ = 9 * kTile * Np;
+  constexpr int IQ = (TQ + kThreads - 1) / kThreads;
+  {
+    float v[IQ];
+#pragma unroll
+    for (int it = 0; it < IQ; ++it) {   // clamped addresses, no per-lane branches
+      const int idx = min(tid + it * kThreads, TQ - 1);
+      const int f = idx / (kTile * Np);
+      const int r = min(idx - f * (kTile * Np), ne * Np - 1);
+      v[it] = A.q_in[f * KNp + e0 * Np + r];
+    }
+    const float gv = tid < kTile * 9 && tid / 9 < ne ? A.geo[e0 * 9 + tid] : 0.f;
+#pragma unroll
+    for (int it = 0; it < IQ; ++it) {
+      const int idx = tid + it * kThreads;
+      const int f = idx / (kTile * Np);
+      const int r = idx - f * (kTile * Np);
+      const int e = r / Np, m = r - e * Np;
+      if (idx < TQ) sq[(f * Np + m) * kES + e] = e < ne ? v[it] : 0.f;
+    }
+    if (tid < kTile * 9) sg[tid] = gv;
+  }
+  __syncthreads();
+
+  // B: face fluxes, one thread per (element, face node), consecutive threads
+  // on consecutive face nodes of one element (so that a wave's neighbour
+  // gathers fall in a few neighbour elements' lines); the index loads, then
+  // the neighbour gathers of all of a thread's face nodes are issued
+  // together.  Slots past the tile (ragged last tile, idx beyond the count)
+  // read a valid element and face node and store zero.
+  constexpr int TF = kTile * NF4;
+  constexpr int IF = (TF + kThreads - 1) / kThreads;
+  {
+    int64_t kk[IF], nb[IF];
+    int vM[IF], vP[IF], face[IF];
+    bool ok[IF];
+    float fg[IF][4], zpM[IF], zsM[IF];
+    int pt[IF];
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+      const int idx = tid + it * kThreads;
+      const int e = min(idx / NF4, kTile - 1);
+      const int jf = idx - (idx / NF4) * NF4;
+      ok[it] = idx < TF && e < ne;
+      kk[it] = ok[it] ? e0 + e : e0;
+      face[it] = jf / Nfp;
+      vM[it] = A.fmask[jf];
+      nb[it] = A.etoe[kk[it] * 4 + face[it]];
+      pt[it] = A.etop[kk[it] * 4 + face[it]];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fg[it][j] = A.fgeo[(kk[it] * 4 + face[it]) * 4 + j];
+      zpM[it] = A.zp[kk[it] * Np + vM[it]];
+      zsM[it] = A.zs[kk[it] * Np + vM[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+      const int idx = tid + it * kThreads;
+      const int jf = idx - (idx / NF4) * NF4;
+      vP[it] = A.pat[pt[it] * Nfp + (jf - face[it] * Nfp)];
+    }
+    float qP[IF][9], zpP[IF], zsP[IF];
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+#pragma unroll
+      for (int f = 0; f < 9; ++f) qP[it][f] = A.q_in[f * KNp + nb[it] * Np + vP[it]];
+      zpP[it] = A.zp[nb[it] * Np + vP[it]];
+      zsP[it] = A.zs[nb[it] * Np + vP[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+      const int idx = tid + it * kThreads;
+      const int e = min(idx / NF4, kTile - 1);
+      const int jf = idx - (idx / NF4) * NF4;
+      float qM[9];
+#pragma unroll
+      for (int f = 0; f < 9; ++f) qM[f] = sq[(f * Np + vM[it]) * kES + e];
+      const float nx = fg[it][0], ny = fg[it][1], nz = fg[it][2], fs = fg[it][3];
+      const float* P = qP[it];
+      const float jtx = (P[3] - qM[3]) * nx + (P[8] - qM[8]) * ny + (P[7] - qM[7]) * nz;
+      const float jty = (P[8] - qM[8]) * nx + (P[4] - qM[4]) * ny + (P[6] - qM[6]) * nz;
+      const float jtz = (P[7] - qM[7]) * nx + (P[6] - qM[6]) * ny + (P[5] - qM[5]) * nz;
+      const float jvx = P[0] - qM[0], jvy = P[1] - qM[1], jvz = P[2] - qM[2];
+      float dvx, dvy, dvz, dtx, dty, dtz;
+      if (A.upwind) {
+        const float ZpM = zpM[it], ZsM = zsM[it], ZpP = zpP[it], ZsP = zsP[it];
+        const float jvn = jvx * nx + jvy * ny + jvz * nz;
+        const float jtn = jtx * nx + jty * ny + jtz * nz;
+        const float dvn = (ZpP * jvn + jtn) / (ZpM + ZpP);
+        const float ivs = 1.f / (ZsM + ZsP);
+        const float dvtx = (ZsP * (jvx - jvn * nx) + (jtx - jtn * nx)) * ivs;
+        const float dvty = (ZsP * (jvy - jvn * ny) + (jty - jtn * ny)) * ivs;
+        const float dvtz = (ZsP * (jvz - jvn * nz) + (jtz - jtn * nz)) * ivs;
+        dvx = dvn * nx + dvtx;
+        dvy = dvn * ny + dvty;
+        dvz = dvn * nz + dvtz;
+        const float dtn = ZpM * dvn;
+        dtx = dtn * nx + ZsM * dvtx;
+        dty = dtn * ny + ZsM * dvty;
+        dtz = dtn * nz + ZsM * dvtz;
+      } else {
+        dvx = 0.5f * jvx; dvy = 0.5f * jvy; dvz = 0.5f * jvz;
+        dtx = 0.5f * jtx; dty = 0.5f * jty; dtz = 0.5f * jtz;
+      }
+      const float z = ok[it] ? fs : 0.f;   // zero flux outside the tile
+      float fl[9];
+      fl[0] = z * dtx;
+      fl[1] = z * dty;
+      fl[2] = z * dtz;
+      fl[3] = z * dvx * nx;
+      fl[4] = z * dvy * ny;
+      fl[5] = z * dvz * nz;
+      fl[6] = z * 0.5f * (dvy * nz + dvz * ny);
+      fl[7] = z * 0.5f * (dvx * nz + dvz * nx);
+      fl[8] = z * 0.5f * (dvx * ny + dvy * nx);
+      if (idx < TF) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) sF[(c * NF4 + jf) * kES + e] = fl[c];
+      }
+    }
+  }
+  __syncthreads();
+
+  // C: volume + LIFT per wave
+  f32x4 acc[3][RT];
+  f32x4 m0[3][2];   // chunk-0 material, in flight during phase C
+  switch (wave) {
+    case 0: mat_chunk<N, 0>(A, tile, lane, 0, m0); vol_lift<N, 0>(A, sq, sg, sF, lane, acc); break;
+    case 1: mat_chunk<N, 1>(A, tile, lane, 0, m0); vol_lift<N, 1>(A, sq, sg, sF, lane, acc); break;
+    case 2: mat_chunk<N, 2>(A, tile, lane, 0, m0); vol_lift<N, 2>(A, sq, sg, sF, lane, acc); break;
+    default: mat_chunk<N, 3>(A, tile, lane, 0, m0); vol_lift<N, 3>(A, sq, sg, sF, lane, acc); break;
+  }
+  __syncthreads();   // fluxes consumed: sr may overwrite them
+
+  // D: quadrature and projection per wave
+  switch (wave) {
+    case 0: quad_proj<N, 0>(A, tile, lane, acc, m0, sr, srl); break;
+    case 1: quad_proj<N, 1>(A, tile, lane, acc, m0, sr, srl); break;
+    case 2: quad_proj<N, 2>(A, tile, lane, acc, m0, sr, srl); break;
+    default: quad_proj<N, 3>(A, tile, lane, acc, m0, sr, srl); break;
+  }
+  __syncthreads();
+
+  // E: right-hand side store or stage update, coalesced.  The residual
+  // loads of a batch of a thread's items are issued together, as
+  // unconditional loads from clamped (valid) addresses: loads under per-lane
+  // conditions get serialised by the wait-count insertion.  Batches bound
+  // the registers the phase holds.
+  constexpr int EB = 10;
+  // the thread index rebuilt from the lane count, which the compiler cannot
+  // match with phase A's index arithmetic: otherwise it keeps phase A's
+  // addresses alive through the whole kernel to reuse them here
+  const int etid = wave * 64 + int(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
+#pragma unroll
+  for (int b0 = 0; b0 < IQ; b0 += EB) {
+    float rs[EB];
+    if (A.lsrk) {
+#pragma unroll
+      for (int jb = 0; jb < EB; ++jb) {
+        const int idx = min(etid + (b0 + jb) * kThreads, TQ - 1);
+        const int f = idx / (kTile * Np);
+        const int r = min(idx - f * (kTile * Np), ne * Np - 1);
+        rs[jb] = A.res[f * KNp + e0 * Np + r];
+      }
+    }
+#pragma unroll
+    for (int jb = 0; jb < EB; ++jb) {
+      const int idx = etid + (b0 + jb) * kThreads;
+      const int f = idx / (kTile * Np);
+      const int r = idx - f * (kTile * Np);
+      const int e = r / Np, m = r - e * Np;
+      if (b0 + jb >= IQ || idx >= TQ || e >= ne) continue;
+      const int64_t gi = f * KNp + e0 * Np + r;
+      const int li = (f * Np + m) * kES + e;
+      const float rv = sr[li];
+      if (A.lsrk) {
+        const float rr = A.a * rs[jb] + A.dt * rv;
+        A.res[gi] = rr;
+        A.q_out[gi] = sq[li] + A.b * rr;
+      } else {
+        A.rhs_out[gi] = rv;
+      }
+    }
+  }
+}
+
+}  // namespace dgb

@@ -1,0 +1,51 @@
+// Sizes, K-slot maps and fragment offsets of the BF16x3 component-group
+// stage kernel for order N, shared by the device kernel and the host code
+// that lays out its operator fragments and material.  No HIP dependencies.
+//
+// MFMA shape: 16x16x32 bf16.  Rows of a contraction are operator rows (nodes
+// or quadrature points), columns are the 16 elements of a tile, K runs over
+// the operator's input index.  Lane l = 16 g + e holds column e and the K
+// slots 8 g + j (j < 8) of the B operand, and rows 4 g + j (j < 4) of each
+// 16-row accumulator tile.  The K order of every contraction is a permutation
+// chosen so that each lane feeds the slots it holds from data it already has:
+//
+//  [Dr|Ds|Dt|LIFT], K step s < SN:  slots j < 6 are the three reference
+//      directions d = j % 3 of node m = g + 4 (2 s + j / 3); slots 6, 7 are
+//      face node jf = g + 4 (2 s + j - 6);
+//  K step s >= SN: face node jf = g + 4 (2 SN + 8 (s - SN) + j);
+//  V_q, K step s: node 16 (2 s + j / 4) + 4 g + j % 4 (the accumulator rows
+//      of node tiles 2 s and 2 s + 1);
+//  P_q, K step c: quadrature point 32 c + 16 (j / 4) + 4 g + j % 4 (the
+//      accumulator rows of quadrature tiles 2 c and 2 c + 1).
+// Slots whose node, face node or point lies beyond the element's count carry
+// a zero operator entry.
+#pragma once
+
+namespace dgb {
+
+template <int N>
+struct BOrd {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  static constexpr int NF4 = 4 * Nfp;
+  static constexpr int Nq = (N + 1) * (N + 1) * (N + 1);
+  static constexpr int RT = (Np + 15) / 16;         // 16-row node tiles
+  static constexpr int NPG = (Np + 3) / 4;          // nodes per lane group
+  static constexpr int SN = (NPG + 1) / 2;          // K steps carrying nodes
+  static constexpr int FPG = (NF4 + 3) / 4;         // face nodes per lane group
+  static constexpr int SF = FPG > 2 * SN ? (FPG - 2 * SN + 7) / 8 : 0;
+  static constexpr int SVL = SN + SF;               // K steps of [Dr|Ds|Dt|LIFT]
+  static constexpr int QT = (Nq + 15) / 16;         // 16-row quadrature tiles
+  static constexpr int QC = (QT + 1) / 2;           // K steps of P_q (32 points each)
+  static constexpr int SVQ = (RT + 1) / 2;          // K steps of V_q
+  // fragments of 64 lanes x 8 bf16; hi and lo of one (tile, step) adjacent
+  static constexpr int NFV = RT * SVL * 2;
+  static constexpr int NFQ = QT * SVQ * 2;
+  static constexpr int NFP = RT * QC * 2;
+  static constexpr int OFF_V = 0, OFF_Q = NFV, OFF_P = NFV + NFQ;
+  static constexpr int NFRAG = NFV + NFQ + NFP;
+  // blocked material: floats per (element tile, field)
+  static constexpr int MATS = QC * 2 * 64 * 4;
+};
+
+}  // namespace dgb

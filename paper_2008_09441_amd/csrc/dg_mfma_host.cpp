@@ -3,7 +3,7 @@
 
 #include <cstring>
 
-#include "dg_mfma_layout.hpp"
+#include "dg_bx_layout.hpp"
 
 namespace dgh {
 namespace {
@@ -21,83 +21,86 @@ float bf16_val(uint16_t h) {
   return f;
 }
 
-// Operator fragments in MFMA A-operand lane order: fragment (t, kb, hl) holds
-// A[16 t + l % 16][32 kb + 8 (l / 16) + j] for lane l, j = 0..7, split into
-// hi = bf16(a), lo = bf16(a - hi).  The K indices of V_q and P_q are permuted
-// so that they consume the previous contraction's accumulator layout.
+// Operator fragments in MFMA A-operand lane order: fragment (t, s, h) holds,
+// for lane l, the operator entries of row 16 t + l % 16 at the K slots
+// 8 (l / 16) + j, j = 0..7, of K step s, as h = 0: hi = bf16(a), h = 1:
+// lo = bf16(a - hi).  The meaning of each K slot (which node, direction,
+// face node or quadrature point it carries) is the permutation described with
+// the kernel's sizes; rows and slots beyond the element's counts are zero.
 template <int N>
 std::vector<uint16_t> build_frags(const RefElement& re) {
-  using O = dgm::MOrd<N>;
+  using O = dgb::BOrd<N>;
   std::vector<uint16_t> out(size_t(O::NFRAG) * 64 * 8, 0);
-  auto put = [&](int off, int KB, int t, int kb, auto&& aval) {
+  auto put = [&](int frag, auto&& aval) {   // aval(row offset in tile, g, j)
     for (int l = 0; l < 64; ++l)
       for (int j = 0; j < 8; ++j) {
-        const int i = 16 * t + (l % 16);
-        const int p = 32 * kb + 8 * (l / 16) + j;
-        const double v = aval(i, p);
+        const double v = aval(l % 16, l / 16, j);
         const uint16_t hi = bf16_rne(float(v));
         const uint16_t lo = bf16_rne(float(v - double(bf16_val(hi))));
-        out[((size_t(off + (t * KB + kb) * 2 + 0) * 64) + l) * 8 + j] = hi;
-        out[((size_t(off + (t * KB + kb) * 2 + 1) * 64) + l) * 8 + j] = lo;
+        out[(size_t(frag) * 64 + l) * 8 + j] = hi;
+        out[(size_t(frag + 1) * 64 + l) * 8 + j] = lo;
       }
   };
   const int Np = O::Np, NF4 = O::NF4, Nq = O::Nq;
-  // [Dr | Ds | Dt | LIFT] with 8-row chunks: chunk h < 3 CV -> derivative
-  // d = h / CV, node 8 (h % CV) + j; next CF chunks -> face node; rest zero
-  auto avol = [&](int i, int p) -> double {
-    if (i >= Np) return 0.0;
-    const int h = p / 8, jj = p % 8;
-    if (h < 3 * O::CV) {
-      const int d = h / O::CV, m = 8 * (h % O::CV) + jj;
-      if (m >= Np) return 0.0;
-      const std::vector<double>& D = d == 0 ? re.Dr : d == 1 ? re.Ds : re.Dt;
-      return D[size_t(i) * Np + m];
-    }
-    if (h < 3 * O::CV + O::CF) {
-      const int jf = 8 * (h - 3 * O::CV) + jj;
-      return jf < NF4 ? re.LIFT[size_t(i) * NF4 + jf] : 0.0;
-    }
-    return 0.0;
-  };
-  // accumulator row of K position p: tile 2 (p / 32) + (p % 8) / 4, row
-  // 4 ((p % 32) / 8) + p % 4
-  auto acc_row = [](int p) {
-    const int kb = p / 32, g = (p % 32) / 8, jj = p % 8;
-    return 16 * (2 * kb + jj / 4) + 4 * g + (jj % 4);
-  };
-  auto avq = [&](int i, int p) -> double {
-    const int n = acc_row(p);
-    return (i < Nq && n < Np) ? re.Vq[size_t(i) * Np + n] : 0.0;
-  };
-  auto apq = [&](int i, int p) -> double {
-    const int qr = acc_row(p);
-    return (i < Np && qr < Nq) ? re.Pq[size_t(i) * Nq + qr] : 0.0;
-  };
-  for (int t = 0; t < O::MT; ++t)
-    for (int kb = 0; kb < O::KVB; ++kb) put(O::OFF_V, O::KVB, t, kb, avol);
+  for (int t = 0; t < O::RT; ++t)
+    for (int s = 0; s < O::SVL; ++s)
+      put(O::OFF_V + (t * O::SVL + s) * 2, [&](int r, int g, int j) -> double {
+        const int n = 16 * t + r;
+        if (n >= Np) return 0.0;
+        if (s < O::SN && j < 6) {
+          const int m = g + 4 * (2 * s + j / 3);
+          if (m >= Np) return 0.0;
+          const std::vector<double>& D = j % 3 == 0 ? re.Dr : j % 3 == 1 ? re.Ds : re.Dt;
+          return D[size_t(n) * Np + m];
+        }
+        const int i = s < O::SN ? 2 * s + (j - 6) : 2 * O::SN + 8 * (s - O::SN) + j;
+        const int jf = g + 4 * i;
+        return jf < NF4 ? re.LIFT[size_t(n) * NF4 + jf] : 0.0;
+      });
   for (int t = 0; t < O::QT; ++t)
-    for (int kb = 0; kb < O::KQB; ++kb) put(O::OFF_Q, O::KQB, t, kb, avq);
-  for (int t = 0; t < O::MT; ++t)
-    for (int kb = 0; kb < O::PKB; ++kb) put(O::OFF_P, O::PKB, t, kb, apq);
+    for (int s = 0; s < O::SVQ; ++s)
+      put(O::OFF_Q + (t * O::SVQ + s) * 2, [&](int r, int g, int j) -> double {
+        const int p = 16 * t + r;
+        const int n = 16 * (2 * s + j / 4) + 4 * g + j % 4;
+        return (p < Nq && n < Np) ? re.Vq[size_t(p) * Np + n] : 0.0;
+      });
+  for (int t = 0; t < O::RT; ++t)
+    for (int c = 0; c < O::QC; ++c)
+      put(O::OFF_P + (t * O::QC + c) * 2, [&](int r, int g, int j) -> double {
+        const int n = 16 * t + r;
+        const int p = 32 * c + 16 * (j / 4) + 4 * g + j % 4;
+        return (n < Np && p < Nq) ? re.Pq[size_t(n) * Nq + p] : 0.0;
+      });
   return out;
 }
 
-
-int mfma_qp(int N) {
-  switch (N) {
-    case 1: return dgm::MOrd<1>::QP;
-    case 2: return dgm::MOrd<2>::QP;
-    case 3: return dgm::MOrd<3>::QP;
-    default: return dgm::MOrd<4>::QP;
-  }
+template <int N>
+std::vector<double> build_material(int64_t K, const double* irho, const double* lam,
+                                   const double* mu) {
+  // [tile][field][chunk c][half u][lane l][4]: element 16 tile + l % 16,
+  // quadrature point 32 c + 16 u + 4 (l / 16) + j
+  using O = dgb::BOrd<N>;
+  const int64_t ntiles = (K + 15) / 16;
+  std::vector<double> blk(size_t(ntiles) * 3 * O::MATS, 0.0);
+  const double* src[3] = {irho, lam, mu};
+  for (int64_t tl = 0; tl < ntiles; ++tl)
+    for (int f = 0; f < 3; ++f)
+      for (int c = 0; c < O::QC; ++c)
+        for (int u = 0; u < 2; ++u)
+          for (int l = 0; l < 64; ++l)
+            for (int j = 0; j < 4; ++j) {
+              const int64_t k = 16 * tl + l % 16;
+              const int p = 32 * c + 16 * u + 4 * (l / 16) + j;
+              if (k >= K || p >= O::Nq) continue;
+              blk[(size_t(tl) * 3 + f) * O::MATS + ((size_t(c) * 2 + u) * 64 + l) * 4 + j] =
+                  src[f][size_t(k) * O::Nq + p];
+            }
+  return blk;
 }
 
 }  // namespace
 
-// N = 4 is switched off: its stage kernel (76 KB of LDS per workgroup, two
-// workgroups per CU) faulted the GPU once although every index it forms is in
-// bounds on the CPU; it stays disabled until the cause is known.
-bool mfma_supported(int N) { return N >= 1 && N <= 3; }
+bool mfma_supported(int N) { return N >= 1 && N <= 4; }
 
 std::vector<uint16_t> mfma_fragments(const RefElement& re) {
   switch (re.N) {
@@ -129,17 +132,12 @@ std::vector<double> col_operators(const RefElement& re) {
 
 std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
                                   const double* mu) {
-  // [tile][field][QP][16]: the accumulator layout reads 16 elements of one
-  // quadrature point contiguously
-  const int QP = mfma_qp(N), Nq = num_quad(N);
-  const int64_t ntiles = (K + 15) / 16;
-  std::vector<double> blk(size_t(ntiles) * 3 * QP * 16, 0.0);
-  const double* src[3] = {irho, lam, mu};
-  for (int64_t k = 0; k < K; ++k)
-    for (int f = 0; f < 3; ++f)
-      for (int qp = 0; qp < Nq; ++qp)
-        blk[((size_t(k / 16) * 3 + f) * QP + qp) * 16 + (k % 16)] = src[f][size_t(k) * Nq + qp];
-  return blk;
+  switch (N) {
+    case 1: return build_material<1>(K, irho, lam, mu);
+    case 2: return build_material<2>(K, irho, lam, mu);
+    case 3: return build_material<3>(K, irho, lam, mu);
+    default: return build_material<4>(K, irho, lam, mu);
+  }
 }
 
 }  // namespace dgh

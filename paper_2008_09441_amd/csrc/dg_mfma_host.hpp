@@ -11,8 +11,8 @@ namespace dgh {
 // orders with a matrix-core stage kernel
 bool mfma_supported(int N);
 
-// hi/lo bf16 bit patterns of the [Dr|Ds|Dt|LIFT], V_q and P_q fragments,
-// [NFRAG][64 lanes][8]
+// hi/lo bf16 bit patterns of the [Dr|Ds|Dt|LIFT], V_q and P_q fragments in
+// the K-slot order of the matrix-core stage kernel, [NFRAG][64 lanes][8]
 std::vector<uint16_t> mfma_fragments(const RefElement& re);
 
 // Column-kernel operator pack: DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],
@@ -20,7 +20,8 @@ std::vector<uint16_t> mfma_fragments(const RefElement& re);
 // QP = 32 ceil(Nq/32)).
 std::vector<double> col_operators(const RefElement& re);
 
-// 1/rho, lam, mu at [K][Nq] -> [ceil(K/16)][3][QP][16] (zero padded)
+// 1/rho, lam, mu at [K][Nq] -> blocked by 16-element tile in the lane order
+// of the kernel's quadrature phase, [ceil(K/16)][3][MATS] (zero padded)
 std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
                                   const double* mu);
 

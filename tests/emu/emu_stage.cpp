@@ -1,4 +1,5 @@
-// Runs the matrix-core stage kernel dgm::stage_mfma<N> on the CPU, for tests:
+// Runs the stage kernels on the CPU, for tests (matrix-core dgb::stage_bx<N>,
+// column dgk::stage_cols<T, N>):
 // each workgroup is 256 host threads with real barriers; the 16x16x32 bf16
 // MFMA is emulated with its hardware lane layout (A: row lane%16, k 8(lane/16)+j;
 // B: column lane%16, k 8(lane/16)+j; D: column lane%16, row 4(lane/16)+j).
@@ -10,9 +11,10 @@
 #include <vector>
 #include <memory>
 #include <cstring>
+#include <cstdlib>
 #include <cmath>
 #include "dg_kernels.hpp"
-#include "dg_mfma.hpp"
+#include "dg_bx.hpp"
 #include "dg_host.hpp"
 #include "dg_mfma_host.hpp"
 
@@ -60,24 +62,30 @@ static void run_grid(int grid, F kern) {
 }
 
 template <int N>
-static void run(dgm::MfmaArgs A, int grid) {
-  run_grid(grid, [=]() { dgm::stage_mfma<N>(A); });
+static void run(dgb::BxArgs A, int grid) {
+  run_grid(grid, [=]() { dgb::stage_bx<N>(A); });
 }
 
+// 128-byte aligned, size rounded up to whole 128-byte lines (the device
+// allocations the kernels see are aligned at least as much)
+template <typename T> static T* alloc(size_t n) {
+  const size_t bytes = ((n * sizeof(T) + 127) / 128) * 128;
+  return static_cast<T*>(std::aligned_alloc(128, bytes ? bytes : 128));
+}
 template <typename T> static T* dup(const std::vector<T>& v) {
-  T* p = new T[v.size()];
+  T* p = alloc<T>(v.size());
   std::memcpy(p, v.data(), v.size() * sizeof(T));
   return p;
 }
 static float* dupf(const std::vector<double>& v) {
-  float* p = new float[v.size()];
+  float* p = alloc<float>(v.size());
   for (size_t i = 0; i < v.size(); ++i) p[i] = float(v[i]);
   return p;
 }
 
 template <typename T>
 static T* dupT(const std::vector<double>& v) {
-  T* p = new T[v.size()];
+  T* p = alloc<T>(v.size());
   for (size_t i = 0; i < v.size(); ++i) p[i] = T(v[i]);
   return p;
 }
@@ -150,22 +158,23 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
     return grid == -1 ? cols_dispatch<float>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk)
                       : cols_dispatch<double>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk);
   std::vector<uint16_t> fr = dgh::mfma_fragments(re);
-  dgm::MfmaArgs A{};
-  float* qin = new float[9 * K * Np];
+  dgb::BxArgs A{};
+  float* qin = alloc<float>(9 * K * Np);
   std::memcpy(qin, q, sizeof(float) * 9 * K * Np);
   A.q_in = qin;
-  A.rhs_out = new float[9 * K * Np];
-  A.q_out = lsrk ? new float[9 * K * Np] : nullptr;
+  A.rhs_out = alloc<float>(9 * K * Np);
+  A.q_out = lsrk ? alloc<float>(9 * K * Np) : nullptr;
   A.res = nullptr;
-  if (lsrk) { A.res = new float[9 * K * Np]; for (int64_t i = 0; i < 9 * K * Np; ++i) A.res[i] = 0.f; }
+  if (lsrk) { A.res = alloc<float>(9 * K * Np); for (int64_t i = 0; i < 9 * K * Np; ++i) A.res[i] = 0.f; }
   A.geo = dupf(m.geo); A.fgeo = dupf(m.fgeo);
   A.etoe = dup(m.EToE); A.etop = dup(m.EToP); A.pat = dup(m.pat);
   std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
   A.fmask = dup(fm);
   A.mat = dupf(dgh::mfma_material(N, K, a.data(), b.data(), d.data()));
   A.zp = dupf(zp); A.zs = dupf(zs);
-  A.frags = reinterpret_cast<const dgm::u32x4*>(dup(fr));
-  A.K = K; A.ntiles = (K + 15) / 16; A.a = 0.f; A.b = 1.f; A.dt = 1.f; A.lsrk = lsrk; A.upwind = upwind;
+  A.frags = reinterpret_cast<const dgb::u32x4*>(dup(fr));
+  A.K = K; A.a = 0.f; A.b = 1.f; A.dt = 1.f; A.lsrk = lsrk; A.upwind = upwind;
+  grid = int((K + dgb::kTile - 1) / dgb::kTile);   // one workgroup per element tile
   switch (N) {
     case 1: run<1>(A, grid); break;
     case 2: run<2>(A, grid); break;
@@ -178,8 +187,8 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
   return 0;
 }
 
-// input file: int32 N, flux_upwind, grid (>0: matrix-core kernel with that
-// grid; -1 / -2: column kernel in FP32 / FP64), lsrk; int64 K; then float64
+// input file: int32 N, flux_upwind, kernel (>0: matrix-core kernel; -1 / -2:
+// column kernel in FP32 / FP64), lsrk; int64 K; then float64
 // vxyz[K*12], period[3], rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n
 // [K*Np each]; then float32 q[9*K*Np]
 int main(int argc, char** argv) {

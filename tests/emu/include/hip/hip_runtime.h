@@ -21,3 +21,17 @@ emu_f32x4 emu_mfma_16x16x32_bf16(emu_bf16x8 a, emu_bf16x8 b, emu_f32x4 c, int, i
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16 emu_mfma_16x16x32_bf16
 #define __align__(n) __attribute__((aligned(n)))
 #define __builtin_amdgcn_readfirstlane(x) (x)
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
+// lane count builtins: number of lanes below this one in the mask (low/high half)
+inline unsigned emu_mbcnt_lo(unsigned m, unsigned a) {
+  const unsigned l = threadIdx.x & 63;
+  return a + __builtin_popcount(l >= 32 ? m : (m & ((1u << l) - 1u)));
+}
+inline unsigned emu_mbcnt_hi(unsigned m, unsigned a) {
+  const unsigned l = threadIdx.x & 63;
+  return a + (l < 32 ? 0u : __builtin_popcount(m & ((1u << (l - 32)) - 1u)));
+}
+#define __builtin_amdgcn_mbcnt_lo emu_mbcnt_lo
+#define __builtin_amdgcn_mbcnt_hi emu_mbcnt_hi
+inline int min(int a, int b) { return a < b ? a : b; }
+inline long min(long a, long b) { return a < b ? a : b; }

@@ -35,7 +35,7 @@ def emu_exe(tmp_path_factory):
     return exe
 
 
-def _run(exe, tmp_path, n, N, flux="upwind", grid=16, lsrk=0):
+def _run(exe, tmp_path, n, N, flux="upwind", grid=1, lsrk=0):
     op = ElasticDG(n, N, synth.fourier_media, flux=flux)
     q = synth.random_state(op.K, op.Np, seed=40 + N).astype(np.float32)
     parts = [np.array([N, 1 if flux == "upwind" else 0, grid, lsrk], np.int32).tobytes(),
@@ -56,7 +56,8 @@ def _run(exe, tmp_path, n, N, flux="upwind", grid=16, lsrk=0):
     return rel_l2_per_field(got, ref)
 
 
-@pytest.mark.parametrize("n,N,flux", [(3, 2, "upwind"), (3, 3, "central"), (3, 4, "upwind")])
+@pytest.mark.parametrize("n,N,flux", [(2, 1, "central"), (3, 2, "upwind"), (3, 3, "central"),
+                                      (3, 4, "upwind"), (2, 4, "central")])
 def test_stage_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flux):
     err = _run(emu_exe, tmp_path, n, N, flux)
     print("per-field rel L2:", np.array2string(err, precision=2))
@@ -65,7 +66,7 @@ def test_stage_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flu
 
 def test_stage_kernel_lsrk_mode(emu_exe, tmp_path):
     # with a = 0, b = dt = 1 the LSRK increment q_out - q_in equals the rhs
-    err = _run(emu_exe, tmp_path, 2, 3, "upwind", grid=8, lsrk=1)
+    err = _run(emu_exe, tmp_path, 2, 4, "upwind", lsrk=1)
     assert err.max() <= 1e-4
 
 
