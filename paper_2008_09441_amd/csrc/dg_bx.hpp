@@ -423,6 +423,19 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   // before the first LDS store (the phase is latency bound otherwise)
   constexpr int TQ = 9 * kTile * Np;
   constexpr int IQ = (TQ + kThreads - 1) / kThreads;
+  // Face-node tasks of phase B: one thread per (element, face node),
+  // consecutive threads on consecutive face nodes of one element (so that a
+  // wave's neighbour gathers fall in a few neighbour elements' lines).  Their
+  // index loads (neighbour, trace pattern, face geometry, own impedances)
+  // are issued here, behind the state loads, so that phase B waits for the
+  // neighbour gathers only.  Slots past the tile (ragged last tile, idx
+  // beyond the count) read a valid element and face node and store zero.
+  constexpr int TF = kTile * NF4;
+  constexpr int IF = (TF + kThreads - 1) / kThreads;
+  int64_t kk[IF], nb[IF];
+  int vM[IF], vP[IF], face[IF];
+  bool ok[IF];
+  float fg[IF][4], zpM[IF], zsM[IF];
   {
     float v[IQ];
 #pragma unroll
@@ -433,31 +446,6 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
       v[it] = A.q_in[f * KNp + e0 * Np + r];
     }
     const float gv = tid < kTile * 9 && tid / 9 < ne ? A.geo[e0 * 9 + tid] : 0.f;
-#pragma unroll
-    for (int it = 0; it < IQ; ++it) {
-      const int idx = tid + it * kThreads;
-      const int f = idx / (kTile * Np);
-      const int r = idx - f * (kTile * Np);
-      const int e = r / Np, m = r - e * Np;
-      if (idx < TQ) sq[(f * Np + m) * kES + e] = e < ne ? v[it] : 0.f;
-    }
-    if (tid < kTile * 9) sg[tid] = gv;
-  }
-  __syncthreads();
-
-  // B: face fluxes, one thread per (element, face node), consecutive threads
-  // on consecutive face nodes of one element (so that a wave's neighbour
-  // gathers fall in a few neighbour elements' lines); the index loads, then
-  // the neighbour gathers of all of a thread's face nodes are issued
-  // together.  Slots past the tile (ragged last tile, idx beyond the count)
-  // read a valid element and face node and store zero.
-  constexpr int TF = kTile * NF4;
-  constexpr int IF = (TF + kThreads - 1) / kThreads;
-  {
-    int64_t kk[IF], nb[IF];
-    int vM[IF], vP[IF], face[IF];
-    bool ok[IF];
-    float fg[IF][4], zpM[IF], zsM[IF];
     int pt[IF];
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
@@ -481,6 +469,21 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
       const int jf = idx - (idx / NF4) * NF4;
       vP[it] = A.pat[pt[it] * Nfp + (jf - face[it] * Nfp)];
     }
+#pragma unroll
+    for (int it = 0; it < IQ; ++it) {
+      const int idx = tid + it * kThreads;
+      const int f = idx / (kTile * Np);
+      const int r = idx - f * (kTile * Np);
+      const int e = r / Np, m = r - e * Np;
+      if (idx < TQ) sq[(f * Np + m) * kES + e] = e < ne ? v[it] : 0.f;
+    }
+    if (tid < kTile * 9) sg[tid] = gv;
+  }
+  __syncthreads();
+
+  // B: face fluxes; the neighbour gathers of all of a thread's face nodes
+  // are issued together
+  {
     float qP[IF][9], zpP[IF], zsP[IF];
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
@@ -568,7 +571,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   // unconditional loads from clamped (valid) addresses: loads under per-lane
   // conditions get serialised by the wait-count insertion.  Batches bound
   // the registers the phase holds.
-  constexpr int EB = 10;
+  constexpr int EB = IQ;
   // the thread index rebuilt from the lane count, which the compiler cannot
   // match with phase A's index arithmetic: otherwise it keeps phase A's
   // addresses alive through the whole kernel to reuse them here
