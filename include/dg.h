@@ -121,21 +121,55 @@ dg_status dg_state_get(dg_ctx* ctx, void* q, int32_t on_device);
  * next dg_step / dg_run, which swap buffers). */
 dg_status dg_state_device_ptr(dg_ctx* ctx, void** ptr);
 
-/* Semi-discrete right-hand side rhs = dq/dt for a caller-owned device state
- * q_dev [9][K][Np] into caller-owned device rhs_dev [9][K][Np] (working
- * precision; must not alias): volume terms div(sigma), eps(v) [HW08, Ch.
- * 10], flux of the selected type at every face node gathered through the
- * neighbour tables [WSG10], LIFT, then the weight-adjusted mass inverse
- * [CHW17, C18].  Stream-ordered, asynchronous. */
-dg_status dg_rhs(dg_ctx* ctx, const void* q_dev, void* rhs_dev);
+/* Semi-discrete right-hand side rhs = dq/dt at time t for a caller-owned
+ * device state q_dev [9][K][Np] into caller-owned device rhs_dev [9][K][Np]
+ * (working precision; must not alias): volume terms div(sigma), eps(v)
+ * [HW08, Ch. 10], flux of the selected type at every face node gathered
+ * through the neighbour tables [WSG10], LIFT, then the weight-adjusted mass
+ * inverse [CHW17, C18], plus the point sources' terms at time t (see
+ * dg_sources_set).  Stream-ordered, asynchronous. */
+dg_status dg_rhs(dg_ctx* ctx, const void* q_dev, void* rhs_dev, double t);
 
 /* One LSRK(5,4) step [CK94] of the context's state from time t with step
- * dt: five fused stages res <- a_s res + dt rhs(q); q <- q + b_s res.
- * Stream-ordered, asynchronous. */
+ * dt: five fused stages res <- a_s res + dt rhs(q, t + c_s dt);
+ * q <- q + b_s res.  Stream-ordered, asynchronous. */
 dg_status dg_step(dg_ctx* ctx, double t, double dt);
 
 /* nsteps LSRK(5,4) steps from t0.  Stream-ordered, asynchronous. */
 dg_status dg_run(dg_ctx* ctx, double t0, double dt, int64_t nsteps);
+
+/* Point forces with Ricker time signals.  Source i acts at xyz[i] (host
+ * [nsrc][3], any periodic image) in direction dir[i] (host [nsrc][3]) with
+ * f_i(t) = amp[i] (1 - 2 a^2) exp(-a^2), a = pi f0[i] (t - t0[i]).  The
+ * force enters the velocity rows of the element containing the point as
+ * M_k^-1 l(x^_i) f_i(t) dir[i] (the nodal basis evaluated at the point,
+ * [HW08, Ch. 10]) and passes through the weight-adjusted mass inverse
+ * [CHW17, C18] like every other term; the responses are precomputed in FP64
+ * on the host from the device material and recomputed when the material
+ * changes.  Replaces any earlier set; nsrc = 0 removes all.  Host arrays
+ * are copied.  Errors: DG_ESTATE before mesh and material, DG_EINVAL for a
+ * point outside the mesh or f0 <= 0, DG_ENONFINITE, DG_EDEVICE for a
+ * host-only context.  Synchronises the context's stream. */
+dg_status dg_sources_set(dg_ctx* ctx, int32_t nsrc, const double* xyz, const double* dir,
+                         const double* f0, const double* t0, const double* amp);
+
+/* Receivers at xyz (host [nrec][3], any periodic image): the velocity there
+ * is the polynomial of the containing element evaluated at the point.
+ * Replaces any earlier set; nrec = 0 removes all.  Errors as for
+ * dg_sources_set (mesh needed, material not).  Synchronises the stream. */
+dg_status dg_receivers_set(dg_ctx* ctx, int32_t nrec, const double* xyz);
+
+/* Velocity at the receivers for the current state into out [nrec][3]
+ * (working precision): device pointer if on_device != 0 (stream-ordered),
+ * else host (synchronous).  DG_ESTATE without receivers or state. */
+dg_status dg_receivers_sample(dg_ctx* ctx, void* out, int32_t on_device);
+
+/* nsteps LSRK(5,4) steps from t0, sampling the receivers after every step
+ * into trace [nsteps][nrec][3] (working precision): device pointer if
+ * on_device != 0 (stream-ordered), else host (the library stages the trace
+ * in device memory it owns and copies it at the end; synchronous). */
+dg_status dg_run_record(dg_ctx* ctx, double t0, double dt, int64_t nsteps, void* trace,
+                        int32_t on_device);
 
 /* Wait for the context's stream; reports asynchronous device errors. */
 dg_status dg_synchronize(dg_ctx* ctx);

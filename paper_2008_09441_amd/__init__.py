@@ -106,12 +106,13 @@ class Solver:
         B.dg_state_get(self.ctx, out, True)
         return out
 
-    def rhs(self, q, out=None):
-        """dq/dt of the device tensor q [9, K, Np] into out (allocated if None)."""
+    def rhs(self, q, out=None, t=0.0):
+        """dq/dt at time t of the device tensor q [9, K, Np] into out
+        (allocated if None)."""
         import torch
         if out is None:
             out = torch.empty_like(q)
-        B.dg_rhs(self.ctx, q, out, self.torch_dtype)
+        B.dg_rhs(self.ctx, q, out, t, self.torch_dtype)
         return out
 
     def step(self, t, dt):
@@ -119,6 +120,30 @@ class Solver:
 
     def run(self, t0, dt, nsteps):
         B.dg_run(self.ctx, t0, dt, nsteps)
+
+    def set_sources(self, xyz, dirs, f0, t0, amp=1.0):
+        """Point forces with Ricker signals (see dg_sources_set)."""
+        B.dg_sources_set(self.ctx, xyz, dirs, f0, t0, amp)
+
+    def set_receivers(self, xyz):
+        B.dg_receivers_set(self.ctx, xyz)
+        self.nrec = int(np.asarray(xyz).reshape(-1, 3).shape[0])
+
+    def sample_receivers(self):
+        """Velocity at the receivers for the current state: host [nrec, 3]."""
+        out = np.empty((self.nrec, 3), dtype=self.dtype)
+        B.dg_receivers_sample(self.ctx, out, False)
+        return out
+
+    def run_record(self, t0, dt, nsteps, out=None):
+        """nsteps steps recording the receivers after each: returns
+        [nsteps, nrec, 3] (a device tensor if out is one, else host)."""
+        if out is not None:
+            B.dg_run_record(self.ctx, t0, dt, nsteps, out, True)
+            return out
+        tr = np.empty((nsteps, self.nrec, 3), dtype=self.dtype)
+        B.dg_run_record(self.ctx, t0, dt, nsteps, tr, False)
+        return tr
 
     def synchronize(self):
         B.dg_synchronize(self.ctx)

@@ -24,7 +24,8 @@ EXPORTS = [
     "dg_node_coords", "dg_quad_coords", "dg_material_upload", "dg_project",
     "dg_state_set", "dg_state_get", "dg_state_device_ptr", "dg_rhs", "dg_step",
     "dg_run", "dg_synchronize", "dg_ref_operator", "dg_face_nodes",
-    "dg_connectivity", "dg_geometry",
+    "dg_connectivity", "dg_geometry", "dg_sources_set", "dg_receivers_set",
+    "dg_receivers_sample", "dg_run_record",
 ]
 
 
@@ -60,7 +61,7 @@ def _load():
         "dg_state_set": ([P, P, I32], I32),
         "dg_state_get": ([P, P, I32], I32),
         "dg_state_device_ptr": ([P, ctypes.POINTER(P)], I32),
-        "dg_rhs": ([P, P, P], I32),
+        "dg_rhs": ([P, P, P, D], I32),
         "dg_step": ([P, D, D], I32),
         "dg_run": ([P, D, D, I64], I32),
         "dg_synchronize": ([P], I32),
@@ -68,6 +69,10 @@ def _load():
         "dg_face_nodes": ([P, P], I32),
         "dg_connectivity": ([P, P, P, P], I32),
         "dg_geometry": ([P, P, P, P], I32),
+        "dg_sources_set": ([P, I32, P, P, P, P, P], I32),
+        "dg_receivers_set": ([P, I32, P], I32),
+        "dg_receivers_sample": ([P, P, I32], I32),
+        "dg_run_record": ([P, D, D, I64, P, I32], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -209,12 +214,12 @@ def _check_device_state(ctx, t, what):
                          f"{9 * K * Np} elements, got {tuple(t.shape)}")
 
 
-def dg_rhs(ctx, q_dev, rhs_dev, dtype=None):
+def dg_rhs(ctx, q_dev, rhs_dev, t=0.0, dtype=None):
     _check_device_state(ctx, q_dev, "q")
     _check_device_state(ctx, rhs_dev, "rhs")
     if q_dev.dtype != rhs_dev.dtype or (dtype is not None and q_dev.dtype != dtype):
         raise ValueError("q and rhs must have the context's working precision")
-    check(ctx, lib.dg_rhs(ctx, _ptr(q_dev), _ptr(rhs_dev)))
+    check(ctx, lib.dg_rhs(ctx, _ptr(q_dev), _ptr(rhs_dev), float(t)))
 
 
 def dg_step(ctx, t, dt):
@@ -223,6 +228,30 @@ def dg_step(ctx, t, dt):
 
 def dg_run(ctx, t0, dt, nsteps):
     check(ctx, lib.dg_run(ctx, float(t0), float(dt), int(nsteps)))
+
+
+def dg_sources_set(ctx, xyz, dirs, f0, t0, amp):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    n = xyz.shape[0]
+    dirs = _f64(np.asarray(dirs, dtype=np.float64).reshape(-1, 3), (n, 3))
+    f0, t0, amp = (_f64(np.broadcast_to(np.asarray(v, dtype=np.float64), (n,)), (n,))
+                   for v in (f0, t0, amp))
+    check(ctx, lib.dg_sources_set(ctx, n, _ptr(xyz), _ptr(dirs), _ptr(f0), _ptr(t0),
+                                  _ptr(amp)))
+
+
+def dg_receivers_set(ctx, xyz):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    check(ctx, lib.dg_receivers_set(ctx, xyz.shape[0], _ptr(xyz)))
+
+
+def dg_receivers_sample(ctx, out, on_device):
+    check(ctx, lib.dg_receivers_sample(ctx, _ptr(out), 1 if on_device else 0))
+
+
+def dg_run_record(ctx, t0, dt, nsteps, trace, on_device):
+    check(ctx, lib.dg_run_record(ctx, float(t0), float(dt), int(nsteps), _ptr(trace),
+                                 1 if on_device else 0))
 
 
 def dg_synchronize(ctx):

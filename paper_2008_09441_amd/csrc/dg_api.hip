@@ -13,6 +13,7 @@
 #include "dg_host.hpp"
 #include "dg_kernels.hpp"
 #include "dg_bx.hpp"
+#include "dg_src.hpp"
 #include "dg_mfma_host.hpp"
 
 namespace {
@@ -28,6 +29,11 @@ const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
                         1720146321549.0 / 2090206949498.0,
                         3134564353537.0 / 4481467310338.0,
                         2277821191437.0 / 14882151754819.0};
+const double kRkC[5] = {0.0,
+                        1432997174477.0 / 9575080441755.0,
+                        2526269341429.0 / 6820363962896.0,
+                        2006345519317.0 / 3224310063776.0,
+                        2802321613138.0 / 2924317926251.0};
 
 struct DevBuf {
   void* p = nullptr;
@@ -54,6 +60,19 @@ struct dg_ctx {
   DevBuf frags;             // BF16x3: operator hi/lo fragments
   DevBuf matblk;            // BF16x3: material blocked by 16-element tile
   int cur = 0;
+  // point sources: specification (host) and device arrays
+  struct Source {
+    double x[3], d[3], f0, t0, amp;
+  };
+  std::vector<Source> src;
+  DevBuf src_elem;          // int64 [nsrc]
+  DevBuf src_w;             // working precision [nsrc][3][Np]
+  DevBuf src_par;           // double [nsrc][3]: f0, t0, amplitude
+  // receivers
+  int32_t nrec = 0;
+  DevBuf rec_elem;          // int64 [nrec]
+  DevBuf rec_w;             // working precision [nrec][Np]
+  DevBuf rec_buf;           // working precision scratch for host-side traces
 };
 
 namespace {
@@ -304,6 +323,121 @@ dg_status fill_zero(dg_ctx* c, void* p, int64_t n) {
   return DG_OK;
 }
 
+// 1/rho at the quadrature points of element k, read back from the device
+// material in the layout of the context's precision
+dg_status device_irho(dg_ctx* c, int64_t k, std::vector<double>& out) {
+  const int Nq = c->re.Nq;
+  out.assign(Nq, 0.0);
+  if (c->opt.precision == DG_FP32_BF16X3) {
+    for (int p = 0; p < Nq; ++p) {
+      float v = 0.f;
+      const size_t idx = dgh::mfma_material_index(c->re.N, k, p, 0);
+      DG_HIP(c, hipMemcpy(&v, static_cast<const float*>(c->matblk.p) + idx, 4,
+                          hipMemcpyDeviceToHost));
+      out[p] = v;
+    }
+  } else if (c->elem == 8) {
+    DG_HIP(c, hipMemcpy(out.data(), static_cast<const double*>(c->irho.p) + k * Nq, 8 * Nq,
+                        hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp(Nq);
+    DG_HIP(c, hipMemcpy(tmp.data(), static_cast<const float*>(c->irho.p) + k * Nq, 4 * Nq,
+                        hipMemcpyDeviceToHost));
+    for (int p = 0; p < Nq; ++p) out[p] = tmp[p];
+  }
+  return DG_OK;
+}
+
+// Device arrays of the point sources: element, response after the mass
+// inverse P_q[(1/rho) V_q (V psi(x^_s) / J_k)] d (FP64 on the host, from the
+// device material), Ricker parameters.
+dg_status upload_sources(dg_ctx* c) {
+  const int Np = c->re.Np, Nq = c->re.Nq;
+  const size_t ns = c->src.size();
+  release(c, c->src_elem);
+  release(c, c->src_w);
+  release(c, c->src_par);
+  if (ns == 0) return DG_OK;
+  std::vector<int64_t> elem(ns);
+  std::vector<double> w(ns * 3 * Np), par(ns * 3);
+  std::vector<double> psi(Np), raw(Np), rq(Nq), irho;
+  for (size_t i = 0; i < ns; ++i) {
+    const dg_ctx::Source& S = c->src[i];
+    int64_t k = -1;
+    double rst[3];
+    if (!dgh::locate_point(c->re, c->mesh, S.x, k, rst))
+      return fail(c, DG_EINVAL, "sources: point outside the mesh");
+    elem[i] = k;
+    dgh::basis_at(c->re, rst[0], rst[1], rst[2], psi.data());
+    for (int n = 0; n < Np; ++n) {
+      double acc = 0.0;
+      for (int m = 0; m < Np; ++m) acc += c->re.V[size_t(n) * Np + m] * psi[m];
+      raw[n] = acc / c->mesh.J[k];
+    }
+    dg_status st = device_irho(c, k, irho);
+    if (st != DG_OK) return st;
+    for (int p = 0; p < Nq; ++p) {
+      double acc = 0.0;
+      for (int n = 0; n < Np; ++n) acc += c->re.Vq[size_t(p) * Np + n] * raw[n];
+      rq[p] = irho[p] * acc;
+    }
+    for (int n = 0; n < Np; ++n) {
+      double acc = 0.0;
+      for (int p = 0; p < Nq; ++p) acc += c->re.Pq[size_t(n) * Nq + p] * rq[p];
+      for (int d = 0; d < 3; ++d) w[(i * 3 + d) * Np + n] = S.d[d] * acc;
+    }
+    par[3 * i] = S.f0;
+    par[3 * i + 1] = S.t0;
+    par[3 * i + 2] = S.amp;
+  }
+  dg_status st;
+  if ((st = upload_raw(c, c->src_elem, elem.data(), ns)) != DG_OK) return st;
+  if ((st = upload_real(c, c->src_w, w.data(), w.size())) != DG_OK) return st;
+  if ((st = upload_raw(c, c->src_par, par.data(), par.size())) != DG_OK) return st;
+  return DG_OK;
+}
+
+// out1 += alpha f(t) w, out2 += beta f(t) w for every source
+dg_status launch_sources(dg_ctx* c, void* out1, void* out2, double t, double alpha,
+                         double beta) {
+  const int ns = int(c->src.size());
+  if (ns == 0) return DG_OK;
+  const int Np = c->re.Np;
+  const int64_t KNp = c->mesh.K * Np;
+  const unsigned nb = unsigned((3 * Np + 255) / 256);
+  const int64_t* el = static_cast<const int64_t*>(c->src_elem.p);
+  const double* par = static_cast<const double*>(c->src_par.p);
+  if (c->elem == 8)
+    dgs::source_add<double><<<nb, 256, 0, c->stream>>>(
+        static_cast<double*>(out1), static_cast<double*>(out2), el,
+        static_cast<const double*>(c->src_w.p), par, ns, Np, KNp, t, alpha, beta);
+  else
+    dgs::source_add<float><<<nb, 256, 0, c->stream>>>(
+        static_cast<float*>(out1), static_cast<float*>(out2), el,
+        static_cast<const float*>(c->src_w.p), par, ns, Np, KNp, t, alpha, beta);
+  DG_HIP(c, hipGetLastError());
+  return DG_OK;
+}
+
+// velocity at the receivers of the current state into out (device, [nrec][3])
+dg_status launch_receivers(dg_ctx* c, void* out) {
+  if (c->nrec == 0) return DG_OK;
+  const int Np = c->re.Np;
+  const int64_t KNp = c->mesh.K * Np;
+  const unsigned nb = unsigned((3 * c->nrec + 255) / 256);
+  const int64_t* el = static_cast<const int64_t*>(c->rec_elem.p);
+  if (c->elem == 8)
+    dgs::receiver_sample<double><<<nb, 256, 0, c->stream>>>(
+        static_cast<double*>(out), static_cast<const double*>(c->q[c->cur].p), el,
+        static_cast<const double*>(c->rec_w.p), c->nrec, Np, KNp);
+  else
+    dgs::receiver_sample<float><<<nb, 256, 0, c->stream>>>(
+        static_cast<float*>(out), static_cast<const float*>(c->q[c->cur].p), el,
+        static_cast<const float*>(c->rec_w.p), c->nrec, Np, KNp);
+  DG_HIP(c, hipGetLastError());
+  return DG_OK;
+}
+
 dg_status ready(dg_ctx* c, bool need_state) {
   if (!c) return DG_EINVAL;
   if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
@@ -379,7 +513,8 @@ void dg_destroy(dg_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (DevBuf* b : {&c->ops, &c->opsT, &c->fmask, &c->geo, &c->fgeo, &c->etoe, &c->etop, &c->pat,
                       &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
-                      &c->res, &c->frags, &c->matblk})
+                      &c->res, &c->frags, &c->matblk, &c->src_elem, &c->src_w,
+                      &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf})
       release(c, *b);
   }
   delete c;
@@ -411,9 +546,13 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
   c->has_mesh = true;
   c->has_mat = false;
   c->has_state = false;
+  c->src.clear();           // sources and receivers belong to the old mesh
+  c->nrec = 0;
   if (!device_ctx(c)) return DG_OK;
   dg_status s = set_device(c);
   if (s != DG_OK) return s;
+  for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf})
+    release(c, *b);
   const dgh::MeshData& md = c->mesh;
   if ((s = upload_real(c, c->geo, md.geo.data(), md.geo.size())) != DG_OK) return s;
   if ((s = upload_real(c, c->fgeo, md.fgeo.data(), md.fgeo.size())) != DG_OK) return s;
@@ -492,6 +631,7 @@ dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
   if ((s = upload_real(c, c->zp, zp.data(), nn)) != DG_OK) return s;
   if ((s = upload_real(c, c->zs, zs.data(), nn)) != DG_OK) return s;
   c->has_mat = true;
+  if (!c->src.empty()) return upload_sources(c);   // source responses depend on 1/rho
   return DG_OK;
 }
 
@@ -552,12 +692,14 @@ dg_status dg_state_device_ptr(dg_ctx* c, void** ptr) {
   return DG_OK;
 }
 
-dg_status dg_rhs(dg_ctx* c, const void* q_dev, void* rhs_dev) {
+dg_status dg_rhs(dg_ctx* c, const void* q_dev, void* rhs_dev, double t) {
   if (!c || !q_dev || !rhs_dev) return DG_EINVAL;
   if (q_dev == rhs_dev) return fail(c, DG_EINVAL, "rhs: q and rhs must not alias");
+  if (!std::isfinite(t)) return fail(c, DG_EINVAL, "rhs: non-finite t");
   dg_status s = ready(c, false);
   if (s != DG_OK) return s;
-  return stage(c, q_dev, nullptr, nullptr, rhs_dev, 0.0, 0.0, 0.0, 0);
+  if ((s = stage(c, q_dev, nullptr, nullptr, rhs_dev, 0.0, 0.0, 0.0, 0)) != DG_OK) return s;
+  return launch_sources(c, rhs_dev, nullptr, t, 1.0, 0.0);
 }
 
 dg_status dg_step(dg_ctx* c, double t, double dt) {
@@ -569,9 +711,10 @@ dg_status dg_step(dg_ctx* c, double t, double dt) {
     s = stage(c, c->q[c->cur].p, c->q[1 - c->cur].p, c->res.p, nullptr, kRkA[st], kRkB[st],
               dt, 1);
     if (s != DG_OK) return s;
+    s = launch_sources(c, c->res.p, c->q[1 - c->cur].p, t + kRkC[st] * dt, dt, kRkB[st] * dt);
+    if (s != DG_OK) return s;
     c->cur = 1 - c->cur;
   }
-  (void)t;
   return DG_OK;
 }
 
@@ -581,6 +724,135 @@ dg_status dg_run(dg_ctx* c, double t0, double dt, int64_t nsteps) {
   for (int64_t i = 0; i < nsteps; ++i) {
     dg_status s = dg_step(c, t0 + double(i) * dt, dt);
     if (s != DG_OK) return s;
+  }
+  return DG_OK;
+}
+
+dg_status dg_sources_set(dg_ctx* c, int32_t nsrc, const double* xyz, const double* dir,
+                         const double* f0, const double* t0, const double* amp) {
+  if (!c) return DG_EINVAL;
+  if (nsrc < 0 || (nsrc > 0 && (!xyz || !dir || !f0 || !t0 || !amp)))
+    return fail(c, DG_EINVAL, "sources: bad arguments");
+  if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
+  if (!c->has_mesh) return fail(c, DG_ESTATE, "sources: no mesh uploaded");
+  if (!c->has_mat) return fail(c, DG_ESTATE, "sources: no material uploaded");
+  std::vector<dg_ctx::Source> src(nsrc);
+  for (int i = 0; i < nsrc; ++i) {
+    for (int d = 0; d < 3; ++d) {
+      src[i].x[d] = xyz[3 * i + d];
+      src[i].d[d] = dir[3 * i + d];
+      if (!std::isfinite(src[i].x[d]) || !std::isfinite(src[i].d[d]))
+        return fail(c, DG_ENONFINITE, "sources: non-finite position or direction");
+    }
+    src[i].f0 = f0[i];
+    src[i].t0 = t0[i];
+    src[i].amp = amp[i];
+    if (!std::isfinite(f0[i]) || !std::isfinite(t0[i]) || !std::isfinite(amp[i]))
+      return fail(c, DG_ENONFINITE, "sources: non-finite wavelet parameter");
+    if (!(f0[i] > 0.0)) return fail(c, DG_EINVAL, "sources: need f0 > 0");
+    int64_t k;
+    double rst[3];
+    if (!dgh::locate_point(c->re, c->mesh, src[i].x, k, rst))
+      return fail(c, DG_EINVAL, "sources: point outside the mesh");
+  }
+  dg_status s = set_device(c);
+  if (s != DG_OK) return s;
+  DG_HIP(c, hipStreamSynchronize(c->stream));   // the old arrays may be in use
+  c->src = std::move(src);
+  return upload_sources(c);
+}
+
+dg_status dg_receivers_set(dg_ctx* c, int32_t nrec, const double* xyz) {
+  if (!c) return DG_EINVAL;
+  if (nrec < 0 || (nrec > 0 && !xyz)) return fail(c, DG_EINVAL, "receivers: bad arguments");
+  if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
+  if (!c->has_mesh) return fail(c, DG_ESTATE, "receivers: no mesh uploaded");
+  const int Np = c->re.Np;
+  std::vector<int64_t> elem(nrec);
+  std::vector<double> w(size_t(nrec) * Np), psi(Np);
+  for (int r = 0; r < nrec; ++r) {
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(xyz[3 * r + d]))
+        return fail(c, DG_ENONFINITE, "receivers: non-finite position");
+    double rst[3];
+    if (!dgh::locate_point(c->re, c->mesh, xyz + 3 * r, elem[r], rst))
+      return fail(c, DG_EINVAL, "receivers: point outside the mesh");
+    // Lagrange basis at the point: l = V^-T psi, i.e. solve V^T l = psi
+    dgh::basis_at(c->re, rst[0], rst[1], rst[2], psi.data());
+    std::vector<double> VT(size_t(Np) * Np), l(Np);
+    for (int i = 0; i < Np; ++i)
+      for (int j = 0; j < Np; ++j) VT[size_t(i) * Np + j] = c->re.V[size_t(j) * Np + i];
+    // Gaussian elimination with partial pivoting
+    std::vector<double> b(psi);
+    for (int col = 0; col < Np; ++col) {
+      int piv = col;
+      for (int i = col + 1; i < Np; ++i)
+        if (std::fabs(VT[size_t(i) * Np + col]) > std::fabs(VT[size_t(piv) * Np + col])) piv = i;
+      if (piv != col) {
+        for (int j = 0; j < Np; ++j) std::swap(VT[size_t(col) * Np + j], VT[size_t(piv) * Np + j]);
+        std::swap(b[col], b[piv]);
+      }
+      for (int i = col + 1; i < Np; ++i) {
+        const double f = VT[size_t(i) * Np + col] / VT[size_t(col) * Np + col];
+        for (int j = col; j < Np; ++j) VT[size_t(i) * Np + j] -= f * VT[size_t(col) * Np + j];
+        b[i] -= f * b[col];
+      }
+    }
+    for (int i = Np - 1; i >= 0; --i) {
+      double acc = b[i];
+      for (int j = i + 1; j < Np; ++j) acc -= VT[size_t(i) * Np + j] * l[j];
+      l[i] = acc / VT[size_t(i) * Np + i];
+    }
+    for (int n = 0; n < Np; ++n) w[size_t(r) * Np + n] = l[n];
+  }
+  dg_status s = set_device(c);
+  if (s != DG_OK) return s;
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  c->nrec = 0;
+  for (DevBuf* b : {&c->rec_elem, &c->rec_w, &c->rec_buf}) release(c, *b);
+  if (nrec == 0) return DG_OK;
+  if ((s = upload_raw(c, c->rec_elem, elem.data(), elem.size())) != DG_OK) return s;
+  if ((s = upload_real(c, c->rec_w, w.data(), w.size())) != DG_OK) return s;
+  c->nrec = nrec;
+  return DG_OK;
+}
+
+dg_status dg_receivers_sample(dg_ctx* c, void* out, int32_t on_device) {
+  if (!c || !out) return DG_EINVAL;
+  dg_status s = ready(c, true);
+  if (s != DG_OK) return s;
+  if (c->nrec == 0) return fail(c, DG_ESTATE, "receivers: none set");
+  const size_t bytes = size_t(c->nrec) * 3 * c->elem;
+  if (on_device) return launch_receivers(c, out);
+  if (c->rec_buf.bytes < bytes && (s = alloc(c, c->rec_buf, bytes)) != DG_OK) return s;
+  if ((s = launch_receivers(c, c->rec_buf.p)) != DG_OK) return s;
+  DG_HIP(c, hipMemcpyAsync(out, c->rec_buf.p, bytes, hipMemcpyDeviceToHost, c->stream));
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  return DG_OK;
+}
+
+dg_status dg_run_record(dg_ctx* c, double t0, double dt, int64_t nsteps, void* trace,
+                        int32_t on_device) {
+  if (!c || !trace) return DG_EINVAL;
+  if (nsteps < 0) return fail(c, DG_EINVAL, "run: negative step count");
+  dg_status s = ready(c, true);
+  if (s != DG_OK) return s;
+  if (c->nrec == 0) return fail(c, DG_ESTATE, "receivers: none set");
+  const size_t per = size_t(c->nrec) * 3 * c->elem;
+  char* dst = static_cast<char*>(trace);
+  if (!on_device) {
+    const size_t bytes = per * size_t(nsteps);
+    if (c->rec_buf.bytes < bytes && (s = alloc(c, c->rec_buf, bytes)) != DG_OK) return s;
+    dst = static_cast<char*>(c->rec_buf.p);
+  }
+  for (int64_t i = 0; i < nsteps; ++i) {
+    if ((s = dg_step(c, t0 + double(i) * dt, dt)) != DG_OK) return s;
+    if ((s = launch_receivers(c, dst + per * size_t(i))) != DG_OK) return s;
+  }
+  if (!on_device && nsteps > 0) {
+    DG_HIP(c, hipMemcpyAsync(trace, c->rec_buf.p, per * size_t(nsteps), hipMemcpyDeviceToHost,
+                             c->stream));
+    DG_HIP(c, hipStreamSynchronize(c->stream));
   }
   return DG_OK;
 }

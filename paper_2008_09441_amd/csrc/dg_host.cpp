@@ -249,6 +249,7 @@ bool build_ref_element(int N, RefElement& re, std::string& err) {
     err = "singular Vandermonde matrix";
     return false;
   }
+  re.V = V;
   re.Dr = matmul(Np, Np, Np, Vr, Vi);
   re.Ds = matmul(Np, Np, Np, Vs, Vi);
   re.Dt = matmul(Np, Np, Np, Vt, Vi);
@@ -360,6 +361,7 @@ bool build_mesh(const RefElement& re, int64_t K, const double* vxyz,
     }
   m = MeshData();
   m.K = K;
+  for (int d = 0; d < 3; ++d) m.period[d] = period[d];
   m.vx.assign(vxyz, vxyz + K * 12);
   m.geo.resize(K * 9);
   m.fgeo.resize(K * 16);
@@ -513,6 +515,39 @@ bool build_mesh(const RefElement& re, int64_t K, const double* vxyz,
     }
   m.npat = int(pat_id.size());
   return true;
+}
+
+void basis_at(const RefElement& re, double r, double s, double t, double* psi) {
+  tet_basis(re.N, r, s, t, psi, nullptr, nullptr, nullptr);
+}
+
+bool locate_point(const RefElement& re, const MeshData& m, const double* x, int64_t& k,
+                  double* rst) {
+  (void)re;
+  for (int64_t e = 0; e < m.K; ++e) {
+    // r + 1 = (d r / d x) (x - x_0) for the affine map of element e, with
+    // x - x_0 taken as the nearest periodic image (elements are smaller
+    // than half the period)
+    const double* v0 = &m.vx[size_t(e) * 12];
+    const double* G = &m.geo[size_t(e) * 9];
+    double dx[3];
+    for (int d = 0; d < 3; ++d) {
+      dx[d] = x[d] - v0[d];
+      dx[d] -= m.period[d] * std::nearbyint(dx[d] / m.period[d]);
+    }
+    double lo[3], mn = 1.0;
+    for (int i = 0; i < 3; ++i) {
+      lo[i] = G[i * 3 + 0] * dx[0] + G[i * 3 + 1] * dx[1] + G[i * 3 + 2] * dx[2] - 1.0;
+      mn = std::min(mn, (1.0 + lo[i]) / 2.0);
+    }
+    mn = std::min(mn, -(1.0 + lo[0] + lo[1] + lo[2]) / 2.0);
+    if (mn >= -1e-12) {
+      k = e;
+      for (int i = 0; i < 3; ++i) rst[i] = lo[i];
+      return true;
+    }
+  }
+  return false;
 }
 
 static void map_points(const RefElement& re, const MeshData& m, const std::vector<double>& r,

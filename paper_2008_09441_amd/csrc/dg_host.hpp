@@ -27,6 +27,7 @@ struct RefElement {
   std::vector<double> rq, sq, tq, wq;   // quadrature points/weights [Nq]
   std::vector<int> Fmask;               // [4][Nfp] volume node of face node
   std::vector<double> Minv;             // [Np][Np]
+  std::vector<double> V;                // Vandermonde [Np][Np]: V[i][m] = psi_m(node i)
   // barycentric coordinates of each face node w.r.t. the face's three
   // vertices (in face-vertex order), [4][Nfp][3]
   std::vector<double> fbary;
@@ -48,6 +49,7 @@ struct MeshData {
   std::vector<int32_t> pat;    // [npat][Nfp] neighbour volume node per own face node
   int npat = 0;
   std::vector<double> vx;      // [K][4][3] vertices as given
+  double period[3] = {0.0, 0.0, 0.0};
 };
 
 // vxyz: per-element vertex coordinates [K][4][3]; period: box lengths [3]
@@ -56,6 +58,15 @@ struct MeshData {
 // periodic mesh.
 bool build_mesh(const RefElement& re, int64_t K, const double* vxyz,
                 const double* period, MeshData& m, std::string& err);
+
+// Orthonormal basis psi[Np] at the reference point (r, s, t) [HW08, Ch. 10].
+void basis_at(const RefElement& re, double r, double s, double t, double* psi);
+
+// Element containing the physical point x (any periodic image) and its
+// reference coordinates: the first element whose barycentric coordinates
+// are all >= -1e-12.  Returns false if there is none.
+bool locate_point(const RefElement& re, const MeshData& m, const double* x, int64_t& k,
+                  double* rst);
 
 // Physical coordinates of the nodes [K][Np][3] or quadrature points
 // [K][Nq][3].

@@ -140,4 +140,19 @@ std::vector<double> mfma_material(int N, int64_t K, const double* irho, const do
   }
 }
 
+size_t mfma_material_index(int N, int64_t k, int p, int f) {
+  int mats = 0;
+  switch (N) {
+    case 1: mats = dgb::BOrd<1>::MATS; break;
+    case 2: mats = dgb::BOrd<2>::MATS; break;
+    case 3: mats = dgb::BOrd<3>::MATS; break;
+    default: mats = dgb::BOrd<4>::MATS; break;
+  }
+  // inverse of the layout of build_material: p = 32 c + 16 u + 4 g + j,
+  // lane l = 16 g + k % 16
+  const int c = p / 32, u = (p % 32) / 16, g = (p % 16) / 4, j = p % 4;
+  const int l = 16 * g + int(k % 16);
+  return (size_t(k / 16) * 3 + f) * mats + ((size_t(c) * 2 + u) * 64 + l) * 4 + j;
+}
+
 }  // namespace dgh

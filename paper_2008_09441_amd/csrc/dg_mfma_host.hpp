@@ -25,4 +25,8 @@ std::vector<double> col_operators(const RefElement& re);
 std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
                                   const double* mu);
 
+// index in the blocked material array of field f (0 1/rho, 1 lam, 2 mu) at
+// quadrature point p of element k
+size_t mfma_material_index(int N, int64_t k, int p, int f);
+
 }  // namespace dgh

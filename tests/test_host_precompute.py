@@ -136,7 +136,7 @@ def test_validation_and_state_errors():
         B.dg_step(s.ctx, 0.0, 1e-3)
     assert e.value.status == B.DG_EDEVICE
     z = np.zeros(9 * K * Np)
-    assert B.lib.dg_rhs(s.ctx, z.ctypes.data, z[1:].ctypes.data) == B.DG_EDEVICE
+    assert B.lib.dg_rhs(s.ctx, z.ctypes.data, z[1:].ctypes.data, 0.0) == B.DG_EDEVICE
     with pytest.raises(ValueError):
         B.dg_rhs(s.ctx, z, z)        # host arrays are rejected by the binding
     s.close()
@@ -148,3 +148,20 @@ def test_wrong_shapes_rejected_before_the_library():
         B.dg_material_upload(s.ctx, *[np.ones((6, 26))] * 3, *[np.ones((6, 10))] * 3)
     with pytest.raises(ValueError):
         B.dg_mesh_upload(s.ctx, np.zeros((6, 3, 3)), np.ones(3))
+
+
+def test_sources_and_receivers_need_a_device_context():
+    """A host-only context refuses sources and receivers (they set up device
+    arrays) with DG_EDEVICE, after argument checks."""
+    from paper_2008_09441_amd import B
+    ctx = B.dg_create(2, B.DG_FP64, B.DG_FLUX_UPWIND, -1)
+    try:
+        B.dg_mesh_upload(ctx, synth.kuhn_cube_vertices(2), np.ones(3))
+        with pytest.raises(B.DGError) as e:
+            B.dg_sources_set(ctx, [[0.5, 0.5, 0.5]], [[0, 0, 1]], 5.0, 0.2, 1.0)
+        assert e.value.status == B.DG_EDEVICE
+        with pytest.raises(B.DGError) as e:
+            B.dg_receivers_set(ctx, [[0.5, 0.5, 0.5]])
+        assert e.value.status == B.DG_EDEVICE
+    finally:
+        B.dg_destroy(ctx)
