@@ -111,6 +111,10 @@ dg_status dg_material_upload(dg_ctx* ctx, const double* rho_q, const double* cp_
  * q: [nfields][K][Np], both host. */
 dg_status dg_project(const dg_ctx* ctx, int32_t nfields, const double* fq, double* q);
 
+/* Set the state (and the LSRK residual) to zero with a device fill kernel:
+ * no host transfer.  Stream-ordered. */
+dg_status dg_state_zero(dg_ctx* ctx);
+
 /* Set / get the context's state [9][K][Np] (working precision).  on_device
  * != 0: q is a device pointer (copied stream-ordered); else host (the call
  * synchronises).  dg_state_set also zeroes the LSRK residual. */
@@ -170,6 +174,53 @@ dg_status dg_receivers_sample(dg_ctx* ctx, void* out, int32_t on_device);
  * in device memory it owns and copies it at the end; synchronous). */
 dg_status dg_run_record(dg_ctx* ctx, double t0, double dt, int64_t nsteps, void* trace,
                         int32_t on_device);
+
+/* ---- Runs on the device clock (for captured graphs and serving) --------
+ * Each context keeps a device-resident clock (time, step count).  Runs on
+ * it read the time from device memory, so their launch arguments do not
+ * depend on the time and a captured run can be replayed at any time. */
+
+/* Set the clock to time t and step count 0 (stream-ordered). */
+dg_status dg_time_set(dg_ctx* ctx, double t);
+
+/* Read the clock (synchronises the stream).  Either pointer may be NULL. */
+dg_status dg_time_get(dg_ctx* ctx, double* t, int64_t* step);
+
+/* Library-owned device trace [max_steps][nrec][3] (working precision) that
+ * dg_advance fills: after the i-th step of a run that starts at clock step
+ * s, row s + i receives the receiver velocities; rows at or beyond
+ * max_steps are not written, rows not yet written are undefined.  Needs
+ * receivers (DG_ESTATE); replaced by a later call or dg_receivers_set.
+ * Counted against the HBM budget.  Synchronises the stream. */
+dg_status dg_trace_reserve(dg_ctx* ctx, int64_t max_steps);
+
+/* Copy the first nrows rows of the trace to host memory out (synchronous). */
+dg_status dg_trace_copy(dg_ctx* ctx, void* out, int64_t nrows);
+
+/* nsteps LSRK(5,4) steps [CK94] from the device clock: stage s of step i
+ * evaluates the sources at clock time + (i + c_s) dt, the receivers are
+ * recorded into the trace after every step, then the clock advances by
+ * nsteps steps.  Stream-ordered, asynchronous. */
+dg_status dg_advance(dg_ctx* ctx, double dt, int64_t nsteps);
+
+/* As dg_advance, but the launches of the run are captured once into a
+ * hipGraph per (dt, nsteps, starting state buffer) and replayed on later
+ * calls.  Needs a context created with its own stream (DG_ESTATE
+ * otherwise).  Graphs are dropped when sources, receivers, the trace, the
+ * material or the mesh change. */
+dg_status dg_graph_advance(dg_ctx* ctx, double dt, int64_t nsteps);
+
+/* Device bytes the context holds (the amount counted against its HBM
+ * budget). */
+dg_status dg_memory(const dg_ctx* ctx, uint64_t* bytes);
+
+/* Device bytes a context of this order and precision will hold for a mesh
+ * of K elements with nsrc sources, nrec receivers and a trace of
+ * trace_steps rows (an upper bound: the face-pattern table is counted at
+ * its maximum size), so that a scheduler can admit work by HBM budget
+ * before creating the context.  No device needed. */
+dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc, int32_t nrec,
+                       int64_t trace_steps, uint64_t* bytes);
 
 /* Wait for the context's stream; reports asynchronous device errors. */
 dg_status dg_synchronize(dg_ctx* ctx);

@@ -25,7 +25,9 @@ EXPORTS = [
     "dg_state_set", "dg_state_get", "dg_state_device_ptr", "dg_rhs", "dg_step",
     "dg_run", "dg_synchronize", "dg_ref_operator", "dg_face_nodes",
     "dg_connectivity", "dg_geometry", "dg_sources_set", "dg_receivers_set",
-    "dg_receivers_sample", "dg_run_record",
+    "dg_receivers_sample", "dg_run_record", "dg_time_set", "dg_time_get",
+    "dg_trace_reserve", "dg_trace_copy", "dg_advance", "dg_graph_advance", "dg_memory",
+    "dg_footprint", "dg_state_zero",
 ]
 
 
@@ -73,6 +75,15 @@ def _load():
         "dg_receivers_set": ([P, I32, P], I32),
         "dg_receivers_sample": ([P, P, I32], I32),
         "dg_run_record": ([P, D, D, I64, P, I32], I32),
+        "dg_time_set": ([P, D], I32),
+        "dg_time_get": ([P, P, P], I32),
+        "dg_trace_reserve": ([P, I64], I32),
+        "dg_trace_copy": ([P, P, I64], I32),
+        "dg_advance": ([P, D, I64], I32),
+        "dg_graph_advance": ([P, D, I64], I32),
+        "dg_memory": ([P, P], I32),
+        "dg_footprint": ([I32, I32, I64, I32, I32, I64, P], I32),
+        "dg_state_zero": ([P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -252,6 +263,51 @@ def dg_receivers_sample(ctx, out, on_device):
 def dg_run_record(ctx, t0, dt, nsteps, trace, on_device):
     check(ctx, lib.dg_run_record(ctx, float(t0), float(dt), int(nsteps), _ptr(trace),
                                  1 if on_device else 0))
+
+
+def dg_state_zero(ctx):
+    check(ctx, lib.dg_state_zero(ctx))
+
+
+def dg_time_set(ctx, t):
+    check(ctx, lib.dg_time_set(ctx, float(t)))
+
+
+def dg_time_get(ctx):
+    t, step = ctypes.c_double(), ctypes.c_int64()
+    check(ctx, lib.dg_time_get(ctx, ctypes.byref(t), ctypes.byref(step)))
+    return t.value, step.value
+
+
+def dg_trace_reserve(ctx, max_steps):
+    check(ctx, lib.dg_trace_reserve(ctx, int(max_steps)))
+
+
+def dg_trace_copy(ctx, out, nrows):
+    check(ctx, lib.dg_trace_copy(ctx, _ptr(out), int(nrows)))
+
+
+def dg_advance(ctx, dt, nsteps):
+    check(ctx, lib.dg_advance(ctx, float(dt), int(nsteps)))
+
+
+def dg_graph_advance(ctx, dt, nsteps):
+    check(ctx, lib.dg_graph_advance(ctx, float(dt), int(nsteps)))
+
+
+def dg_memory(ctx):
+    b = ctypes.c_uint64()
+    check(ctx, lib.dg_memory(ctx, ctypes.byref(b)))
+    return b.value
+
+
+def dg_footprint(order, precision, K, nsrc=0, nrec=0, trace_steps=0):
+    b = ctypes.c_uint64()
+    st = lib.dg_footprint(int(order), int(precision), int(K), int(nsrc), int(nrec),
+                          int(trace_steps), ctypes.byref(b))
+    if st != DG_OK:
+        raise DGError(st, "dg_footprint: bad arguments")
+    return b.value
 
 
 def dg_synchronize(ctx):

@@ -73,6 +73,18 @@ struct dg_ctx {
   DevBuf rec_elem;          // int64 [nrec]
   DevBuf rec_w;             // working precision [nrec][Np]
   DevBuf rec_buf;           // working precision scratch for host-side traces
+  // device clock (time, step count) and the receiver trace it indexes
+  DevBuf clk;               // double [2]
+  DevBuf trace;             // working precision [trace_cap][nrec][3]
+  int64_t trace_cap = 0;
+  // captured runs: (dt, steps, starting state buffer) -> executable graph
+  struct Graph {
+    double dt;
+    int64_t nsteps;
+    int cur;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
 };
 
 namespace {
@@ -120,16 +132,26 @@ dg_status alloc(dg_ctx* c, DevBuf& b, size_t bytes) {
   return DG_OK;
 }
 
+// synchronous copy ordered on the context's own stream: the library never
+// uses the legacy null stream when the context has a stream of its own, so
+// other contexts' captures and non-blocking streams are not disturbed
+hipError_t copy_sync(const dg_ctx* c, void* dst, const void* src, size_t bytes,
+                     hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
 // upload an FP64 host array cast to the working precision
 dg_status upload_real(dg_ctx* c, DevBuf& b, const double* src, size_t n) {
   dg_status s = alloc(c, b, n * c->elem);
   if (s != DG_OK) return s;
   if (c->elem == 8) {
-    DG_HIP(c, hipMemcpy(b.p, src, n * 8, hipMemcpyHostToDevice));
+    DG_HIP(c, copy_sync(c, b.p, src, n * 8, hipMemcpyHostToDevice));
   } else {
     std::vector<float> tmp(n);
     for (size_t i = 0; i < n; ++i) tmp[i] = float(src[i]);
-    DG_HIP(c, hipMemcpy(b.p, tmp.data(), n * 4, hipMemcpyHostToDevice));
+    DG_HIP(c, copy_sync(c, b.p, tmp.data(), n * 4, hipMemcpyHostToDevice));
   }
   return DG_OK;
 }
@@ -138,7 +160,7 @@ template <typename U>
 dg_status upload_raw(dg_ctx* c, DevBuf& b, const U* src, size_t n) {
   dg_status s = alloc(c, b, n * sizeof(U));
   if (s != DG_OK) return s;
-  DG_HIP(c, hipMemcpy(b.p, src, n * sizeof(U), hipMemcpyHostToDevice));
+  DG_HIP(c, copy_sync(c, b.p, src, n * sizeof(U), hipMemcpyHostToDevice));
   return DG_OK;
 }
 
@@ -332,16 +354,16 @@ dg_status device_irho(dg_ctx* c, int64_t k, std::vector<double>& out) {
     for (int p = 0; p < Nq; ++p) {
       float v = 0.f;
       const size_t idx = dgh::mfma_material_index(c->re.N, k, p, 0);
-      DG_HIP(c, hipMemcpy(&v, static_cast<const float*>(c->matblk.p) + idx, 4,
+      DG_HIP(c, copy_sync(c, &v, static_cast<const float*>(c->matblk.p) + idx, 4,
                           hipMemcpyDeviceToHost));
       out[p] = v;
     }
   } else if (c->elem == 8) {
-    DG_HIP(c, hipMemcpy(out.data(), static_cast<const double*>(c->irho.p) + k * Nq, 8 * Nq,
+    DG_HIP(c, copy_sync(c, out.data(), static_cast<const double*>(c->irho.p) + k * Nq, 8 * Nq,
                         hipMemcpyDeviceToHost));
   } else {
     std::vector<float> tmp(Nq);
-    DG_HIP(c, hipMemcpy(tmp.data(), static_cast<const float*>(c->irho.p) + k * Nq, 4 * Nq,
+    DG_HIP(c, copy_sync(c, tmp.data(), static_cast<const float*>(c->irho.p) + k * Nq, 4 * Nq,
                         hipMemcpyDeviceToHost));
     for (int p = 0; p < Nq; ++p) out[p] = tmp[p];
   }
@@ -438,6 +460,67 @@ dg_status launch_receivers(dg_ctx* c, void* out) {
   return DG_OK;
 }
 
+// captured graphs hold buffer addresses and source/receiver counts: drop
+// them whenever those change
+void drop_graphs(dg_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+// nsteps LSRK(5,4) steps from the device clock: sources read the clock,
+// receivers (if a trace is reserved) write row clk_step + i after step i,
+// and the clock advances at the end.  Every launch argument is independent
+// of the time, so the sequence can be captured once and replayed.
+dg_status advance_impl(dg_ctx* c, double dt, int64_t nsteps) {
+  const int Np = c->re.Np;
+  const int64_t KNp = c->mesh.K * Np;
+  double* clk = static_cast<double*>(c->clk.p);
+  const int ns = int(c->src.size());
+  for (int64_t i = 0; i < nsteps; ++i) {
+    for (int st = 0; st < 5; ++st) {
+      dg_status s = stage(c, c->q[c->cur].p, c->q[1 - c->cur].p, c->res.p, nullptr, kRkA[st],
+                          kRkB[st], dt, 1);
+      if (s != DG_OK) return s;
+      if (ns > 0) {
+        const unsigned nb = unsigned((3 * Np + 255) / 256);
+        const int64_t* el = static_cast<const int64_t*>(c->src_elem.p);
+        const double* par = static_cast<const double*>(c->src_par.p);
+        const double toff = (double(i) + kRkC[st]) * dt;
+        if (c->elem == 8)
+          dgs::source_add_clk<double><<<nb, 256, 0, c->stream>>>(
+              static_cast<double*>(c->res.p), static_cast<double*>(c->q[1 - c->cur].p), el,
+              static_cast<const double*>(c->src_w.p), par, ns, Np, KNp, clk, toff, dt,
+              kRkB[st] * dt);
+        else
+          dgs::source_add_clk<float><<<nb, 256, 0, c->stream>>>(
+              static_cast<float*>(c->res.p), static_cast<float*>(c->q[1 - c->cur].p), el,
+              static_cast<const float*>(c->src_w.p), par, ns, Np, KNp, clk, toff, dt,
+              kRkB[st] * dt);
+        DG_HIP(c, hipGetLastError());
+      }
+      c->cur = 1 - c->cur;
+    }
+    if (c->nrec > 0 && c->trace_cap > 0) {
+      const unsigned nb = unsigned((3 * c->nrec + 255) / 256);
+      const int64_t* el = static_cast<const int64_t*>(c->rec_elem.p);
+      if (c->elem == 8)
+        dgs::receiver_sample_clk<double><<<nb, 256, 0, c->stream>>>(
+            static_cast<double*>(c->trace.p), c->trace_cap, clk, i,
+            static_cast<const double*>(c->q[c->cur].p), el,
+            static_cast<const double*>(c->rec_w.p), c->nrec, Np, KNp);
+      else
+        dgs::receiver_sample_clk<float><<<nb, 256, 0, c->stream>>>(
+            static_cast<float*>(c->trace.p), c->trace_cap, clk, i,
+            static_cast<const float*>(c->q[c->cur].p), el,
+            static_cast<const float*>(c->rec_w.p), c->nrec, Np, KNp);
+      DG_HIP(c, hipGetLastError());
+    }
+  }
+  dgs::clock_advance<<<1, 64, 0, c->stream>>>(clk, dt, nsteps);
+  DG_HIP(c, hipGetLastError());
+  return DG_OK;
+}
+
 dg_status ready(dg_ctx* c, bool need_state) {
   if (!c) return DG_EINVAL;
   if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
@@ -511,6 +594,9 @@ void dg_destroy(dg_ctx* c) {
   if (!c) return;
   if (device_ctx(c) && hipSetDevice(c->opt.device) == hipSuccess) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    release(c, c->clk);
+    release(c, c->trace);
     for (DevBuf* b : {&c->ops, &c->opsT, &c->fmask, &c->geo, &c->fgeo, &c->etoe, &c->etop, &c->pat,
                       &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
                       &c->res, &c->frags, &c->matblk, &c->src_elem, &c->src_w,
@@ -551,8 +637,16 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
   if (!device_ctx(c)) return DG_OK;
   dg_status s = set_device(c);
   if (s != DG_OK) return s;
-  for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf})
+  drop_graphs(c);
+  for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf,
+                    &c->trace})
     release(c, *b);
+  c->trace_cap = 0;
+  if (!c->clk.p) {
+    if ((s = alloc(c, c->clk, 2 * sizeof(double))) != DG_OK) return s;
+  }
+  dgs::clock_set<<<1, 64, 0, c->stream>>>(static_cast<double*>(c->clk.p), 0.0);
+  DG_HIP(c, hipGetLastError());
   const dgh::MeshData& md = c->mesh;
   if ((s = upload_real(c, c->geo, md.geo.data(), md.geo.size())) != DG_OK) return s;
   if ((s = upload_real(c, c->fgeo, md.fgeo.data(), md.fgeo.size())) != DG_OK) return s;
@@ -631,6 +725,7 @@ dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
   if ((s = upload_real(c, c->zp, zp.data(), nn)) != DG_OK) return s;
   if ((s = upload_real(c, c->zs, zs.data(), nn)) != DG_OK) return s;
   c->has_mat = true;
+  drop_graphs(c);
   if (!c->src.empty()) return upload_sources(c);   // source responses depend on 1/rho
   return DG_OK;
 }
@@ -662,10 +757,20 @@ dg_status dg_state_set(dg_ctx* c, const void* q, int32_t on_device) {
     DG_HIP(c, hipMemcpyAsync(c->q[c->cur].p, q, n * c->elem, hipMemcpyDeviceToDevice,
                              c->stream));
   else {
-    DG_HIP(c, hipStreamSynchronize(c->stream));
-    DG_HIP(c, hipMemcpy(c->q[c->cur].p, q, n * c->elem, hipMemcpyHostToDevice));
+    DG_HIP(c, copy_sync(c, c->q[c->cur].p, q, n * c->elem, hipMemcpyHostToDevice));
   }
   if ((s = fill_zero(c, c->res.p, int64_t(n))) != DG_OK) return s;
+  c->has_state = true;
+  return DG_OK;
+}
+
+dg_status dg_state_zero(dg_ctx* c) {
+  if (!c) return DG_EINVAL;
+  dg_status s = ready(c, false);
+  if (s != DG_OK) return s;
+  const int64_t n = int64_t(9) * c->mesh.K * c->re.Np;
+  if ((s = fill_zero(c, c->q[c->cur].p, n)) != DG_OK) return s;
+  if ((s = fill_zero(c, c->res.p, n)) != DG_OK) return s;
   c->has_state = true;
   return DG_OK;
 }
@@ -758,6 +863,7 @@ dg_status dg_sources_set(dg_ctx* c, int32_t nsrc, const double* xyz, const doubl
   dg_status s = set_device(c);
   if (s != DG_OK) return s;
   DG_HIP(c, hipStreamSynchronize(c->stream));   // the old arrays may be in use
+  drop_graphs(c);
   c->src = std::move(src);
   return upload_sources(c);
 }
@@ -808,8 +914,10 @@ dg_status dg_receivers_set(dg_ctx* c, int32_t nrec, const double* xyz) {
   dg_status s = set_device(c);
   if (s != DG_OK) return s;
   DG_HIP(c, hipStreamSynchronize(c->stream));
+  drop_graphs(c);
   c->nrec = 0;
-  for (DevBuf* b : {&c->rec_elem, &c->rec_w, &c->rec_buf}) release(c, *b);
+  c->trace_cap = 0;
+  for (DevBuf* b : {&c->rec_elem, &c->rec_w, &c->rec_buf, &c->trace}) release(c, *b);
   if (nrec == 0) return DG_OK;
   if ((s = upload_raw(c, c->rec_elem, elem.data(), elem.size())) != DG_OK) return s;
   if ((s = upload_real(c, c->rec_w, w.data(), w.size())) != DG_OK) return s;
@@ -854,6 +962,134 @@ dg_status dg_run_record(dg_ctx* c, double t0, double dt, int64_t nsteps, void* t
                              c->stream));
     DG_HIP(c, hipStreamSynchronize(c->stream));
   }
+  return DG_OK;
+}
+
+dg_status dg_time_set(dg_ctx* c, double t) {
+  if (!c) return DG_EINVAL;
+  if (!std::isfinite(t)) return fail(c, DG_EINVAL, "time: non-finite");
+  dg_status s = ready(c, false);
+  if (s != DG_OK) return s;
+  dgs::clock_set<<<1, 64, 0, c->stream>>>(static_cast<double*>(c->clk.p), t);
+  DG_HIP(c, hipGetLastError());
+  return DG_OK;
+}
+
+dg_status dg_time_get(dg_ctx* c, double* t, int64_t* step) {
+  if (!c) return DG_EINVAL;
+  dg_status s = ready(c, false);
+  if (s != DG_OK) return s;
+  double h[2];
+  DG_HIP(c, hipMemcpyAsync(h, c->clk.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  if (t) *t = h[0];
+  if (step) *step = int64_t(h[1]);
+  return DG_OK;
+}
+
+dg_status dg_trace_reserve(dg_ctx* c, int64_t max_steps) {
+  if (!c) return DG_EINVAL;
+  if (max_steps < 0) return fail(c, DG_EINVAL, "trace: negative capacity");
+  if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
+  if (c->nrec == 0) return fail(c, DG_ESTATE, "trace: no receivers set");
+  dg_status s = set_device(c);
+  if (s != DG_OK) return s;
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  c->trace_cap = 0;
+  if ((s = alloc(c, c->trace, size_t(max_steps) * c->nrec * 3 * c->elem)) != DG_OK) return s;
+  c->trace_cap = max_steps;
+  return DG_OK;
+}
+
+dg_status dg_trace_copy(dg_ctx* c, void* out, int64_t nrows) {
+  if (!c || !out) return DG_EINVAL;
+  if (nrows < 0 || nrows > c->trace_cap) return fail(c, DG_EINVAL, "trace: rows out of range");
+  dg_status s = set_device(c);
+  if (s != DG_OK) return s;
+  const size_t bytes = size_t(nrows) * c->nrec * 3 * c->elem;
+  if (bytes) DG_HIP(c, hipMemcpyAsync(out, c->trace.p, bytes, hipMemcpyDeviceToHost, c->stream));
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  return DG_OK;
+}
+
+dg_status dg_advance(dg_ctx* c, double dt, int64_t nsteps) {
+  if (!c) return DG_EINVAL;
+  if (!std::isfinite(dt) || nsteps < 0) return fail(c, DG_EINVAL, "advance: bad dt or steps");
+  dg_status s = ready(c, true);
+  if (s != DG_OK) return s;
+  return advance_impl(c, dt, nsteps);
+}
+
+dg_status dg_graph_advance(dg_ctx* c, double dt, int64_t nsteps) {
+  if (!c) return DG_EINVAL;
+  if (!std::isfinite(dt) || nsteps < 1) return fail(c, DG_EINVAL, "graph: bad dt or steps");
+  dg_status s = ready(c, true);
+  if (s != DG_OK) return s;
+  if (!c->stream) return fail(c, DG_ESTATE, "graph: the context needs its own stream");
+  const int cur0 = c->cur;
+  const int cur1 = int((cur0 + 5 * nsteps) & 1);
+  const dg_ctx::Graph* g = nullptr;
+  for (const auto& x : c->graphs)
+    if (x.dt == dt && x.nsteps == nsteps && x.cur == cur0) g = &x;
+  if (!g) {
+    hipGraph_t graph = nullptr;
+    // relaxed: other threads (other requests' set-up) keep calling HIP
+    DG_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    s = advance_impl(c, dt, nsteps);
+    const hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+    c->cur = cur0;   // capture recorded the launches without running them
+    if (s != DG_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (ec != hipSuccess)
+      return fail(c, DG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess)
+      return fail(c, DG_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    c->graphs.push_back({dt, nsteps, cur0, exec});
+    g = &c->graphs.back();
+  }
+  DG_HIP(c, hipGraphLaunch(g->exec, c->stream));
+  c->cur = cur1;
+  return DG_OK;
+}
+
+dg_status dg_memory(const dg_ctx* c, uint64_t* bytes) {
+  if (!c || !bytes) return DG_EINVAL;
+  *bytes = c->allocated;
+  return DG_OK;
+}
+
+dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc, int32_t nrec,
+                       int64_t trace_steps, uint64_t* bytes) {
+  if (!bytes || order < 1 || order > 7 || K < 1 || nsrc < 0 || nrec < 0 || trace_steps < 0)
+    return DG_EINVAL;
+  if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_FP32_BF16X3)
+    return DG_EINVAL;
+  if (precision == DG_FP32_BF16X3 && !dgh::mfma_supported(order)) return DG_EINVAL;
+  const uint64_t N = uint64_t(order), Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  const uint64_t Nfp = (N + 1) * (N + 2) / 2, Nq = (N + 1) * (N + 1) * (N + 1), NF4 = 4 * Nfp;
+  const uint64_t NpP = 4 * ((Np + 3) / 4), QP = 32 * ((Nq + 31) / 32);
+  const uint64_t e = precision == DG_FP64 ? 8 : 4, k = uint64_t(K);
+  uint64_t b = 0;
+  b += (3 * Np * Np + Np * NF4 + Nq * Np + Np * Nq) * e;              // operators
+  b += (3 * Np * NpP + NF4 * NpP + Np * QP + QP * NpP) * e;           // transposed operators
+  b += NF4 * 4;                                                       // face masks
+  if (precision == DG_FP32_BF16X3) b += uint64_t(dgh::mfma_frag_count(order)) * 64 * 8 * 2;
+  b += k * (9 + 16) * e + k * 4 * 4 + k * 4 + 96 * Nfp * 4;          // geometry, tables
+  b += 3 * 9 * k * Np * e + 2 * sizeof(double);                      // q[2], res, clock
+  if (precision == DG_FP32_BF16X3)
+    b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * 4;   // blocked material
+  else
+    b += 3 * k * Nq * e;                                              // 1/rho, lam, mu
+  b += 2 * k * Np * e;                                                // impedances
+  b += uint64_t(nsrc) * (8 + 3 * Np * e + 3 * 8);                     // sources
+  b += uint64_t(nrec) * (8 + Np * e) + uint64_t(trace_steps) * nrec * 3 * e;   // receivers
+  *bytes = b;
   return DG_OK;
 }
 

@@ -140,14 +140,26 @@ std::vector<double> mfma_material(int N, int64_t K, const double* irho, const do
   }
 }
 
-size_t mfma_material_index(int N, int64_t k, int p, int f) {
-  int mats = 0;
+int mfma_frag_count(int N) {
   switch (N) {
-    case 1: mats = dgb::BOrd<1>::MATS; break;
-    case 2: mats = dgb::BOrd<2>::MATS; break;
-    case 3: mats = dgb::BOrd<3>::MATS; break;
-    default: mats = dgb::BOrd<4>::MATS; break;
+    case 1: return dgb::BOrd<1>::NFRAG;
+    case 2: return dgb::BOrd<2>::NFRAG;
+    case 3: return dgb::BOrd<3>::NFRAG;
+    default: return dgb::BOrd<4>::NFRAG;
   }
+}
+
+int mfma_mats(int N) {
+  switch (N) {
+    case 1: return dgb::BOrd<1>::MATS;
+    case 2: return dgb::BOrd<2>::MATS;
+    case 3: return dgb::BOrd<3>::MATS;
+    default: return dgb::BOrd<4>::MATS;
+  }
+}
+
+size_t mfma_material_index(int N, int64_t k, int p, int f) {
+  const int mats = mfma_mats(N);
   // inverse of the layout of build_material: p = 32 c + 16 u + 4 g + j,
   // lane l = 16 g + k % 16
   const int c = p / 32, u = (p % 32) / 16, g = (p % 16) / 4, j = p % 4;

@@ -25,6 +25,10 @@ std::vector<double> col_operators(const RefElement& re);
 std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
                                   const double* mu);
 
+// fragment count and blocked-material floats per (tile, field) of order N
+int mfma_frag_count(int N);
+int mfma_mats(int N);
+
 // index in the blocked material array of field f (0 1/rho, 1 lam, 2 mu) at
 // quadrature point p of element k
 size_t mfma_material_index(int N, int64_t k, int p, int f);

@@ -50,3 +50,63 @@ __global__ void receiver_sample(T* out, const T* q, const int64_t* elem, const T
 }
 
 }  // namespace dgs
+
+namespace dgs {
+
+// Device-resident clock of a context: clk[0] = time (double), clk[1] = step
+// count (stored as a double holding an exact integer, < 2^53).  Launches that
+// read it have arguments independent of the time, so a captured graph of a
+// run can be replayed at any time.
+__global__ void clock_set(double* clk, double t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    clk[0] = t;
+    clk[1] = 0.0;
+  }
+}
+
+__global__ void clock_advance(double* clk, double dt, int64_t nsteps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    // t0 + n dt from the step count, not a running sum (no drift)
+    clk[1] += double(nsteps);
+    clk[0] += double(nsteps) * dt;
+  }
+}
+
+// source_add with the time read from the clock: t = clk[0] + toff
+template <typename T>
+__global__ void source_add_clk(T* out1, T* out2, const int64_t* elem, const T* w,
+                               const double* par, int nsrc, int Np, int64_t KNp,
+                               const double* clk, double toff, double alpha, double beta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * Np) return;
+  const double t = clk[0] + toff;
+  const int c = i / Np, n = i - c * Np;
+  for (int s = 0; s < nsrc; ++s) {
+    const double a = 3.14159265358979323846 * par[3 * s] * (t - par[3 * s + 1]);
+    const double f = par[3 * s + 2] * (1.0 - 2.0 * a * a) * exp(-a * a);
+    const int64_t idx = c * KNp + elem[s] * Np + n;
+    const T v = T(f) * w[(s * 3 + c) * Np + n];
+    out1[idx] += T(alpha) * v;
+    if (out2) out2[idx] += T(beta) * v;
+  }
+}
+
+// receiver_sample into row (clk[1] + soff) of a trace with cap rows; rows
+// beyond the capacity are not written
+template <typename T>
+__global__ void receiver_sample_clk(T* trace, int64_t cap, const double* clk, int64_t soff,
+                                    const T* q, const int64_t* elem, const T* w, int nrec,
+                                    int Np, int64_t KNp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * nrec) return;
+  const int64_t row = int64_t(clk[1]) + soff;
+  if (row < 0 || row >= cap) return;
+  const int r = i / 3, c = i - 3 * r;
+  const T* qe = q + c * KNp + elem[r] * Np;
+  const T* wr = w + int64_t(r) * Np;
+  T acc = T(0);
+  for (int n = 0; n < Np; ++n) acc += wr[n] * qe[n];
+  trace[(row * nrec + r) * 3 + c] = acc;
+}
+
+}  // namespace dgs

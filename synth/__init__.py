@@ -56,12 +56,13 @@ def _fourier_unit(x, seed, n_modes=16, kmax=3):
     return 0.5 * (1.0 + g / np.sum(np.abs(a)))
 
 
-def fourier_media(x, seed=9441):
-    """Smooth heterogeneous media from three independent seeded sums of 16
-    random Fourier modes: rho in [1, 3], cp in [2, 4], cs = cp / [1.6, 2.0]."""
-    s_rho = _fourier_unit(x, seed + 0)
-    s_p = _fourier_unit(x, seed + 1)
-    s_r = _fourier_unit(x, seed + 2)
+def fourier_media(x, seed=9441, n_modes=16):
+    """Smooth heterogeneous media from three independent seeded sums of
+    n_modes (16) random Fourier modes: rho in [1, 3], cp in [2, 4],
+    cs = cp / [1.6, 2.0]."""
+    s_rho = _fourier_unit(x, seed + 0, n_modes)
+    s_p = _fourier_unit(x, seed + 1, n_modes)
+    s_r = _fourier_unit(x, seed + 2, n_modes)
     rho = 1.0 + 2.0 * s_rho
     cp = 2.0 + 2.0 * s_p
     cs = cp / (1.6 + 0.4 * s_r)
