@@ -74,6 +74,11 @@ def parse():
     p.add_argument("--order", type=int, default=4)
     p.add_argument("--no-fp64-reference", action="store_true")
     p.add_argument("--no-fp32-path", action="store_true")
+    p.add_argument("--no-sources", action="store_true",
+                   help="skip the point-source / receiver measurement")
+    p.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    p.add_argument("--serving-requests", type=int, default=64)
+    p.add_argument("--serving-rate", type=float, default=3.0, help="arrivals per second")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-n", type=int, default=12)
     p.add_argument("--calibrate-copy", action="store_true",
@@ -157,6 +162,71 @@ class QuadNorm:
         grp = np.array([r2[:3].sum()] * 3 + [r2[3:].sum()] * 6)
         return {"rel_per_field": [float(x) for x in np.sqrt(e2 / np.maximum(r2, 1e-300))],
                 "rel_per_field_of_group": [float(x) for x in np.sqrt(e2 / grp)]}
+
+
+def sources_receivers(args, steps=50):
+    """The order-4 Kuhn cube of 24^3 x 6 tets with Fourier media, 4 Ricker
+    point forces and 64 receivers: DOF-updates/s of the recorded run
+    (receivers sampled after every step) against the same run without
+    sources and receivers."""
+    import synth
+    from paper_2008_09441_amd import B, Solver
+    n, N = 24, args.order
+    s = Solver(N, precision=args.precision, flux="upwind", device=0)
+    s.upload_mesh(synth.kuhn_cube_vertices(n))
+    B.dg_material_upload(s.ctx, *(synth.fourier_media(s.quad_coords())
+                                  + synth.fourier_media(s.node_coords())))
+    K, Np, _, _ = s.sizes()
+    rng = np.random.default_rng(2024)
+    f0 = rng.uniform(5.0, 15.0, 4)
+    dt = 0.5 * (1.0 / n) / math.sqrt(2.0) / (4.0 * (N + 1) ** 2)
+    zero = np.zeros((9, K, Np))
+
+    def timed(record):
+        s.set_state(zero)
+        s.synchronize()
+        t0 = time.perf_counter()
+        if record:
+            tr = s.run_record(0.0, dt, steps)
+        else:
+            s.run(0.0, dt, steps)
+            s.synchronize()
+            tr = None
+        return time.perf_counter() - t0, tr
+    plain, _ = timed(False)
+    s.set_sources(rng.random((4, 3)), rng.standard_normal((4, 3)), f0, 1.2 / f0, 1.0)
+    s.set_receivers(rng.random((64, 3)))
+    timed(True)                                       # warm-up of the recorded path
+    rec, tr = timed(True)
+    s.close()
+    dofs = 9 * K * Np * steps
+    return {"workload": f"N={N}, {n}^3x6 = {K} tets, Fourier media, 4 Ricker forces "
+                        f"(f0 in [5,15]), 64 receivers sampled every step, {steps} steps, "
+                        f"{args.precision}",
+            "value": dofs / rec, "unit": "DOF-updates/s", "plain_value": dofs / plain,
+            "overhead_frac": rec / plain - 1.0,
+            "max_abs_trace": float(np.abs(tr).max())}
+
+
+def serving(args):
+    """Continuous batching of independent solves: a seeded Poisson stream of
+    requests (periodic Kuhn cubes, n in [8, 24], N in {3, 4, 5}, 100-200 LSRK
+    steps, FP32, smooth random media, one Ricker force with f0 in [5, 15],
+    16 receivers), admitted by HBM budget, advanced by captured hipGraphs of
+    10 steps.  Latency = finish - arrival."""
+    from paper_2008_09441_amd.serving import Server, poisson_workload
+    reqs = poisson_workload(args.serving_requests, rate=args.serving_rate, n_range=(8, 24),
+                            orders=(3, 4, 5), steps=(100, 200), nrec=16, precision="fp32",
+                            seed=2008)
+    srv = Server(hbm_budget=64 << 30, max_active=16, chunk=10, graphs=True, workers=4)
+    srv.run(reqs)
+    st = dict(srv.stats)
+    st["workload"] = (f"{len(reqs)} Poisson requests at {args.serving_rate}/s, periodic "
+                      "n^3x6 Kuhn cubes n in [8,24], N in {3,4,5}, 100-200 LSRK(5,4) steps, "
+                      "fp32, smooth random media (4 Fourier modes), 1 Ricker force "
+                      "(f0 in [5,15]), 16 receivers; 16 slots, 64 GiB budget, 10-step "
+                      "captured graphs")
+    return st
 
 
 def cpu_baseline(args, N):
@@ -281,6 +351,10 @@ def main():
         out["l2_vs_fp64"] = {"norm": "quadrature L2 after warmup+steps", **norm.errors(q_lo, q64)}
         if "fp32_path" in out:
             out["fp32_path"]["l2_vs_fp64"] = norm.errors(q32, q64)
+    if not args.no_sources:
+        out["sources_receivers"] = sources_receivers(args)
+    if not args.no_serving:
+        out["serving"] = serving(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, N)
     print(json.dumps(out), flush=True)
