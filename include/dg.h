@@ -210,6 +210,37 @@ dg_status dg_advance(dg_ctx* ctx, double dt, int64_t nsteps);
  * material or the mesh change. */
 dg_status dg_graph_advance(dg_ctx* ctx, double dt, int64_t nsteps);
 
+/* ---- Discrete adjoint ---------------------------------------------------
+ * Gradient of a receiver misfit with respect to the weight-adjusted
+ * material weights m = (1/rho, lam, mu) at the quadrature points, holding
+ * the flux impedances fixed [CHW17, C18].  FP64 and FP32 contexts
+ * (DG_EINVAL for DG_FP32_BF16X3). */
+
+/* Set the weights directly: 1/rho, lam, mu host [K][Nq], impedances Zp, Zs
+ * host [K][Np] (all copied).  Errors: DG_ESTATE before the mesh,
+ * DG_ENONFINITE, DG_EINVAL for non-positive impedances. */
+dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const double* lam_q,
+                                  const double* mu_q, const double* zp_n, const double* zs_n);
+
+/* nsteps LSRK(5,4) steps from the current state (host time t0 + i dt),
+ * keeping a copy of the state every `every` steps on the device and writing
+ * the receiver velocities after every step to trace (host
+ * [nsteps][nrec][3], working precision).  Leaves the context at the end of
+ * the run.  Needs receivers (DG_ESTATE).  Library-owned device memory:
+ * ceil(nsteps/every) + every + 11 states plus face and quadrature work
+ * arrays, counted against the HBM budget. */
+dg_status dg_adjoint_forward(dg_ctx* ctx, double t0, double dt, int64_t nsteps, int64_t every,
+                             void* trace);
+
+/* Reverse sweep of the last dg_adjoint_forward run for a misfit J with
+ * dJ/d(trace) = resid (host [nsteps][nrec][3], working precision): the
+ * discrete adjoint of every stage (transposed weight-adjusted inverse,
+ * transposed volume, flux and LIFT operators, receiver adjoint), with the
+ * states of each checkpoint interval recomputed from its checkpoint.
+ * grad: host double [3][K][Nq] = dJ/d(1/rho, lam, mu).  The context's state
+ * is not changed.  Synchronous. */
+dg_status dg_adjoint_backward(dg_ctx* ctx, const void* resid, double* grad);
+
 /* Device bytes the context holds (the amount counted against its HBM
  * budget). */
 dg_status dg_memory(const dg_ctx* ctx, uint64_t* bytes);

@@ -27,7 +27,8 @@ EXPORTS = [
     "dg_connectivity", "dg_geometry", "dg_sources_set", "dg_receivers_set",
     "dg_receivers_sample", "dg_run_record", "dg_time_set", "dg_time_get",
     "dg_trace_reserve", "dg_trace_copy", "dg_advance", "dg_graph_advance", "dg_memory",
-    "dg_footprint", "dg_state_zero",
+    "dg_footprint", "dg_state_zero", "dg_material_set_weights", "dg_adjoint_forward",
+    "dg_adjoint_backward",
 ]
 
 
@@ -84,6 +85,9 @@ def _load():
         "dg_memory": ([P, P], I32),
         "dg_footprint": ([I32, I32, I64, I32, I32, I64, P], I32),
         "dg_state_zero": ([P], I32),
+        "dg_material_set_weights": ([P, P, P, P, P, P], I32),
+        "dg_adjoint_forward": ([P, D, D, I64, I64, P], I32),
+        "dg_adjoint_backward": ([P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -263,6 +267,26 @@ def dg_receivers_sample(ctx, out, on_device):
 def dg_run_record(ctx, t0, dt, nsteps, trace, on_device):
     check(ctx, lib.dg_run_record(ctx, float(t0), float(dt), int(nsteps), _ptr(trace),
                                  1 if on_device else 0))
+
+
+def dg_material_set_weights(ctx, irho_q, lam_q, mu_q, zp_n, zs_n):
+    K, Np, _, Nq = dg_sizes(ctx)
+    a = [_f64(x, (K, Nq)) for x in (irho_q, lam_q, mu_q)] + \
+        [_f64(x, (K, Np)) for x in (zp_n, zs_n)]
+    check(ctx, lib.dg_material_set_weights(ctx, *[_ptr(x) for x in a]))
+
+
+def dg_adjoint_forward(ctx, t0, dt, nsteps, every, trace):
+    if not isinstance(trace, np.ndarray) or not trace.flags["C_CONTIGUOUS"]:
+        raise ValueError("trace must be a C-contiguous host array")
+    check(ctx, lib.dg_adjoint_forward(ctx, float(t0), float(dt), int(nsteps), int(every),
+                                      _ptr(trace)))
+
+
+def dg_adjoint_backward(ctx, resid, grad):
+    if grad.dtype != np.float64 or not grad.flags["C_CONTIGUOUS"]:
+        raise ValueError("grad must be a C-contiguous float64 host array")
+    check(ctx, lib.dg_adjoint_backward(ctx, _ptr(np.ascontiguousarray(resid)), _ptr(grad)))
 
 
 def dg_state_zero(ctx):

@@ -1,0 +1,396 @@
+// Device kernels of the discrete adjoint of the DG elastic-wave stage (FP64
+// and FP32): the raw right-hand side R q (volume terms, face fluxes, LIFT,
+// before the mass inverse), the transposes W^T and R^T, the gradient with
+// respect to the weight-adjusted material weights, the receiver adjoint and
+// vector updates.  Simple one-thread-per-item kernels over runtime sizes; the
+// adjoint sweep calls them a few times per stage.
+//
+// Transposes, per element (W(m) r = P_q[weights . V_q r], [CHW17, C18]):
+//   (W^T l)_v = V_q^T (1/rho) P_q^T l_v,
+//   (W^T l)_s = V_q^T [lam tr(P_q^T l_s) I + 2 mu P_q^T l_s];
+// R = volume + LIFT Fscale flux(q-, q+) [HW08, Ch. 10], [WSG10]:
+//   R^T mu = volume^T mu + per face node: (d flux / d q-)^T g at the own node
+//            plus (d flux_nb / d q+)^T g_nb from the neighbour's face node
+//            that reads this node, with g = Fscale LIFT^T mu at face nodes.
+// The flux transpose is the reverse-mode derivative of the flux formula
+// written out step by step (rev_flux).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dga {
+
+template <typename T>
+struct AdjArgs {
+  const T* geo;          // [K][9]
+  const T* fgeo;         // [K][4][4]
+  const int32_t* etoe;   // [K][4]
+  const uint8_t* etop;   // [K][4]
+  const int32_t* pat;    // [npat][Nfp]
+  const int32_t* fmask;  // [4][Nfp]
+  const int32_t* nbface; // [K][4 Nfp]: neighbour element * 4 Nfp + its face node
+  const int32_t* invf;   // [Np][3]: face nodes on each volume node (-1 padded)
+  const T* zp;           // [K][Np]
+  const T* zs;
+  const T* Dr;           // [Np][Np]
+  const T* Ds;
+  const T* Dt;
+  const T* LIFT;         // [Np][4 Nfp]
+  const T* Vq;           // [Nq][Np]
+  const T* Pq;           // [Np][Nq]
+  const T* irho;         // [K][Nq]
+  const T* lam;
+  const T* mu;
+  int64_t K;
+  int Np, Nfp, Nq;
+  int upwind;
+};
+
+// output component c of the volume term: sum_d D_d sum_j G_dj w(c,j) q_f(c,j)
+// (the stress row of c for the velocity components, the symmetrised
+// velocity pattern for the strain components)
+__device__ inline int vf(int c, int j) {
+  return c == 0 ? (j == 0 ? 3 : j == 1 ? 8 : 7)
+       : c == 1 ? (j == 0 ? 8 : j == 1 ? 4 : 6)
+       : c == 2 ? (j == 0 ? 7 : j == 1 ? 6 : 5)
+       : c == 3 ? 0
+       : c == 4 ? 1
+       : c == 5 ? 2
+       : c == 6 ? (j == 1 ? 2 : 1)
+       : c == 7 ? (j == 0 ? 2 : 0)
+       : (j == 0 ? 1 : 0);
+}
+template <typename T>
+__device__ inline T vw(int c, int j) {
+  if (c < 3) return T(1);
+  if (c < 6) return j == c - 3 ? T(1) : T(0);
+  return j == c - 6 ? T(0) : T(0.5);
+}
+
+// forward flux (times Fscale) at one face node, fl[9]
+template <typename T>
+__device__ inline void flux(const T* qM, const T* qP, T nx, T ny, T nz, T fs, T ZpM, T ZsM,
+                            T ZpP, T ZsP, int upwind, T* fl) {
+  const T tMx = qM[3] * nx + qM[8] * ny + qM[7] * nz;
+  const T tMy = qM[8] * nx + qM[4] * ny + qM[6] * nz;
+  const T tMz = qM[7] * nx + qM[6] * ny + qM[5] * nz;
+  const T tPx = qP[3] * nx + qP[8] * ny + qP[7] * nz;
+  const T tPy = qP[8] * nx + qP[4] * ny + qP[6] * nz;
+  const T tPz = qP[7] * nx + qP[6] * ny + qP[5] * nz;
+  const T jvx = qP[0] - qM[0], jvy = qP[1] - qM[1], jvz = qP[2] - qM[2];
+  const T jtx = tPx - tMx, jty = tPy - tMy, jtz = tPz - tMz;
+  T dvx, dvy, dvz, dtx, dty, dtz;
+  if (upwind) {
+    const T jvn = jvx * nx + jvy * ny + jvz * nz;
+    const T jtn = jtx * nx + jty * ny + jtz * nz;
+    const T dvn = (ZpP * jvn + jtn) / (ZpM + ZpP);
+    const T ivs = T(1) / (ZsM + ZsP);
+    const T dvtx = (ZsP * (jvx - jvn * nx) + (jtx - jtn * nx)) * ivs;
+    const T dvty = (ZsP * (jvy - jvn * ny) + (jty - jtn * ny)) * ivs;
+    const T dvtz = (ZsP * (jvz - jvn * nz) + (jtz - jtn * nz)) * ivs;
+    dvx = dvn * nx + dvtx;
+    dvy = dvn * ny + dvty;
+    dvz = dvn * nz + dvtz;
+    dtx = ZpM * dvn * nx + ZsM * dvtx;
+    dty = ZpM * dvn * ny + ZsM * dvty;
+    dtz = ZpM * dvn * nz + ZsM * dvtz;
+  } else {
+    dvx = T(0.5) * jvx; dvy = T(0.5) * jvy; dvz = T(0.5) * jvz;
+    dtx = T(0.5) * jtx; dty = T(0.5) * jty; dtz = T(0.5) * jtz;
+  }
+  fl[0] = fs * dtx;
+  fl[1] = fs * dty;
+  fl[2] = fs * dtz;
+  fl[3] = fs * dvx * nx;
+  fl[4] = fs * dvy * ny;
+  fl[5] = fs * dvz * nz;
+  fl[6] = fs * T(0.5) * (dvy * nz + dvz * ny);
+  fl[7] = fs * T(0.5) * (dvx * nz + dvz * nx);
+  fl[8] = fs * T(0.5) * (dvx * ny + dvy * nx);
+}
+
+// reverse of flux(): the flux is linear in (qM, qP); given g = adjoint of
+// fl, returns qMbar = (d fl / d qM)^T g and qPbar = (d fl / d qP)^T g
+template <typename T>
+__device__ inline void rev_flux(const T* g, T nx, T ny, T nz, T fs, T ZpM, T ZsM, T ZpP, T ZsP,
+                                int upwind, T* qMb, T* qPb) {
+  // fl -> (dv, dt)
+  const T dtbx = fs * g[0], dtby = fs * g[1], dtbz = fs * g[2];
+  const T dvbx = fs * (g[3] * nx + T(0.5) * (g[7] * nz + g[8] * ny));
+  const T dvby = fs * (g[4] * ny + T(0.5) * (g[6] * nz + g[8] * nx));
+  const T dvbz = fs * (g[5] * nz + T(0.5) * (g[6] * ny + g[7] * nx));
+  T jvbx, jvby, jvbz, jtbx, jtby, jtbz;
+  if (upwind) {
+    // dv = dvn n + dvt;  dt = ZpM dvn n + ZsM dvt
+    const T dvnb = dvbx * nx + dvby * ny + dvbz * nz + ZpM * (dtbx * nx + dtby * ny + dtbz * nz);
+    const T dvtbx = dvbx + ZsM * dtbx, dvtby = dvby + ZsM * dtby, dvtbz = dvbz + ZsM * dtbz;
+    // dvn = (ZpP jvn + jtn) / (ZpM + ZpP);  dvt = (ZsP jvt + jtt) / (ZsM + ZsP)
+    const T ip = T(1) / (ZpM + ZpP), is = T(1) / (ZsM + ZsP);
+    const T jvnb = ZpP * ip * dvnb, jtnb = ip * dvnb;
+    const T jvtbx = ZsP * is * dvtbx, jvtby = ZsP * is * dvtby, jvtbz = ZsP * is * dvtbz;
+    const T jttbx = is * dvtbx, jttby = is * dvtby, jttbz = is * dvtbz;
+    // jvt = jv - (jv.n) n, jvn = jv.n: jvbar = jvtbar + (jvnbar - n.jvtbar) n
+    const T av = jvnb - (jvtbx * nx + jvtby * ny + jvtbz * nz);
+    const T at = jtnb - (jttbx * nx + jttby * ny + jttbz * nz);
+    jvbx = jvtbx + av * nx; jvby = jvtby + av * ny; jvbz = jvtbz + av * nz;
+    jtbx = jttbx + at * nx; jtby = jttby + at * ny; jtbz = jttbz + at * nz;
+  } else {
+    jvbx = T(0.5) * dvbx; jvby = T(0.5) * dvby; jvbz = T(0.5) * dvbz;
+    jtbx = T(0.5) * dtbx; jtby = T(0.5) * dtby; jtbz = T(0.5) * dtbz;
+  }
+  // jv = vP - vM; jt = t(P) - t(M), t = sigma n (Voigt xx yy zz yz xz xy)
+  const T s[9] = {jvbx, jvby, jvbz, jtbx * nx, jtby * ny, jtbz * nz,
+                  jtby * nz + jtbz * ny, jtbx * nz + jtbz * nx, jtbx * ny + jtby * nx};
+  for (int f = 0; f < 9; ++f) {
+    qPb[f] = s[f];
+    qMb[f] = -s[f];
+  }
+}
+
+// raw right-hand side, pass 1: Fscale flux at every face node of q,
+// fb[(k * NF4 + j) * 9 + f]
+template <typename T>
+__global__ void raw_flux(AdjArgs<T> A, const T* q, T* fb) {
+  const int NF4 = 4 * A.Nfp, Np = A.Np, Nfp = A.Nfp;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * NF4) return;
+  const int64_t k = i / NF4;
+  const int j = int(i - k * NF4), face = j / Nfp, ii = j - face * Nfp;
+  const int64_t KNp = A.K * Np;
+  const int vM = A.fmask[j];
+  const int64_t nb = A.etoe[k * 4 + face];
+  const int vP = A.pat[int(A.etop[k * 4 + face]) * Nfp + ii];
+  T qM[9], qP[9], fl[9];
+  for (int f = 0; f < 9; ++f) {
+    qM[f] = q[f * KNp + k * Np + vM];
+    qP[f] = q[f * KNp + nb * Np + vP];
+  }
+  const T* fg = A.fgeo + (k * 4 + face) * 4;
+  flux(qM, qP, fg[0], fg[1], fg[2], fg[3], A.zp[k * Np + vM], A.zs[k * Np + vM],
+       A.zp[nb * Np + vP], A.zs[nb * Np + vP], A.upwind, fl);
+  for (int f = 0; f < 9; ++f) fb[i * 9 + f] = fl[f];
+}
+
+// raw right-hand side, pass 2: volume terms + LIFT of the fluxes, r[9][K][Np]
+template <typename T>
+__global__ void raw_nodes(AdjArgs<T> A, const T* q, const T* fb, T* r) {
+  const int Np = A.Np, NF4 = 4 * A.Nfp;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * Np) return;
+  const int64_t k = i / Np;
+  const int n = int(i - k * Np);
+  const int64_t KNp = A.K * Np;
+  T dq[3][9];
+  for (int d = 0; d < 3; ++d)
+    for (int f = 0; f < 9; ++f) dq[d][f] = T(0);
+  for (int m = 0; m < Np; ++m) {
+    const T dr = A.Dr[n * Np + m], ds = A.Ds[n * Np + m], dt = A.Dt[n * Np + m];
+    for (int f = 0; f < 9; ++f) {
+      const T v = q[f * KNp + k * Np + m];
+      dq[0][f] += dr * v;
+      dq[1][f] += ds * v;
+      dq[2][f] += dt * v;
+    }
+  }
+  const T* G = A.geo + k * 9;
+  T out[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T w = vw<T>(c, j);
+      if (w == T(0)) continue;
+      const int f = vf(c, j);
+      for (int d = 0; d < 3; ++d) acc += w * G[d * 3 + j] * dq[d][f];
+    }
+    out[c] = acc;
+  }
+  for (int j = 0; j < NF4; ++j) {
+    const T l = A.LIFT[n * NF4 + j];
+    for (int c = 0; c < 9; ++c) out[c] += l * fb[(k * NF4 + j) * 9 + c];
+  }
+  for (int c = 0; c < 9; ++c) r[c * KNp + i] = out[c];
+}
+
+// W^T, pass 1: material-weighted P_q^T l at every quadrature point,
+// ob[(k * Nq + qp) * 9 + f]
+template <typename T>
+__global__ void wadgT_quad(AdjArgs<T> A, const T* l, T* ob) {
+  const int Np = A.Np, Nq = A.Nq;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * Nq) return;
+  const int64_t k = i / Nq;
+  const int qp = int(i - k * Nq);
+  const int64_t KNp = A.K * Np;
+  T p[9];
+  for (int f = 0; f < 9; ++f) p[f] = T(0);
+  for (int n = 0; n < Np; ++n) {
+    const T w = A.Pq[n * Nq + qp];
+    for (int f = 0; f < 9; ++f) p[f] += w * l[f * KNp + k * Np + n];
+  }
+  const T ir = A.irho[i], la = A.lam[i], m2 = T(2) * A.mu[i];
+  const T tr = p[3] + p[4] + p[5];
+  T o[9];
+  for (int f = 0; f < 3; ++f) o[f] = ir * p[f];
+  for (int f = 3; f < 6; ++f) o[f] = la * tr + m2 * p[f];
+  for (int f = 6; f < 9; ++f) o[f] = m2 * p[f];
+  for (int f = 0; f < 9; ++f) ob[i * 9 + f] = o[f];
+}
+
+// W^T, pass 2: V_q^T back to the nodes, out[9][K][Np]
+template <typename T>
+__global__ void wadgT_nodes(AdjArgs<T> A, const T* ob, T* out) {
+  const int Np = A.Np, Nq = A.Nq;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * Np) return;
+  const int64_t k = i / Np;
+  const int n = int(i - k * Np);
+  const int64_t KNp = A.K * Np;
+  T acc[9];
+  for (int f = 0; f < 9; ++f) acc[f] = T(0);
+  for (int qp = 0; qp < Nq; ++qp) {
+    const T w = A.Vq[qp * Np + n];
+    for (int f = 0; f < 9; ++f) acc[f] += w * ob[(k * Nq + qp) * 9 + f];
+  }
+  for (int f = 0; f < 9; ++f) out[f * KNp + i] = acc[f];
+}
+
+// R^T, pass 1: g = LIFT^T mu at every face node, gb[(k * NF4 + j) * 9 + f]
+template <typename T>
+__global__ void liftT_faces(AdjArgs<T> A, const T* mu, T* gb) {
+  const int Np = A.Np, NF4 = 4 * A.Nfp;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * NF4) return;
+  const int64_t k = i / NF4;
+  const int j = int(i - k * NF4);
+  const int64_t KNp = A.K * Np;
+  T acc[9];
+  for (int f = 0; f < 9; ++f) acc[f] = T(0);
+  for (int n = 0; n < Np; ++n) {
+    const T l = A.LIFT[n * NF4 + j];
+    for (int f = 0; f < 9; ++f) acc[f] += l * mu[f * KNp + k * Np + n];
+  }
+  for (int f = 0; f < 9; ++f) gb[i * 9 + f] = acc[f];
+}
+
+// R^T, pass 2: at every face node, own-side flux transpose plus the
+// neighbour's other-side flux transpose, hb[(k * NF4 + j) * 9 + f]
+template <typename T>
+__global__ void fluxT_faces(AdjArgs<T> A, const T* gb, T* hb) {
+  const int Np = A.Np, Nfp = A.Nfp, NF4 = 4 * Nfp;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * NF4) return;
+  const int64_t k = i / NF4;
+  const int j = int(i - k * NF4), face = j / Nfp, ii = j - face * Nfp;
+  const int vM = A.fmask[j];
+  const int64_t nb = A.etoe[k * 4 + face];
+  const int vP = A.pat[int(A.etop[k * 4 + face]) * Nfp + ii];
+  const int64_t jn = A.nbface[i];                // neighbour's face node (flat)
+  const int fn = int(jn - nb * NF4) / Nfp;       // neighbour's face
+  const T ZpM = A.zp[k * Np + vM], ZsM = A.zs[k * Np + vM];
+  const T ZpP = A.zp[nb * Np + vP], ZsP = A.zs[nb * Np + vP];
+  T a[9], b[9], h[9];
+  const T* fg = A.fgeo + (k * 4 + face) * 4;
+  rev_flux(gb + i * 9, fg[0], fg[1], fg[2], fg[3], ZpM, ZsM, ZpP, ZsP, A.upwind, a, b);
+  for (int f = 0; f < 9; ++f) h[f] = a[f];
+  // the neighbour's flux at its face node jn reads this node as its "+" side
+  const T* fn4 = A.fgeo + (nb * 4 + fn) * 4;
+  rev_flux(gb + jn * 9, fn4[0], fn4[1], fn4[2], fn4[3], ZpP, ZsP, ZpM, ZsM, A.upwind, a, b);
+  for (int f = 0; f < 9; ++f) h[f] += b[f];
+  for (int f = 0; f < 9; ++f) hb[i * 9 + f] = h[f];
+}
+
+// R^T, pass 3: volume transpose plus the face contributions gathered onto
+// the volume nodes, out[9][K][Np] (= R^T mu)
+template <typename T>
+__global__ void volT_nodes(AdjArgs<T> A, const T* mu, const T* hb, T* out) {
+  const int Np = A.Np, NF4 = 4 * A.Nfp;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * Np) return;
+  const int64_t k = i / Np;
+  const int n = int(i - k * Np);
+  const int64_t KNp = A.K * Np;
+  // t[d][c] = (D_d^T mu_c)_n
+  T t[3][9];
+  for (int d = 0; d < 3; ++d)
+    for (int c = 0; c < 9; ++c) t[d][c] = T(0);
+  for (int m = 0; m < Np; ++m) {
+    const T dr = A.Dr[m * Np + n], ds = A.Ds[m * Np + n], dt = A.Dt[m * Np + n];
+    for (int c = 0; c < 9; ++c) {
+      const T v = mu[c * KNp + k * Np + m];
+      t[0][c] += dr * v;
+      t[1][c] += ds * v;
+      t[2][c] += dt * v;
+    }
+  }
+  const T* G = A.geo + k * 9;
+  T acc[9];
+  for (int f = 0; f < 9; ++f) acc[f] = T(0);
+#pragma unroll
+  for (int c = 0; c < 9; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T w = vw<T>(c, j);
+      if (w == T(0)) continue;
+      const int f = vf(c, j);
+      for (int d = 0; d < 3; ++d) acc[f] += w * G[d * 3 + j] * t[d][c];
+    }
+  for (int s = 0; s < 3; ++s) {
+    const int jf = A.invf[n * 3 + s];
+    if (jf < 0) continue;
+    for (int f = 0; f < 9; ++f) acc[f] += hb[(k * NF4 + jf) * 9 + f];
+  }
+  for (int f = 0; f < 9; ++f) out[f * KNp + i] = acc[f];
+}
+
+// gradient: grad[3][K][Nq] += s d/dm <l, W(m) r>
+template <typename T>
+__global__ void grad_accum(AdjArgs<T> A, const T* l, const T* r, double* grad, double s) {
+  const int Np = A.Np, Nq = A.Nq;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * Nq) return;
+  const int64_t k = i / Nq;
+  const int qp = int(i - k * Nq);
+  const int64_t KNp = A.K * Np;
+  T p[9], w[9];
+  for (int f = 0; f < 9; ++f) p[f] = w[f] = T(0);
+  for (int n = 0; n < Np; ++n) {
+    const T pq = A.Pq[n * Nq + qp], vq = A.Vq[qp * Np + n];
+    for (int f = 0; f < 9; ++f) {
+      p[f] += pq * l[f * KNp + k * Np + n];
+      w[f] += vq * r[f * KNp + k * Np + n];
+    }
+  }
+  double g0 = 0.0, g2 = 0.0;
+  for (int f = 0; f < 3; ++f) g0 += double(p[f]) * double(w[f]);
+  for (int f = 3; f < 9; ++f) g2 += double(p[f]) * double(w[f]);
+  const double g1 = (double(p[3]) + double(p[4]) + double(p[5])) *
+                    (double(w[3]) + double(w[4]) + double(w[5]));
+  const int64_t KNq = A.K * Nq;
+  grad[i] += s * g0;
+  grad[KNq + i] += s * g1;
+  grad[2 * KNq + i] += s * 2.0 * g2;
+}
+
+// receiver adjoint: l[c][k_r][n] += w_r[n] resid[r][c] for every receiver;
+// one thread per (component, node), looping over the receivers
+template <typename T>
+__global__ void receiver_adjoint(T* l, const T* resid, const int64_t* elem, const T* w,
+                                 int nrec, int Np, int64_t KNp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * Np) return;
+  const int c = i / Np, n = i - c * Np;
+  for (int r = 0; r < nrec; ++r)
+    l[c * KNp + elem[r] * Np + n] += w[int64_t(r) * Np + n] * resid[r * 3 + c];
+}
+
+// y = a x + b y
+template <typename T>
+__global__ void axpby(T* y, const T* x, double a, double b, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = T(a) * x[i] + T(b) * y[i];
+}
+
+}  // namespace dga

@@ -2,6 +2,7 @@
 // The function contracts are documented in include/dg.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include "dg_kernels.hpp"
 #include "dg_bx.hpp"
 #include "dg_src.hpp"
+#include "dg_adj.hpp"
 #include "dg_mfma_host.hpp"
 
 namespace {
@@ -85,6 +87,20 @@ struct dg_ctx {
     hipGraphExec_t exec;
   };
   std::vector<Graph> graphs;
+  DevBuf src_wraw;          // raw source vectors (before the mass inverse)
+  // discrete adjoint: tables, checkpoints and work arrays
+  DevBuf adj_nbface, adj_invf;
+  DevBuf adj_ck;            // checkpoints [nck][9][K][Np]
+  DevBuf adj_seg;           // step-start states of one segment [every][9][K][Np]
+  DevBuf adj_y;             // stage inputs [5][9][K][Np]
+  DevBuf adj_v;             // ly, lres, mu, nu, r, res [6][9][K][Np]
+  DevBuf adj_fb, adj_gb, adj_hb;   // face-node work [K][4 Nfp][9]
+  DevBuf adj_ob;            // quadrature work [K][Nq][9]
+  DevBuf adj_grad;          // double [3][K][Nq]
+  DevBuf adj_trace;         // [nsteps][nrec][3]
+  bool adj_ready = false;
+  double adj_t0 = 0.0, adj_dt = 0.0;
+  int64_t adj_nsteps = 0, adj_every = 0;
 };
 
 namespace {
@@ -378,10 +394,11 @@ dg_status upload_sources(dg_ctx* c) {
   const size_t ns = c->src.size();
   release(c, c->src_elem);
   release(c, c->src_w);
+  release(c, c->src_wraw);
   release(c, c->src_par);
   if (ns == 0) return DG_OK;
   std::vector<int64_t> elem(ns);
-  std::vector<double> w(ns * 3 * Np), par(ns * 3);
+  std::vector<double> w(ns * 3 * Np), wraw(ns * 3 * Np), par(ns * 3);
   std::vector<double> psi(Np), raw(Np), rq(Nq), irho;
   for (size_t i = 0; i < ns; ++i) {
     const dg_ctx::Source& S = c->src[i];
@@ -395,6 +412,7 @@ dg_status upload_sources(dg_ctx* c) {
       double acc = 0.0;
       for (int m = 0; m < Np; ++m) acc += c->re.V[size_t(n) * Np + m] * psi[m];
       raw[n] = acc / c->mesh.J[k];
+      for (int d = 0; d < 3; ++d) wraw[(i * 3 + d) * Np + n] = S.d[d] * raw[n];
     }
     dg_status st = device_irho(c, k, irho);
     if (st != DG_OK) return st;
@@ -415,6 +433,7 @@ dg_status upload_sources(dg_ctx* c) {
   dg_status st;
   if ((st = upload_raw(c, c->src_elem, elem.data(), ns)) != DG_OK) return st;
   if ((st = upload_real(c, c->src_w, w.data(), w.size())) != DG_OK) return st;
+  if ((st = upload_real(c, c->src_wraw, wraw.data(), wraw.size())) != DG_OK) return st;
   if ((st = upload_raw(c, c->src_par, par.data(), par.size())) != DG_OK) return st;
   return DG_OK;
 }
@@ -521,6 +540,177 @@ dg_status advance_impl(dg_ctx* c, double dt, int64_t nsteps) {
   return DG_OK;
 }
 
+// ------------------------------------------------------------ adjoint ---
+template <typename T>
+dga::AdjArgs<T> adj_args(const dg_ctx* c) {
+  const dgh::RefElement& re = c->re;
+  const int Np = re.Np, NF4 = 4 * re.Nfp, Nq = re.Nq;
+  const T* ops = static_cast<const T*>(c->ops.p);   // Dr | Ds | Dt | LIFT | Vq | Pq
+  dga::AdjArgs<T> A;
+  A.geo = static_cast<const T*>(c->geo.p);
+  A.fgeo = static_cast<const T*>(c->fgeo.p);
+  A.etoe = static_cast<const int32_t*>(c->etoe.p);
+  A.etop = static_cast<const uint8_t*>(c->etop.p);
+  A.pat = static_cast<const int32_t*>(c->pat.p);
+  A.fmask = static_cast<const int32_t*>(c->fmask.p);
+  A.nbface = static_cast<const int32_t*>(c->adj_nbface.p);
+  A.invf = static_cast<const int32_t*>(c->adj_invf.p);
+  A.zp = static_cast<const T*>(c->zp.p);
+  A.zs = static_cast<const T*>(c->zs.p);
+  A.Dr = ops;
+  A.Ds = ops + size_t(Np) * Np;
+  A.Dt = ops + 2 * size_t(Np) * Np;
+  A.LIFT = ops + 3 * size_t(Np) * Np;
+  A.Vq = A.LIFT + size_t(Np) * NF4;
+  A.Pq = A.Vq + size_t(Nq) * Np;
+  A.irho = static_cast<const T*>(c->irho.p);
+  A.lam = static_cast<const T*>(c->lam.p);
+  A.mu = static_cast<const T*>(c->mu.p);
+  A.K = c->mesh.K;
+  A.Np = Np;
+  A.Nfp = re.Nfp;
+  A.Nq = Nq;
+  A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+  return A;
+}
+
+inline unsigned nblocks(int64_t n) { return unsigned((n + 255) / 256); }
+
+// tables of the flux transpose: for every face node, the neighbour's face
+// node that reads it (flat index nb * 4 Nfp + j'), and for every volume node
+// the face nodes that lie on it
+dg_status adj_tables(dg_ctx* c) {
+  if (c->adj_nbface.p) return DG_OK;
+  const dgh::RefElement& re = c->re;
+  const dgh::MeshData& m = c->mesh;
+  const int Nfp = re.Nfp, NF4 = 4 * Nfp, Np = re.Np;
+  if (m.K * NF4 >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "adjoint: mesh too large");
+  std::vector<int32_t> nbf(size_t(m.K) * NF4), invf(size_t(Np) * 3, -1);
+  for (int64_t k = 0; k < m.K; ++k)
+    for (int f = 0; f < 4; ++f) {
+      const int64_t nb = m.EToE[k * 4 + f];
+      const int fn = m.EToF[k * 4 + f];
+      for (int i = 0; i < Nfp; ++i) {
+        const int vP = m.pat[size_t(m.EToP[k * 4 + f]) * Nfp + i];
+        int jn = -1;
+        for (int i2 = 0; i2 < Nfp; ++i2)
+          if (re.Fmask[fn * Nfp + i2] == vP) jn = fn * Nfp + i2;
+        if (jn < 0) return fail(c, DG_EINVAL, "adjoint: face tables inconsistent");
+        nbf[size_t(k) * NF4 + f * Nfp + i] = int32_t(nb * NF4 + jn);
+      }
+    }
+  for (int j = 0; j < NF4; ++j) {
+    const int n = re.Fmask[j];
+    int s = 0;
+    while (s < 3 && invf[n * 3 + s] >= 0) ++s;
+    if (s == 3) return fail(c, DG_EINVAL, "adjoint: node on more than three faces");
+    invf[n * 3 + s] = j;
+  }
+  dg_status st;
+  if ((st = upload_raw(c, c->adj_nbface, nbf.data(), nbf.size())) != DG_OK) return st;
+  return upload_raw(c, c->adj_invf, invf.data(), invf.size());
+}
+
+// one LSRK(5,4) step from qin into qout through the temporaries t0, t1 and
+// residual res (sources at host time t)
+dg_status full_step(dg_ctx* c, const void* qin, void* qout, void* t0, void* t1, void* res,
+                    double t, double dt) {
+  const int64_t n = int64_t(9) * c->mesh.K * c->re.Np;
+  dg_status s = fill_zero(c, res, n);
+  if (s != DG_OK) return s;
+  const void* in = qin;
+  void* outs[5] = {t0, t1, t0, t1, qout};
+  for (int st = 0; st < 5; ++st) {
+    if ((s = stage(c, in, outs[st], res, nullptr, kRkA[st], kRkB[st], dt, 1)) != DG_OK) return s;
+    if ((s = launch_sources(c, res, outs[st], t + kRkC[st] * dt, dt, kRkB[st] * dt)) != DG_OK)
+      return s;
+    in = outs[st];
+  }
+  return DG_OK;
+}
+
+template <typename T>
+dg_status adj_backward_t(dg_ctx* c, const T* resid) {
+  const int Np = c->re.Np, NF4 = 4 * c->re.Nfp, Nq = c->re.Nq;
+  const int64_t K = c->mesh.K, n = int64_t(9) * K * Np, KNp = K * Np;
+  const dga::AdjArgs<T> A = adj_args<T>(c);
+  T* ck = static_cast<T*>(c->adj_ck.p);
+  T* seg = static_cast<T*>(c->adj_seg.p);
+  T* ys = static_cast<T*>(c->adj_y.p);
+  T* v = static_cast<T*>(c->adj_v.p);
+  T *ly = v, *lres = v + n, *mu = v + 2 * n, *nu = v + 3 * n, *r = v + 4 * n, *res = v + 5 * n;
+  T* fb = static_cast<T*>(c->adj_fb.p);
+  T* gb = static_cast<T*>(c->adj_gb.p);
+  T* hb = static_cast<T*>(c->adj_hb.p);
+  T* ob = static_cast<T*>(c->adj_ob.p);
+  double* grad = static_cast<double*>(c->adj_grad.p);
+  const double t0 = c->adj_t0, dt = c->adj_dt;
+  const int64_t nsteps = c->adj_nsteps, every = c->adj_every;
+  const int64_t nck = (nsteps + every - 1) / every;
+  const int ns = int(c->src.size());
+  hipStream_t st = c->stream;
+  dg_status s;
+  if ((s = fill_zero(c, ly, n)) != DG_OK) return s;
+  if ((s = fill_zero(c, lres, n)) != DG_OK) return s;
+  dgk::fill_kernel<double><<<nblocks(3 * K * Nq), 256, 0, st>>>(grad, 3 * K * Nq, 0.0);
+  DG_HIP(c, hipGetLastError());
+  for (int64_t sg = nck - 1; sg >= 0; --sg) {
+    const int64_t n0 = sg * every, n1 = std::min(n0 + every, nsteps);
+    // step-start states of the segment, recomputed from its checkpoint
+    DG_HIP(c, hipMemcpyAsync(seg, ck + sg * n, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    for (int64_t i = n0; i + 1 < n1; ++i)
+      if ((s = full_step(c, seg + (i - n0) * n, seg + (i - n0 + 1) * n, ys, ys + n, res,
+                         t0 + double(i) * dt, dt)) != DG_OK)
+        return s;
+    for (int64_t i = n1 - 1; i >= n0; --i) {
+      // misfit sensitivity of the trace row of step i (state after step i)
+      if (c->nrec > 0) {
+        dga::receiver_adjoint<T><<<nblocks(3 * Np), 256, 0, st>>>(
+            ly, resid + i * c->nrec * 3, static_cast<const int64_t*>(c->rec_elem.p),
+            static_cast<const T*>(c->rec_w.p), c->nrec, Np, KNp);
+        DG_HIP(c, hipGetLastError());
+      }
+      // the step's stage inputs y_0 .. y_4
+      const double ti = t0 + double(i) * dt;
+      DG_HIP(c, hipMemcpyAsync(ys, seg + (i - n0) * n, n * sizeof(T), hipMemcpyDeviceToDevice,
+                               st));
+      if ((s = fill_zero(c, res, n)) != DG_OK) return s;
+      for (int q = 0; q < 4; ++q) {
+        if ((s = stage(c, ys + q * n, ys + (q + 1) * n, res, nullptr, kRkA[q], kRkB[q], dt, 1)) !=
+            DG_OK)
+          return s;
+        if ((s = launch_sources(c, res, ys + (q + 1) * n, ti + kRkC[q] * dt, dt, kRkB[q] * dt)) !=
+            DG_OK)
+          return s;
+      }
+      for (int q = 4; q >= 0; --q) {
+        const double ts = ti + kRkC[q] * dt;
+        dga::axpby<T><<<nblocks(n), 256, 0, st>>>(lres, ly, kRkB[q], 1.0, n);
+        // gradient: dt d/dm <lres, W(m) (R y_q + raw sources(ts))>
+        dga::raw_flux<T><<<nblocks(K * NF4), 256, 0, st>>>(A, ys + q * n, fb);
+        dga::raw_nodes<T><<<nblocks(K * Np), 256, 0, st>>>(A, ys + q * n, fb, r);
+        if (ns > 0) {
+          dgs::source_add<T><<<nblocks(3 * Np), 256, 0, st>>>(
+              r, static_cast<T*>(nullptr), static_cast<const int64_t*>(c->src_elem.p),
+              static_cast<const T*>(c->src_wraw.p), static_cast<const double*>(c->src_par.p),
+              ns, Np, KNp, ts, 1.0, 0.0);
+        }
+        dga::grad_accum<T><<<nblocks(K * Nq), 256, 0, st>>>(A, lres, r, grad, dt);
+        // ly += dt R^T W^T lres
+        dga::wadgT_quad<T><<<nblocks(K * Nq), 256, 0, st>>>(A, lres, ob);
+        dga::wadgT_nodes<T><<<nblocks(K * Np), 256, 0, st>>>(A, ob, mu);
+        dga::liftT_faces<T><<<nblocks(K * NF4), 256, 0, st>>>(A, mu, gb);
+        dga::fluxT_faces<T><<<nblocks(K * NF4), 256, 0, st>>>(A, gb, hb);
+        dga::volT_nodes<T><<<nblocks(K * Np), 256, 0, st>>>(A, mu, hb, nu);
+        dga::axpby<T><<<nblocks(n), 256, 0, st>>>(ly, nu, dt, 1.0, n);
+        dga::axpby<T><<<nblocks(n), 256, 0, st>>>(lres, lres, 0.0, kRkA[q], n);
+        DG_HIP(c, hipGetLastError());
+      }
+    }
+  }
+  return DG_OK;
+}
+
 dg_status ready(dg_ctx* c, bool need_state) {
   if (!c) return DG_EINVAL;
   if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
@@ -600,7 +790,10 @@ void dg_destroy(dg_ctx* c) {
     for (DevBuf* b : {&c->ops, &c->opsT, &c->fmask, &c->geo, &c->fgeo, &c->etoe, &c->etop, &c->pat,
                       &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
                       &c->res, &c->frags, &c->matblk, &c->src_elem, &c->src_w,
-                      &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf})
+                      &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf, &c->src_wraw,
+                      &c->adj_nbface, &c->adj_invf, &c->adj_ck, &c->adj_seg, &c->adj_y,
+                      &c->adj_v, &c->adj_fb, &c->adj_gb, &c->adj_hb, &c->adj_ob,
+                      &c->adj_grad, &c->adj_trace})
       release(c, *b);
   }
   delete c;
@@ -639,8 +832,11 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
   if (s != DG_OK) return s;
   drop_graphs(c);
   for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf,
-                    &c->trace})
+                    &c->trace, &c->src_wraw, &c->adj_nbface, &c->adj_invf, &c->adj_ck,
+                    &c->adj_seg, &c->adj_y, &c->adj_v, &c->adj_fb, &c->adj_gb, &c->adj_hb,
+                    &c->adj_ob, &c->adj_grad, &c->adj_trace})
     release(c, *b);
+  c->adj_ready = false;
   c->trace_cap = 0;
   if (!c->clk.p) {
     if ((s = alloc(c, c->clk, 2 * sizeof(double))) != DG_OK) return s;
@@ -1090,6 +1286,117 @@ dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc
   b += uint64_t(nsrc) * (8 + 3 * Np * e + 3 * 8);                     // sources
   b += uint64_t(nrec) * (8 + Np * e) + uint64_t(trace_steps) * nrec * 3 * e;   // receivers
   *bytes = b;
+  return DG_OK;
+}
+
+dg_status dg_material_set_weights(dg_ctx* c, const double* irho_q, const double* lam_q,
+                                  const double* mu_q, const double* zp_n, const double* zs_n) {
+  if (!c) return DG_EINVAL;
+  if (!c->has_mesh) return fail(c, DG_ESTATE, "weights: no mesh uploaded");
+  if (!irho_q || !lam_q || !mu_q || !zp_n || !zs_n) return fail(c, DG_EINVAL, "weights: null");
+  const int64_t K = c->mesh.K;
+  const size_t nq = size_t(K) * c->re.Nq, nn = size_t(K) * c->re.Np;
+  for (size_t i = 0; i < nq; ++i)
+    if (!std::isfinite(irho_q[i]) || !std::isfinite(lam_q[i]) || !std::isfinite(mu_q[i]))
+      return fail(c, DG_ENONFINITE, "weights: non-finite value");
+  for (size_t i = 0; i < nn; ++i) {
+    if (!std::isfinite(zp_n[i]) || !std::isfinite(zs_n[i]))
+      return fail(c, DG_ENONFINITE, "weights: non-finite impedance");
+    if (!(zp_n[i] > 0.0) || !(zs_n[i] > 0.0))
+      return fail(c, DG_EINVAL, "weights: impedances must be positive");
+  }
+  c->has_mat = false;
+  if (!device_ctx(c)) {
+    c->has_mat = true;
+    return DG_OK;
+  }
+  dg_status s = set_device(c);
+  if (s != DG_OK) return s;
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  if (c->opt.precision == DG_FP32_BF16X3) {
+    const std::vector<double> blk = dgh::mfma_material(c->re.N, K, irho_q, lam_q, mu_q);
+    if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
+  } else {
+    if ((s = upload_real(c, c->irho, irho_q, nq)) != DG_OK) return s;
+    if ((s = upload_real(c, c->lam, lam_q, nq)) != DG_OK) return s;
+    if ((s = upload_real(c, c->mu, mu_q, nq)) != DG_OK) return s;
+  }
+  if ((s = upload_real(c, c->zp, zp_n, nn)) != DG_OK) return s;
+  if ((s = upload_real(c, c->zs, zs_n, nn)) != DG_OK) return s;
+  c->has_mat = true;
+  drop_graphs(c);
+  if (!c->src.empty()) return upload_sources(c);
+  return DG_OK;
+}
+
+dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, int64_t every,
+                             void* trace) {
+  if (!c || !trace) return DG_EINVAL;
+  if (!std::isfinite(t0) || !std::isfinite(dt) || nsteps < 1 || every < 1)
+    return fail(c, DG_EINVAL, "adjoint: bad t0, dt, step count or checkpoint interval");
+  dg_status s = ready(c, true);
+  if (s != DG_OK) return s;
+  if (c->opt.precision == DG_FP32_BF16X3)
+    return fail(c, DG_EINVAL, "adjoint: FP64 and FP32 contexts only");
+  if (c->nrec == 0) return fail(c, DG_ESTATE, "adjoint: no receivers set");
+  if ((s = adj_tables(c)) != DG_OK) return s;
+  const int64_t K = c->mesh.K, n = int64_t(9) * K * c->re.Np;
+  const int NF4 = 4 * c->re.Nfp, Nq = c->re.Nq;
+  const size_t S = size_t(n) * c->elem;
+  const int64_t nck = (nsteps + every - 1) / every;
+  const size_t tb = size_t(nsteps) * c->nrec * 3 * c->elem;
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  c->adj_ready = false;
+  struct Need {
+    DevBuf* b;
+    size_t bytes;
+  } need[] = {{&c->adj_ck, S * nck},
+              {&c->adj_seg, S * size_t(every)},
+              {&c->adj_y, S * 5},
+              {&c->adj_v, S * 6},
+              {&c->adj_fb, size_t(K) * NF4 * 9 * c->elem},
+              {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
+              {&c->adj_hb, size_t(K) * NF4 * 9 * c->elem},
+              {&c->adj_ob, size_t(K) * Nq * 9 * c->elem},
+              {&c->adj_grad, size_t(K) * Nq * 3 * sizeof(double)},
+              {&c->adj_trace, tb}};
+  for (auto& x : need)
+    if (x.b->bytes != x.bytes && (s = alloc(c, *x.b, x.bytes)) != DG_OK) return s;
+  char* ck = static_cast<char*>(c->adj_ck.p);
+  char* tr = static_cast<char*>(c->adj_trace.p);
+  const size_t per = size_t(c->nrec) * 3 * c->elem;
+  for (int64_t i = 0; i < nsteps; ++i) {
+    if (i % every == 0)
+      DG_HIP(c, hipMemcpyAsync(ck + S * size_t(i / every), c->q[c->cur].p, S,
+                               hipMemcpyDeviceToDevice, c->stream));
+    if ((s = dg_step(c, t0 + double(i) * dt, dt)) != DG_OK) return s;
+    if ((s = launch_receivers(c, tr + per * size_t(i))) != DG_OK) return s;
+  }
+  DG_HIP(c, copy_sync(c, trace, tr, tb, hipMemcpyDeviceToHost));
+  c->adj_t0 = t0;
+  c->adj_dt = dt;
+  c->adj_nsteps = nsteps;
+  c->adj_every = every;
+  c->adj_ready = true;
+  return DG_OK;
+}
+
+dg_status dg_adjoint_backward(dg_ctx* c, const void* resid, double* grad) {
+  if (!c || !resid || !grad) return DG_EINVAL;
+  dg_status s = ready(c, true);
+  if (s != DG_OK) return s;
+  if (!c->adj_ready) return fail(c, DG_ESTATE, "adjoint: no checkpointed forward run");
+  const size_t tb = size_t(c->adj_nsteps) * c->nrec * 3 * c->elem;
+  DG_HIP(c, copy_sync(c, c->adj_trace.p, resid, tb, hipMemcpyHostToDevice));
+  // the sweep recomputes states in its own buffers: the context's state (the
+  // end of the forward run) is left as it is
+  if (c->elem == 8)
+    s = adj_backward_t<double>(c, static_cast<const double*>(c->adj_trace.p));
+  else
+    s = adj_backward_t<float>(c, static_cast<const float*>(c->adj_trace.p));
+  if (s != DG_OK) return s;
+  const size_t gb = size_t(c->mesh.K) * c->re.Nq * 3 * sizeof(double);
+  DG_HIP(c, copy_sync(c, grad, c->adj_grad.p, gb, hipMemcpyDeviceToHost));
   return DG_OK;
 }
 
