@@ -77,6 +77,8 @@ def parse():
     p.add_argument("--no-sources", action="store_true",
                    help="skip the point-source / receiver measurement")
     p.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    p.add_argument("--adjoint-steps", type=int, default=100)
     p.add_argument("--serving-requests", type=int, default=64)
     p.add_argument("--serving-rate", type=float, default=3.0, help="arrivals per second")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -229,6 +231,64 @@ def serving(args):
     return st
 
 
+def adjoint(args):
+    """Gradient of an L2 receiver misfit with respect to the weight-adjusted
+    material weights (1/rho, lam, mu at the quadrature points): order 4 on
+    24^3 x 6 tets, smooth random media, 4 Ricker forces, 64 receivers,
+    checkpoint every 20 steps, FP32.  Times the checkpointed forward run and
+    the reverse sweep; the gradient is checked against a central difference
+    of the same GPU run along one random direction."""
+    import synth
+    from paper_2008_09441_amd import B, Solver
+    n, N, steps, every = 24, 4, args.adjoint_steps, 20
+    s = Solver(N, precision="fp32", flux="upwind", device=0)
+    s.upload_mesh(synth.kuhn_cube_vertices(n))
+    xq, xn = s.quad_coords(), s.node_coords()
+    rq, pq, sq = synth.fourier_media(xq, seed=77)
+    rn, pn, sn = synth.fourier_media(xn, seed=77)
+    m = np.stack([1.0 / rq, rq * (pq ** 2 - 2 * sq ** 2), rq * sq ** 2])
+    zp, zs = rn * pn, rn * sn
+    del xq, xn
+    K, Np, _, Nq = s.sizes()
+    rng = np.random.default_rng(5)
+    f0 = rng.uniform(5.0, 15.0, 4)
+    B.dg_material_set_weights(s.ctx, m[0], m[1], m[2], zp, zs)
+    s.set_sources(rng.random((4, 3)), rng.standard_normal((4, 3)), f0, 1.2 / f0, 1.0)
+    s.set_receivers(rng.random((64, 3)))
+    dt = 0.5 * (1.0 / n) / math.sqrt(2.0) / (4.0 * (N + 1) ** 2)
+    zero = np.zeros((9, K, Np), np.float32)
+    tr = np.empty((steps, 64, 3), np.float32)
+
+    def J(mm):
+        B.dg_material_set_weights(s.ctx, mm[0], mm[1], mm[2], zp, zs)
+        s.set_state(zero)
+        B.dg_adjoint_forward(s.ctx, 0.0, dt, steps, every, tr)
+        return tr.astype(np.float64)
+    d = 0.5 * J(m)                                 # synthetic data: half the signal
+    s.set_state(zero)
+    t0 = time.perf_counter()
+    B.dg_adjoint_forward(s.ctx, 0.0, dt, steps, every, tr)
+    t_fwd = time.perf_counter() - t0
+    resid = (tr.astype(np.float64) - d).astype(np.float32)
+    g = np.empty((3, K, Nq))
+    t0 = time.perf_counter()
+    B.dg_adjoint_backward(s.ctx, resid, g)
+    t_bwd = time.perf_counter() - t0
+    delta = rng.standard_normal(m.shape) * m
+    eps = 1e-3
+    fd = (0.5 * np.sum((J(m + eps * delta) - d) ** 2)
+          - 0.5 * np.sum((J(m - eps * delta) - d) ** 2)) / (2 * eps)
+    an = float(np.sum(g * delta))
+    s.close()
+    dofs = 9 * K * Np * steps
+    return {"workload": f"N={N}, {n}^3x6 = {K} tets, smooth random media, 4 Ricker forces, "
+                        f"64 receivers, {steps} LSRK steps, checkpoint every {every}, fp32",
+            "forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
+            "adjoint_dof_updates_per_s": dofs / t_bwd,
+            "directional_derivative": an, "central_difference": fd,
+            "rel_diff_vs_central_difference": abs(fd - an) / max(abs(fd), 1e-300)}
+
+
 def cpu_baseline(args, N):
     """The oracle (FP64 NumPy, untuned) on a bounded sample: one LSRK(5,4)
     step on the n_s^3 x 6 periodic cube with the same order, media and
@@ -355,6 +415,8 @@ def main():
         out["sources_receivers"] = sources_receivers(args)
     if not args.no_serving:
         out["serving"] = serving(args)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, N)
     print(json.dumps(out), flush=True)

@@ -45,6 +45,12 @@ class DGError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime; loading it first makes libdg bind to
+    # the same runtime instead of bringing in a second one
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libdg.so is not built ({LIB_PATH}); run "
                           "python -m paper_2008_09441_amd.build")
