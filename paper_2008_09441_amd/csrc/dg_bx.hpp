@@ -60,9 +60,7 @@ struct BxArgs {
   float* rhs_out;        // [9][K][Np] (rhs mode)
   const float* geo;      // [K][9]: d(r,s,t)_i / d(x,y,z)_j at i*3+j
   const float* fgeo;     // [K][4][4]: outward unit normal, Fscale
-  const int32_t* etoe;   // [K][4]
-  const uint8_t* etop;   // [K][4]
-  const int32_t* pat;    // [npat][Nfp]
+  const int32_t* nbn;    // [K][4 Nfp]: neighbour volume node nb * Np + vP of each face node
   const int32_t* fmask;  // [4][Nfp]
   const float* mat;      // [ceil(K/16)][3][MATS]: 1/rho, lam, mu blocked
   const float* zp;       // [K][Np]
@@ -426,16 +424,16 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   // Face-node tasks of phase B: one thread per (element, face node),
   // consecutive threads on consecutive face nodes of one element (so that a
   // wave's neighbour gathers fall in a few neighbour elements' lines).  Their
-  // index loads (neighbour, trace pattern, face geometry, own impedances)
-  // are issued here, behind the state loads, so that phase B waits for the
-  // neighbour gathers only.  Slots past the tile (ragged last tile, idx
-  // beyond the count) read a valid element and face node and store zero.
+  // loads (neighbour node, face geometry, impedances) are issued here, behind
+  // the state loads, and the neighbour gathers right after the state is
+  // stored, so that phase B waits for data already in flight.  Slots past
+  // the tile (ragged last tile, idx beyond the count) read a valid element
+  // and face node and store zero.
   constexpr int TF = kTile * NF4;
   constexpr int IF = (TF + kThreads - 1) / kThreads;
-  int64_t kk[IF], nb[IF];
-  int vM[IF], vP[IF], face[IF];
+  int vM[IF];
   bool ok[IF];
-  float fg[IF][4], zpM[IF], zsM[IF];
+  float fg[IF][4], zpM[IF], zsM[IF], qP[IF][9], zpP[IF], zsP[IF];
   {
     float v[IQ];
 #pragma unroll
@@ -446,28 +444,21 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
       v[it] = A.q_in[f * KNp + e0 * Np + r];
     }
     const float gv = tid < kTile * 9 && tid / 9 < ne ? A.geo[e0 * 9 + tid] : 0.f;
-    int pt[IF];
+    int64_t nbi[IF];
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
       const int idx = tid + it * kThreads;
       const int e = min(idx / NF4, kTile - 1);
       const int jf = idx - (idx / NF4) * NF4;
       ok[it] = idx < TF && e < ne;
-      kk[it] = ok[it] ? e0 + e : e0;
-      face[it] = jf / Nfp;
+      const int64_t kk = ok[it] ? e0 + e : e0;
+      const int face = jf / Nfp;
       vM[it] = A.fmask[jf];
-      nb[it] = A.etoe[kk[it] * 4 + face[it]];
-      pt[it] = A.etop[kk[it] * 4 + face[it]];
+      nbi[it] = A.nbn[kk * NF4 + jf];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) fg[it][j] = A.fgeo[(kk[it] * 4 + face[it]) * 4 + j];
-      zpM[it] = A.zp[kk[it] * Np + vM[it]];
-      zsM[it] = A.zs[kk[it] * Np + vM[it]];
-    }
-#pragma unroll
-    for (int it = 0; it < IF; ++it) {
-      const int idx = tid + it * kThreads;
-      const int jf = idx - (idx / NF4) * NF4;
-      vP[it] = A.pat[pt[it] * Nfp + (jf - face[it] * Nfp)];
+      for (int j = 0; j < 4; ++j) fg[it][j] = A.fgeo[(kk * 4 + face) * 4 + j];
+      zpM[it] = A.zp[kk * Np + vM[it]];
+      zsM[it] = A.zs[kk * Np + vM[it]];
     }
 #pragma unroll
     for (int it = 0; it < IQ; ++it) {
@@ -478,20 +469,18 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
       if (idx < TQ) sq[(f * Np + m) * kES + e] = e < ne ? v[it] : 0.f;
     }
     if (tid < kTile * 9) sg[tid] = gv;
-  }
-  __syncthreads();
-
-  // B: face fluxes; the neighbour gathers of all of a thread's face nodes
-  // are issued together
-  {
-    float qP[IF][9], zpP[IF], zsP[IF];
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
 #pragma unroll
-      for (int f = 0; f < 9; ++f) qP[it][f] = A.q_in[f * KNp + nb[it] * Np + vP[it]];
-      zpP[it] = A.zp[nb[it] * Np + vP[it]];
-      zsP[it] = A.zs[nb[it] * Np + vP[it]];
+      for (int f = 0; f < 9; ++f) qP[it][f] = A.q_in[f * KNp + nbi[it]];
+      zpP[it] = A.zp[nbi[it]];
+      zsP[it] = A.zs[nbi[it]];
     }
+  }
+  __syncthreads();
+
+  // B: face fluxes
+  {
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
       const int idx = tid + it * kThreads;

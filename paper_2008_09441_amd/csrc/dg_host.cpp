@@ -517,6 +517,18 @@ bool build_mesh(const RefElement& re, int64_t K, const double* vxyz,
   return true;
 }
 
+std::vector<int32_t> neighbour_nodes(const RefElement& re, const MeshData& m) {
+  const int Nfp = re.Nfp, NF4 = 4 * Nfp, Np = re.Np;
+  std::vector<int32_t> out(size_t(m.K) * NF4);
+  for (int64_t k = 0; k < m.K; ++k)
+    for (int f = 0; f < 4; ++f) {
+      const int64_t nb = m.EToE[k * 4 + f];
+      const int32_t* pt = &m.pat[size_t(m.EToP[k * 4 + f]) * Nfp];
+      for (int i = 0; i < Nfp; ++i) out[size_t(k) * NF4 + f * Nfp + i] = int32_t(nb * Np + pt[i]);
+    }
+  return out;
+}
+
 void basis_at(const RefElement& re, double r, double s, double t, double* psi) {
   tet_basis(re.N, r, s, t, psi, nullptr, nullptr, nullptr);
 }

@@ -59,6 +59,10 @@ struct MeshData {
 bool build_mesh(const RefElement& re, int64_t K, const double* vxyz,
                 const double* period, MeshData& m, std::string& err);
 
+// Flat index nb * Np + vP of the neighbour volume node that each face node
+// of each element is paired with, [K][4 Nfp] (requires K Np < 2^31).
+std::vector<int32_t> neighbour_nodes(const RefElement& re, const MeshData& m);
+
 // Orthonormal basis psi[Np] at the reference point (r, s, t) [HW08, Ch. 10].
 void basis_at(const RefElement& re, double r, double s, double t, double* psi);
 

@@ -167,7 +167,7 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
   A.res = nullptr;
   if (lsrk) { A.res = alloc<float>(9 * K * Np); for (int64_t i = 0; i < 9 * K * Np; ++i) A.res[i] = 0.f; }
   A.geo = dupf(m.geo); A.fgeo = dupf(m.fgeo);
-  A.etoe = dup(m.EToE); A.etop = dup(m.EToP); A.pat = dup(m.pat);
+  A.nbn = dup(dgh::neighbour_nodes(re, m));
   std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
   A.fmask = dup(fm);
   A.mat = dupf(dgh::mfma_material(N, K, a.data(), b.data(), d.data()));
