@@ -48,6 +48,8 @@ namespace dgb {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;   // four waves
 constexpr int kTile = 16;       // elements per workgroup
@@ -112,12 +114,19 @@ __device__ __forceinline__ f32x4 mma3(const u32x4& ah, const u32x4& al, const bf
   return c;
 }
 
+// hi = bf16(x) (round to nearest even), lo = bf16(x - hi), converted in
+// pairs (one packed conversion per pair and part)
 __device__ __forceinline__ void split8(const float* v, bf16x8& hi, bf16x8& lo) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const __bf16 h = (__bf16)v[j];
-    hi[j] = h;
-    lo[j] = (__bf16)(v[j] - (float)h);
+  for (int p = 0; p < 4; ++p) {
+    const f32x2 x = {v[2 * p], v[2 * p + 1]};
+    const bf16x2 h = __builtin_convertvector(x, bf16x2);
+    const f32x2 r = x - __builtin_convertvector(h, f32x2);
+    const bf16x2 l = __builtin_convertvector(r, bf16x2);
+    hi[2 * p] = h[0];
+    hi[2 * p + 1] = h[1];
+    lo[2 * p] = l[0];
+    lo[2 * p + 1] = l[1];
   }
 }
 
@@ -391,6 +400,38 @@ __device__ __forceinline__ void quad_proj(const BxArgs& A, int64_t tile, int lan
       }
 }
 
+// Item map of the tile's state, shared by the staging loads and the final
+// update: field f of the tile is TS = 16 Np consecutive floats.  Main items
+// r = tid + 256 it (it < MI) cover rows below 256 MI of every field; the TT
+// rows left per field form 9 TT tail items t = tid + 256 j, clamped to the
+// last one (duplicates repeat its load and store).  Rows are clamped to the
+// tile's last valid row.
+template <int N>
+struct TileMap {
+  static constexpr int Np = BOrd<N>::Np;
+  static constexpr int TS = kTile * Np;
+  static constexpr int MI = TS / kThreads;
+  static constexpr int TT = TS - MI * kThreads;
+  static constexpr int IT = (9 * TT + kThreads - 1) / kThreads;
+  static_assert(TT > 0, "tail items assume 16 Np is not a multiple of 256");
+  int rmax;   // last valid row: ne Np - 1
+  __device__ explicit TileMap(int ne) : rmax(ne * Np - 1) {}
+  __device__ unsigned main_row(int tid, int it) const {
+    return min(unsigned(tid + it * kThreads), unsigned(rmax));
+  }
+  __device__ int tail_item(int tid, int j) const { return min(tid + j * kThreads, 9 * TT - 1); }
+  __device__ int tail_field(int tid, int j) const { return tail_item(tid, j) / TT; }
+  __device__ unsigned tail_row(int tid, int j) const {
+    const int t = tail_item(tid, j);
+    return min(unsigned(MI * kThreads + t - (t / TT) * TT), unsigned(rmax));
+  }
+  // LDS offset of row r (element r / Np, node r % Np) in a [Np][17] field block
+  __device__ static int lds_row(unsigned r) {
+    const unsigned e = r / Np;
+    return int((r - e * Np) * kES + e);
+  }
+};
+
 template <int N>
 __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   using O = BOrd<N>;
@@ -418,9 +459,14 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   const int ne = int((K - e0) < kTile ? (K - e0) : kTile);
 
   // A: stage q and the metric terms; every thread issues all its loads
-  // before the first LDS store (the phase is latency bound otherwise)
-  constexpr int TQ = 9 * kTile * Np;
-  constexpr int IQ = (TQ + kThreads - 1) / kThreads;
+  // before the first LDS store (the phase is latency bound otherwise).  The
+  // tile's values of field f are the TS = 16 Np consecutive floats at
+  // f K Np + e0 Np.  Rows r < 256 MI of every field are read as
+  // r = tid + 256 it from a per-field uniform base (no per-item index
+  // arithmetic); the TT values left per field are spread over the threads
+  // (item t: field t / TT).  Rows past the last element of a ragged tile are
+  // clamped to its last value: their columns never reach memory.
+  const TileMap<N> tm(ne);
   // Face-node tasks of phase B: one thread per (element, face node),
   // consecutive threads on consecutive face nodes of one element (so that a
   // wave's neighbour gathers fall in a few neighbour elements' lines).  Their
@@ -435,44 +481,50 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   bool ok[IF];
   float fg[IF][4], zpM[IF], zsM[IF], qP[IF][9], zpP[IF], zsP[IF];
   {
-    float v[IQ];
+    const float* qt = A.q_in + e0 * Np;
+    float vm[TileMap<N>::MI > 0 ? TileMap<N>::MI : 1][9], vt[TileMap<N>::IT];
 #pragma unroll
-    for (int it = 0; it < IQ; ++it) {   // clamped addresses, no per-lane branches
-      const int idx = min(tid + it * kThreads, TQ - 1);
-      const int f = idx / (kTile * Np);
-      const int r = min(idx - f * (kTile * Np), ne * Np - 1);
-      v[it] = A.q_in[f * KNp + e0 * Np + r];
-    }
+    for (int it = 0; it < TileMap<N>::MI; ++it)
+#pragma unroll
+      for (int f = 0; f < 9; ++f) vm[it][f] = (qt + f * KNp)[tm.main_row(tid, it)];
+#pragma unroll
+    for (int j = 0; j < TileMap<N>::IT; ++j) vt[j] = qt[tm.tail_field(tid, j) * KNp + tm.tail_row(tid, j)];
     const float gv = tid < kTile * 9 && tid / 9 < ne ? A.geo[e0 * 9 + tid] : 0.f;
-    int64_t nbi[IF];
+    // per-tile bases (uniform) and 32-bit per-lane offsets
+    const int32_t* nbt = A.nbn + e0 * NF4;
+    const f32x4* fgt = reinterpret_cast<const f32x4*>(A.fgeo) + e0 * 4;
+    const float* zpt = A.zp + e0 * Np;
+    const float* zst = A.zs + e0 * Np;
+    unsigned nbi[IF];
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
       const int idx = tid + it * kThreads;
-      const int e = min(idx / NF4, kTile - 1);
-      const int jf = idx - (idx / NF4) * NF4;
-      ok[it] = idx < TF && e < ne;
-      const int64_t kk = ok[it] ? e0 + e : e0;
-      const int face = jf / Nfp;
+      const unsigned ic = min(unsigned(idx), unsigned(TF - 1));
+      const unsigned e = ic / NF4, jf = ic - e * NF4;
+      ok[it] = idx < TF && int(e) < ne;
+      const unsigned ec = min(e, unsigned(ne - 1));   // a valid element of the tile
       vM[it] = A.fmask[jf];
-      nbi[it] = A.nbn[kk * NF4 + jf];
+      nbi[it] = unsigned(nbt[ec * NF4 + jf]);
+      const f32x4 g4 = fgt[ec * 4 + jf / Nfp];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) fg[it][j] = A.fgeo[(kk * 4 + face) * 4 + j];
-      zpM[it] = A.zp[kk * Np + vM[it]];
-      zsM[it] = A.zs[kk * Np + vM[it]];
+      for (int j = 0; j < 4; ++j) fg[it][j] = g4[j];
+      zpM[it] = zpt[ec * Np + unsigned(vM[it])];
+      zsM[it] = zst[ec * Np + unsigned(vM[it])];
     }
 #pragma unroll
-    for (int it = 0; it < IQ; ++it) {
-      const int idx = tid + it * kThreads;
-      const int f = idx / (kTile * Np);
-      const int r = idx - f * (kTile * Np);
-      const int e = r / Np, m = r - e * Np;
-      if (idx < TQ) sq[(f * Np + m) * kES + e] = e < ne ? v[it] : 0.f;
+    for (int it = 0; it < TileMap<N>::MI; ++it) {
+      const int li = tm.lds_row(tm.main_row(tid, it));
+#pragma unroll
+      for (int f = 0; f < 9; ++f) sq[f * Np * kES + li] = vm[it][f];
     }
+#pragma unroll
+    for (int j = 0; j < TileMap<N>::IT; ++j)   // clamped duplicates store equal values
+      sq[tm.tail_field(tid, j) * Np * kES + tm.lds_row(tm.tail_row(tid, j))] = vt[j];
     if (tid < kTile * 9) sg[tid] = gv;
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
 #pragma unroll
-      for (int f = 0; f < 9; ++f) qP[it][f] = A.q_in[f * KNp + nbi[it]];
+      for (int f = 0; f < 9; ++f) qP[it][f] = (A.q_in + f * KNp)[nbi[it]];
       zpP[it] = A.zp[nbi[it]];
       zsP[it] = A.zs[nbi[it]];
     }
@@ -500,8 +552,9 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
         const float ZpM = zpM[it], ZsM = zsM[it], ZpP = zpP[it], ZsP = zsP[it];
         const float jvn = jvx * nx + jvy * ny + jvz * nz;
         const float jtn = jtx * nx + jty * ny + jtz * nz;
-        const float dvn = (ZpP * jvn + jtn) / (ZpM + ZpP);
-        const float ivs = 1.f / (ZsM + ZsP);
+        // hardware reciprocals (1 ulp): the impedance sums are positive
+        const float dvn = (ZpP * jvn + jtn) * __builtin_amdgcn_rcpf(ZpM + ZpP);
+        const float ivs = __builtin_amdgcn_rcpf(ZsM + ZsP);
         const float dvtx = (ZsP * (jvx - jvn * nx) + (jtx - jtn * nx)) * ivs;
         const float dvty = (ZsP * (jvy - jvn * ny) + (jty - jtn * ny)) * ivs;
         const float dvtz = (ZsP * (jvz - jvn * nz) + (jtz - jtn * nz)) * ivs;
@@ -555,45 +608,49 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   }
   __syncthreads();
 
-  // E: right-hand side store or stage update, coalesced.  The residual
-  // loads of a batch of a thread's items are issued together, as
-  // unconditional loads from clamped (valid) addresses: loads under per-lane
-  // conditions get serialised by the wait-count insertion.  Batches bound
-  // the registers the phase holds.
-  constexpr int EB = IQ;
-  // the thread index rebuilt from the lane count, which the compiler cannot
-  // match with phase A's index arithmetic: otherwise it keeps phase A's
-  // addresses alive through the whole kernel to reuse them here
-  const int etid = wave * 64 + int(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
-#pragma unroll
-  for (int b0 = 0; b0 < IQ; b0 += EB) {
-    float rs[EB];
+  // E: right-hand side store or stage update, coalesced, over the same
+  // items as phase A (clamped rows of a ragged tile write the value their
+  // row's owner writes).  The residual loads are all issued before the first
+  // store.  The thread index is rebuilt from the lane count, which the
+  // compiler cannot match with phase A's index arithmetic: otherwise it
+  // keeps phase A's addresses alive through the whole kernel to reuse them.
+  {
+    const int etid = wave * 64 + int(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
+    constexpr int MI = TileMap<N>::MI, IT = TileMap<N>::IT;
+    const int64_t t0 = e0 * Np;
+    float rm[MI > 0 ? MI : 1][9], rt[IT];
     if (A.lsrk) {
 #pragma unroll
-      for (int jb = 0; jb < EB; ++jb) {
-        const int idx = min(etid + (b0 + jb) * kThreads, TQ - 1);
-        const int f = idx / (kTile * Np);
-        const int r = min(idx - f * (kTile * Np), ne * Np - 1);
-        rs[jb] = A.res[f * KNp + e0 * Np + r];
-      }
-    }
+      for (int it = 0; it < MI; ++it)
 #pragma unroll
-    for (int jb = 0; jb < EB; ++jb) {
-      const int idx = etid + (b0 + jb) * kThreads;
-      const int f = idx / (kTile * Np);
-      const int r = idx - f * (kTile * Np);
-      const int e = r / Np, m = r - e * Np;
-      if (b0 + jb >= IQ || idx >= TQ || e >= ne) continue;
-      const int64_t gi = f * KNp + e0 * Np + r;
-      const int li = (f * Np + m) * kES + e;
+        for (int f = 0; f < 9; ++f) rm[it][f] = (A.res + t0 + f * KNp)[tm.main_row(etid, it)];
+#pragma unroll
+      for (int j = 0; j < IT; ++j)
+        rt[j] = A.res[t0 + tm.tail_field(etid, j) * KNp + tm.tail_row(etid, j)];
+    }
+    // fb: the field's offset (uniform for main items), r: row in the tile
+    auto put = [&](int64_t fb, unsigned r, int li, float rs) {
       const float rv = sr[li];
       if (A.lsrk) {
-        const float rr = A.a * rs[jb] + A.dt * rv;
-        A.res[gi] = rr;
-        A.q_out[gi] = sq[li] + A.b * rr;
+        const float rr = A.a * rs + A.dt * rv;
+        (A.res + fb)[r] = rr;
+        (A.q_out + fb)[r] = sq[li] + A.b * rr;
       } else {
-        A.rhs_out[gi] = rv;
+        (A.rhs_out + fb)[r] = rv;
       }
+    };
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      const unsigned r = tm.main_row(etid, it);
+      const int li = tm.lds_row(r);
+#pragma unroll
+      for (int f = 0; f < 9; ++f) put(t0 + f * KNp, r, f * Np * kES + li, rm[it][f]);
+    }
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const int f = tm.tail_field(etid, j);
+      const unsigned r = tm.tail_row(etid, j);
+      put(t0 + f * KNp, r, f * Np * kES + tm.lds_row(r), rt[j]);
     }
   }
 }

@@ -35,3 +35,5 @@ inline unsigned emu_mbcnt_hi(unsigned m, unsigned a) {
 #define __builtin_amdgcn_mbcnt_hi emu_mbcnt_hi
 inline int min(int a, int b) { return a < b ? a : b; }
 inline long min(long a, long b) { return a < b ? a : b; }
+inline unsigned min(unsigned a, unsigned b) { return a < b ? a : b; }
+#define __builtin_amdgcn_rcpf(x) (1.f / (x))
