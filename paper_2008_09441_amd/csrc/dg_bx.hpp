@@ -481,6 +481,29 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   bool ok[IF];
   float fg[IF][4], zpM[IF], zsM[IF], qP[IF][9], zpP[IF], zsP[IF];
   {
+    // level 1: the face-node task tables (the gathers depend on nbn), the
+    // state and the metric terms; level 2: the own-side impedances (through
+    // fmask) and the neighbour gathers.  Issue order matters: the load counter is in
+    // order, so the gathers wait for nbn but not for the state loads.
+    const int32_t* nbt = A.nbn + e0 * NF4;
+    const f32x4* fgt = reinterpret_cast<const f32x4*>(A.fgeo) + e0 * 4;
+    const float* zpt = A.zp + e0 * Np;
+    const float* zst = A.zs + e0 * Np;
+    unsigned nbi[IF], ecs[IF];
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+      const int idx = tid + it * kThreads;
+      const unsigned ic = min(unsigned(idx), unsigned(TF - 1));
+      const unsigned e = ic / NF4, jf = ic - e * NF4;
+      ok[it] = idx < TF && int(e) < ne;
+      ecs[it] = min(e, unsigned(ne - 1));   // a valid element of the tile
+      nbi[it] = unsigned(nbt[ecs[it] * NF4 + jf]);
+      vM[it] = A.fmask[jf];
+      const f32x4 g4 = fgt[ecs[it] * 4 + jf / Nfp];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fg[it][j] = g4[j];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     const float* qt = A.q_in + e0 * Np;
     float vm[TileMap<N>::MI > 0 ? TileMap<N>::MI : 1][9], vt[TileMap<N>::IT];
 #pragma unroll
@@ -490,26 +513,15 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
 #pragma unroll
     for (int j = 0; j < TileMap<N>::IT; ++j) vt[j] = qt[tm.tail_field(tid, j) * KNp + tm.tail_row(tid, j)];
     const float gv = tid < kTile * 9 && tid / 9 < ne ? A.geo[e0 * 9 + tid] : 0.f;
-    // per-tile bases (uniform) and 32-bit per-lane offsets
-    const int32_t* nbt = A.nbn + e0 * NF4;
-    const f32x4* fgt = reinterpret_cast<const f32x4*>(A.fgeo) + e0 * 4;
-    const float* zpt = A.zp + e0 * Np;
-    const float* zst = A.zs + e0 * Np;
-    unsigned nbi[IF];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
-      const int idx = tid + it * kThreads;
-      const unsigned ic = min(unsigned(idx), unsigned(TF - 1));
-      const unsigned e = ic / NF4, jf = ic - e * NF4;
-      ok[it] = idx < TF && int(e) < ne;
-      const unsigned ec = min(e, unsigned(ne - 1));   // a valid element of the tile
-      vM[it] = A.fmask[jf];
-      nbi[it] = unsigned(nbt[ec * NF4 + jf]);
-      const f32x4 g4 = fgt[ec * 4 + jf / Nfp];
+      zpM[it] = zpt[ecs[it] * Np + unsigned(vM[it])];
+      zsM[it] = zst[ecs[it] * Np + unsigned(vM[it])];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) fg[it][j] = g4[j];
-      zpM[it] = zpt[ec * Np + unsigned(vM[it])];
-      zsM[it] = zst[ec * Np + unsigned(vM[it])];
+      for (int f = 0; f < 9; ++f) qP[it][f] = (A.q_in + f * KNp)[nbi[it]];
+      zpP[it] = A.zp[nbi[it]];
+      zsP[it] = A.zs[nbi[it]];
     }
 #pragma unroll
     for (int it = 0; it < TileMap<N>::MI; ++it) {
@@ -521,13 +533,6 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
     for (int j = 0; j < TileMap<N>::IT; ++j)   // clamped duplicates store equal values
       sq[tm.tail_field(tid, j) * Np * kES + tm.lds_row(tm.tail_row(tid, j))] = vt[j];
     if (tid < kTile * 9) sg[tid] = gv;
-#pragma unroll
-    for (int it = 0; it < IF; ++it) {
-#pragma unroll
-      for (int f = 0; f < 9; ++f) qP[it][f] = (A.q_in + f * KNp)[nbi[it]];
-      zpP[it] = A.zp[nbi[it]];
-      zsP[it] = A.zs[nbi[it]];
-    }
   }
   __syncthreads();
 
@@ -606,51 +611,49 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
     case 2: quad_proj<N, 2>(A, tile, lane, acc, m0, sr, srl); break;
     default: quad_proj<N, 3>(A, tile, lane, acc, m0, sr, srl); break;
   }
-  __syncthreads();
 
-  // E: right-hand side store or stage update, coalesced, over the same
-  // items as phase A (clamped rows of a ragged tile write the value their
-  // row's owner writes).  The residual loads are all issued before the first
-  // store.  The thread index is rebuilt from the lane count, which the
-  // compiler cannot match with phase A's index arithmetic: otherwise it
-  // keeps phase A's addresses alive through the whole kernel to reuse them.
-  {
-    const int etid = wave * 64 + int(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
-    constexpr int MI = TileMap<N>::MI, IT = TileMap<N>::IT;
-    const int64_t t0 = e0 * Np;
-    float rm[MI > 0 ? MI : 1][9], rt[IT];
+  // E: right-hand side store or fused stage update, coalesced, done by the
+  // three waves other than the three-component one (whose phase D is the
+  // longest).  Updater thread u (0..191) owns rows u + 192 it of every
+  // field; rows past the tile's last valid row are clamped to it (a
+  // duplicate writes the value the row's owner writes).  The residual loads
+  // are issued before the barrier, so that they overlap the end of phase D.
+  // The thread index is rebuilt from the lane count, which the compiler
+  // cannot match with phase A's index arithmetic: otherwise it keeps phase
+  // A's addresses alive through the whole kernel to reuse them.
+  constexpr int EP = 3 * 64, EI = (kTile * Np + EP - 1) / EP;
+  const int64_t t0 = e0 * Np;
+  unsigned er[EI];
+  float rs[9][EI];
+  if (wave != 2) {
+    const int u = (wave > 2 ? wave - 1 : wave) * 64 +
+                  int(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
+#pragma unroll
+    for (int it = 0; it < EI; ++it) er[it] = min(unsigned(u + it * EP), unsigned(tm.rmax));
     if (A.lsrk) {
 #pragma unroll
-      for (int it = 0; it < MI; ++it)
+      for (int f = 0; f < 9; ++f)
 #pragma unroll
-        for (int f = 0; f < 9; ++f) rm[it][f] = (A.res + t0 + f * KNp)[tm.main_row(etid, it)];
-#pragma unroll
-      for (int j = 0; j < IT; ++j)
-        rt[j] = A.res[t0 + tm.tail_field(etid, j) * KNp + tm.tail_row(etid, j)];
+        for (int it = 0; it < EI; ++it) rs[f][it] = (A.res + t0 + f * KNp)[er[it]];
     }
-    // fb: the field's offset (uniform for main items), r: row in the tile
-    auto put = [&](int64_t fb, unsigned r, int li, float rs) {
-      const float rv = sr[li];
-      if (A.lsrk) {
-        const float rr = A.a * rs + A.dt * rv;
-        (A.res + fb)[r] = rr;
-        (A.q_out + fb)[r] = sq[li] + A.b * rr;
-      } else {
-        (A.rhs_out + fb)[r] = rv;
+  }
+  __syncthreads();
+  if (wave != 2) {
+#pragma unroll
+    for (int it = 0; it < EI; ++it) {
+      const int li = tm.lds_row(er[it]);
+#pragma unroll
+      for (int f = 0; f < 9; ++f) {
+        const int64_t fb = t0 + f * KNp;
+        const float rv = sr[f * Np * kES + li];
+        if (A.lsrk) {
+          const float rr = A.a * rs[f][it] + A.dt * rv;
+          (A.res + fb)[er[it]] = rr;
+          (A.q_out + fb)[er[it]] = sq[f * Np * kES + li] + A.b * rr;
+        } else {
+          (A.rhs_out + fb)[er[it]] = rv;
+        }
       }
-    };
-#pragma unroll
-    for (int it = 0; it < MI; ++it) {
-      const unsigned r = tm.main_row(etid, it);
-      const int li = tm.lds_row(r);
-#pragma unroll
-      for (int f = 0; f < 9; ++f) put(t0 + f * KNp, r, f * Np * kES + li, rm[it][f]);
-    }
-#pragma unroll
-    for (int j = 0; j < IT; ++j) {
-      const int f = tm.tail_field(etid, j);
-      const unsigned r = tm.tail_row(etid, j);
-      put(t0 + f * KNp, r, f * Np * kES + tm.lds_row(r), rt[j]);
     }
   }
 }
