@@ -136,6 +136,7 @@ struct BLds {
   using O = BOrd<N>;
   static constexpr int SQ = 9 * O::Np * kES;             // q       [9][Np][17]
   static constexpr int SG = kTile * 9;                   // metric  [16][9]
+  static constexpr int SZ = 2 * O::Np * kES;             // Z_p, Z_s [2][Np][17]
   static constexpr int SF = 9 * O::NF4 * kES;            // fluxes  [9][4 Nfp][17]
   static constexpr int SR = 9 * O::Np * kES;             // result  [9][Np][17] (over the fluxes)
   // the three-component wave keeps its V_q B operands (hi/lo, lane order)
@@ -143,7 +144,7 @@ struct BLds {
   static constexpr int RO = (SR + 3) & ~3;
   static constexpr int SRL = 3 * O::SVQ * 2 * 64 * 4;
   static constexpr int SU = SF > RO + SRL ? SF : RO + SRL;
-  static constexpr int OFF_U = (SQ + SG + 3) & ~3;       // 16-byte aligned union
+  static constexpr int OFF_U = (SQ + SG + SZ + 3) & ~3;  // 16-byte aligned union
   static constexpr int USED = (OFF_U + SU) * 4;
   // Padded so that the workgroups one CU can hold (160 KiB of LDS) never use
   // more than 128 KiB together (at most 3 per CU at >40 KiB each, or 2 at
@@ -440,6 +441,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   __shared__ __align__(16) float smem[L::BYTES / 4];
   float* sq = smem;               // [9][Np][17]
   float* sg = sq + L::SQ;         // [16][9]
+  float* sz = sg + L::SG;         // [2][Np][17]: Z_p, Z_s of the tile's nodes
   float* sF = smem + L::OFF_U;    // [9][NF4][17]  (phases B, C)
   float* sr = sF;                 // [9][Np][17]   (phases D, E)
   bf16x8* srl = reinterpret_cast<bf16x8*>(sF + L::RO);   // wave 2, phase D
@@ -457,6 +459,10 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   const int64_t KNp = K * Np;
   const int64_t e0 = tile * kTile;
   const int ne = int((K - e0) < kTile ? (K - e0) : kTile);
+  // component group of this wave, rotated with the tile: the waves of a
+  // workgroup go to the CU's four SIMDs in order, so the three-component
+  // group of two workgroups sharing a CU then mostly runs on different SIMDs
+  const int grp = (wave + int(bid >> 3)) & 3;
 
   // A: stage q and the metric terms; every thread issues all its loads
   // before the first LDS store (the phase is latency bound otherwise).  The
@@ -479,17 +485,16 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   constexpr int IF = (TF + kThreads - 1) / kThreads;
   int vM[IF];
   bool ok[IF];
-  float fg[IF][4], zpM[IF], zsM[IF], qP[IF][9], zpP[IF], zsP[IF];
+  float fg[IF][4], qP[IF][9], zpP[IF], zsP[IF];
+  unsigned nbi[IF];
   {
     // level 1: the face-node task tables (the gathers depend on nbn), the
-    // state and the metric terms; level 2: the own-side impedances (through
-    // fmask) and the neighbour gathers.  Issue order matters: the load counter is in
-    // order, so the gathers wait for nbn but not for the state loads.
+    // state, the impedances and the metric terms; level 2: the neighbour
+    // gathers.  Issue order matters: the load counter is in order, so the
+    // gathers wait for nbn but not for the state loads.
     const int32_t* nbt = A.nbn + e0 * NF4;
     const f32x4* fgt = reinterpret_cast<const f32x4*>(A.fgeo) + e0 * 4;
-    const float* zpt = A.zp + e0 * Np;
-    const float* zst = A.zs + e0 * Np;
-    unsigned nbi[IF], ecs[IF];
+    unsigned ecs[IF];
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
       const int idx = tid + it * kThreads;
@@ -513,15 +518,25 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
 #pragma unroll
     for (int j = 0; j < TileMap<N>::IT; ++j) vt[j] = qt[tm.tail_field(tid, j) * KNp + tm.tail_row(tid, j)];
     const float gv = tid < kTile * 9 && tid / 9 < ne ? A.geo[e0 * 9 + tid] : 0.f;
+    constexpr int IZ = (kTile * Np + kThreads - 1) / kThreads;
+    float zv[2][IZ];
+#pragma unroll
+    for (int it = 0; it < IZ; ++it) {
+      const unsigned r = min(unsigned(tid + it * kThreads), unsigned(tm.rmax));
+      zv[0][it] = (A.zp + e0 * Np)[r];
+      zv[1][it] = (A.zs + e0 * Np)[r];
+    }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
-      zpM[it] = zpt[ecs[it] * Np + unsigned(vM[it])];
-      zsM[it] = zst[ecs[it] * Np + unsigned(vM[it])];
+      // a neighbour inside the tile is read from LDS in phase B; its lanes
+      // load the tile's first row instead (one hot line for all of them)
+      const unsigned lr = unsigned(nbi[it] - unsigned(e0 * Np)) < unsigned(kTile * Np)
+                              ? unsigned(e0 * Np) : nbi[it];
 #pragma unroll
-      for (int f = 0; f < 9; ++f) qP[it][f] = (A.q_in + f * KNp)[nbi[it]];
-      zpP[it] = A.zp[nbi[it]];
-      zsP[it] = A.zs[nbi[it]];
+      for (int f = 0; f < 9; ++f) qP[it][f] = (A.q_in + f * KNp)[lr];
+      zpP[it] = A.zp[lr];
+      zsP[it] = A.zs[lr];
     }
 #pragma unroll
     for (int it = 0; it < TileMap<N>::MI; ++it) {
@@ -533,6 +548,15 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
     for (int j = 0; j < TileMap<N>::IT; ++j)   // clamped duplicates store equal values
       sq[tm.tail_field(tid, j) * Np * kES + tm.lds_row(tm.tail_row(tid, j))] = vt[j];
     if (tid < kTile * 9) sg[tid] = gv;
+#pragma unroll
+    for (int it = 0; it < IZ; ++it) {
+      const int r = tid + it * kThreads;
+      if (r < kTile * Np) {
+        const int li = tm.lds_row(unsigned(r));
+        sz[li] = zv[0][it];
+        sz[Np * kES + li] = zv[1][it];
+      }
+    }
   }
   __syncthreads();
 
@@ -547,6 +571,22 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
 #pragma unroll
       for (int f = 0; f < 9; ++f) qM[f] = sq[(f * Np + vM[it]) * kES + e];
       const float nx = fg[it][0], ny = fg[it][1], nz = fg[it][2], fs = fg[it][3];
+      // neighbour trace: from LDS when the neighbour is in the tile
+      const unsigned rl = nbi[it] - unsigned(e0 * Np);
+      const bool inT = rl < unsigned(kTile * Np);
+      {
+        const unsigned rc = inT ? rl : 0u;
+        const unsigned en = rc / Np;
+        const int ln = int((rc - en * Np) * kES + en);
+#pragma unroll
+        for (int f = 0; f < 9; ++f) {
+          const float x = sq[f * Np * kES + ln];
+          qP[it][f] = inT ? x : qP[it][f];
+        }
+        const float zpl = sz[ln], zsl = sz[Np * kES + ln];
+        zpP[it] = inT ? zpl : zpP[it];
+        zsP[it] = inT ? zsl : zsP[it];
+      }
       const float* P = qP[it];
       const float jtx = (P[3] - qM[3]) * nx + (P[8] - qM[8]) * ny + (P[7] - qM[7]) * nz;
       const float jty = (P[8] - qM[8]) * nx + (P[4] - qM[4]) * ny + (P[6] - qM[6]) * nz;
@@ -554,7 +594,8 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
       const float jvx = P[0] - qM[0], jvy = P[1] - qM[1], jvz = P[2] - qM[2];
       float dvx, dvy, dvz, dtx, dty, dtz;
       if (A.upwind) {
-        const float ZpM = zpM[it], ZsM = zsM[it], ZpP = zpP[it], ZsP = zsP[it];
+        const int lm = vM[it] * kES + e;
+        const float ZpM = sz[lm], ZsM = sz[Np * kES + lm], ZpP = zpP[it], ZsP = zsP[it];
         const float jvn = jvx * nx + jvy * ny + jvz * nz;
         const float jtn = jtx * nx + jty * ny + jtz * nz;
         // hardware reciprocals (1 ulp): the impedance sums are positive
@@ -596,7 +637,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   // C: volume + LIFT per wave
   f32x4 acc[3][RT];
   f32x4 m0[3][2];   // chunk-0 material, in flight during phase C
-  switch (wave) {
+  switch (grp) {
     case 0: mat_chunk<N, 0>(A, tile, lane, 0, m0); vol_lift<N, 0>(A, sq, sg, sF, lane, acc); break;
     case 1: mat_chunk<N, 1>(A, tile, lane, 0, m0); vol_lift<N, 1>(A, sq, sg, sF, lane, acc); break;
     case 2: mat_chunk<N, 2>(A, tile, lane, 0, m0); vol_lift<N, 2>(A, sq, sg, sF, lane, acc); break;
@@ -605,7 +646,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   __syncthreads();   // fluxes consumed: sr may overwrite them
 
   // D: quadrature and projection per wave
-  switch (wave) {
+  switch (grp) {
     case 0: quad_proj<N, 0>(A, tile, lane, acc, m0, sr, srl); break;
     case 1: quad_proj<N, 1>(A, tile, lane, acc, m0, sr, srl); break;
     case 2: quad_proj<N, 2>(A, tile, lane, acc, m0, sr, srl); break;
@@ -625,8 +666,8 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   const int64_t t0 = e0 * Np;
   unsigned er[EI];
   float rs[9][EI];
-  if (wave != 2) {
-    const int u = (wave > 2 ? wave - 1 : wave) * 64 +
+  if (grp != 2) {
+    const int u = (grp > 2 ? grp - 1 : grp) * 64 +
                   int(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
 #pragma unroll
     for (int it = 0; it < EI; ++it) er[it] = min(unsigned(u + it * EP), unsigned(tm.rmax));
@@ -638,7 +679,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
     }
   }
   __syncthreads();
-  if (wave != 2) {
+  if (grp != 2) {
 #pragma unroll
     for (int it = 0; it < EI; ++it) {
       const int li = tm.lds_row(er[it]);
