@@ -62,6 +62,7 @@ struct dg_ctx {
   DevBuf frags;             // BF16x3: operator hi/lo fragments
   DevBuf matblk;            // BF16x3: material blocked by 16-element tile
   DevBuf nbn;               // BF16x3: neighbour volume node of each face node
+  DevBuf torder;            // BF16x3: tile processed at each launch position
   int cur = 0;
   // point sources: specification (host) and device arrays
   struct Source {
@@ -304,6 +305,7 @@ hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res,
   A.geo = static_cast<const float*>(c->geo.p);
   A.fgeo = static_cast<const float*>(c->fgeo.p);
   A.nbn = static_cast<const int32_t*>(c->nbn.p);
+  A.torder = static_cast<const int32_t*>(c->torder.p);
   A.fmask = static_cast<const int32_t*>(c->fmask.p);
   A.mat = static_cast<const float*>(c->matblk.p);
   A.zp = static_cast<const float*>(c->zp.p);
@@ -788,7 +790,7 @@ void dg_destroy(dg_ctx* c) {
     release(c, c->trace);
     for (DevBuf* b : {&c->ops, &c->opsT, &c->fmask, &c->geo, &c->fgeo, &c->etoe, &c->etop, &c->pat,
                       &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
-                      &c->res, &c->frags, &c->matblk, &c->nbn, &c->src_elem, &c->src_w,
+                      &c->res, &c->frags, &c->matblk, &c->nbn, &c->torder, &c->src_elem, &c->src_w,
                       &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf, &c->src_wraw,
                       &c->adj_nbface, &c->adj_invf, &c->adj_ck, &c->adj_seg, &c->adj_y,
                       &c->adj_v, &c->adj_fb, &c->adj_gb, &c->adj_hb, &c->adj_ob,
@@ -852,6 +854,8 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
     if (K * c->re.Np >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "mesh: K Np too large");
     const std::vector<int32_t> nbn = dgh::neighbour_nodes(c->re, md);
     if ((s = upload_raw(c, c->nbn, nbn.data(), nbn.size())) != DG_OK) return s;
+    const std::vector<int32_t> tord = dgh::tile_order(md, dgb::kTile, 8);
+    if ((s = upload_raw(c, c->torder, tord.data(), tord.size())) != DG_OK) return s;
   }
   const size_t nstate = size_t(9) * K * c->re.Np * c->elem;
   for (DevBuf* b : {&c->q[0], &c->q[1], &c->res})
@@ -1285,6 +1289,7 @@ dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc
   if (precision == DG_FP32_BF16X3) {
     b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * 4;   // blocked material
     b += k * NF4 * 4;                                                 // neighbour nodes
+    b += (k + 15) / 16 * 4;                                           // tile order
   }
   else
     b += 3 * k * Nq * e;                                              // 1/rho, lam, mu

@@ -64,6 +64,7 @@ struct BxArgs {
   const float* fgeo;     // [K][4][4]: outward unit normal, Fscale
   const int32_t* nbn;    // [K][4 Nfp]: neighbour volume node nb * Np + vP of each face node
   const int32_t* fmask;  // [4][Nfp]
+  const int32_t* torder; // [ceil(K/16)]: tile processed at each launch position
   const float* mat;      // [ceil(K/16)][3][MATS]: 1/rho, lam, mu blocked
   const float* zp;       // [K][Np]
   const float* zs;
@@ -450,11 +451,12 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // XCD-aware tile order: consecutive workgroups go round-robin to the eight
-  // XCDs, so give each XCD one contiguous range of tiles (neighbour traces
-  // then mostly hit its own L2)
+  // XCDs, so give each XCD one contiguous range of launch positions; the
+  // host's tile order sweeps each range so that face neighbours run close
+  // together (neighbour traces then mostly hit that XCD's L2)
   const int64_t G = gridDim.x, bid = blockIdx.x;
   const int64_t xcd = bid & 7, per = G >> 3, rem8 = G & 7;
-  const int64_t tile = xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3);
+  const int64_t tile = A.torder[xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3)];
   const int64_t K = A.K;
   const int64_t KNp = K * Np;
   const int64_t e0 = tile * kTile;

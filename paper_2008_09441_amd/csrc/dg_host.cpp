@@ -529,6 +529,63 @@ std::vector<int32_t> neighbour_nodes(const RefElement& re, const MeshData& m) {
   return out;
 }
 
+std::vector<int32_t> tile_order(const MeshData& m, int tile, int parts) {
+  const int64_t K = m.K, T = (K + tile - 1) / tile;
+  std::vector<double> c(size_t(T) * 3, 0.0);
+  double vol = 0.0;
+  for (int64_t k = 0; k < K; ++k) {
+    const int64_t t = k / tile;
+    const int64_t nt = std::min<int64_t>(tile, K - t * tile);
+    for (int d = 0; d < 3; ++d) {
+      double x = 0.0;
+      for (int v = 0; v < 4; ++v) x += m.vx[size_t(k) * 12 + v * 3 + d];
+      c[size_t(t) * 3 + d] += x / (4.0 * double(nt));
+    }
+    vol += std::fabs(m.J[k]) * 4.0 / 3.0;   // reference tet volume 4/3
+  }
+  // typical element length: the edge of a cube of six elements' volume
+  const double h = K > 0 ? std::cbrt(6.0 * vol / double(K)) : 1.0;
+  std::vector<int32_t> ord(static_cast<size_t>(T));
+  for (int64_t t = 0; t < T; ++t) ord[size_t(t)] = int32_t(t);
+  // axis of largest centroid extent over ord[b, e); ties go to the higher axis
+  auto longest = [&](int64_t b, int64_t e, int skip) {
+    int best = -1;
+    double ext = -1.0;
+    for (int d = 2; d >= 0; --d) {
+      if (d == skip) continue;
+      double lo = 1e300, hi = -1e300;
+      for (int64_t i = b; i < e; ++i) {
+        const double x = c[size_t(ord[size_t(i)]) * 3 + d];
+        lo = std::min(lo, x);
+        hi = std::max(hi, x);
+      }
+      if (hi - lo > ext * (1.0 + 1e-9) + 1e-12) { ext = hi - lo; best = d; }
+    }
+    return best;
+  };
+  auto sweep = [&](int64_t b, int64_t e, int d) {
+    double lo = 1e300;
+    for (int64_t i = b; i < e; ++i) lo = std::min(lo, c[size_t(ord[size_t(i)]) * 3 + d]);
+    std::stable_sort(ord.begin() + b, ord.begin() + e, [&](int32_t x, int32_t y) {
+      const int64_t bx = int64_t(std::floor((c[size_t(x) * 3 + d] - lo) / h));
+      const int64_t by = int64_t(std::floor((c[size_t(y) * 3 + d] - lo) / h));
+      return bx != by ? bx < by : x < y;
+    });
+  };
+  if (T == 0) return ord;
+  const int a0 = longest(0, T, -1);
+  sweep(0, T, a0);
+  const int64_t per = T / parts, rem = T % parts;
+  for (int x = 0; x < parts; ++x) {
+    const int64_t b = x * per + std::min<int64_t>(x, rem);
+    const int64_t e = b + per + (x < rem ? 1 : 0);
+    if (e - b < 2) continue;
+    std::sort(ord.begin() + b, ord.begin() + e);   // element order within the slab
+    sweep(b, e, longest(b, e, a0));
+  }
+  return ord;
+}
+
 void basis_at(const RefElement& re, double r, double s, double t, double* psi) {
   tet_basis(re.N, r, s, t, psi, nullptr, nullptr, nullptr);
 }

@@ -63,6 +63,15 @@ bool build_mesh(const RefElement& re, int64_t K, const double* vxyz,
 // of each element is paired with, [K][4 Nfp] (requires K Np < 2^31).
 std::vector<int32_t> neighbour_nodes(const RefElement& re, const MeshData& m);
 
+// Processing order of the tiles of `tile` consecutive elements, for a launch
+// whose workgroups are dealt to `parts` caches (XCDs) in contiguous ranges
+// of launch positions: the tiles are sorted into `parts` slabs along the
+// axis of largest extent of their centroids, and each slab is swept along
+// its own longest remaining axis.  Coordinates are bucketed by the typical
+// element size, ties keep the element order.  Face neighbours then run
+// close together in time on one cache.  Returns the tile of each position.
+std::vector<int32_t> tile_order(const MeshData& m, int tile, int parts);
+
 // Orthonormal basis psi[Np] at the reference point (r, s, t) [HW08, Ch. 10].
 void basis_at(const RefElement& re, double r, double s, double t, double* psi);
 

@@ -168,6 +168,7 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
   if (lsrk) { A.res = alloc<float>(9 * K * Np); for (int64_t i = 0; i < 9 * K * Np; ++i) A.res[i] = 0.f; }
   A.geo = dupf(m.geo); A.fgeo = dupf(m.fgeo);
   A.nbn = dup(dgh::neighbour_nodes(re, m));
+  A.torder = dup(dgh::tile_order(m, dgb::kTile, 8));
   std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
   A.fmask = dup(fm);
   A.mat = dupf(dgh::mfma_material(N, K, a.data(), b.data(), d.data()));
