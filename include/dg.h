@@ -274,6 +274,16 @@ dg_status dg_connectivity(const dg_ctx* ctx, int32_t* etoe, int32_t* etof,
                           int32_t* nbnode);
 dg_status dg_geometry(const dg_ctx* ctx, double* geo, double* fgeo, double* J);
 
+/* Tile processing order of the matrix-core stage (any precision; no device
+ * needed): out[ceil(K/16)] is the 16-element tile that launch position p
+ * processes.  Positions are dealt to the eight XCDs in contiguous ranges;
+ * the order puts the tiles into eight slabs along the axis of largest
+ * extent and sweeps each slab along its longest remaining axis (coordinates
+ * bucketed by the typical element size, ties in element order), so that
+ * face-neighbour tiles run close together on one XCD's L2.  A permutation
+ * of 0 .. ceil(K/16) - 1.  DG_ESTATE before dg_mesh_upload. */
+dg_status dg_tile_order(const dg_ctx* ctx, int32_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,7 @@ EXPORTS = [
     "dg_node_coords", "dg_quad_coords", "dg_material_upload", "dg_project",
     "dg_state_set", "dg_state_get", "dg_state_device_ptr", "dg_rhs", "dg_step",
     "dg_run", "dg_synchronize", "dg_ref_operator", "dg_face_nodes",
-    "dg_connectivity", "dg_geometry", "dg_sources_set", "dg_receivers_set",
+    "dg_connectivity", "dg_geometry", "dg_tile_order", "dg_sources_set", "dg_receivers_set",
     "dg_receivers_sample", "dg_run_record", "dg_time_set", "dg_time_get",
     "dg_trace_reserve", "dg_trace_copy", "dg_advance", "dg_graph_advance", "dg_memory",
     "dg_footprint", "dg_state_zero", "dg_material_set_weights", "dg_adjoint_forward",
@@ -77,6 +77,7 @@ def _load():
         "dg_ref_operator": ([P, I32, P], I32),
         "dg_face_nodes": ([P, P], I32),
         "dg_connectivity": ([P, P, P, P], I32),
+        "dg_tile_order": ([P, P], I32),
         "dg_geometry": ([P, P, P, P], I32),
         "dg_sources_set": ([P, I32, P, P, P, P, P], I32),
         "dg_receivers_set": ([P, I32, P], I32),
@@ -367,6 +368,13 @@ def dg_connectivity(ctx):
     nbn = np.empty((K, 4, Nfp), dtype=np.int32)
     check(ctx, lib.dg_connectivity(ctx, _ptr(etoe), _ptr(etof), _ptr(nbn)))
     return etoe, etof, nbn
+
+
+def dg_tile_order(ctx):
+    K, _, _, _ = dg_sizes(ctx)
+    out = np.empty((K + 15) // 16, dtype=np.int32)
+    check(ctx, lib.dg_tile_order(ctx, _ptr(out)))
+    return out
 
 
 def dg_geometry(ctx):

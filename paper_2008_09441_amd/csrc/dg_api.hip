@@ -1472,6 +1472,14 @@ dg_status dg_connectivity(const dg_ctx* c, int32_t* etoe, int32_t* etof, int32_t
   return DG_OK;
 }
 
+dg_status dg_tile_order(const dg_ctx* c, int32_t* out) {
+  if (!c || !out) return DG_EINVAL;
+  if (!c->has_mesh) return DG_ESTATE;
+  const std::vector<int32_t> t = dgh::tile_order(c->mesh, dgb::kTile, 8);
+  std::memcpy(out, t.data(), t.size() * sizeof(int32_t));
+  return DG_OK;
+}
+
 dg_status dg_geometry(const dg_ctx* c, double* geo, double* fgeo, double* J) {
   if (!c) return DG_EINVAL;
   if (!c->has_mesh) return DG_ESTATE;

@@ -567,8 +567,10 @@ std::vector<int32_t> tile_order(const MeshData& m, int tile, int parts) {
     double lo = 1e300;
     for (int64_t i = b; i < e; ++i) lo = std::min(lo, c[size_t(ord[size_t(i)]) * 3 + d]);
     std::stable_sort(ord.begin() + b, ord.begin() + e, [&](int32_t x, int32_t y) {
-      const int64_t bx = int64_t(std::floor((c[size_t(x) * 3 + d] - lo) / h));
-      const int64_t by = int64_t(std::floor((c[size_t(y) * 3 + d] - lo) / h));
+      // bucket boundaries half a length above the multiples of h: tiles of
+      // one layer sit at or just above them, not straddling
+      const int64_t bx = int64_t(std::floor((c[size_t(x) * 3 + d] - lo) / h + 0.5));
+      const int64_t by = int64_t(std::floor((c[size_t(y) * 3 + d] - lo) / h + 0.5));
       return bx != by ? bx < by : x < y;
     });
   };

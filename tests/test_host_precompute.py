@@ -165,3 +165,40 @@ def test_sources_and_receivers_need_a_device_context():
         assert e.value.status == B.DG_EDEVICE
     finally:
         B.dg_destroy(ctx)
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_tile_order_sweeps_slabs(n):
+    # tile processing order of the matrix-core stage on the Kuhn cube: a
+    # permutation; each of the eight launch ranges is one slab of hexahedron
+    # layers, swept so that face-neighbour tiles in the same range run at
+    # most two rows of tiles apart (except across the periodic seam)
+    s = _host(4, n)
+    order = B.dg_tile_order(s.ctx)
+    K = 6 * n ** 3
+    T = (K + 15) // 16
+    assert np.array_equal(np.sort(order), np.arange(T))
+    pos = np.empty(T, dtype=np.int64)
+    pos[order] = np.arange(T)
+    per, rem = divmod(T, 8)
+    part = np.empty(T, dtype=np.int64)
+    for x in range(8):
+        b = x * per + min(x, rem)
+        part[order[b:b + per + (1 if x < rem else 0)]] = x
+    hexes = np.arange(K) // 6
+    ijk = np.stack([hexes % n, (hexes // n) % n, hexes // (n * n)], 1)
+    tile_of = np.arange(K) // 16
+    # one slab axis: every range covers n / 8 layers along it (or one layer)
+    layers = [max(len(np.unique(ijk[part[tile_of] == x, a])) for x in range(8))
+              for a in range(3)]
+    assert min(layers) == max(1, n // 8)
+    etoe, _, _ = B.dg_connectivity(s.ctx)
+    ea = np.repeat(np.arange(K), 4)
+    eb = etoe.reshape(-1)
+    ta, tb = tile_of[ea], tile_of[eb]
+    # pairs across the periodic seam are the sweep's two ends
+    seam = (np.abs(ijk[ea] - ijk[eb]) == n - 1).any(1)
+    same = (part[ta] == part[tb]) & (ta != tb) & ~seam
+    row_tiles = -(-6 * n // 16)
+    assert same.sum() > 0
+    assert np.abs(pos[ta[same]] - pos[tb[same]]).max() <= 2 * row_tiles
