@@ -13,6 +13,7 @@
 #include "../../include/dg.h"
 #include "dg_host.hpp"
 #include "dg_kernels.hpp"
+#include "dg_be.hpp"
 #include "dg_bx.hpp"
 #include "dg_src.hpp"
 #include "dg_adj.hpp"
@@ -324,6 +325,36 @@ hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res,
   return hipGetLastError();
 }
 
+template <int N>
+hipError_t launch_mfma_e(dg_ctx* c, const float* q_in, float* q_out, float* res, float* rhs_out,
+                         double a, double b, double dt, int lsrk) {
+  dgb::BeArgs A;
+  A.q_in = q_in;
+  A.q_out = q_out;
+  A.res = res;
+  A.rhs_out = rhs_out;
+  A.geo = static_cast<const float*>(c->geo.p);
+  A.fgeo = static_cast<const float*>(c->fgeo.p);
+  A.nbn = static_cast<const int32_t*>(c->nbn.p);
+  A.fmask = static_cast<const int32_t*>(c->fmask.p);
+  A.irho = static_cast<const float*>(c->irho.p);
+  A.lam = static_cast<const float*>(c->lam.p);
+  A.mu = static_cast<const float*>(c->mu.p);
+  A.zp = static_cast<const float*>(c->zp.p);
+  A.zs = static_cast<const float*>(c->zs.p);
+  A.frags = static_cast<const dgb::u32x4*>(c->frags.p);
+  A.K = c->mesh.K;
+  A.a = float(a);
+  A.b = float(b);
+  A.dt = float(dt);
+  A.lsrk = lsrk;
+  A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+  // one workgroup per element
+  if (c->mesh.K > 0x7fffffff) return hipErrorInvalidValue;
+  dgb::stage_be<N><<<dim3(unsigned(c->mesh.K)), dim3(dgb::kThreads), 0, c->stream>>>(A);
+  return hipGetLastError();
+}
+
 dg_status launch_mfma(dg_ctx* c, const void* q_in, void* q_out, void* res, void* rhs_out,
                       double a, double b, double dt, int lsrk) {
   const float* qi = static_cast<const float*>(q_in);
@@ -336,6 +367,9 @@ dg_status launch_mfma(dg_ctx* c, const void* q_in, void* q_out, void* res, void*
     case 2: e = launch_mfma_n<2>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
     case 3: e = launch_mfma_n<3>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
     case 4: e = launch_mfma_n<4>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 5: e = launch_mfma_e<5>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 6: e = launch_mfma_e<6>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 7: e = launch_mfma_e<7>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
     default: e = hipErrorInvalidValue;
   }
   if (e != hipSuccess)
@@ -367,7 +401,7 @@ dg_status fill_zero(dg_ctx* c, void* p, int64_t n) {
 dg_status device_irho(dg_ctx* c, int64_t k, std::vector<double>& out) {
   const int Nq = c->re.Nq;
   out.assign(Nq, 0.0);
-  if (c->opt.precision == DG_FP32_BF16X3) {
+  if (c->opt.precision == DG_FP32_BF16X3 && dgh::mfma_blocked_material(c->re.N)) {
     for (int p = 0; p < Nq; ++p) {
       float v = 0.f;
       const size_t idx = dgh::mfma_material_index(c->re.N, k, p, 0);
@@ -854,8 +888,10 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
     if (K * c->re.Np >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "mesh: K Np too large");
     const std::vector<int32_t> nbn = dgh::neighbour_nodes(c->re, md);
     if ((s = upload_raw(c, c->nbn, nbn.data(), nbn.size())) != DG_OK) return s;
-    const std::vector<int32_t> tord = dgh::tile_order(md, dgb::kTile, 8);
-    if ((s = upload_raw(c, c->torder, tord.data(), tord.size())) != DG_OK) return s;
+    if (dgh::mfma_blocked_material(c->re.N)) {
+      const std::vector<int32_t> tord = dgh::tile_order(md, dgb::kTile, 8);
+      if ((s = upload_raw(c, c->torder, tord.data(), tord.size())) != DG_OK) return s;
+    }
   }
   const size_t nstate = size_t(9) * K * c->re.Np * c->elem;
   for (DevBuf* b : {&c->q[0], &c->q[1], &c->res})
@@ -912,7 +948,7 @@ dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
     b[i] = r * (p * p - 2.0 * v * v);
     d[i] = r * v * v;
   }
-  if (c->opt.precision == DG_FP32_BF16X3) {
+  if (c->opt.precision == DG_FP32_BF16X3 && dgh::mfma_blocked_material(c->re.N)) {
     const std::vector<double> blk =
         dgh::mfma_material(c->re.N, K, a.data(), b.data(), d.data());
     if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
@@ -1286,13 +1322,13 @@ dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc
   if (precision == DG_FP32_BF16X3) b += uint64_t(dgh::mfma_frag_count(order)) * 64 * 8 * 2;
   b += k * (9 + 16) * e + k * 4 * 4 + k * 4 + 96 * Nfp * 4;          // geometry, tables
   b += 3 * 9 * k * Np * e + 2 * sizeof(double);                      // q[2], res, clock
-  if (precision == DG_FP32_BF16X3) {
+  if (precision == DG_FP32_BF16X3) b += k * NF4 * 4;                 // neighbour nodes
+  if (precision == DG_FP32_BF16X3 && dgh::mfma_blocked_material(order)) {
     b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * 4;   // blocked material
-    b += k * NF4 * 4;                                                 // neighbour nodes
     b += (k + 15) / 16 * 4;                                           // tile order
-  }
-  else
+  } else {
     b += 3 * k * Nq * e;                                              // 1/rho, lam, mu
+  }
   b += 2 * k * Np * e;                                                // impedances
   b += uint64_t(nsrc) * (8 + 3 * Np * e + 3 * 8);                     // sources
   b += uint64_t(nrec) * (8 + Np * e) + uint64_t(trace_steps) * nrec * 3 * e;   // receivers
@@ -1324,7 +1360,7 @@ dg_status dg_material_set_weights(dg_ctx* c, const double* irho_q, const double*
   dg_status s = set_device(c);
   if (s != DG_OK) return s;
   DG_HIP(c, hipStreamSynchronize(c->stream));
-  if (c->opt.precision == DG_FP32_BF16X3) {
+  if (c->opt.precision == DG_FP32_BF16X3 && dgh::mfma_blocked_material(c->re.N)) {
     const std::vector<double> blk = dgh::mfma_material(c->re.N, K, irho_q, lam_q, mu_q);
     if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
   } else {

@@ -49,3 +49,30 @@ struct BOrd {
 };
 
 }  // namespace dgb
+
+namespace dgb {
+
+// Sizes and fragment offsets of the BF16x3 stage for orders 5-7, which
+// works on one element per workgroup with the nine fields (or output
+// components) as the MFMA columns.  Operator fragments are in plain K order:
+// fragment (t, s) holds, for lane l, rows 16 t + l % 16 and K slots
+// 32 s + 8 (l / 16) + j (j < 8) of the operator, hi and lo adjacent.
+template <int N>
+struct EOrd {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  static constexpr int NF4 = 4 * Nfp;
+  static constexpr int Nq = (N + 1) * (N + 1) * (N + 1);
+  static constexpr int RT = (Np + 15) / 16;         // node row tiles
+  static constexpr int KN = (Np + 31) / 32;         // K steps over nodes
+  static constexpr int KF = (NF4 + 31) / 32;        // K steps over face nodes
+  static constexpr int KQ = (Nq + 31) / 32;         // K steps over quadrature points
+  static constexpr int QT = 2 * KQ;                 // quadrature row tiles
+  static constexpr int OFF_D = 0;                              // [3][RT][KN]
+  static constexpr int OFF_L = OFF_D + 2 * 3 * RT * KN;        // [RT][KF]
+  static constexpr int OFF_V = OFF_L + 2 * RT * KF;            // V_q [QT][KN]
+  static constexpr int OFF_P = OFF_V + 2 * QT * KN;            // P_q [RT][KQ]
+  static constexpr int NFRAG = OFF_P + 2 * RT * KQ;
+};
+
+}  // namespace dgb

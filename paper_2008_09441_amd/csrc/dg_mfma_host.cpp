@@ -74,6 +74,38 @@ std::vector<uint16_t> build_frags(const RefElement& re) {
   return out;
 }
 
+// Fragments of the high-order stage (EOrd): D_r, D_s, D_t, LIFT, V_q, P_q in
+// plain K order, zero beyond the operator's rows and columns
+template <int N>
+std::vector<uint16_t> build_frags_e(const RefElement& re) {
+  using O = dgb::EOrd<N>;
+  std::vector<uint16_t> out(size_t(O::NFRAG) * 64 * 8, 0);
+  auto put = [&](int frag, const std::vector<double>& M, int rows, int cols, int t, int s) {
+    for (int l = 0; l < 64; ++l)
+      for (int j = 0; j < 8; ++j) {
+        const int r = 16 * t + l % 16, k = 32 * s + 8 * (l / 16) + j;
+        const double v = (r < rows && k < cols) ? M[size_t(r) * cols + k] : 0.0;
+        const uint16_t hi = bf16_rne(float(v));
+        const uint16_t lo = bf16_rne(float(v - double(bf16_val(hi))));
+        out[(size_t(frag) * 64 + l) * 8 + j] = hi;
+        out[(size_t(frag + 1) * 64 + l) * 8 + j] = lo;
+      }
+  };
+  const int Np = O::Np, NF4 = O::NF4, Nq = O::Nq;
+  const std::vector<double>* D[3] = {&re.Dr, &re.Ds, &re.Dt};
+  for (int d = 0; d < 3; ++d)
+    for (int t = 0; t < O::RT; ++t)
+      for (int s = 0; s < O::KN; ++s)
+        put(O::OFF_D + ((d * O::RT + t) * O::KN + s) * 2, *D[d], Np, Np, t, s);
+  for (int t = 0; t < O::RT; ++t)
+    for (int s = 0; s < O::KF; ++s) put(O::OFF_L + (t * O::KF + s) * 2, re.LIFT, Np, NF4, t, s);
+  for (int t = 0; t < O::QT; ++t)
+    for (int s = 0; s < O::KN; ++s) put(O::OFF_V + (t * O::KN + s) * 2, re.Vq, Nq, Np, t, s);
+  for (int t = 0; t < O::RT; ++t)
+    for (int s = 0; s < O::KQ; ++s) put(O::OFF_P + (t * O::KQ + s) * 2, re.Pq, Np, Nq, t, s);
+  return out;
+}
+
 template <int N>
 std::vector<double> build_material(int64_t K, const double* irho, const double* lam,
                                    const double* mu) {
@@ -100,14 +132,19 @@ std::vector<double> build_material(int64_t K, const double* irho, const double* 
 
 }  // namespace
 
-bool mfma_supported(int N) { return N >= 1 && N <= 4; }
+bool mfma_supported(int N) { return N >= 1 && N <= 7; }
+
+bool mfma_blocked_material(int N) { return N >= 1 && N <= 4; }
 
 std::vector<uint16_t> mfma_fragments(const RefElement& re) {
   switch (re.N) {
     case 1: return build_frags<1>(re);
     case 2: return build_frags<2>(re);
     case 3: return build_frags<3>(re);
-    default: return build_frags<4>(re);
+    case 4: return build_frags<4>(re);
+    case 5: return build_frags_e<5>(re);
+    case 6: return build_frags_e<6>(re);
+    default: return build_frags_e<7>(re);
   }
 }
 
@@ -145,7 +182,10 @@ int mfma_frag_count(int N) {
     case 1: return dgb::BOrd<1>::NFRAG;
     case 2: return dgb::BOrd<2>::NFRAG;
     case 3: return dgb::BOrd<3>::NFRAG;
-    default: return dgb::BOrd<4>::NFRAG;
+    case 4: return dgb::BOrd<4>::NFRAG;
+    case 5: return dgb::EOrd<5>::NFRAG;
+    case 6: return dgb::EOrd<6>::NFRAG;
+    default: return dgb::EOrd<7>::NFRAG;
   }
 }
 

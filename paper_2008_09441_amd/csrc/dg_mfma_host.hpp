@@ -8,11 +8,14 @@
 
 namespace dgh {
 
-// orders with a matrix-core stage kernel
+// orders with a matrix-core stage kernel (1-4: 16-element tiles, blocked
+// material; 5-7: one element per workgroup, material in [K][Nq] order)
 bool mfma_supported(int N);
+bool mfma_blocked_material(int N);
 
 // hi/lo bf16 bit patterns of the [Dr|Ds|Dt|LIFT], V_q and P_q fragments in
-// the K-slot order of the matrix-core stage kernel, [NFRAG][64 lanes][8]
+// the K-slot order of the matrix-core stage kernel of order N, [NFRAG][64
+// lanes][8]
 std::vector<uint16_t> mfma_fragments(const RefElement& re);
 
 // Column-kernel operator pack: DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],

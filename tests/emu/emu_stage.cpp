@@ -1,5 +1,5 @@
-// Runs the stage kernels on the CPU, for tests (matrix-core dgb::stage_bx<N>,
-// column dgk::stage_cols<T, N>):
+// Runs the stage kernels on the CPU, for tests (matrix-core dgb::stage_bx<N>
+// and dgb::stage_be<N>, column dgk::stage_cols<T, N>):
 // each workgroup is 256 host threads with real barriers; the 16x16x32 bf16
 // MFMA is emulated with its hardware lane layout (A: row lane%16, k 8(lane/16)+j;
 // B: column lane%16, k 8(lane/16)+j; D: column lane%16, row 4(lane/16)+j).
@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cmath>
 #include "dg_kernels.hpp"
+#include "dg_be.hpp"
 #include "dg_bx.hpp"
 #include "dg_host.hpp"
 #include "dg_mfma_host.hpp"
@@ -22,7 +23,7 @@ thread_local emu_dim3 threadIdx, blockIdx;
 emu_dim3 gridDim, blockDim;
 static std::unique_ptr<std::barrier<>> g_bar;
 static std::unique_ptr<std::barrier<>> g_wbar[4];
-struct Slot { emu_bf16x8 a[64], b[64]; };
+struct Slot { emu_bf16x8 a[64], b[64]; float x[64]; };
 static Slot g_slot[4];
 
 void __syncthreads() { g_bar->arrive_and_wait(); }
@@ -46,6 +47,16 @@ emu_f32x4 emu_mfma_16x16x32_bf16(emu_bf16x8 a, emu_bf16x8 b, emu_f32x4 c, int, i
   }
   g_wbar[w]->arrive_and_wait();
   return d;
+}
+
+// lane shuffle: every lane of the wave publishes its value, then reads lane src's
+float emu_shfl(float v, int src, int) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  g_slot[w].x[lane] = v;
+  g_wbar[w]->arrive_and_wait();
+  const float r = g_slot[w].x[src & 63];
+  g_wbar[w]->arrive_and_wait();
+  return r;
 }
 
 template <typename F>
@@ -158,6 +169,32 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
     return grid == -1 ? cols_dispatch<float>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk)
                       : cols_dispatch<double>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk);
   std::vector<uint16_t> fr = dgh::mfma_fragments(re);
+  if (N >= 5) {   // one element per workgroup
+    dgb::BeArgs E{};
+    float* qe = alloc<float>(9 * K * Np);
+    std::memcpy(qe, q, sizeof(float) * 9 * K * Np);
+    E.q_in = qe;
+    E.rhs_out = alloc<float>(9 * K * Np);
+    E.q_out = lsrk ? alloc<float>(9 * K * Np) : nullptr;
+    E.res = nullptr;
+    if (lsrk) { E.res = alloc<float>(9 * K * Np); for (int64_t i = 0; i < 9 * K * Np; ++i) E.res[i] = 0.f; }
+    E.geo = dupf(m.geo); E.fgeo = dupf(m.fgeo);
+    E.nbn = dup(dgh::neighbour_nodes(re, m));
+    std::vector<int32_t> fme(re.Fmask.begin(), re.Fmask.end());
+    E.fmask = dup(fme);
+    E.irho = dupf(a); E.lam = dupf(b); E.mu = dupf(d);
+    E.zp = dupf(zp); E.zs = dupf(zs);
+    E.frags = reinterpret_cast<const dgb::u32x4*>(dup(fr));
+    E.K = K; E.a = 0.f; E.b = 1.f; E.dt = 1.f; E.lsrk = lsrk; E.upwind = upwind;
+    switch (N) {
+      case 5: run_grid(int(K), [=]() { dgb::stage_be<5>(E); }); break;
+      case 6: run_grid(int(K), [=]() { dgb::stage_be<6>(E); }); break;
+      default: run_grid(int(K), [=]() { dgb::stage_be<7>(E); }); break;
+    }
+    for (int64_t i = 0; i < 9 * K * Np; ++i)
+      out[i] = lsrk ? double(E.q_out[i]) - double(E.q_in[i]) : double(E.rhs_out[i]);
+    return 0;
+  }
   dgb::BxArgs A{};
   float* qin = alloc<float>(9 * K * Np);
   std::memcpy(qin, q, sizeof(float) * 9 * K * Np);

@@ -37,3 +37,5 @@ inline int min(int a, int b) { return a < b ? a : b; }
 inline long min(long a, long b) { return a < b ? a : b; }
 inline unsigned min(unsigned a, unsigned b) { return a < b ? a : b; }
 #define __builtin_amdgcn_rcpf(x) (1.f / (x))
+float emu_shfl(float v, int src, int width);
+inline float __shfl(float v, int src, int width = 64) { return emu_shfl(v, src, width); }

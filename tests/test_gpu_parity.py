@@ -109,7 +109,8 @@ def test_plane_wave_order3_workload_fp64():
 # are printed.
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,N", [(3, 1), (3, 2), (3, 3), (4, 3), (3, 4), (5, 4)])
+@pytest.mark.parametrize("n,N", [(3, 1), (3, 2), (3, 3), (4, 3), (3, 4), (5, 4), (2, 5),
+                                 (2, 6), (2, 7)])
 @pytest.mark.parametrize("flux", ["upwind", "central"])
 def test_rhs_bf16x3_matches_oracle(n, N, flux):
     print(f"case rhs bf16x3 n={n} N={N} flux={flux}", flush=True)
@@ -137,7 +138,7 @@ def test_rhs_bf16x3_smooth_state():
     assert err.max() <= 1e-4
 
 
-@pytest.mark.parametrize("n,N", [(3, 4), (4, 3), (3, 2)])
+@pytest.mark.parametrize("n,N", [(3, 4), (4, 3), (3, 2), (2, 7)])
 def test_one_lsrk_step_bf16x3_matches_oracle(n, N):
     op, s = make_pair(n, N, synth.fourier_media, "upwind", "bf16x3")
     q0 = synth.random_state(op.K, op.Np, seed=50 + N).astype(np.float32).astype(np.float64)
@@ -153,6 +154,6 @@ def test_one_lsrk_step_bf16x3_matches_oracle(n, N):
 
 def test_bf16x3_rejects_unsupported_order():
     from paper_2008_09441_amd import B
-    for N in (5, 6):
+    for N in (0, 8):
         with pytest.raises(B.DGError):
             B.dg_create(N, B.DG_FP32_BF16X3, B.DG_FLUX_UPWIND, 0)

@@ -1,5 +1,5 @@
 """CPU check of the stage kernel sources: the unchanged kernels (the BF16x3
-matrix-core kernel and the FP32/FP64 column kernel) run on host threads
+matrix-core kernels of orders 1-4 and 5-7, and the FP32/FP64 column kernel) run on host threads
 (tests/emu) built with AddressSanitizer, so any out-of-bounds index fails the
 test, and their results are compared with the FP64 oracle (BF16x3: 1e-4,
 FP32: 2e-5, FP64: 1e-12 per-field relative L2)."""
@@ -57,16 +57,18 @@ def _run(exe, tmp_path, n, N, flux="upwind", grid=1, lsrk=0):
 
 
 @pytest.mark.parametrize("n,N,flux", [(2, 1, "central"), (3, 2, "upwind"), (3, 3, "central"),
-                                      (3, 4, "upwind"), (2, 4, "central")])
+                                      (3, 4, "upwind"), (2, 4, "central"), (1, 5, "upwind"),
+                                      (1, 6, "central"), (2, 7, "upwind")])
 def test_stage_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flux):
     err = _run(emu_exe, tmp_path, n, N, flux)
     print("per-field rel L2:", np.array2string(err, precision=2))
     assert err.max() <= 1e-4
 
 
-def test_stage_kernel_lsrk_mode(emu_exe, tmp_path):
+@pytest.mark.parametrize("n,N", [(2, 4), (1, 7)])
+def test_stage_kernel_lsrk_mode(emu_exe, tmp_path, n, N):
     # with a = 0, b = dt = 1 the LSRK increment q_out - q_in equals the rhs
-    err = _run(emu_exe, tmp_path, 2, 4, "upwind", lsrk=1)
+    err = _run(emu_exe, tmp_path, n, N, "upwind", lsrk=1)
     assert err.max() <= 1e-4
 
 
