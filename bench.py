@@ -78,6 +78,8 @@ def parse():
                    help="skip the point-source / receiver measurement")
     p.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    p.add_argument("--no-order7", action="store_true",
+                   help="skip the order-7 layered-media measurement")
     p.add_argument("--adjoint-steps", type=int, default=100)
     p.add_argument("--serving-requests", type=int, default=64)
     p.add_argument("--serving-rate", type=float, default=3.0, help="arrivals per second")
@@ -92,7 +94,7 @@ def parse():
 def stage_kernel_name(precision, N):
     """The kernel one stage launches for this precision and order."""
     if precision == "bf16x3":
-        return f"stage_bx<{N}>"
+        return f"stage_bx<{N}>" if N <= 4 else f"stage_be<{N}>"
     if N <= 4:
         return f"stage_cols<{'double' if precision == 'fp64' else 'float'},{N}>"
     return f"stage_generic<{'double' if precision == 'fp64' else 'float'},{N}>"
@@ -208,6 +210,50 @@ def sources_receivers(args, steps=50):
             "value": dofs / rec, "unit": "DOF-updates/s", "plain_value": dofs / plain,
             "overhead_frac": rec / plain - 1.0,
             "max_abs_trace": float(np.abs(tr).max())}
+
+
+def order7_layered(args, steps=20):
+    """The order-7 workload: 24^3 x 6 = 82,944 tets, five layers whose
+    interfaces cut through elements, BF16x3 contractions.  Rate of the
+    BF16x3 and FP64 GPU paths over `steps` steps of a smooth state (plane P
+    and S waves plus a Gaussian pulse) and the per-field error of the BF16x3
+    state against the FP64 one."""
+    import synth
+    from paper_2008_09441_amd import B, Solver
+    n, N = 24, 7
+    dt = 0.5 * (1.0 / n) / math.sqrt(2.0) / (4.5 * (N + 1) ** 2)
+    res, states = {}, {}
+    q0 = None
+    for prec in ("bf16x3", "fp64"):
+        s = Solver(N, precision=prec, flux="upwind", device=0)
+        s.upload_mesh(synth.kuhn_cube_vertices(n))
+        B.dg_material_upload(s.ctx, *(synth.layered_media(s.quad_coords())
+                                      + synth.layered_media(s.node_coords())))
+        if q0 is None:
+            q0 = s.project_function(lambda x: synth.plane_p_wave(x, 0.1) + synth.plane_s_wave(x, 0.2)
+                                    + synth.gaussian_pulse(x, width=0.1))
+            q0 = q0.astype(np.float32).astype(np.float64)
+        K, Np, _, _ = s.sizes()
+        s.set_state(q0)
+        s.run(0.0, dt, 1)                              # warm-up step
+        s.set_state(q0)
+        s.synchronize()
+        t0 = time.perf_counter()
+        s.run(0.0, dt, steps)
+        s.synchronize()
+        sec = time.perf_counter() - t0
+        res[prec] = {"value": 9 * K * Np * steps / sec, "ms_per_stage": sec / (5 * steps) * 1e3}
+        states[prec] = s.get_state().astype(np.float64)
+        s.close()
+    d = (states["bf16x3"] - states["fp64"]).reshape(9, -1)
+    r = states["fp64"].reshape(9, -1)
+    err = np.linalg.norm(d, axis=1) / np.linalg.norm(r, axis=1)
+    return {"workload": f"N=7 (Np=120), {n}^3x6 = 82944 tets, 5 layers (interfaces inside "
+                        f"elements, cp contrast 3x), smooth state, upwind, {steps} steps",
+            "kernel": stage_kernel_name("bf16x3", N), "unit": "DOF-updates/s",
+            "bf16x3": res["bf16x3"], "fp64_path": res["fp64"],
+            "speedup_vs_fp64_path": res["bf16x3"]["value"] / res["fp64"]["value"],
+            "rel_l2_vs_fp64_per_field": [float(x) for x in err]}
 
 
 def serving(args):
@@ -413,6 +459,8 @@ def main():
             out["fp32_path"]["l2_vs_fp64"] = norm.errors(q32, q64)
     if not args.no_sources:
         out["sources_receivers"] = sources_receivers(args)
+    if not args.no_order7:
+        out["order7_layered"] = order7_layered(args)
     if not args.no_serving:
         out["serving"] = serving(args)
     if not args.no_adjoint:
