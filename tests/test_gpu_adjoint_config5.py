@@ -1,0 +1,102 @@
+"""Discrete adjoint at the adjoint workload's size (run on an MI355X): order 4
+on the 24^3 x 6 cube (82,944 tets), smooth random media, 4 Ricker forces,
+64 receivers, a checkpoint every 20 steps.  40 LSRK(5,4) steps of a smooth
+initial state (the workload's 400 would make the 65 forward runs of this
+test take minutes).
+
+* FP64: the gradient of J = 1/2 |traces - d|^2 with respect to (1/rho, lam,
+  mu) at the quadrature points against central differences of the same GPU
+  run along 32 random directions, within 1e-6 relative (step 1e-5: the
+  quotient's truncation error ~1e-10, its rounding error ~1e-16 |J| / 1e-5);
+* FP32: the gradient against the FP64 one, within 1e-3 relative L2 (the
+  bound of the small-mesh FP32 test)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+N_CELLS, ORDER, STEPS, EVERY = 24, 4, 40, 20
+
+
+def _problem():
+    rng = np.random.default_rng(55)
+    f0 = rng.uniform(5.0, 15.0, 4)
+    return dict(src_x=rng.random((4, 3)), src_d=rng.standard_normal((4, 3)), f0=f0,
+                t0=1.2 / f0, recs=rng.random((64, 3)), rng=rng)
+
+
+def _context(precision, pb):
+    from paper_2008_09441_amd import B, Solver
+    s = Solver(ORDER, precision=precision, flux="upwind", device=0)
+    s.upload_mesh(synth.kuhn_cube_vertices(N_CELLS))
+    xq, xn = s.quad_coords(), s.node_coords()
+    rq, pq, sq = synth.fourier_media(xq, seed=77)
+    rn, pn, sn = synth.fourier_media(xn, seed=77)
+    m = np.stack([1.0 / rq, rq * (pq ** 2 - 2 * sq ** 2), rq * sq ** 2])
+    zp, zs = rn * pn, rn * sn
+    B.dg_material_set_weights(s.ctx, m[0], m[1], m[2], zp, zs)
+    s.set_sources(pb["src_x"], pb["src_d"], pb["f0"], pb["t0"], 1.0)
+    s.set_receivers(pb["recs"])
+    q0 = s.project_function(lambda x: synth.plane_p_wave(x, 0.1) + synth.plane_s_wave(x, 0.2)
+                            + synth.gaussian_pulse(x, width=0.1))
+    return s, m, zp, zs, q0
+
+
+def _dt():
+    return 0.5 * (1.0 / N_CELLS) / math.sqrt(2.0) / (4.0 * (ORDER + 1) ** 2)
+
+
+def _forward(s, m, zp, zs, q0):
+    from paper_2008_09441_amd import B
+    B.dg_material_set_weights(s.ctx, m[0], m[1], m[2], zp, zs)
+    s.set_state(q0)
+    tr = np.empty((STEPS, 64, 3), dtype=s.dtype)
+    B.dg_adjoint_forward(s.ctx, 0.0, _dt(), STEPS, EVERY, tr)
+    return tr.astype(np.float64)
+
+
+def _gradient(s, m, zp, zs, q0, d):
+    from paper_2008_09441_amd import B
+    tr = _forward(s, m, zp, zs, q0)
+    g = np.empty(m.shape)
+    B.dg_adjoint_backward(s.ctx, (tr - d).astype(s.dtype), g)
+    return g
+
+
+def test_config5_gradient_fp64_matches_central_differences_and_fp32():
+    pb = _problem()
+    s, m, zp, zs, q0 = _context("fp64", pb)
+    d = 0.5 * _forward(s, m, zp, zs, q0)          # synthetic data: half the signal
+    g = _gradient(s, m, zp, zs, q0, d)
+
+    def J(mm):
+        return 0.5 * float(np.sum((_forward(s, mm, zp, zs, q0) - d) ** 2))
+    rng = pb["rng"]
+    worst = 0.0
+    for _ in range(32):
+        delta = rng.standard_normal(m.shape) * m
+        eps = 1e-5   # truncation ~eps^2, rounding of J ~1e-16 |J| / eps
+        fd = (J(m + eps * delta) - J(m - eps * delta)) / (2 * eps)
+        an = float(np.sum(g * delta))
+        worst = max(worst, abs(fd - an) / abs(fd))
+    print(f"32 directions: max |fd - adjoint| / |fd| = {worst:.2e}", flush=True)
+    assert worst <= 1e-6
+    s.close()
+    s32, m32, zp32, zs32, q032 = _context("fp32", pb)
+    g32 = _gradient(s32, m32, zp32, zs32, q032, d)
+    s32.close()
+    rel = float(np.linalg.norm(g32 - g) / np.linalg.norm(g))
+    print(f"fp32 gradient vs fp64: {rel:.2e}", flush=True)
+    assert rel <= 1e-3
