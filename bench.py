@@ -256,22 +256,22 @@ def order7_layered(args, steps=20):
             "rel_l2_vs_fp64_per_field": [float(x) for x in err]}
 
 
-def serving(args):
+def serving(args, precision="fp32"):
     """Continuous batching of independent solves: a seeded Poisson stream of
     requests (periodic Kuhn cubes, n in [8, 24], N in {3, 4, 5}, 100-200 LSRK
-    steps, FP32, smooth random media, one Ricker force with f0 in [5, 15],
-    16 receivers), admitted by HBM budget, advanced by captured hipGraphs of
-    10 steps.  Latency = finish - arrival."""
+    steps, smooth random media, one Ricker force with f0 in [5, 15], 16
+    receivers), admitted by HBM budget, advanced by captured hipGraphs of 10
+    steps.  Latency = finish - arrival."""
     from paper_2008_09441_amd.serving import Server, poisson_workload
     reqs = poisson_workload(args.serving_requests, rate=args.serving_rate, n_range=(8, 24),
-                            orders=(3, 4, 5), steps=(100, 200), nrec=16, precision="fp32",
+                            orders=(3, 4, 5), steps=(100, 200), nrec=16, precision=precision,
                             seed=2008)
     srv = Server(hbm_budget=64 << 30, max_active=16, chunk=10, graphs=True, workers=4)
     srv.run(reqs)
     st = dict(srv.stats)
     st["workload"] = (f"{len(reqs)} Poisson requests at {args.serving_rate}/s, periodic "
                       "n^3x6 Kuhn cubes n in [8,24], N in {3,4,5}, 100-200 LSRK(5,4) steps, "
-                      "fp32, smooth random media (4 Fourier modes), 1 Ricker force "
+                      f"{precision}, smooth random media (4 Fourier modes), 1 Ricker force "
                       "(f0 in [5,15]), 16 receivers; 16 slots, 64 GiB budget, 10-step "
                       "captured graphs")
     return st
@@ -463,6 +463,7 @@ def main():
         out["order7_layered"] = order7_layered(args)
     if not args.no_serving:
         out["serving"] = serving(args)
+        out["serving_bf16x3"] = serving(args, "bf16x3")
     if not args.no_adjoint:
         out["adjoint"] = adjoint(args)
     if not args.no_cpu_baseline:
