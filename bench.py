@@ -83,6 +83,10 @@ def parse():
     p.add_argument("--adjoint-steps", type=int, default=100)
     p.add_argument("--serving-requests", type=int, default=64)
     p.add_argument("--serving-rate", type=float, default=3.0, help="arrivals per second")
+    p.add_argument("--serving-full", action="store_true",
+                   help="serve the full stream (256 requests, n in [8,32], 100-800 steps)")
+    p.add_argument("--serving-precisions", default="fp32,bf16x3",
+                   help="comma-separated precisions of the serving measurement")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-n", type=int, default=12)
     p.add_argument("--calibrate-copy", action="store_true",
@@ -258,22 +262,31 @@ def order7_layered(args, steps=20):
 
 def serving(args, precision="fp32"):
     """Continuous batching of independent solves: a seeded Poisson stream of
-    requests (periodic Kuhn cubes, n in [8, 24], N in {3, 4, 5}, 100-200 LSRK
-    steps, smooth random media, one Ricker force with f0 in [5, 15], 16
-    receivers), admitted by HBM budget, advanced by captured hipGraphs of 10
-    steps.  Latency = finish - arrival."""
+    requests (periodic Kuhn cubes, N in {3, 4, 5}, smooth random media, one
+    Ricker force with f0 in [5, 15], 16 receivers), admitted by HBM budget,
+    advanced by captured hipGraphs of 10 steps.  Latency = finish - arrival.
+    Default: 64 requests, n in [8, 24], 100-200 steps; --serving-full: the
+    full stream, 256 requests, n in [8, 32], 100-800 steps (progress on
+    stderr as requests complete)."""
     from paper_2008_09441_amd.serving import Server, poisson_workload
-    reqs = poisson_workload(args.serving_requests, rate=args.serving_rate, n_range=(8, 24),
-                            orders=(3, 4, 5), steps=(100, 200), nrec=16, precision=precision,
-                            seed=2008)
+    if args.serving_full:
+        nreq, n_range, steps = 256, (8, 32), (100, 800)
+    else:
+        nreq, n_range, steps = args.serving_requests, (8, 24), (100, 200)
+    reqs = poisson_workload(nreq, rate=args.serving_rate, n_range=n_range, orders=(3, 4, 5),
+                            steps=steps, nrec=16, precision=precision, seed=2008)
     srv = Server(hbm_budget=64 << 30, max_active=16, chunk=10, graphs=True, workers=4)
-    srv.run(reqs)
+
+    def progress(r):
+        print(f"serving {precision}: request {r.rid} done, latency {r.latency:.2f} s",
+              file=sys.stderr, flush=True)
+    srv.run(reqs, on_result=progress if args.serving_full else None)
     st = dict(srv.stats)
     st["workload"] = (f"{len(reqs)} Poisson requests at {args.serving_rate}/s, periodic "
-                      "n^3x6 Kuhn cubes n in [8,24], N in {3,4,5}, 100-200 LSRK(5,4) steps, "
-                      f"{precision}, smooth random media (4 Fourier modes), 1 Ricker force "
-                      "(f0 in [5,15]), 16 receivers; 16 slots, 64 GiB budget, 10-step "
-                      "captured graphs")
+                      f"n^3x6 Kuhn cubes n in [{n_range[0]},{n_range[1]}], N in {{3,4,5}}, "
+                      f"{steps[0]}-{steps[1]} LSRK(5,4) steps, {precision}, smooth random media "
+                      "(4 Fourier modes), 1 Ricker force (f0 in [5,15]), 16 receivers; 16 slots, "
+                      "64 GiB budget, 10-step captured graphs")
     return st
 
 
@@ -462,8 +475,8 @@ def main():
     if not args.no_order7:
         out["order7_layered"] = order7_layered(args)
     if not args.no_serving:
-        out["serving"] = serving(args)
-        out["serving_bf16x3"] = serving(args, "bf16x3")
+        for prec in args.serving_precisions.split(","):
+            out["serving" if prec == "fp32" else f"serving_{prec}"] = serving(args, prec)
     if not args.no_adjoint:
         out["adjoint"] = adjoint(args)
     if not args.no_cpu_baseline:

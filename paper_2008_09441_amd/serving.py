@@ -156,9 +156,10 @@ class Server:
         ev.record(a.stream)
         a.event = ev
 
-    def run(self, requests, clock=time.perf_counter):
+    def run(self, requests, clock=time.perf_counter, on_result=None):
         """Serve the requests (arrival times relative to the start); returns
-        the results in request order."""
+        the results in request order.  on_result(result), if given, is
+        called as each request completes."""
         import torch
         for r in requests:
             if r.footprint() > self.hbm_budget:
@@ -218,6 +219,8 @@ class Server:
                     results[a.req.rid] = Result(a.req.rid, tr, a.req.arrival, a.admitted,
                                                 a.started, fin, a.req.footprint(),
                                                 a.req.dofs())
+                    if on_result is not None:
+                        on_result(results[a.req.rid])
                     active.remove(a)
                     used -= a.req.footprint()
                 if not progressed:
