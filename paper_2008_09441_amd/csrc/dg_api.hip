@@ -122,6 +122,20 @@ dg_status fail(dg_ctx* c, dg_status s, const std::string& msg) {
 
 bool device_ctx(const dg_ctx* c) { return c->opt.device >= 0; }
 
+// The 16-element-tile matrix-core stage (dg_bx.hpp) runs BF16x3 and FP32 at
+// orders 1-4; it reads the blocked material, the neighbour-node table and
+// the tile order.  The [K][Nq] material is held by every other context and
+// by FP32 ones too (adjoint, sources).
+bool tiled_kernel(int32_t precision, int order) {
+  return order <= 4 && (precision == DG_FP32_BF16X3 || precision == DG_FP32);
+}
+bool plain_material(int32_t precision, int order) {
+  return !(precision == DG_FP32_BF16X3 && order <= 4);
+}
+bool tiled_mfma(const dg_ctx* c) {
+  return c->opt.precision == DG_FP32_BF16X3 || tiled_kernel(c->opt.precision, c->re.N);
+}
+
 dg_status set_device(dg_ctx* c) {
   if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
   DG_HIP(c, hipSetDevice(c->opt.device));
@@ -268,11 +282,17 @@ hipError_t launch_cols(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_
 template <typename T>
 hipError_t launch_stage_t(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_out,
                           double a, double b, double dt, int lsrk) {
+  // FP32 at orders 1-4 runs on the matrix-core kernel (launch_mfma)
+  if constexpr (sizeof(T) == 8) {
+    switch (c->re.N) {
+      case 1: return launch_cols<T, 1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+      case 2: return launch_cols<T, 2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+      case 3: return launch_cols<T, 3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+      case 4: return launch_cols<T, 4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+      default: break;
+    }
+  }
   switch (c->re.N) {
-    case 1: return launch_cols<T, 1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 2: return launch_cols<T, 2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 3: return launch_cols<T, 3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 4: return launch_cols<T, 4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 5: return launch_generic<T, 5>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 6: return launch_generic<T, 6>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 7: return launch_generic<T, 7>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
@@ -295,7 +315,7 @@ dg_status launch_stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void
   return DG_OK;
 }
 
-template <int N>
+template <int N, bool F32>
 hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res, float* rhs_out,
                          double a, double b, double dt, int lsrk) {
   dgb::BxArgs A;
@@ -321,7 +341,7 @@ hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res,
   // one workgroup per tile of 16 elements
   const int64_t tiles = (c->mesh.K + dgb::kTile - 1) / dgb::kTile;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  dgb::stage_bx<N><<<dim3(unsigned(tiles)), dim3(dgb::kThreads), 0, c->stream>>>(A);
+  dgb::stage_bx<N, F32><<<dim3(unsigned(tiles)), dim3(dgb::kThreads), 0, c->stream>>>(A);
   return hipGetLastError();
 }
 
@@ -362,11 +382,16 @@ dg_status launch_mfma(dg_ctx* c, const void* q_in, void* q_out, void* res, void*
   float* rs = static_cast<float*>(res);
   float* ro = static_cast<float*>(rhs_out);
   hipError_t e;
+  const bool f32 = c->opt.precision == DG_FP32;
   switch (c->re.N) {
-    case 1: e = launch_mfma_n<1>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
-    case 2: e = launch_mfma_n<2>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
-    case 3: e = launch_mfma_n<3>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
-    case 4: e = launch_mfma_n<4>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 1: e = f32 ? launch_mfma_n<1, true>(c, qi, qo, rs, ro, a, b, dt, lsrk)
+                    : launch_mfma_n<1, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 2: e = f32 ? launch_mfma_n<2, true>(c, qi, qo, rs, ro, a, b, dt, lsrk)
+                    : launch_mfma_n<2, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 3: e = f32 ? launch_mfma_n<3, true>(c, qi, qo, rs, ro, a, b, dt, lsrk)
+                    : launch_mfma_n<3, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 4: e = f32 ? launch_mfma_n<4, true>(c, qi, qo, rs, ro, a, b, dt, lsrk)
+                    : launch_mfma_n<4, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
     case 5: e = launch_mfma_e<5>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
     case 6: e = launch_mfma_e<6>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
     case 7: e = launch_mfma_e<7>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
@@ -379,8 +404,7 @@ dg_status launch_mfma(dg_ctx* c, const void* q_in, void* q_out, void* res, void*
 
 dg_status stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void* rhs_out, double a,
                 double b, double dt, int lsrk) {
-  if (c->opt.precision == DG_FP32_BF16X3)
-    return launch_mfma(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+  if (tiled_mfma(c)) return launch_mfma(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
   return launch_stage(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
 }
 
@@ -401,7 +425,7 @@ dg_status fill_zero(dg_ctx* c, void* p, int64_t n) {
 dg_status device_irho(dg_ctx* c, int64_t k, std::vector<double>& out) {
   const int Nq = c->re.Nq;
   out.assign(Nq, 0.0);
-  if (c->opt.precision == DG_FP32_BF16X3 && dgh::mfma_blocked_material(c->re.N)) {
+  if (!plain_material(c->opt.precision, c->re.N)) {
     for (int p = 0; p < Nq; ++p) {
       float v = 0.f;
       const size_t idx = dgh::mfma_material_index(c->re.N, k, p, 0);
@@ -809,6 +833,12 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
         dg_destroy(c);
         return DG_ENOMEM;
       }
+    } else if (tiled_kernel(opt->precision, opt->order)) {
+      const std::vector<float> fr = dgh::mfma_fragments_f32(re);
+      if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
+        dg_destroy(c);
+        return DG_ENOMEM;
+      }
     }
   }
   *out = c;
@@ -884,11 +914,11 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
   if ((s = upload_raw(c, c->etoe, md.EToE.data(), md.EToE.size())) != DG_OK) return s;
   if ((s = upload_raw(c, c->etop, md.EToP.data(), md.EToP.size())) != DG_OK) return s;
   if ((s = upload_raw(c, c->pat, md.pat.data(), md.pat.size())) != DG_OK) return s;
-  if (c->opt.precision == DG_FP32_BF16X3) {
+  if (tiled_mfma(c)) {
     if (K * c->re.Np >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "mesh: K Np too large");
     const std::vector<int32_t> nbn = dgh::neighbour_nodes(c->re, md);
     if ((s = upload_raw(c, c->nbn, nbn.data(), nbn.size())) != DG_OK) return s;
-    if (dgh::mfma_blocked_material(c->re.N)) {
+    if (tiled_kernel(c->opt.precision, c->re.N)) {
       const std::vector<int32_t> tord = dgh::tile_order(md, dgb::kTile, 8);
       if ((s = upload_raw(c, c->torder, tord.data(), tord.size())) != DG_OK) return s;
     }
@@ -948,11 +978,12 @@ dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
     b[i] = r * (p * p - 2.0 * v * v);
     d[i] = r * v * v;
   }
-  if (c->opt.precision == DG_FP32_BF16X3 && dgh::mfma_blocked_material(c->re.N)) {
+  if (tiled_kernel(c->opt.precision, c->re.N)) {
     const std::vector<double> blk =
         dgh::mfma_material(c->re.N, K, a.data(), b.data(), d.data());
     if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
-  } else {
+  }
+  if (plain_material(c->opt.precision, c->re.N)) {
     if ((s = upload_real(c, c->irho, a.data(), nq)) != DG_OK) return s;
     if ((s = upload_real(c, c->lam, b.data(), nq)) != DG_OK) return s;
     if ((s = upload_real(c, c->mu, d.data(), nq)) != DG_OK) return s;
@@ -1320,15 +1351,16 @@ dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc
   b += (3 * Np * NpP + NF4 * NpP + Np * QP + QP * NpP) * e;           // transposed operators
   b += NF4 * 4;                                                       // face masks
   if (precision == DG_FP32_BF16X3) b += uint64_t(dgh::mfma_frag_count(order)) * 64 * 8 * 2;
+  else if (tiled_kernel(precision, order)) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 16;
   b += k * (9 + 16) * e + k * 4 * 4 + k * 4 + 96 * Nfp * 4;          // geometry, tables
   b += 3 * 9 * k * Np * e + 2 * sizeof(double);                      // q[2], res, clock
-  if (precision == DG_FP32_BF16X3) b += k * NF4 * 4;                 // neighbour nodes
-  if (precision == DG_FP32_BF16X3 && dgh::mfma_blocked_material(order)) {
+  if (precision == DG_FP32_BF16X3 || tiled_kernel(precision, order))
+    b += k * NF4 * 4;                                                 // neighbour nodes
+  if (tiled_kernel(precision, order)) {
     b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * 4;   // blocked material
     b += (k + 15) / 16 * 4;                                           // tile order
-  } else {
-    b += 3 * k * Nq * e;                                              // 1/rho, lam, mu
   }
+  if (plain_material(precision, order)) b += 3 * k * Nq * e;          // 1/rho, lam, mu
   b += 2 * k * Np * e;                                                // impedances
   b += uint64_t(nsrc) * (8 + 3 * Np * e + 3 * 8);                     // sources
   b += uint64_t(nrec) * (8 + Np * e) + uint64_t(trace_steps) * nrec * 3 * e;   // receivers
@@ -1360,10 +1392,11 @@ dg_status dg_material_set_weights(dg_ctx* c, const double* irho_q, const double*
   dg_status s = set_device(c);
   if (s != DG_OK) return s;
   DG_HIP(c, hipStreamSynchronize(c->stream));
-  if (c->opt.precision == DG_FP32_BF16X3 && dgh::mfma_blocked_material(c->re.N)) {
+  if (tiled_kernel(c->opt.precision, c->re.N)) {
     const std::vector<double> blk = dgh::mfma_material(c->re.N, K, irho_q, lam_q, mu_q);
     if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
-  } else {
+  }
+  if (plain_material(c->opt.precision, c->re.N)) {
     if ((s = upload_real(c, c->irho, irho_q, nq)) != DG_OK) return s;
     if ((s = upload_real(c, c->lam, lam_q, nq)) != DG_OK) return s;
     if ((s = upload_real(c, c->mu, mu_q, nq)) != DG_OK) return s;

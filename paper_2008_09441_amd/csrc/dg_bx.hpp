@@ -402,6 +402,172 @@ __device__ __forceinline__ void quad_proj(const BxArgs& A, int64_t tile, int lan
       }
 }
 
+__device__ __forceinline__ f32x4 mma_f(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Phase C of the FP32 kernel for wave W: acc[i][t] = rows 16 t + 4 g + j of
+// r_{comp i}, one K slot per lane and step (the order of FOrd); operator
+// fragments are fetched one group of four steps ahead.
+template <int N, int W>
+__device__ __forceinline__ void vol_lift_f(const BxArgs& A, const float* sq, const float* sg,
+                                           const float* sF, int lane,
+                                           f32x4 (&acc)[3][BOrd<N>::RT]) {
+  using O = FOrd<N>;
+  constexpr int Np = O::Np, NF4 = O::NF4, RT = O::RT, NB = O::NB, SV = O::SV, SV4 = O::SV4;
+  constexpr int NC = wave_ncomp(W);
+  const int e = lane & 15, g = lane >> 4;
+  const f32x4* fr = reinterpret_cast<const f32x4*>(A.frags) + O::OFF_V;
+  float G[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) G[i] = sg[e * 9 + i];
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 fc[RT], fn[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) fc[t] = fr[(t * SV4) * 64 + lane];
+#pragma unroll
+  for (int q = 0; q < SV4; ++q) {
+    if (q + 1 < SV4) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) fn[t] = fr[(t * SV4 + q + 1) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int s = 4 * q + j;
+      if (s >= SV) break;
+      float b[NC];
+      if (s < 3 * NB) {
+        // U_{c,d} at node 4 (s / 3) + g (clamped: beyond Np the operator is zero)
+        const int d = s % 3, m = min(4 * (s / 3) + g, Np - 1);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          const int c = wave_comp(W, i);
+          float u = 0.f;
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj)
+            if (comp_weight(c, jj) != 0.f)
+              u += G[d * 3 + jj] * comp_weight(c, jj) * sq[(comp_field(c, jj) * Np + m) * kES + e];
+          b[i] = u;
+        }
+      } else {
+        const int jf = min(4 * (s - 3 * NB) + g, NF4 - 1);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) b[i] = sF[(wave_comp(W, i) * NF4 + jf) * kES + e];
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < NC; ++i) acc[i][t] = mma_f(fc[t][j], b[i], acc[i][t]);
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) fc[t] = fn[t];
+  }
+}
+
+// Phase D of the FP32 kernel for wave W: per chunk of two quadrature tiles,
+// V_q with the node accumulators as the B operand (K step (t, j) is row
+// 16 t + 4 g + j), the pointwise weight-adjusted material operator, and
+// P_q with the weighted values as the B operand (K step (u, j) is point
+// 16 u + 4 g + j); the nodal result goes to sr.
+template <int N, int W>
+__device__ __forceinline__ void quad_proj_f(const BxArgs& A, int64_t tile, int lane,
+                                            const f32x4 (&acc)[3][BOrd<N>::RT],
+                                            const f32x4 (&m0)[3][2], float* sr) {
+  using O = FOrd<N>;
+  constexpr int Np = O::Np, RT = O::RT, QT = O::QT, QC = O::QC;
+  constexpr int NC = wave_ncomp(W);
+  const int e = lane & 15, g = lane >> 4;
+  const f32x4* frq = reinterpret_cast<const f32x4*>(A.frags) + O::OFF_Q;
+  const f32x4* frp = reinterpret_cast<const f32x4*>(A.frags) + O::OFF_P;
+  f32x4 out[NC][RT];
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) out[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 m[3][2];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) m[f][0] = m0[f][0], m[f][1] = m0[f][1];
+#pragma unroll
+  for (int ch = 0; ch < QC; ++ch) {
+    f32x4 fv[2][RT], fp[RT][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int qt = 2 * ch + u < QT ? 2 * ch + u : QT - 1;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        fv[u][t] = frq[(qt * RT + t) * 64 + lane];
+        fp[t][u] = frp[(t * QT + qt) * 64 + lane];
+      }
+    }
+    f32x4 mn[3][2];
+    if (ch + 1 < QC) mat_chunk<N, W>(A, tile, lane, ch + 1, mn);
+    __builtin_amdgcn_sched_barrier(0);
+    f32x4 w[NC][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        w[i][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (2 * ch + u < QT) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[i][u] = mma_f(fv[u][t][j], acc[i][t][j], w[i][u]);
+        }
+      }
+    }
+    const f32x4* mi = m[0];
+    const f32x4* ml = m[1];
+    const f32x4* mm = m[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if constexpr (W == 0) {
+        w[0][u] *= mi[u];
+        w[1][u] *= mi[u];
+      } else if constexpr (W == 1) {
+        w[0][u] *= mi[u];
+        w[1][u] *= 2.f * mm[u];
+      } else if constexpr (W == 2) {
+        const f32x4 tr = w[0][u] + w[1][u] + w[2][u];
+        const f32x4 m2 = 2.f * mm[u];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) w[i][u] = ml[u] * tr + m2 * w[i][u];
+      } else {
+        w[0][u] *= 2.f * mm[u];
+        w[1][u] *= 2.f * mm[u];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (2 * ch + u < QT) {
+#pragma unroll
+          for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[i][t] = mma_f(fp[t][u][j], w[i][u][j], out[i][t]);
+        }
+      }
+    if (ch + 1 < QC) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) m[f][0] = mn[f][0], m[f][1] = mn[f][1];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 16 * t + 4 * g + j;
+        if (n < Np) sr[(wave_comp(W, i) * Np + n) * kES + e] = out[i][t][j];
+      }
+}
+
 // Item map of the tile's state, shared by the staging loads and the final
 // update: field f of the tile is TS = 16 Np consecutive floats.  Main items
 // r = tid + 256 it (it < MI) cover rows below 256 MI of every field; the TT
@@ -434,7 +600,7 @@ struct TileMap {
   }
 };
 
-template <int N>
+template <int N, bool F32>
 __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   using O = BOrd<N>;
   using L = BLds<N>;
@@ -639,20 +805,38 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   // C: volume + LIFT per wave
   f32x4 acc[3][RT];
   f32x4 m0[3][2];   // chunk-0 material, in flight during phase C
-  switch (grp) {
-    case 0: mat_chunk<N, 0>(A, tile, lane, 0, m0); vol_lift<N, 0>(A, sq, sg, sF, lane, acc); break;
-    case 1: mat_chunk<N, 1>(A, tile, lane, 0, m0); vol_lift<N, 1>(A, sq, sg, sF, lane, acc); break;
-    case 2: mat_chunk<N, 2>(A, tile, lane, 0, m0); vol_lift<N, 2>(A, sq, sg, sF, lane, acc); break;
-    default: mat_chunk<N, 3>(A, tile, lane, 0, m0); vol_lift<N, 3>(A, sq, sg, sF, lane, acc); break;
+  if constexpr (F32) {
+    switch (grp) {
+      case 0: mat_chunk<N, 0>(A, tile, lane, 0, m0); vol_lift_f<N, 0>(A, sq, sg, sF, lane, acc); break;
+      case 1: mat_chunk<N, 1>(A, tile, lane, 0, m0); vol_lift_f<N, 1>(A, sq, sg, sF, lane, acc); break;
+      case 2: mat_chunk<N, 2>(A, tile, lane, 0, m0); vol_lift_f<N, 2>(A, sq, sg, sF, lane, acc); break;
+      default: mat_chunk<N, 3>(A, tile, lane, 0, m0); vol_lift_f<N, 3>(A, sq, sg, sF, lane, acc); break;
+    }
+  } else {
+    switch (grp) {
+      case 0: mat_chunk<N, 0>(A, tile, lane, 0, m0); vol_lift<N, 0>(A, sq, sg, sF, lane, acc); break;
+      case 1: mat_chunk<N, 1>(A, tile, lane, 0, m0); vol_lift<N, 1>(A, sq, sg, sF, lane, acc); break;
+      case 2: mat_chunk<N, 2>(A, tile, lane, 0, m0); vol_lift<N, 2>(A, sq, sg, sF, lane, acc); break;
+      default: mat_chunk<N, 3>(A, tile, lane, 0, m0); vol_lift<N, 3>(A, sq, sg, sF, lane, acc); break;
+    }
   }
   __syncthreads();   // fluxes consumed: sr may overwrite them
 
   // D: quadrature and projection per wave
-  switch (grp) {
-    case 0: quad_proj<N, 0>(A, tile, lane, acc, m0, sr, srl); break;
-    case 1: quad_proj<N, 1>(A, tile, lane, acc, m0, sr, srl); break;
-    case 2: quad_proj<N, 2>(A, tile, lane, acc, m0, sr, srl); break;
-    default: quad_proj<N, 3>(A, tile, lane, acc, m0, sr, srl); break;
+  if constexpr (F32) {
+    switch (grp) {
+      case 0: quad_proj_f<N, 0>(A, tile, lane, acc, m0, sr); break;
+      case 1: quad_proj_f<N, 1>(A, tile, lane, acc, m0, sr); break;
+      case 2: quad_proj_f<N, 2>(A, tile, lane, acc, m0, sr); break;
+      default: quad_proj_f<N, 3>(A, tile, lane, acc, m0, sr); break;
+    }
+  } else {
+    switch (grp) {
+      case 0: quad_proj<N, 0>(A, tile, lane, acc, m0, sr, srl); break;
+      case 1: quad_proj<N, 1>(A, tile, lane, acc, m0, sr, srl); break;
+      case 2: quad_proj<N, 2>(A, tile, lane, acc, m0, sr, srl); break;
+      default: quad_proj<N, 3>(A, tile, lane, acc, m0, sr, srl); break;
+    }
   }
 
   // E: right-hand side store or fused stage update, coalesced, done by the

@@ -76,3 +76,37 @@ struct EOrd {
 };
 
 }  // namespace dgb
+
+namespace dgb {
+
+// Sizes and fragment offsets of the FP32 matrix-core stage (orders 1-4,
+// v_mfma_f32_16x16x4_f32): the tiling of BOrd, with FP32 operator
+// fragments.  Lane l = 16 g + e supplies K slot g of each 4-slot step.
+//  [Dr|Ds|Dt|LIFT], step s < 3 NB (NB = ceil(Np / 4) node blocks): node
+//      4 (s / 3) + g in reference direction s % 3; step s >= 3 NB: face
+//      node 4 (s - 3 NB) + g;
+//  V_q, quadrature tile u, step (t, j): node 16 t + 4 g + j (node tile t's
+//      accumulator row);
+//  P_q, node tile t, step (u, j): quadrature point 16 u + 4 g + j.
+// Fragments hold four consecutive steps per lane (one float4): vol
+// [RT][SV4][64][4], V_q [QT][RT][64][4], P_q [RT][QT][64][4]; lane l of
+// tile t has operator row 16 t + l % 16.  Slots beyond the counts are zero.
+template <int N>
+struct FOrd {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  static constexpr int NF4 = 4 * Nfp;
+  static constexpr int Nq = (N + 1) * (N + 1) * (N + 1);
+  static constexpr int RT = (Np + 15) / 16;
+  static constexpr int QT = (Nq + 15) / 16;
+  static constexpr int QC = (QT + 1) / 2;
+  static constexpr int NB = (Np + 3) / 4;
+  static constexpr int SV = 3 * NB + (NF4 + 3) / 4;   // steps of [Dr|Ds|Dt|LIFT]
+  static constexpr int SV4 = (SV + 3) / 4;
+  static constexpr int OFF_V = 0;                                  // in float4 units
+  static constexpr int OFF_Q = OFF_V + RT * SV4 * 64;
+  static constexpr int OFF_P = OFF_Q + QT * RT * 64;
+  static constexpr int NF4S = OFF_P + RT * QT * 64;                // float4 count
+};
+
+}  // namespace dgb

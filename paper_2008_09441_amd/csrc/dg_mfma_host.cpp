@@ -74,6 +74,49 @@ std::vector<uint16_t> build_frags(const RefElement& re) {
   return out;
 }
 
+// FP32 fragments of the FP32 matrix-core stage (FOrd), four steps per lane
+template <int N>
+std::vector<float> build_frags_f(const RefElement& re) {
+  using O = dgb::FOrd<N>;
+  const int Np = O::Np, NF4 = O::NF4, Nq = O::Nq;
+  std::vector<float> out(size_t(O::NF4S) * 4, 0.f);
+  const std::vector<double>* D[3] = {&re.Dr, &re.Ds, &re.Dt};
+  for (int t = 0; t < O::RT; ++t)
+    for (int q = 0; q < O::SV4; ++q)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 4; ++j) {
+          const int s = 4 * q + j, r = 16 * t + l % 16, g = l / 16;
+          double v = 0.0;
+          if (r < Np && s < O::SV) {
+            if (s < 3 * O::NB) {
+              const int m = 4 * (s / 3) + g;
+              if (m < Np) v = (*D[s % 3])[size_t(r) * Np + m];
+            } else {
+              const int jf = 4 * (s - 3 * O::NB) + g;
+              if (jf < NF4) v = re.LIFT[size_t(r) * NF4 + jf];
+            }
+          }
+          out[((size_t(O::OFF_V) + size_t(t * O::SV4 + q) * 64) + l) * 4 + j] = float(v);
+        }
+  for (int u = 0; u < O::QT; ++u)
+    for (int t = 0; t < O::RT; ++t)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 4; ++j) {
+          const int p = 16 * u + l % 16, n = 16 * t + 4 * (l / 16) + j;
+          const double v = (p < Nq && n < Np) ? re.Vq[size_t(p) * Np + n] : 0.0;
+          out[((size_t(O::OFF_Q) + size_t(u * O::RT + t) * 64) + l) * 4 + j] = float(v);
+        }
+  for (int t = 0; t < O::RT; ++t)
+    for (int u = 0; u < O::QT; ++u)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 4; ++j) {
+          const int r = 16 * t + l % 16, p = 16 * u + 4 * (l / 16) + j;
+          const double v = (r < Np && p < Nq) ? re.Pq[size_t(r) * Nq + p] : 0.0;
+          out[((size_t(O::OFF_P) + size_t(t * O::QT + u) * 64) + l) * 4 + j] = float(v);
+        }
+  return out;
+}
+
 // Fragments of the high-order stage (EOrd): D_r, D_s, D_t, LIFT, V_q, P_q in
 // plain K order, zero beyond the operator's rows and columns
 template <int N>
@@ -134,7 +177,6 @@ std::vector<double> build_material(int64_t K, const double* irho, const double* 
 
 bool mfma_supported(int N) { return N >= 1 && N <= 7; }
 
-bool mfma_blocked_material(int N) { return N >= 1 && N <= 4; }
 
 std::vector<uint16_t> mfma_fragments(const RefElement& re) {
   switch (re.N) {
@@ -145,6 +187,15 @@ std::vector<uint16_t> mfma_fragments(const RefElement& re) {
     case 5: return build_frags_e<5>(re);
     case 6: return build_frags_e<6>(re);
     default: return build_frags_e<7>(re);
+  }
+}
+
+std::vector<float> mfma_fragments_f32(const RefElement& re) {
+  switch (re.N) {
+    case 1: return build_frags_f<1>(re);
+    case 2: return build_frags_f<2>(re);
+    case 3: return build_frags_f<3>(re);
+    default: return build_frags_f<4>(re);
   }
 }
 
@@ -186,6 +237,15 @@ int mfma_frag_count(int N) {
     case 5: return dgb::EOrd<5>::NFRAG;
     case 6: return dgb::EOrd<6>::NFRAG;
     default: return dgb::EOrd<7>::NFRAG;
+  }
+}
+
+int mfma_f32_frag_count(int N) {
+  switch (N) {
+    case 1: return dgb::FOrd<1>::NF4S;
+    case 2: return dgb::FOrd<2>::NF4S;
+    case 3: return dgb::FOrd<3>::NF4S;
+    default: return dgb::FOrd<4>::NF4S;
   }
 }
 

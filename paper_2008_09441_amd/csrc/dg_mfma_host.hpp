@@ -8,15 +8,19 @@
 
 namespace dgh {
 
-// orders with a matrix-core stage kernel (1-4: 16-element tiles, blocked
-// material; 5-7: one element per workgroup, material in [K][Nq] order)
+// orders with a BF16x3 matrix-core stage kernel (1-4: 16-element tiles,
+// blocked material; 5-7: one element per workgroup, material in [K][Nq]
+// order)
 bool mfma_supported(int N);
-bool mfma_blocked_material(int N);
 
 // hi/lo bf16 bit patterns of the [Dr|Ds|Dt|LIFT], V_q and P_q fragments in
 // the K-slot order of the matrix-core stage kernel of order N, [NFRAG][64
 // lanes][8]
 std::vector<uint16_t> mfma_fragments(const RefElement& re);
+
+// FP32 operator fragments of the FP32 matrix-core stage (orders 1-4),
+// [NF4S][64 lanes][4] floats
+std::vector<float> mfma_fragments_f32(const RefElement& re);
 
 // Column-kernel operator pack: DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],
 // VqT [Np][QP], PqT [QP][NpP] (transposed, zero padded; NpP = 4 ceil(Np/4),
@@ -30,6 +34,8 @@ std::vector<double> mfma_material(int N, int64_t K, const double* irho, const do
 
 // fragment count and blocked-material floats per (tile, field) of order N
 int mfma_frag_count(int N);
+// float4 count of the FP32 fragments of order N (1-4)
+int mfma_f32_frag_count(int N);
 int mfma_mats(int N);
 
 // index in the blocked material array of field f (0 1/rho, 1 lam, 2 mu) at

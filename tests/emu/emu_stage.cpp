@@ -23,7 +23,7 @@ thread_local emu_dim3 threadIdx, blockIdx;
 emu_dim3 gridDim, blockDim;
 static std::unique_ptr<std::barrier<>> g_bar;
 static std::unique_ptr<std::barrier<>> g_wbar[4];
-struct Slot { emu_bf16x8 a[64], b[64]; float x[64]; };
+struct Slot { emu_bf16x8 a[64], b[64]; float x[64], fa[64], fb[64]; };
 static Slot g_slot[4];
 
 void __syncthreads() { g_bar->arrive_and_wait(); }
@@ -59,6 +59,25 @@ float emu_shfl(float v, int src, int) {
   return r;
 }
 
+// FP32 MFMA 16x16x4: A lane l holds row l % 16, k = l / 16; B lane l holds
+// column l % 16, k = l / 16; D as for the bf16 form
+emu_f32x4 emu_mfma_16x16x4_f32(float a, float b, emu_f32x4 c, int, int, int) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  g_slot[w].fa[lane] = a;
+  g_slot[w].fb[lane] = b;
+  g_wbar[w]->arrive_and_wait();
+  emu_f32x4 d = c;
+  const int n = lane % 16;
+  for (int j = 0; j < 4; ++j) {
+    const int i = 4 * (lane / 16) + j;
+    float acc = c[j];
+    for (int k = 0; k < 4; ++k) acc += g_slot[w].fa[i + 16 * k] * g_slot[w].fb[n + 16 * k];
+    d[j] = acc;
+  }
+  g_wbar[w]->arrive_and_wait();
+  return d;
+}
+
 template <typename F>
 static void run_grid(int grid, F kern) {
   gridDim.x = grid; blockDim.x = 256;
@@ -72,9 +91,9 @@ static void run_grid(int grid, F kern) {
   }
 }
 
-template <int N>
+template <int N, bool F32>
 static void run(dgb::BxArgs A, int grid) {
-  run_grid(grid, [=]() { dgb::stage_bx<N>(A); });
+  run_grid(grid, [=]() { dgb::stage_bx<N, F32>(A); });
 }
 
 // 128-byte aligned, size rounded up to whole 128-byte lines (the device
@@ -210,14 +229,20 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
   A.fmask = dup(fm);
   A.mat = dupf(dgh::mfma_material(N, K, a.data(), b.data(), d.data()));
   A.zp = dupf(zp); A.zs = dupf(zs);
-  A.frags = reinterpret_cast<const dgb::u32x4*>(dup(fr));
+  const bool f32 = grid == 2;   // FP32 matrix-core kernel
+  if (f32) {
+    const std::vector<float> ff = dgh::mfma_fragments_f32(re);
+    A.frags = reinterpret_cast<const dgb::u32x4*>(dup(ff));
+  } else {
+    A.frags = reinterpret_cast<const dgb::u32x4*>(dup(fr));
+  }
   A.K = K; A.a = 0.f; A.b = 1.f; A.dt = 1.f; A.lsrk = lsrk; A.upwind = upwind;
   grid = int((K + dgb::kTile - 1) / dgb::kTile);   // one workgroup per element tile
   switch (N) {
-    case 1: run<1>(A, grid); break;
-    case 2: run<2>(A, grid); break;
-    case 3: run<3>(A, grid); break;
-    case 4: run<4>(A, grid); break;
+    case 1: f32 ? run<1, true>(A, grid) : run<1, false>(A, grid); break;
+    case 2: f32 ? run<2, true>(A, grid) : run<2, false>(A, grid); break;
+    case 3: f32 ? run<3, true>(A, grid) : run<3, false>(A, grid); break;
+    case 4: f32 ? run<4, true>(A, grid) : run<4, false>(A, grid); break;
     default: return 3;
   }
   for (int64_t i = 0; i < 9 * K * Np; ++i)
@@ -225,8 +250,8 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
   return 0;
 }
 
-// input file: int32 N, flux_upwind, kernel (>0: matrix-core kernel; -1 / -2:
-// column kernel in FP32 / FP64), lsrk; int64 K; then float64
+// input file: int32 N, flux_upwind, kernel (1: BF16x3 matrix-core kernel, 2:
+// FP32 matrix-core kernel; -1 / -2: column kernel in FP32 / FP64), lsrk; int64 K; then float64
 // vxyz[K*12], period[3], rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n
 // [K*Np each]; then float32 q[9*K*Np]
 int main(int argc, char** argv) {

@@ -1,5 +1,6 @@
 """CPU check of the stage kernel sources: the unchanged kernels (the BF16x3
-matrix-core kernels of orders 1-4 and 5-7, and the FP32/FP64 column kernel) run on host threads
+matrix-core kernels of orders 1-4 and 5-7, the FP32 matrix-core kernel and the
+FP64 column kernel) run on host threads
 (tests/emu) built with AddressSanitizer, so any out-of-bounds index fails the
 test, and their results are compared with the FP64 oracle (BF16x3: 1e-4,
 FP32: 2e-5, FP64: 1e-12 per-field relative L2)."""
@@ -65,6 +66,19 @@ def test_stage_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flu
     assert err.max() <= 1e-4
 
 
+@pytest.mark.parametrize("n,N,flux", [(2, 1, "upwind"), (3, 2, "central"), (3, 3, "upwind"),
+                                      (3, 4, "upwind"), (2, 4, "central")])
+def test_fp32_matrix_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flux):
+    err = _run(emu_exe, tmp_path, n, N, flux, grid=2)
+    print("per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 2e-5
+
+
+def test_fp32_matrix_kernel_lsrk_mode(emu_exe, tmp_path):
+    err = _run(emu_exe, tmp_path, 2, 4, "upwind", grid=2, lsrk=1)
+    assert err.max() <= 2e-5
+
+
 @pytest.mark.parametrize("n,N", [(2, 4), (1, 7)])
 def test_stage_kernel_lsrk_mode(emu_exe, tmp_path, n, N):
     # with a = 0, b = dt = 1 the LSRK increment q_out - q_in equals the rhs
@@ -72,13 +86,13 @@ def test_stage_kernel_lsrk_mode(emu_exe, tmp_path, n, N):
     assert err.max() <= 1e-4
 
 
-@pytest.mark.parametrize("n,N,prec,flux", [(3, 1, "f64", "upwind"), (3, 2, "f32", "central"),
-                                           (3, 3, "f64", "upwind"), (3, 4, "f64", "upwind"),
-                                           (3, 4, "f32", "upwind")])
-def test_column_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, prec, flux):
-    err = _run(emu_exe, tmp_path, n, N, flux, grid=-1 if prec == "f32" else -2)
-    print(prec, "per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= (2e-5 if prec == "f32" else 1e-12)
+@pytest.mark.parametrize("n,N,flux", [(3, 1, "upwind"), (3, 2, "central"), (3, 3, "upwind"),
+                                      (3, 4, "upwind")])
+def test_column_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flux):
+    # the FP64 column kernel (FP32 runs on the matrix-core kernel at these orders)
+    err = _run(emu_exe, tmp_path, n, N, flux, grid=-2)
+    print("per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 1e-12
 
 
 def test_column_kernel_lsrk_mode(emu_exe, tmp_path):
