@@ -8,9 +8,11 @@
 // split product with FP32 accumulation, exactly as in the 16-element kernel
 // (dg_bx.hpp): the reference derivatives D_r, D_s, D_t and LIFT [HW08,
 // Ch. 10], and V_q and P_q of the weight-adjusted mass inverse [CHW17, C18].
-// Operator rows (nodes or quadrature points) are split over the four waves.
+// Operator rows (nodes or quadrature points) are split over the four waves;
+// each wave streams its operator fragments from L2 several products ahead.
 // Phases, with a workgroup barrier after each shared one:
-//   1  stage q [Np][9] in LDS; issue the face-node loads and neighbour gathers;
+//   1  stage q [Np][9] in LDS; issue the face-node loads, the material and
+//      residual loads of phases 6 and 7, and the neighbour gathers;
 //   2  D_d q for d = r, s, t (rows split by wave) into LDS;
 //   3  face fluxes [WSG10] into LDS, one thread per face node;
 //   4  chain rule with the element's metric terms: r = div(sigma), eps(v);
@@ -71,21 +73,48 @@ struct BeLds {
   static constexpr int BYTES = USED > FLOOR ? USED : FLOOR;
 };
 
-// B operand of K step s from an LDS buffer [rows][17]: lane (column e, group
-// g) holds rows 32 s + 8 g + j (j < 8) of column e
-__device__ __forceinline__ void be_bload(const float* buf, int s, int g, int e, bf16x8& bh,
-                                         bf16x8& bl) {
-  float v[8];
+// Operator fragments in flight per wave: each BF16x3 product waits for its
+// two fragments (an L2 round trip), so they are loaded this many products
+// ahead
+constexpr int kBePD = 4;
+
+// LDS rows of the B operand of K step s from a buffer [rows][17]: lane
+// (column e, group g) takes rows 32 s + 8 g + j (j < 8) of column e
+__device__ __forceinline__ void be_bread(const float* buf, int s, int g, int e, float (&v)[8]) {
 #pragma unroll
   for (int j = 0; j < 8; ++j) v[j] = buf[(32 * s + 8 * g + j) * kCS + e];
-  split8(v, bh, bl);
 }
 
-__device__ __forceinline__ f32x4 be_mma(const BeArgs& A, int frag, int lane, const bf16x8& bh,
-                                        const bf16x8& bl, f32x4 c) {
-  const u32x4 ah = A.frags[(frag + 0) * 64 + lane];
-  const u32x4 al = A.frags[(frag + 1) * 64 + lane];
-  return mma3(ah, al, bh, bl, c);
+__device__ __forceinline__ void be_fload(const BeArgs& A, int frag, int lane, u32x4& ah,
+                                         u32x4& al) {
+  ah = A.frags[(frag + 0) * 64 + lane];
+  al = A.frags[(frag + 1) * 64 + lane];
+}
+
+// acc[i] += A_{frag(s, i)} B_s for K steps s < NS and targets i < JS, in the
+// order (s, i): the fragments of a product are loaded PD products ahead and
+// the LDS rows of B_{s+1} while step s runs
+template <int NS, int JS, typename Frag, typename BRead>
+__device__ __forceinline__ void be_pipe(const BeArgs& A, int lane, Frag frag, BRead bread,
+                                        f32x4 (&acc)[JS]) {
+  constexpr int NJ = NS * JS, P = kBePD < NJ ? kBePD : NJ;
+  u32x4 fh[P], fl[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) be_fload(A, frag(j / JS, j % JS), lane, fh[j], fl[j]);
+  float vn[8];
+  bread(0, vn);
+  bf16x8 bh, bl;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int s = j / JS, i = j % JS;
+    if (i == 0) {
+      split8(vn, bh, bl);
+      if (s + 1 < NS) bread(s + 1, vn);
+    }
+    acc[i] = mma3(fh[j % P], fl[j % P], bh, bl, acc[i]);
+    if (j + P < NJ) be_fload(A, frag((j + P) / JS, (j + P) % JS), lane, fh[j % P], fl[j % P]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 template <int N>
@@ -96,6 +125,8 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
   constexpr int RT = O::RT, KN = O::KN, KF = O::KF, KQ = O::KQ, QT = O::QT;
   constexpr int NK = L::NK, FK = L::FK;
   constexpr int TW = (RT + 3) / 4;   // node tiles per wave (at most)
+  constexpr int QW = (QT + 3) / 4;   // quadrature tiles per wave (at most)
+  constexpr int ML = (QW + 3) / 4;   // material loads per lane and field
   static_assert(NF4 <= kThreads && NK <= kThreads && FK <= kThreads, "one item per thread");
   __shared__ __align__(16) float smem[L::BYTES / 4];
   float* sq = smem;                  // [NK][17]: q, columns = fields
@@ -113,8 +144,16 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
   const int64_t xcd = bid & 7, per = Gd >> 3, rem8 = Gd & 7;
   const int64_t k = xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3);
   const int64_t K = A.K, KNp = K * Np;
+  // the wave's node tiles t = wave + 4 i (clamped: a tile past RT repeats the
+  // last one and is never stored)
+  int tn[TW];
+#pragma unroll
+  for (int i = 0; i < TW; ++i) tn[i] = min(wave + 4 * i, RT - 1);
 
-  // 1: level-1 loads (face-node tables, state), then the neighbour gathers
+  // 1: level-1 loads (face-node tables, state, and everything later phases
+  // read from HBM: the wave's material values and residual rows), then the
+  // neighbour gathers.  The load counter is in order, so an HBM load issued
+  // among the operator-fragment loads of phases 2-7 would stall them.
   const bool ft = tid < NF4;                       // face-node task of this thread
   const int jf = ft ? tid : NF4 - 1;
   const int vM = A.fmask[jf];
@@ -126,6 +165,28 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
     const unsigned nc = unsigned(n < Np ? n : Np - 1);
 #pragma unroll
     for (int f = 0; f < 9; ++f) qv[f] = (A.q_in + k * Np + f * KNp)[nc];
+  }
+  // material: lane l holds quadrature point 16 t + l % 16 of the wave's
+  // quadrature tile t = wave + 4 (4 m + l / 16), for m < ML
+  float mt[3][ML];
+#pragma unroll
+  for (int m = 0; m < ML; ++m) {
+    const int t = min(wave + 4 * (4 * m + g), QT - 1);
+    const int p = min(16 * t + e, Nq - 1);
+    mt[0][m] = (A.irho + k * Nq)[p];
+    mt[1][m] = (A.lam + k * Nq)[p];
+    mt[2][m] = (A.mu + k * Nq)[p];
+  }
+  // residual of component e at the lane's output rows 16 t + 4 g + j (read
+  // from the state in right-hand-side mode, where it is not used)
+  const int ec = e < 9 ? e : 8;
+  float rv[TW][4];
+  {
+    const float* rb = (A.lsrk ? A.res : A.q_in) + ec * KNp + k * Np;
+#pragma unroll
+    for (int i = 0; i < TW; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rv[i][j] = rb[min(16 * tn[i] + 4 * g + j, Np - 1)];
   }
   __builtin_amdgcn_sched_barrier(0);
   const float zpM = A.zp[k * Np + vM], zsM = A.zs[k * Np + vM];
@@ -139,27 +200,15 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
   }
   __syncthreads();
 
-  // 2: D_d q for the wave's node tiles t = wave + 4 i
+  // 2: D_d q for the wave's node tiles (target i = 3 tile + d)
   {
-    f32x4 acc[3][TW];
+    f32x4 acc[3 * TW];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int i = 0; i < TW; ++i) acc[d][i] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < KN; ++s) {
-      bf16x8 bh, bl;
-      be_bload(sq, s, g, e, bh, bl);
-#pragma unroll
-      for (int i = 0; i < TW; ++i) {
-        const int t = wave + 4 * i;
-        if (t < RT) {
-#pragma unroll
-          for (int d = 0; d < 3; ++d)
-            acc[d][i] = be_mma(A, O::OFF_D + ((d * RT + t) * KN + s) * 2, lane, bh, bl, acc[d][i]);
-        }
-      }
-    }
+    for (int i = 0; i < 3 * TW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    be_pipe<KN, 3 * TW>(
+        A, lane,
+        [&](int s, int i) { return O::OFF_D + (((i % 3) * RT + tn[i / 3]) * KN + s) * 2; },
+        [&](int s, float(&v)[8]) { be_bread(sq, s, g, e, v); }, acc);
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
       const int t = wave + 4 * i;
@@ -168,7 +217,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
         const int n = 16 * t + 4 * g + j;
         if (t < RT && n < Np) {
 #pragma unroll
-          for (int d = 0; d < 3; ++d) sd[(d * Np + n) * kCS + e] = acc[d][i][j];
+          for (int d = 0; d < 3; ++d) sd[(d * Np + n) * kCS + e] = acc[3 * i + d][j];
         }
       }
     }
@@ -250,45 +299,69 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
 
   // 5: r += LIFT f for the wave's node tiles, in place
   {
+    f32x4 acc[TW];
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
-      const int t = wave + 4 * i;
-      if (t < RT) {
-        f32x4 acc;
+      acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (wave + 4 * i < RT) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = sr[(16 * t + 4 * g + j) * kCS + e];
+        for (int j = 0; j < 4; ++j) acc[i][j] = sr[(16 * tn[i] + 4 * g + j) * kCS + e];
+      }
+    }
+    be_pipe<KF, TW>(
+        A, lane, [&](int s, int i) { return O::OFF_L + (tn[i] * KF + s) * 2; },
+        [&](int s, float(&v)[8]) { be_bread(sf, s, g, e, v); }, acc);
 #pragma unroll
-        for (int s = 0; s < KF; ++s) {
-          bf16x8 bh, bl;
-          be_bload(sf, s, g, e, bh, bl);
-          acc = be_mma(A, O::OFF_L + (t * KF + s) * 2, lane, bh, bl, acc);
-        }
+    for (int i = 0; i < TW; ++i) {
+      if (wave + 4 * i < RT) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) sr[(16 * t + 4 * g + j) * kCS + e] = acc[j];
+        for (int j = 0; j < 4; ++j) sr[(16 * tn[i] + 4 * g + j) * kCS + e] = acc[i][j];
       }
     }
   }
   __syncthreads();
 
-  // 6: V_q r at the wave's quadrature tiles, then the weight-adjusted
-  // material operator: v rows times 1/rho, normal stresses lam tr + 2 mu,
-  // shear stresses 2 mu
+  // 6: V_q r at the wave's quadrature tiles t = wave + 4 u, then the
+  // weight-adjusted material operator: v rows times 1/rho, normal stresses
+  // lam tr + 2 mu, shear stresses 2 mu
   {
     bf16x8 bh[KN], bl[KN];
 #pragma unroll
-    for (int s = 0; s < KN; ++s) be_bload(sr, s, g, e, bh[s], bl[s]);
-    for (int t = wave; t < QT; t += 4) {
+    for (int s = 0; s < KN; ++s) {
+      float v[8];
+      be_bread(sr, s, g, e, v);
+      split8(v, bh[s], bl[s]);
+    }
+    constexpr int NJ = QW * KN, P = kBePD < NJ ? kBePD : NJ;
+    auto frag = [&](int j) {
+      const int t = min(wave + 4 * (j / KN), QT - 1);
+      return O::OFF_V + (t * KN + j % KN) * 2;
+    };
+    u32x4 fh[P], fl[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) be_fload(A, frag(j), lane, fh[j], fl[j]);
+#pragma unroll
+    for (int u = 0; u < QW; ++u) {
       f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < KN; ++s) w = be_mma(A, O::OFF_V + (t * KN + s) * 2, lane, bh[s], bl[s], w);
+      for (int s = 0; s < KN; ++s) {
+        const int j = u * KN + s;
+        w = mma3(fh[j % P], fl[j % P], bh[s], bl[s], w);
+        if (j + P < NJ) be_fload(A, frag(j + P), lane, fh[j % P], fl[j % P]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      const int t = wave + 4 * u;
+      if (t < QT) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int p = 16 * t + 4 * g + j;
-        const unsigned pc = unsigned(p < Nq ? p : Nq - 1);
-        const float ir = (A.irho + k * Nq)[pc], la = (A.lam + k * Nq)[pc], m2 = 2.f * (A.mu + k * Nq)[pc];
-        const float tr = __shfl(w[j], 16 * g + 3) + __shfl(w[j], 16 * g + 4) + __shfl(w[j], 16 * g + 5);
-        const float v = e < 3 ? ir * w[j] : e < 6 ? la * tr + m2 * w[j] : e < 9 ? m2 * w[j] : 0.f;
-        sw[p * kCS + e] = p < Nq ? v : 0.f;
+        for (int j = 0; j < 4; ++j) {
+          const int p = 16 * t + 4 * g + j;
+          const int src = ((u & 3) << 4) + 4 * g + j;   // holder of point p
+          const float ir = __shfl(mt[0][u >> 2], src), la = __shfl(mt[1][u >> 2], src);
+          const float m2 = 2.f * __shfl(mt[2][u >> 2], src);
+          const float tr = __shfl(w[j], 16 * g + 3) + __shfl(w[j], 16 * g + 4) + __shfl(w[j], 16 * g + 5);
+          const float v = e < 3 ? ir * w[j] : e < 6 ? la * tr + m2 * w[j] : e < 9 ? m2 * w[j] : 0.f;
+          sw[p * kCS + e] = p < Nq ? v : 0.f;
+        }
       }
     }
   }
@@ -296,29 +369,27 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
 
   // 7: P_q for the wave's node tiles, then the store or stage update of
   // component e at nodes 16 t + 4 g + j
+  {
+    f32x4 acc[TW];
 #pragma unroll
-  for (int i = 0; i < TW; ++i) {
-    const int t = wave + 4 * i;
-    if (t < RT) {
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < TW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    be_pipe<KQ, TW>(
+        A, lane, [&](int s, int i) { return O::OFF_P + (tn[i] * KQ + s) * 2; },
+        [&](int s, float(&v)[8]) { be_bread(sw, s, g, e, v); }, acc);
 #pragma unroll
-      for (int s = 0; s < KQ; ++s) {
-        bf16x8 bh, bl;
-        be_bload(sw, s, g, e, bh, bl);
-        acc = be_mma(A, O::OFF_P + (t * KQ + s) * 2, lane, bh, bl, acc);
-      }
-      const int ec = e < 9 ? e : 8;
+    for (int i = 0; i < TW; ++i) {
+      const int t = wave + 4 * i;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int n = 16 * t + 4 * g + j;
-        if (e < 9 && n < Np) {
+        if (t < RT && e < 9 && n < Np) {
           const int64_t gi = ec * KNp + k * Np + n;
           if (A.lsrk) {
-            const float rr = A.a * A.res[gi] + A.dt * acc[j];
+            const float rr = A.a * rv[i][j] + A.dt * acc[i][j];
             A.res[gi] = rr;
             A.q_out[gi] = sq[n * kCS + ec] + A.b * rr;
           } else {
-            A.rhs_out[gi] = acc[j];
+            A.rhs_out[gi] = acc[i][j];
           }
         }
       }
