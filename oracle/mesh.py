@@ -7,6 +7,9 @@ along its main diagonal, one per permutation (a, b, c) of the axes in
 lexicographic order: corner x0, then x0 + H e_a, x0 + H (e_a + e_b),
 x0 + H (1,1,1).  For odd permutations the last two vertices are swapped so
 that every element has positive orientation.  Element index = 6*hex + perm.
+build_mesh also takes other meshes of the same cube whose face centroids lie
+on the lattice of H/12: the Kuhn cube with elements split at their centroids
+into four, which gives odd element counts and non-Kuhn element shapes.
 Vertex coordinates are kept unwrapped per element; periodicity enters only
 through face matching (face centroids compared modulo 1) and trace pairing
 (node coordinates compared after shifting the neighbour face by the integer
@@ -84,10 +87,12 @@ class Mesh:
 
 def _face_keys(VX, n):
     """Integer key of each face centroid modulo the period.  Centroids of
-    Kuhn faces are multiples of H/3, so 3n * centroid is integral."""
+    Kuhn faces are multiples of H/3, and those of the faces made by splitting
+    a Kuhn element at its centroid multiples of H/12, so 12n * centroid is
+    integral."""
     K = VX.shape[0]
     keys = np.empty((K, 4), dtype=np.int64)
-    m = 3 * n
+    m = 12 * n
     for f, fv in enumerate(FACE_VERTS):
         c = VX[:, list(fv), :].sum(axis=1) / 3.0            # [K, 3]
         ci = np.mod(np.rint(c * m).astype(np.int64), m)
@@ -95,8 +100,12 @@ def _face_keys(VX, n):
     return keys
 
 
-def build_mesh(n: int, ref: RefElement) -> Mesh:
-    VX = kuhn_vertices(n)
+def build_mesh(n: int, ref: RefElement, VX: np.ndarray | None = None) -> Mesh:
+    """Geometry and connectivity of the periodic unit cube meshed by VX
+    [K, 4, 3] (positively oriented tetrahedra; default the Kuhn cube of n^3 x
+    6 elements).  Face centroids must lie on the lattice of H/12, H = 1/n:
+    the Kuhn cube, possibly with elements split at their centroids."""
+    VX = kuhn_vertices(n) if VX is None else np.asarray(VX, dtype=np.float64)
     K = VX.shape[0]
     Np, Nfp = ref.Np, ref.Nfp
 

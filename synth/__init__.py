@@ -204,3 +204,21 @@ def kuhn_cube_vertices(n, length=1.0):
             for i in range(n):
                 out[k, j, i] = local + np.array([i, j, k], dtype=np.float64)
     return (out * (length / n)).reshape(-1, 4, 3)
+
+def split_tet_vertices(vx, k=0):
+    """Element k of a tetrahedral mesh [K, 4, 3] replaced by the four
+    tetrahedra that join its centroid to its faces (sub-tetrahedron i takes
+    the centroid in place of vertex i, so each keeps the orientation of k):
+    the first takes k's place, the other three are appended.  From the Kuhn
+    cube this gives K = 6 n^3 + 3 elements, an odd count."""
+    v = np.asarray(vx, dtype=np.float64)
+    c = v[k].mean(axis=0)
+    subs = []
+    for i in range(4):
+        t = v[k].copy()
+        t[i] = c
+        subs.append(t)
+    out = np.concatenate([v, np.stack(subs[1:])])
+    out[k] = subs[0]
+    return out
+

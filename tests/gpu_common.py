@@ -12,13 +12,20 @@ def rel_l2_per_field(a, b):
     return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
 
 
-def make_pair(n, N, media, flux="upwind", precision="fp64", oracle=True):
-    """Oracle operator and libdg solver on the periodic Kuhn cube n^3 x 6 with
+def make_pair(n, N, media, flux="upwind", precision="fp64", oracle=True, vertices=None):
+    """Oracle operator and libdg solver on the periodic Kuhn cube n^3 x 6 (or
+    on the mesh `vertices` derived from it, e.g. with a split element) with
     identical media samples (taken at the oracle's coordinates)."""
     from paper_2008_09441_amd import Solver
-    op = ElasticDG(n, N, media, flux=flux) if oracle else None
+    vx = synth.kuhn_cube_vertices(n) if vertices is None else vertices
+    mesh = None
+    if vertices is not None and oracle:
+        from oracle.mesh import build_mesh
+        from oracle.refelem import ref_element
+        mesh = build_mesh(n, ref_element(N), vertices)
+    op = ElasticDG(n, N, media, flux=flux, mesh=mesh) if oracle else None
     s = Solver(N, precision=precision, flux=flux, device=0)
-    s.upload_mesh(synth.kuhn_cube_vertices(n))
+    s.upload_mesh(vx)
     if op is not None:
         xq, xn = op.mesh.xq, op.mesh.x
     else:

@@ -152,6 +152,30 @@ def test_one_lsrk_step_bf16x3_matches_oracle(n, N):
     assert err.max() <= 1e-5
 
 
+@pytest.mark.parametrize("N", [2, 4, 5, 6, 7])
+def test_bf16x3_odd_element_count(N):
+    """Kuhn cube n = 2 with element 0 split at its centroid (K = 51, odd):
+    four elements of a non-Kuhn shape, with face pairings the Kuhn cube does
+    not have, and a last 16-element tile of three elements at orders 1-4.
+    Right-hand side (bound 1e-4) and one LSRK step (1e-5) against the oracle
+    on the same mesh."""
+    print(f"case odd K bf16x3 N={N}", flush=True)
+    vx = synth.split_tet_vertices(synth.kuhn_cube_vertices(2))
+    op, s = make_pair(2, N, synth.fourier_media, "upwind", "bf16x3", vertices=vx)
+    assert op.K == 51
+    q = synth.random_state(op.K, op.Np, seed=60 + N).astype(np.float32).astype(np.float64)
+    err = rel_l2_per_field(s.rhs(_dev(q, torch.float32)).cpu().numpy(), op.rhs(q))
+    print("rhs per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 1e-4
+    dt = 1e-3
+    ref, _ = op.step(q, np.zeros_like(q), dt)
+    s.set_state(q)
+    s.step(0.0, dt)
+    err = rel_l2_per_field(s.get_state(), ref)
+    print("one step per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 1e-5
+
+
 def test_bf16x3_rejects_unsupported_order():
     from paper_2008_09441_amd import B
     for N in (0, 8):

@@ -14,6 +14,8 @@ import pytest
 import synth
 from gpu_common import rel_l2_per_field
 from oracle.dg import ElasticDG
+from oracle.mesh import build_mesh
+from oracle.refelem import ref_element
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -36,12 +38,17 @@ def emu_exe(tmp_path_factory):
     return exe
 
 
-def _run(exe, tmp_path, n, N, flux="upwind", grid=1, lsrk=0):
-    op = ElasticDG(n, N, synth.fourier_media, flux=flux)
+def _run(exe, tmp_path, n, N, flux="upwind", grid=1, lsrk=0, split=False):
+    vx = synth.kuhn_cube_vertices(n)
+    mesh = None
+    if split:   # one element split at its centroid: K = 6 n^3 + 3 (odd)
+        vx = synth.split_tet_vertices(vx)
+        mesh = build_mesh(n, ref_element(N), vx)
+    op = ElasticDG(n, N, synth.fourier_media, flux=flux, mesh=mesh)
     q = synth.random_state(op.K, op.Np, seed=40 + N).astype(np.float32)
     parts = [np.array([N, 1 if flux == "upwind" else 0, grid, lsrk], np.int32).tobytes(),
              np.array([op.K], np.int64).tobytes(),
-             synth.kuhn_cube_vertices(n).astype(np.float64).tobytes(),
+             vx.astype(np.float64).tobytes(),
              np.ones(3).tobytes()]
     for a in synth.fourier_media(op.mesh.xq) + synth.fourier_media(op.mesh.x):
         parts.append(np.ascontiguousarray(a, np.float64).tobytes())
@@ -62,6 +69,17 @@ def _run(exe, tmp_path, n, N, flux="upwind", grid=1, lsrk=0):
                                       (1, 6, "central"), (2, 7, "upwind")])
 def test_stage_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flux):
     err = _run(emu_exe, tmp_path, n, N, flux)
+    print("per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("n,N,flux,lsrk", [(1, 5, "upwind", 0), (1, 6, "central", 1),
+                                           (1, 7, "upwind", 0), (2, 4, "upwind", 0)])
+def test_stage_kernel_odd_element_count(emu_exe, tmp_path, n, N, flux, lsrk):
+    """A mesh with an odd element count (one Kuhn element split at its
+    centroid): elements of a non-Kuhn shape, and a ragged last 16-element
+    tile at order 4."""
+    err = _run(emu_exe, tmp_path, n, N, flux, lsrk=lsrk, split=True)
     print("per-field rel L2:", np.array2string(err, precision=2))
     assert err.max() <= 1e-4
 
