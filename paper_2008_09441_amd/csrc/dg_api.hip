@@ -97,8 +97,7 @@ struct dg_ctx {
   DevBuf adj_seg;           // step-start states of one segment [every][9][K][Np]
   DevBuf adj_y;             // stage inputs [5][9][K][Np]
   DevBuf adj_v;             // ly, lres, mu, nu, r, res [6][9][K][Np]
-  DevBuf adj_fb, adj_gb, adj_hb;   // face-node work [K][4 Nfp][9]
-  DevBuf adj_ob;            // quadrature work [K][Nq][9]
+  DevBuf adj_gb, adj_hb;    // face-node work [K][4 Nfp][9]
   DevBuf adj_grad;          // double [3][K][Nq]
   DevBuf adj_trace;         // [nsteps][nrec][3]
   bool adj_ready = false;
@@ -622,6 +621,15 @@ dga::AdjArgs<T> adj_args(const dg_ctx* c) {
   A.LIFT = ops + 3 * size_t(Np) * Np;
   A.Vq = A.LIFT + size_t(Np) * NF4;
   A.Pq = A.Vq + size_t(Nq) * Np;
+  // the transposed pack of the column kernel: DrT | DsT | DtT | LIFTT | VqT | PqT
+  A.NpP = 4 * ((Np + 3) / 4);
+  A.QP = 32 * ((Nq + 31) / 32);
+  const T* opsT = static_cast<const T*>(c->opsT.p);
+  A.DrT = opsT;
+  A.DsT = opsT + size_t(Np) * A.NpP;
+  A.DtT = opsT + 2 * size_t(Np) * A.NpP;
+  A.LIFTT = opsT + 3 * size_t(Np) * A.NpP;
+  A.VqT = A.LIFTT + size_t(NF4) * A.NpP;
   A.irho = static_cast<const T*>(c->irho.p);
   A.lam = static_cast<const T*>(c->lam.p);
   A.mu = static_cast<const T*>(c->mu.p);
@@ -698,11 +706,15 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
   T* ys = static_cast<T*>(c->adj_y.p);
   T* v = static_cast<T*>(c->adj_v.p);
   T *ly = v, *lres = v + n, *mu = v + 2 * n, *nu = v + 3 * n, *r = v + 4 * n, *res = v + 5 * n;
-  T* fb = static_cast<T*>(c->adj_fb.p);
   T* gb = static_cast<T*>(c->adj_gb.p);
   T* hb = static_cast<T*>(c->adj_hb.p);
-  T* ob = static_cast<T*>(c->adj_ob.p);
   double* grad = static_cast<double*>(c->adj_grad.p);
+  // per-element kernels: one workgroup per element, the element's vectors in LDS
+  if (K > 0x7fffffff) return fail(c, DG_EINVAL, "adjoint: too many elements for one grid");
+  const dim3 eg(static_cast<unsigned>(K)), et(static_cast<unsigned>(dga::kAdjThreads));
+  const size_t lraw = size_t(dga::raw_lds_elems(Np, c->re.Nfp)) * sizeof(T);
+  const size_t lgw = size_t(dga::gradw_lds_elems(Np, Nq)) * sizeof(T);
+  const size_t l9 = size_t(9) * Np * sizeof(T);
   const double t0 = c->adj_t0, dt = c->adj_dt;
   const int64_t nsteps = c->adj_nsteps, every = c->adj_every;
   const int64_t nck = (nsteps + every - 1) / every;
@@ -746,21 +758,18 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
         const double ts = ti + kRkC[q] * dt;
         dga::axpby<T><<<nblocks(n), 256, 0, st>>>(lres, ly, kRkB[q], 1.0, n);
         // gradient: dt d/dm <lres, W(m) (R y_q + raw sources(ts))>
-        dga::raw_flux<T><<<nblocks(K * NF4), 256, 0, st>>>(A, ys + q * n, fb);
-        dga::raw_nodes<T><<<nblocks(K * Np), 256, 0, st>>>(A, ys + q * n, fb, r);
+        dga::raw_rhs<T><<<eg, et, lraw, st>>>(A, ys + q * n, r);
         if (ns > 0) {
           dgs::source_add<T><<<nblocks(3 * Np), 256, 0, st>>>(
               r, static_cast<T*>(nullptr), static_cast<const int64_t*>(c->src_elem.p),
               static_cast<const T*>(c->src_wraw.p), static_cast<const double*>(c->src_par.p),
               ns, Np, KNp, ts, 1.0, 0.0);
         }
-        dga::grad_accum<T><<<nblocks(K * Nq), 256, 0, st>>>(A, lres, r, grad, dt);
-        // ly += dt R^T W^T lres
-        dga::wadgT_quad<T><<<nblocks(K * Nq), 256, 0, st>>>(A, lres, ob);
-        dga::wadgT_nodes<T><<<nblocks(K * Np), 256, 0, st>>>(A, ob, mu);
-        dga::liftT_faces<T><<<nblocks(K * NF4), 256, 0, st>>>(A, mu, gb);
+        // and mu = W^T lres (one kernel); then ly += dt R^T mu
+        dga::grad_wadgT<T><<<eg, et, lgw, st>>>(A, lres, r, grad, dt, mu);
+        dga::liftT_faces<T><<<eg, et, l9, st>>>(A, mu, gb);
         dga::fluxT_faces<T><<<nblocks(K * NF4), 256, 0, st>>>(A, gb, hb);
-        dga::volT_nodes<T><<<nblocks(K * Np), 256, 0, st>>>(A, mu, hb, nu);
+        dga::volT_nodes<T><<<eg, et, l9, st>>>(A, mu, hb, nu);
         dga::axpby<T><<<nblocks(n), 256, 0, st>>>(ly, nu, dt, 1.0, n);
         dga::axpby<T><<<nblocks(n), 256, 0, st>>>(lres, lres, 0.0, kRkA[q], n);
         DG_HIP(c, hipGetLastError());
@@ -857,7 +866,7 @@ void dg_destroy(dg_ctx* c) {
                       &c->res, &c->frags, &c->matblk, &c->nbn, &c->torder, &c->src_elem, &c->src_w,
                       &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf, &c->src_wraw,
                       &c->adj_nbface, &c->adj_invf, &c->adj_ck, &c->adj_seg, &c->adj_y,
-                      &c->adj_v, &c->adj_fb, &c->adj_gb, &c->adj_hb, &c->adj_ob,
+                      &c->adj_v, &c->adj_gb, &c->adj_hb,
                       &c->adj_grad, &c->adj_trace})
       release(c, *b);
   }
@@ -898,8 +907,8 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
   drop_graphs(c);
   for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf,
                     &c->trace, &c->src_wraw, &c->adj_nbface, &c->adj_invf, &c->adj_ck,
-                    &c->adj_seg, &c->adj_y, &c->adj_v, &c->adj_fb, &c->adj_gb, &c->adj_hb,
-                    &c->adj_ob, &c->adj_grad, &c->adj_trace})
+                    &c->adj_seg, &c->adj_y, &c->adj_v, &c->adj_gb, &c->adj_hb,
+                    &c->adj_grad, &c->adj_trace})
     release(c, *b);
   c->adj_ready = false;
   c->trace_cap = 0;
@@ -1434,10 +1443,8 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
               {&c->adj_seg, S * size_t(every)},
               {&c->adj_y, S * 5},
               {&c->adj_v, S * 6},
-              {&c->adj_fb, size_t(K) * NF4 * 9 * c->elem},
               {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
               {&c->adj_hb, size_t(K) * NF4 * 9 * c->elem},
-              {&c->adj_ob, size_t(K) * Nq * 9 * c->elem},
               {&c->adj_grad, size_t(K) * Nq * 3 * sizeof(double)},
               {&c->adj_trace, tb}};
   for (auto& x : need)
