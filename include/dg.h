@@ -227,8 +227,9 @@ dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const doubl
  * the receiver velocities after every step to trace (host
  * [nsteps][nrec][3], working precision).  Leaves the context at the end of
  * the run.  Needs receivers (DG_ESTATE).  Library-owned device memory:
- * ceil(nsteps/every) + every + 11 states plus face and quadrature work
- * arrays, counted against the HBM budget. */
+ * ceil(nsteps/every) + every + 11 states plus two face-node work arrays
+ * [K][4 Nfp][9] and the FP64 gradient [3][K][Nq], counted against the HBM
+ * budget. */
 dg_status dg_adjoint_forward(dg_ctx* ctx, double t0, double dt, int64_t nsteps, int64_t every,
                              void* trace);
 
