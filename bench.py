@@ -42,11 +42,21 @@ def alg_bytes_per_elem_stage(N, elem_bytes):
     return reals * elem_bytes + 4 * 4 + 4
 
 
+def kernel_build_hash(source):
+    """First 16 hex digits of the sha256 of a kernel source followed by the
+    hipcc flags it is built with: a record of counters taken on that build
+    holds only while both are unchanged."""
+    import hashlib
+    from paper_2008_09441_amd.build import HIPCC_FLAGS
+    h = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel, precision, order, elements):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE record of
     this kernel and workload, or None when there is none or the kernel source
-    has changed since the counters were taken."""
-    import hashlib
+    or its build flags have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_records.txt")
     if not os.path.exists(path):
         return None
@@ -57,8 +67,7 @@ def measured_traffic(kernel, precision, order, elements):
         r = json.loads(line)
         if (r["kernel"], r["precision"], r["order"], r["elements"]) != (kernel, precision, order, elements):
             continue
-        src = open(os.path.join(ROOT, r["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest()[:16] != r["source_sha256_16"]:
+        if kernel_build_hash(r["source"]) != r["kernel_build_sha256_16"]:
             return None
         return 1024.0 * (r["fetch_kib"] * r["fetch_factor"] + r["write_kib"] * r["write_factor"])
     return None

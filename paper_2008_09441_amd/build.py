@@ -15,6 +15,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the instruction-level-parallelism scheduling strategy: 1.2% faster on
+    # the order-4 BF16x3 stage and 3% on the FP32 one (measured on MI355X)
+    "-mllvm", "-amdgpu-sched-strategy=max-ilp",
     "-Wno-unused-command-line-argument",
 ]
 
