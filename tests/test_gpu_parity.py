@@ -53,6 +53,32 @@ def test_rhs_fp32_matches_oracle(n, N):
     assert err.max() <= 2e-5
 
 
+@pytest.mark.parametrize("N", [2, 4, 6])
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_odd_element_count_fp64_fp32(N, precision, bound):
+    """The centroid-split Kuhn cube (K = 51, non-Kuhn element shapes) on the
+    FP64 column kernel and the FP32 matrix-core kernel (orders 1-4) and on
+    the generic kernel (orders 5-7): right-hand side and one LSRK step
+    against the oracle on the same mesh."""
+    print(f"case odd K {precision} N={N}", flush=True)
+    vx = synth.split_tet_vertices(synth.kuhn_cube_vertices(2))
+    op, s = make_pair(2, N, synth.fourier_media, "upwind", precision, vertices=vx)
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    q = synth.random_state(op.K, op.Np, seed=70 + N)
+    if precision == "fp32":
+        q = q.astype(np.float32).astype(np.float64)
+    err = rel_l2_per_field(s.rhs(_dev(q, dtype)).cpu().numpy(), op.rhs(q))
+    print("rhs per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= bound
+    dt = 1e-3
+    ref, _ = op.step(q, np.zeros_like(q), dt)
+    s.set_state(q)
+    s.step(0.0, dt)
+    err = rel_l2_per_field(s.get_state(), ref)
+    print("one step per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= bound
+
+
 @pytest.mark.parametrize("n,N", [(3, 3), (3, 4)])
 def test_one_lsrk_step_fp64_matches_oracle(n, N):
     print(f"case step fp64 n={n} N={N}", flush=True)

@@ -92,6 +92,11 @@ def test_fp32_matrix_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, 
     assert err.max() <= 2e-5
 
 
+def test_fp32_matrix_kernel_odd_element_count(emu_exe, tmp_path):
+    err = _run(emu_exe, tmp_path, 2, 4, "upwind", grid=2, split=True)
+    assert err.max() <= 2e-5
+
+
 def test_fp32_matrix_kernel_lsrk_mode(emu_exe, tmp_path):
     err = _run(emu_exe, tmp_path, 2, 4, "upwind", grid=2, lsrk=1)
     assert err.max() <= 2e-5
