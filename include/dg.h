@@ -42,10 +42,12 @@ extern "C" {
 
 typedef struct dg_ctx dg_ctx;
 
+/* No C++ exception crosses this interface: a host allocation failure inside
+ * a call returns DG_ENOMEM, any other internal exception DG_EINVAL. */
 typedef enum {
   DG_OK = 0,
   DG_EINVAL = 1,      /* bad argument, size or mesh/material           */
-  DG_ENOMEM = 2,      /* device allocation failed or over HBM budget   */
+  DG_ENOMEM = 2,      /* device or host allocation failed, or over the HBM budget */
   DG_EDEVICE = 3,     /* HIP error, or compute call on host-only ctx   */
   DG_ESTATE = 4,      /* call out of order (e.g. rhs before material)  */
   DG_ENONFINITE = 5   /* non-finite input                              */

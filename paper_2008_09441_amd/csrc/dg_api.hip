@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -788,70 +789,88 @@ dg_status ready(dg_ctx* c, bool need_state) {
   return set_device(c);
 }
 
+// No C++ exception crosses the C boundary: host allocation failures (the
+// precompute's containers) become DG_ENOMEM, anything else DG_EINVAL.
+dg_status exception_status() {
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    return DG_ENOMEM;
+  } catch (const std::length_error&) {
+    return DG_ENOMEM;
+  } catch (...) {
+    return DG_EINVAL;
+  }
+}
+
 }  // namespace
 
 // ====================================================================== ABI
 extern "C" {
 
 dg_status dg_create(dg_ctx** out, const dg_options* opt) {
-  if (!out) return DG_EINVAL;
-  *out = nullptr;
-  if (!opt) return DG_EINVAL;
-  if (opt->order < 1 || opt->order > 7) return DG_EINVAL;
-  if (opt->precision != DG_FP64 && opt->precision != DG_FP32 &&
-      opt->precision != DG_FP32_BF16X3)
-    return DG_EINVAL;
-  if (opt->flux != DG_FLUX_UPWIND && opt->flux != DG_FLUX_CENTRAL) return DG_EINVAL;
-  if (opt->precision == DG_FP32_BF16X3 && !dgh::mfma_supported(opt->order)) return DG_EINVAL;
-  dg_ctx* c = new (std::nothrow) dg_ctx();
-  if (!c) return DG_ENOMEM;
-  c->opt = *opt;
-  c->elem = (opt->precision == DG_FP64) ? 8 : 4;
-  c->stream = static_cast<hipStream_t>(opt->stream);
-  std::string err;
-  if (!dgh::build_ref_element(opt->order, c->re, err)) {
-    delete c;
-    return DG_EINVAL;
-  }
-  if (device_ctx(c)) {
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device >= ndev) {
+  try {
+    if (!out) return DG_EINVAL;
+    *out = nullptr;
+    if (!opt) return DG_EINVAL;
+    if (opt->order < 1 || opt->order > 7) return DG_EINVAL;
+    if (opt->precision != DG_FP64 && opt->precision != DG_FP32 &&
+        opt->precision != DG_FP32_BF16X3)
+      return DG_EINVAL;
+    if (opt->flux != DG_FLUX_UPWIND && opt->flux != DG_FLUX_CENTRAL) return DG_EINVAL;
+    if (opt->precision == DG_FP32_BF16X3 && !dgh::mfma_supported(opt->order)) return DG_EINVAL;
+    dg_ctx* c = new (std::nothrow) dg_ctx();
+    if (!c) return DG_ENOMEM;
+    c->opt = *opt;
+    c->elem = (opt->precision == DG_FP64) ? 8 : 4;
+    c->stream = static_cast<hipStream_t>(opt->stream);
+    std::string err;
+    if (!dgh::build_ref_element(opt->order, c->re, err)) {
       delete c;
-      return DG_EDEVICE;
+      return DG_EINVAL;
     }
-    if (hipSetDevice(opt->device) != hipSuccess) {
-      delete c;
-      return DG_EDEVICE;
-    }
-    // reference operators and face masks, cast to the working precision
-    std::vector<double> ops;
-    const dgh::RefElement& re = c->re;
-    for (const auto* v : {&re.Dr, &re.Ds, &re.Dt, &re.LIFT, &re.Vq, &re.Pq})
-      ops.insert(ops.end(), v->begin(), v->end());
-    // transposed, padded operators for the column kernel
-    const std::vector<double> opsT = dgh::col_operators(re);
-    if (upload_real(c, c->opsT, opsT.data(), opsT.size()) != DG_OK ||
-        upload_real(c, c->ops, ops.data(), ops.size()) != DG_OK ||
-        upload_raw(c, c->fmask, re.Fmask.data(), re.Fmask.size()) != DG_OK) {
-      dg_destroy(c);
-      return DG_ENOMEM;
-    }
-    if (opt->precision == DG_FP32_BF16X3) {
-      const std::vector<uint16_t> fr = dgh::mfma_fragments(re);
-      if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
+    if (device_ctx(c)) {
+      int ndev = 0;
+      if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device >= ndev) {
+        delete c;
+        return DG_EDEVICE;
+      }
+      if (hipSetDevice(opt->device) != hipSuccess) {
+        delete c;
+        return DG_EDEVICE;
+      }
+      // reference operators and face masks, cast to the working precision
+      std::vector<double> ops;
+      const dgh::RefElement& re = c->re;
+      for (const auto* v : {&re.Dr, &re.Ds, &re.Dt, &re.LIFT, &re.Vq, &re.Pq})
+        ops.insert(ops.end(), v->begin(), v->end());
+      // transposed, padded operators for the column kernel
+      const std::vector<double> opsT = dgh::col_operators(re);
+      if (upload_real(c, c->opsT, opsT.data(), opsT.size()) != DG_OK ||
+          upload_real(c, c->ops, ops.data(), ops.size()) != DG_OK ||
+          upload_raw(c, c->fmask, re.Fmask.data(), re.Fmask.size()) != DG_OK) {
         dg_destroy(c);
         return DG_ENOMEM;
       }
-    } else if (tiled_kernel(opt->precision, opt->order)) {
-      const std::vector<float> fr = dgh::mfma_fragments_f32(re);
-      if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
-        dg_destroy(c);
-        return DG_ENOMEM;
+      if (opt->precision == DG_FP32_BF16X3) {
+        const std::vector<uint16_t> fr = dgh::mfma_fragments(re);
+        if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
+          dg_destroy(c);
+          return DG_ENOMEM;
+        }
+      } else if (tiled_kernel(opt->precision, opt->order)) {
+        const std::vector<float> fr = dgh::mfma_fragments_f32(re);
+        if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
+          dg_destroy(c);
+          return DG_ENOMEM;
+        }
       }
     }
+    *out = c;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  *out = c;
-  return DG_OK;
 }
 
 void dg_destroy(dg_ctx* c) {
@@ -879,691 +898,827 @@ const char* dg_last_error(const dg_ctx* c) {
 }
 
 dg_status dg_sizes(const dg_ctx* c, int64_t* K, int32_t* Np, int32_t* Nfp, int32_t* Nq) {
-  if (!c) return DG_EINVAL;
-  if (K) *K = c->has_mesh ? c->mesh.K : 0;
-  if (Np) *Np = c->re.Np;
-  if (Nfp) *Nfp = c->re.Nfp;
-  if (Nq) *Nq = c->re.Nq;
-  return DG_OK;
+  try {
+    if (!c) return DG_EINVAL;
+    if (K) *K = c->has_mesh ? c->mesh.K : 0;
+    if (Np) *Np = c->re.Np;
+    if (Nfp) *Nfp = c->re.Nfp;
+    if (Nq) *Nq = c->re.Nq;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double* period) {
-  if (!c) return DG_EINVAL;
-  if (!vxyz || !period || K <= 0) return fail(c, DG_EINVAL, "mesh: bad arguments");
-  for (int64_t i = 0; i < K * 12; ++i)
-    if (!std::isfinite(vxyz[i])) return fail(c, DG_ENONFINITE, "mesh: non-finite vertex");
-  std::string err;
-  dgh::MeshData m;
-  if (!dgh::build_mesh(c->re, K, vxyz, period, m, err)) return fail(c, DG_EINVAL, err);
-  c->mesh = std::move(m);
-  c->has_mesh = true;
-  c->has_mat = false;
-  c->has_state = false;
-  c->src.clear();           // sources and receivers belong to the old mesh
-  c->nrec = 0;
-  if (!device_ctx(c)) return DG_OK;
-  dg_status s = set_device(c);
-  if (s != DG_OK) return s;
-  drop_graphs(c);
-  for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf,
-                    &c->trace, &c->src_wraw, &c->adj_nbface, &c->adj_invf, &c->adj_ck,
-                    &c->adj_seg, &c->adj_y, &c->adj_v, &c->adj_gb, &c->adj_hb,
-                    &c->adj_grad, &c->adj_trace})
-    release(c, *b);
-  c->adj_ready = false;
-  c->trace_cap = 0;
-  if (!c->clk.p) {
-    if ((s = alloc(c, c->clk, 2 * sizeof(double))) != DG_OK) return s;
-  }
-  dgs::clock_set<<<1, 64, 0, c->stream>>>(static_cast<double*>(c->clk.p), 0.0);
-  DG_HIP(c, hipGetLastError());
-  const dgh::MeshData& md = c->mesh;
-  if ((s = upload_real(c, c->geo, md.geo.data(), md.geo.size())) != DG_OK) return s;
-  if ((s = upload_real(c, c->fgeo, md.fgeo.data(), md.fgeo.size())) != DG_OK) return s;
-  if ((s = upload_raw(c, c->etoe, md.EToE.data(), md.EToE.size())) != DG_OK) return s;
-  if ((s = upload_raw(c, c->etop, md.EToP.data(), md.EToP.size())) != DG_OK) return s;
-  if ((s = upload_raw(c, c->pat, md.pat.data(), md.pat.size())) != DG_OK) return s;
-  if (tiled_mfma(c)) {
-    if (K * c->re.Np >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "mesh: K Np too large");
-    const std::vector<int32_t> nbn = dgh::neighbour_nodes(c->re, md);
-    if ((s = upload_raw(c, c->nbn, nbn.data(), nbn.size())) != DG_OK) return s;
-    if (tiled_kernel(c->opt.precision, c->re.N)) {
-      const std::vector<int32_t> tord = dgh::tile_order(md, dgb::kTile, 8);
-      if ((s = upload_raw(c, c->torder, tord.data(), tord.size())) != DG_OK) return s;
+  try {
+    if (!c) return DG_EINVAL;
+    if (!vxyz || !period || K <= 0) return fail(c, DG_EINVAL, "mesh: bad arguments");
+    for (int64_t i = 0; i < K * 12; ++i)
+      if (!std::isfinite(vxyz[i])) return fail(c, DG_ENONFINITE, "mesh: non-finite vertex");
+    std::string err;
+    dgh::MeshData m;
+    if (!dgh::build_mesh(c->re, K, vxyz, period, m, err)) return fail(c, DG_EINVAL, err);
+    c->mesh = std::move(m);
+    c->has_mesh = true;
+    c->has_mat = false;
+    c->has_state = false;
+    c->src.clear();           // sources and receivers belong to the old mesh
+    c->nrec = 0;
+    if (!device_ctx(c)) return DG_OK;
+    dg_status s = set_device(c);
+    if (s != DG_OK) return s;
+    drop_graphs(c);
+    for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf,
+                      &c->trace, &c->src_wraw, &c->adj_nbface, &c->adj_invf, &c->adj_ck,
+                      &c->adj_seg, &c->adj_y, &c->adj_v, &c->adj_gb, &c->adj_hb,
+                      &c->adj_grad, &c->adj_trace})
+      release(c, *b);
+    c->adj_ready = false;
+    c->trace_cap = 0;
+    if (!c->clk.p) {
+      if ((s = alloc(c, c->clk, 2 * sizeof(double))) != DG_OK) return s;
     }
+    dgs::clock_set<<<1, 64, 0, c->stream>>>(static_cast<double*>(c->clk.p), 0.0);
+    DG_HIP(c, hipGetLastError());
+    const dgh::MeshData& md = c->mesh;
+    if ((s = upload_real(c, c->geo, md.geo.data(), md.geo.size())) != DG_OK) return s;
+    if ((s = upload_real(c, c->fgeo, md.fgeo.data(), md.fgeo.size())) != DG_OK) return s;
+    if ((s = upload_raw(c, c->etoe, md.EToE.data(), md.EToE.size())) != DG_OK) return s;
+    if ((s = upload_raw(c, c->etop, md.EToP.data(), md.EToP.size())) != DG_OK) return s;
+    if ((s = upload_raw(c, c->pat, md.pat.data(), md.pat.size())) != DG_OK) return s;
+    if (tiled_mfma(c)) {
+      if (K * c->re.Np >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "mesh: K Np too large");
+      const std::vector<int32_t> nbn = dgh::neighbour_nodes(c->re, md);
+      if ((s = upload_raw(c, c->nbn, nbn.data(), nbn.size())) != DG_OK) return s;
+      if (tiled_kernel(c->opt.precision, c->re.N)) {
+        const std::vector<int32_t> tord = dgh::tile_order(md, dgb::kTile, 8);
+        if ((s = upload_raw(c, c->torder, tord.data(), tord.size())) != DG_OK) return s;
+      }
+    }
+    const size_t nstate = size_t(9) * K * c->re.Np * c->elem;
+    for (DevBuf* b : {&c->q[0], &c->q[1], &c->res})
+      if ((s = alloc(c, *b, nstate)) != DG_OK) return s;
+    c->cur = 0;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  const size_t nstate = size_t(9) * K * c->re.Np * c->elem;
-  for (DevBuf* b : {&c->q[0], &c->q[1], &c->res})
-    if ((s = alloc(c, *b, nstate)) != DG_OK) return s;
-  c->cur = 0;
-  return DG_OK;
 }
 
 dg_status dg_node_coords(const dg_ctx* c, double* xyz) {
-  if (!c || !xyz) return DG_EINVAL;
-  if (!c->has_mesh) return DG_ESTATE;
-  dgh::node_coords(c->re, c->mesh, xyz);
-  return DG_OK;
+  try {
+    if (!c || !xyz) return DG_EINVAL;
+    if (!c->has_mesh) return DG_ESTATE;
+    dgh::node_coords(c->re, c->mesh, xyz);
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_quad_coords(const dg_ctx* c, double* xyz) {
-  if (!c || !xyz) return DG_EINVAL;
-  if (!c->has_mesh) return DG_ESTATE;
-  dgh::quad_coords(c->re, c->mesh, xyz);
-  return DG_OK;
+  try {
+    if (!c || !xyz) return DG_EINVAL;
+    if (!c->has_mesh) return DG_ESTATE;
+    dgh::quad_coords(c->re, c->mesh, xyz);
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
                              const double* cs_q, const double* rho_n, const double* cp_n,
                              const double* cs_n) {
-  if (!c) return DG_EINVAL;
-  if (!c->has_mesh) return fail(c, DG_ESTATE, "material: no mesh uploaded");
-  if (!rho_q || !cp_q || !cs_q || !rho_n || !cp_n || !cs_n)
-    return fail(c, DG_EINVAL, "material: null array");
-  const int64_t K = c->mesh.K;
-  const size_t nq = size_t(K) * c->re.Nq, nn = size_t(K) * c->re.Np;
-  auto check = [&](const double* r, const double* p, const double* s, size_t n) -> dg_status {
-    for (size_t i = 0; i < n; ++i) {
-      if (!std::isfinite(r[i]) || !std::isfinite(p[i]) || !std::isfinite(s[i]))
-        return fail(c, DG_ENONFINITE, "material: non-finite sample");
-      if (!(r[i] > 0.0) || !(s[i] > 0.0) || p[i] * p[i] < 2.0 * s[i] * s[i])
-        return fail(c, DG_EINVAL, "material: need rho > 0, cs > 0, cp >= sqrt(2) cs");
+  try {
+    if (!c) return DG_EINVAL;
+    if (!c->has_mesh) return fail(c, DG_ESTATE, "material: no mesh uploaded");
+    if (!rho_q || !cp_q || !cs_q || !rho_n || !cp_n || !cs_n)
+      return fail(c, DG_EINVAL, "material: null array");
+    const int64_t K = c->mesh.K;
+    const size_t nq = size_t(K) * c->re.Nq, nn = size_t(K) * c->re.Np;
+    auto check = [&](const double* r, const double* p, const double* s, size_t n) -> dg_status {
+      for (size_t i = 0; i < n; ++i) {
+        if (!std::isfinite(r[i]) || !std::isfinite(p[i]) || !std::isfinite(s[i]))
+          return fail(c, DG_ENONFINITE, "material: non-finite sample");
+        if (!(r[i] > 0.0) || !(s[i] > 0.0) || p[i] * p[i] < 2.0 * s[i] * s[i])
+          return fail(c, DG_EINVAL, "material: need rho > 0, cs > 0, cp >= sqrt(2) cs");
+      }
+      return DG_OK;
+    };
+    dg_status s = check(rho_q, cp_q, cs_q, nq);
+    if (s != DG_OK) return s;
+    if ((s = check(rho_n, cp_n, cs_n, nn)) != DG_OK) return s;
+    c->has_mat = false;
+    if (!device_ctx(c)) {
+      c->has_mat = true;
+      return DG_OK;
     }
-    return DG_OK;
-  };
-  dg_status s = check(rho_q, cp_q, cs_q, nq);
-  if (s != DG_OK) return s;
-  if ((s = check(rho_n, cp_n, cs_n, nn)) != DG_OK) return s;
-  c->has_mat = false;
-  if (!device_ctx(c)) {
+    if ((s = set_device(c)) != DG_OK) return s;
+    std::vector<double> a(nq), b(nq), d(nq);
+    for (size_t i = 0; i < nq; ++i) {
+      const double r = rho_q[i], p = cp_q[i], v = cs_q[i];
+      a[i] = 1.0 / r;
+      b[i] = r * (p * p - 2.0 * v * v);
+      d[i] = r * v * v;
+    }
+    if (tiled_kernel(c->opt.precision, c->re.N)) {
+      const std::vector<double> blk =
+          dgh::mfma_material(c->re.N, K, a.data(), b.data(), d.data());
+      if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
+    }
+    if (plain_material(c->opt.precision, c->re.N)) {
+      if ((s = upload_real(c, c->irho, a.data(), nq)) != DG_OK) return s;
+      if ((s = upload_real(c, c->lam, b.data(), nq)) != DG_OK) return s;
+      if ((s = upload_real(c, c->mu, d.data(), nq)) != DG_OK) return s;
+    }
+    std::vector<double> zp(nn), zs(nn);
+    for (size_t i = 0; i < nn; ++i) {
+      zp[i] = rho_n[i] * cp_n[i];
+      zs[i] = rho_n[i] * cs_n[i];
+    }
+    if ((s = upload_real(c, c->zp, zp.data(), nn)) != DG_OK) return s;
+    if ((s = upload_real(c, c->zs, zs.data(), nn)) != DG_OK) return s;
     c->has_mat = true;
+    drop_graphs(c);
+    if (!c->src.empty()) return upload_sources(c);   // source responses depend on 1/rho
     return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  if ((s = set_device(c)) != DG_OK) return s;
-  std::vector<double> a(nq), b(nq), d(nq);
-  for (size_t i = 0; i < nq; ++i) {
-    const double r = rho_q[i], p = cp_q[i], v = cs_q[i];
-    a[i] = 1.0 / r;
-    b[i] = r * (p * p - 2.0 * v * v);
-    d[i] = r * v * v;
-  }
-  if (tiled_kernel(c->opt.precision, c->re.N)) {
-    const std::vector<double> blk =
-        dgh::mfma_material(c->re.N, K, a.data(), b.data(), d.data());
-    if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
-  }
-  if (plain_material(c->opt.precision, c->re.N)) {
-    if ((s = upload_real(c, c->irho, a.data(), nq)) != DG_OK) return s;
-    if ((s = upload_real(c, c->lam, b.data(), nq)) != DG_OK) return s;
-    if ((s = upload_real(c, c->mu, d.data(), nq)) != DG_OK) return s;
-  }
-  std::vector<double> zp(nn), zs(nn);
-  for (size_t i = 0; i < nn; ++i) {
-    zp[i] = rho_n[i] * cp_n[i];
-    zs[i] = rho_n[i] * cs_n[i];
-  }
-  if ((s = upload_real(c, c->zp, zp.data(), nn)) != DG_OK) return s;
-  if ((s = upload_real(c, c->zs, zs.data(), nn)) != DG_OK) return s;
-  c->has_mat = true;
-  drop_graphs(c);
-  if (!c->src.empty()) return upload_sources(c);   // source responses depend on 1/rho
-  return DG_OK;
 }
 
 dg_status dg_project(const dg_ctx* c, int32_t nfields, const double* fq, double* q) {
-  if (!c || !fq || !q || nfields < 1) return DG_EINVAL;
-  if (!c->has_mesh) return DG_ESTATE;
-  const int Np = c->re.Np, Nq = c->re.Nq;
-  const int64_t K = c->mesh.K;
-  for (int64_t fk = 0; fk < int64_t(nfields) * K; ++fk) {
-    const double* src = fq + fk * Nq;
-    double* dst = q + fk * Np;
-    for (int n = 0; n < Np; ++n) {
-      double acc = 0.0;
-      const double* P = &c->re.Pq[size_t(n) * Nq];
-      for (int j = 0; j < Nq; ++j) acc += P[j] * src[j];
-      dst[n] = acc;
+  try {
+    if (!c || !fq || !q || nfields < 1) return DG_EINVAL;
+    if (!c->has_mesh) return DG_ESTATE;
+    const int Np = c->re.Np, Nq = c->re.Nq;
+    const int64_t K = c->mesh.K;
+    for (int64_t fk = 0; fk < int64_t(nfields) * K; ++fk) {
+      const double* src = fq + fk * Nq;
+      double* dst = q + fk * Np;
+      for (int n = 0; n < Np; ++n) {
+        double acc = 0.0;
+        const double* P = &c->re.Pq[size_t(n) * Nq];
+        for (int j = 0; j < Nq; ++j) acc += P[j] * src[j];
+        dst[n] = acc;
+      }
     }
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  return DG_OK;
 }
 
 dg_status dg_state_set(dg_ctx* c, const void* q, int32_t on_device) {
-  if (!c || !q) return DG_EINVAL;
-  dg_status s = ready(c, false);
-  if (s != DG_OK) return s;
-  const size_t n = size_t(9) * c->mesh.K * c->re.Np;
-  if (on_device)
-    DG_HIP(c, hipMemcpyAsync(c->q[c->cur].p, q, n * c->elem, hipMemcpyDeviceToDevice,
-                             c->stream));
-  else {
-    DG_HIP(c, copy_sync(c, c->q[c->cur].p, q, n * c->elem, hipMemcpyHostToDevice));
+  try {
+    if (!c || !q) return DG_EINVAL;
+    dg_status s = ready(c, false);
+    if (s != DG_OK) return s;
+    const size_t n = size_t(9) * c->mesh.K * c->re.Np;
+    if (on_device)
+      DG_HIP(c, hipMemcpyAsync(c->q[c->cur].p, q, n * c->elem, hipMemcpyDeviceToDevice,
+                               c->stream));
+    else {
+      DG_HIP(c, copy_sync(c, c->q[c->cur].p, q, n * c->elem, hipMemcpyHostToDevice));
+    }
+    if ((s = fill_zero(c, c->res.p, int64_t(n))) != DG_OK) return s;
+    c->has_state = true;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  if ((s = fill_zero(c, c->res.p, int64_t(n))) != DG_OK) return s;
-  c->has_state = true;
-  return DG_OK;
 }
 
 dg_status dg_state_zero(dg_ctx* c) {
-  if (!c) return DG_EINVAL;
-  dg_status s = ready(c, false);
-  if (s != DG_OK) return s;
-  const int64_t n = int64_t(9) * c->mesh.K * c->re.Np;
-  if ((s = fill_zero(c, c->q[c->cur].p, n)) != DG_OK) return s;
-  if ((s = fill_zero(c, c->res.p, n)) != DG_OK) return s;
-  c->has_state = true;
-  return DG_OK;
+  try {
+    if (!c) return DG_EINVAL;
+    dg_status s = ready(c, false);
+    if (s != DG_OK) return s;
+    const int64_t n = int64_t(9) * c->mesh.K * c->re.Np;
+    if ((s = fill_zero(c, c->q[c->cur].p, n)) != DG_OK) return s;
+    if ((s = fill_zero(c, c->res.p, n)) != DG_OK) return s;
+    c->has_state = true;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_state_get(dg_ctx* c, void* q, int32_t on_device) {
-  if (!c || !q) return DG_EINVAL;
-  dg_status s = ready(c, true);
-  if (s != DG_OK) return s;
-  const size_t n = size_t(9) * c->mesh.K * c->re.Np * c->elem;
-  if (on_device)
-    DG_HIP(c, hipMemcpyAsync(q, c->q[c->cur].p, n, hipMemcpyDeviceToDevice, c->stream));
-  else {
-    DG_HIP(c, hipMemcpyAsync(q, c->q[c->cur].p, n, hipMemcpyDeviceToHost, c->stream));
-    DG_HIP(c, hipStreamSynchronize(c->stream));
+  try {
+    if (!c || !q) return DG_EINVAL;
+    dg_status s = ready(c, true);
+    if (s != DG_OK) return s;
+    const size_t n = size_t(9) * c->mesh.K * c->re.Np * c->elem;
+    if (on_device)
+      DG_HIP(c, hipMemcpyAsync(q, c->q[c->cur].p, n, hipMemcpyDeviceToDevice, c->stream));
+    else {
+      DG_HIP(c, hipMemcpyAsync(q, c->q[c->cur].p, n, hipMemcpyDeviceToHost, c->stream));
+      DG_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  return DG_OK;
 }
 
 dg_status dg_state_device_ptr(dg_ctx* c, void** ptr) {
-  if (!c || !ptr) return DG_EINVAL;
-  dg_status s = ready(c, false);
-  if (s != DG_OK) return s;
-  *ptr = c->q[c->cur].p;
-  return DG_OK;
+  try {
+    if (!c || !ptr) return DG_EINVAL;
+    dg_status s = ready(c, false);
+    if (s != DG_OK) return s;
+    *ptr = c->q[c->cur].p;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_rhs(dg_ctx* c, const void* q_dev, void* rhs_dev, double t) {
-  if (!c || !q_dev || !rhs_dev) return DG_EINVAL;
-  if (q_dev == rhs_dev) return fail(c, DG_EINVAL, "rhs: q and rhs must not alias");
-  if (!std::isfinite(t)) return fail(c, DG_EINVAL, "rhs: non-finite t");
-  dg_status s = ready(c, false);
-  if (s != DG_OK) return s;
-  if ((s = stage(c, q_dev, nullptr, nullptr, rhs_dev, 0.0, 0.0, 0.0, 0)) != DG_OK) return s;
-  return launch_sources(c, rhs_dev, nullptr, t, 1.0, 0.0);
+  try {
+    if (!c || !q_dev || !rhs_dev) return DG_EINVAL;
+    if (q_dev == rhs_dev) return fail(c, DG_EINVAL, "rhs: q and rhs must not alias");
+    if (!std::isfinite(t)) return fail(c, DG_EINVAL, "rhs: non-finite t");
+    dg_status s = ready(c, false);
+    if (s != DG_OK) return s;
+    if ((s = stage(c, q_dev, nullptr, nullptr, rhs_dev, 0.0, 0.0, 0.0, 0)) != DG_OK) return s;
+    return launch_sources(c, rhs_dev, nullptr, t, 1.0, 0.0);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_step(dg_ctx* c, double t, double dt) {
-  if (!c) return DG_EINVAL;
-  if (!std::isfinite(t) || !std::isfinite(dt)) return fail(c, DG_EINVAL, "step: non-finite t/dt");
-  dg_status s = ready(c, true);
-  if (s != DG_OK) return s;
-  for (int st = 0; st < 5; ++st) {
-    s = stage(c, c->q[c->cur].p, c->q[1 - c->cur].p, c->res.p, nullptr, kRkA[st], kRkB[st],
-              dt, 1);
+  try {
+    if (!c) return DG_EINVAL;
+    if (!std::isfinite(t) || !std::isfinite(dt)) return fail(c, DG_EINVAL, "step: non-finite t/dt");
+    dg_status s = ready(c, true);
     if (s != DG_OK) return s;
-    s = launch_sources(c, c->res.p, c->q[1 - c->cur].p, t + kRkC[st] * dt, dt, kRkB[st] * dt);
-    if (s != DG_OK) return s;
-    c->cur = 1 - c->cur;
+    for (int st = 0; st < 5; ++st) {
+      s = stage(c, c->q[c->cur].p, c->q[1 - c->cur].p, c->res.p, nullptr, kRkA[st], kRkB[st],
+                dt, 1);
+      if (s != DG_OK) return s;
+      s = launch_sources(c, c->res.p, c->q[1 - c->cur].p, t + kRkC[st] * dt, dt, kRkB[st] * dt);
+      if (s != DG_OK) return s;
+      c->cur = 1 - c->cur;
+    }
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  return DG_OK;
 }
 
 dg_status dg_run(dg_ctx* c, double t0, double dt, int64_t nsteps) {
-  if (!c) return DG_EINVAL;
-  if (nsteps < 0) return fail(c, DG_EINVAL, "run: negative step count");
-  for (int64_t i = 0; i < nsteps; ++i) {
-    dg_status s = dg_step(c, t0 + double(i) * dt, dt);
-    if (s != DG_OK) return s;
+  try {
+    if (!c) return DG_EINVAL;
+    if (nsteps < 0) return fail(c, DG_EINVAL, "run: negative step count");
+    for (int64_t i = 0; i < nsteps; ++i) {
+      dg_status s = dg_step(c, t0 + double(i) * dt, dt);
+      if (s != DG_OK) return s;
+    }
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  return DG_OK;
 }
 
 dg_status dg_sources_set(dg_ctx* c, int32_t nsrc, const double* xyz, const double* dir,
                          const double* f0, const double* t0, const double* amp) {
-  if (!c) return DG_EINVAL;
-  if (nsrc < 0 || (nsrc > 0 && (!xyz || !dir || !f0 || !t0 || !amp)))
-    return fail(c, DG_EINVAL, "sources: bad arguments");
-  if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
-  if (!c->has_mesh) return fail(c, DG_ESTATE, "sources: no mesh uploaded");
-  if (!c->has_mat) return fail(c, DG_ESTATE, "sources: no material uploaded");
-  std::vector<dg_ctx::Source> src(nsrc);
-  for (int i = 0; i < nsrc; ++i) {
-    for (int d = 0; d < 3; ++d) {
-      src[i].x[d] = xyz[3 * i + d];
-      src[i].d[d] = dir[3 * i + d];
-      if (!std::isfinite(src[i].x[d]) || !std::isfinite(src[i].d[d]))
-        return fail(c, DG_ENONFINITE, "sources: non-finite position or direction");
+  try {
+    if (!c) return DG_EINVAL;
+    if (nsrc < 0 || (nsrc > 0 && (!xyz || !dir || !f0 || !t0 || !amp)))
+      return fail(c, DG_EINVAL, "sources: bad arguments");
+    if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
+    if (!c->has_mesh) return fail(c, DG_ESTATE, "sources: no mesh uploaded");
+    if (!c->has_mat) return fail(c, DG_ESTATE, "sources: no material uploaded");
+    std::vector<dg_ctx::Source> src(nsrc);
+    for (int i = 0; i < nsrc; ++i) {
+      for (int d = 0; d < 3; ++d) {
+        src[i].x[d] = xyz[3 * i + d];
+        src[i].d[d] = dir[3 * i + d];
+        if (!std::isfinite(src[i].x[d]) || !std::isfinite(src[i].d[d]))
+          return fail(c, DG_ENONFINITE, "sources: non-finite position or direction");
+      }
+      src[i].f0 = f0[i];
+      src[i].t0 = t0[i];
+      src[i].amp = amp[i];
+      if (!std::isfinite(f0[i]) || !std::isfinite(t0[i]) || !std::isfinite(amp[i]))
+        return fail(c, DG_ENONFINITE, "sources: non-finite wavelet parameter");
+      if (!(f0[i] > 0.0)) return fail(c, DG_EINVAL, "sources: need f0 > 0");
+      int64_t k;
+      double rst[3];
+      if (!dgh::locate_point(c->re, c->mesh, src[i].x, k, rst))
+        return fail(c, DG_EINVAL, "sources: point outside the mesh");
     }
-    src[i].f0 = f0[i];
-    src[i].t0 = t0[i];
-    src[i].amp = amp[i];
-    if (!std::isfinite(f0[i]) || !std::isfinite(t0[i]) || !std::isfinite(amp[i]))
-      return fail(c, DG_ENONFINITE, "sources: non-finite wavelet parameter");
-    if (!(f0[i] > 0.0)) return fail(c, DG_EINVAL, "sources: need f0 > 0");
-    int64_t k;
-    double rst[3];
-    if (!dgh::locate_point(c->re, c->mesh, src[i].x, k, rst))
-      return fail(c, DG_EINVAL, "sources: point outside the mesh");
+    dg_status s = set_device(c);
+    if (s != DG_OK) return s;
+    DG_HIP(c, hipStreamSynchronize(c->stream));   // the old arrays may be in use
+    drop_graphs(c);
+    c->src = std::move(src);
+    return upload_sources(c);
+  } catch (...) {
+    return exception_status();
   }
-  dg_status s = set_device(c);
-  if (s != DG_OK) return s;
-  DG_HIP(c, hipStreamSynchronize(c->stream));   // the old arrays may be in use
-  drop_graphs(c);
-  c->src = std::move(src);
-  return upload_sources(c);
 }
 
 dg_status dg_receivers_set(dg_ctx* c, int32_t nrec, const double* xyz) {
-  if (!c) return DG_EINVAL;
-  if (nrec < 0 || (nrec > 0 && !xyz)) return fail(c, DG_EINVAL, "receivers: bad arguments");
-  if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
-  if (!c->has_mesh) return fail(c, DG_ESTATE, "receivers: no mesh uploaded");
-  const int Np = c->re.Np;
-  std::vector<int64_t> elem(nrec);
-  std::vector<double> w(size_t(nrec) * Np), psi(Np);
-  for (int r = 0; r < nrec; ++r) {
-    for (int d = 0; d < 3; ++d)
-      if (!std::isfinite(xyz[3 * r + d]))
-        return fail(c, DG_ENONFINITE, "receivers: non-finite position");
-    double rst[3];
-    if (!dgh::locate_point(c->re, c->mesh, xyz + 3 * r, elem[r], rst))
-      return fail(c, DG_EINVAL, "receivers: point outside the mesh");
-    // Lagrange basis at the point: l = V^-T psi, i.e. solve V^T l = psi
-    dgh::basis_at(c->re, rst[0], rst[1], rst[2], psi.data());
-    std::vector<double> VT(size_t(Np) * Np), l(Np);
-    for (int i = 0; i < Np; ++i)
-      for (int j = 0; j < Np; ++j) VT[size_t(i) * Np + j] = c->re.V[size_t(j) * Np + i];
-    // Gaussian elimination with partial pivoting
-    std::vector<double> b(psi);
-    for (int col = 0; col < Np; ++col) {
-      int piv = col;
-      for (int i = col + 1; i < Np; ++i)
-        if (std::fabs(VT[size_t(i) * Np + col]) > std::fabs(VT[size_t(piv) * Np + col])) piv = i;
-      if (piv != col) {
-        for (int j = 0; j < Np; ++j) std::swap(VT[size_t(col) * Np + j], VT[size_t(piv) * Np + j]);
-        std::swap(b[col], b[piv]);
+  try {
+    if (!c) return DG_EINVAL;
+    if (nrec < 0 || (nrec > 0 && !xyz)) return fail(c, DG_EINVAL, "receivers: bad arguments");
+    if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
+    if (!c->has_mesh) return fail(c, DG_ESTATE, "receivers: no mesh uploaded");
+    const int Np = c->re.Np;
+    std::vector<int64_t> elem(nrec);
+    std::vector<double> w(size_t(nrec) * Np), psi(Np);
+    for (int r = 0; r < nrec; ++r) {
+      for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(xyz[3 * r + d]))
+          return fail(c, DG_ENONFINITE, "receivers: non-finite position");
+      double rst[3];
+      if (!dgh::locate_point(c->re, c->mesh, xyz + 3 * r, elem[r], rst))
+        return fail(c, DG_EINVAL, "receivers: point outside the mesh");
+      // Lagrange basis at the point: l = V^-T psi, i.e. solve V^T l = psi
+      dgh::basis_at(c->re, rst[0], rst[1], rst[2], psi.data());
+      std::vector<double> VT(size_t(Np) * Np), l(Np);
+      for (int i = 0; i < Np; ++i)
+        for (int j = 0; j < Np; ++j) VT[size_t(i) * Np + j] = c->re.V[size_t(j) * Np + i];
+      // Gaussian elimination with partial pivoting
+      std::vector<double> b(psi);
+      for (int col = 0; col < Np; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < Np; ++i)
+          if (std::fabs(VT[size_t(i) * Np + col]) > std::fabs(VT[size_t(piv) * Np + col])) piv = i;
+        if (piv != col) {
+          for (int j = 0; j < Np; ++j) std::swap(VT[size_t(col) * Np + j], VT[size_t(piv) * Np + j]);
+          std::swap(b[col], b[piv]);
+        }
+        for (int i = col + 1; i < Np; ++i) {
+          const double f = VT[size_t(i) * Np + col] / VT[size_t(col) * Np + col];
+          for (int j = col; j < Np; ++j) VT[size_t(i) * Np + j] -= f * VT[size_t(col) * Np + j];
+          b[i] -= f * b[col];
+        }
       }
-      for (int i = col + 1; i < Np; ++i) {
-        const double f = VT[size_t(i) * Np + col] / VT[size_t(col) * Np + col];
-        for (int j = col; j < Np; ++j) VT[size_t(i) * Np + j] -= f * VT[size_t(col) * Np + j];
-        b[i] -= f * b[col];
+      for (int i = Np - 1; i >= 0; --i) {
+        double acc = b[i];
+        for (int j = i + 1; j < Np; ++j) acc -= VT[size_t(i) * Np + j] * l[j];
+        l[i] = acc / VT[size_t(i) * Np + i];
       }
+      for (int n = 0; n < Np; ++n) w[size_t(r) * Np + n] = l[n];
     }
-    for (int i = Np - 1; i >= 0; --i) {
-      double acc = b[i];
-      for (int j = i + 1; j < Np; ++j) acc -= VT[size_t(i) * Np + j] * l[j];
-      l[i] = acc / VT[size_t(i) * Np + i];
-    }
-    for (int n = 0; n < Np; ++n) w[size_t(r) * Np + n] = l[n];
+    dg_status s = set_device(c);
+    if (s != DG_OK) return s;
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->nrec = 0;
+    c->trace_cap = 0;
+    for (DevBuf* b : {&c->rec_elem, &c->rec_w, &c->rec_buf, &c->trace}) release(c, *b);
+    if (nrec == 0) return DG_OK;
+    if ((s = upload_raw(c, c->rec_elem, elem.data(), elem.size())) != DG_OK) return s;
+    if ((s = upload_real(c, c->rec_w, w.data(), w.size())) != DG_OK) return s;
+    c->nrec = nrec;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  dg_status s = set_device(c);
-  if (s != DG_OK) return s;
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  drop_graphs(c);
-  c->nrec = 0;
-  c->trace_cap = 0;
-  for (DevBuf* b : {&c->rec_elem, &c->rec_w, &c->rec_buf, &c->trace}) release(c, *b);
-  if (nrec == 0) return DG_OK;
-  if ((s = upload_raw(c, c->rec_elem, elem.data(), elem.size())) != DG_OK) return s;
-  if ((s = upload_real(c, c->rec_w, w.data(), w.size())) != DG_OK) return s;
-  c->nrec = nrec;
-  return DG_OK;
 }
 
 dg_status dg_receivers_sample(dg_ctx* c, void* out, int32_t on_device) {
-  if (!c || !out) return DG_EINVAL;
-  dg_status s = ready(c, true);
-  if (s != DG_OK) return s;
-  if (c->nrec == 0) return fail(c, DG_ESTATE, "receivers: none set");
-  const size_t bytes = size_t(c->nrec) * 3 * c->elem;
-  if (on_device) return launch_receivers(c, out);
-  if (c->rec_buf.bytes < bytes && (s = alloc(c, c->rec_buf, bytes)) != DG_OK) return s;
-  if ((s = launch_receivers(c, c->rec_buf.p)) != DG_OK) return s;
-  DG_HIP(c, hipMemcpyAsync(out, c->rec_buf.p, bytes, hipMemcpyDeviceToHost, c->stream));
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  return DG_OK;
+  try {
+    if (!c || !out) return DG_EINVAL;
+    dg_status s = ready(c, true);
+    if (s != DG_OK) return s;
+    if (c->nrec == 0) return fail(c, DG_ESTATE, "receivers: none set");
+    const size_t bytes = size_t(c->nrec) * 3 * c->elem;
+    if (on_device) return launch_receivers(c, out);
+    if (c->rec_buf.bytes < bytes && (s = alloc(c, c->rec_buf, bytes)) != DG_OK) return s;
+    if ((s = launch_receivers(c, c->rec_buf.p)) != DG_OK) return s;
+    DG_HIP(c, hipMemcpyAsync(out, c->rec_buf.p, bytes, hipMemcpyDeviceToHost, c->stream));
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_run_record(dg_ctx* c, double t0, double dt, int64_t nsteps, void* trace,
                         int32_t on_device) {
-  if (!c || !trace) return DG_EINVAL;
-  if (nsteps < 0) return fail(c, DG_EINVAL, "run: negative step count");
-  dg_status s = ready(c, true);
-  if (s != DG_OK) return s;
-  if (c->nrec == 0) return fail(c, DG_ESTATE, "receivers: none set");
-  const size_t per = size_t(c->nrec) * 3 * c->elem;
-  char* dst = static_cast<char*>(trace);
-  if (!on_device) {
-    const size_t bytes = per * size_t(nsteps);
-    if (c->rec_buf.bytes < bytes && (s = alloc(c, c->rec_buf, bytes)) != DG_OK) return s;
-    dst = static_cast<char*>(c->rec_buf.p);
+  try {
+    if (!c || !trace) return DG_EINVAL;
+    if (nsteps < 0) return fail(c, DG_EINVAL, "run: negative step count");
+    dg_status s = ready(c, true);
+    if (s != DG_OK) return s;
+    if (c->nrec == 0) return fail(c, DG_ESTATE, "receivers: none set");
+    const size_t per = size_t(c->nrec) * 3 * c->elem;
+    char* dst = static_cast<char*>(trace);
+    if (!on_device) {
+      const size_t bytes = per * size_t(nsteps);
+      if (c->rec_buf.bytes < bytes && (s = alloc(c, c->rec_buf, bytes)) != DG_OK) return s;
+      dst = static_cast<char*>(c->rec_buf.p);
+    }
+    for (int64_t i = 0; i < nsteps; ++i) {
+      if ((s = dg_step(c, t0 + double(i) * dt, dt)) != DG_OK) return s;
+      if ((s = launch_receivers(c, dst + per * size_t(i))) != DG_OK) return s;
+    }
+    if (!on_device && nsteps > 0) {
+      DG_HIP(c, hipMemcpyAsync(trace, c->rec_buf.p, per * size_t(nsteps), hipMemcpyDeviceToHost,
+                               c->stream));
+      DG_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  for (int64_t i = 0; i < nsteps; ++i) {
-    if ((s = dg_step(c, t0 + double(i) * dt, dt)) != DG_OK) return s;
-    if ((s = launch_receivers(c, dst + per * size_t(i))) != DG_OK) return s;
-  }
-  if (!on_device && nsteps > 0) {
-    DG_HIP(c, hipMemcpyAsync(trace, c->rec_buf.p, per * size_t(nsteps), hipMemcpyDeviceToHost,
-                             c->stream));
-    DG_HIP(c, hipStreamSynchronize(c->stream));
-  }
-  return DG_OK;
 }
 
 dg_status dg_time_set(dg_ctx* c, double t) {
-  if (!c) return DG_EINVAL;
-  if (!std::isfinite(t)) return fail(c, DG_EINVAL, "time: non-finite");
-  dg_status s = ready(c, false);
-  if (s != DG_OK) return s;
-  dgs::clock_set<<<1, 64, 0, c->stream>>>(static_cast<double*>(c->clk.p), t);
-  DG_HIP(c, hipGetLastError());
-  return DG_OK;
+  try {
+    if (!c) return DG_EINVAL;
+    if (!std::isfinite(t)) return fail(c, DG_EINVAL, "time: non-finite");
+    dg_status s = ready(c, false);
+    if (s != DG_OK) return s;
+    dgs::clock_set<<<1, 64, 0, c->stream>>>(static_cast<double*>(c->clk.p), t);
+    DG_HIP(c, hipGetLastError());
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_time_get(dg_ctx* c, double* t, int64_t* step) {
-  if (!c) return DG_EINVAL;
-  dg_status s = ready(c, false);
-  if (s != DG_OK) return s;
-  double h[2];
-  DG_HIP(c, hipMemcpyAsync(h, c->clk.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  if (t) *t = h[0];
-  if (step) *step = int64_t(h[1]);
-  return DG_OK;
+  try {
+    if (!c) return DG_EINVAL;
+    dg_status s = ready(c, false);
+    if (s != DG_OK) return s;
+    double h[2];
+    DG_HIP(c, hipMemcpyAsync(h, c->clk.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    if (t) *t = h[0];
+    if (step) *step = int64_t(h[1]);
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_trace_reserve(dg_ctx* c, int64_t max_steps) {
-  if (!c) return DG_EINVAL;
-  if (max_steps < 0) return fail(c, DG_EINVAL, "trace: negative capacity");
-  if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
-  if (c->nrec == 0) return fail(c, DG_ESTATE, "trace: no receivers set");
-  dg_status s = set_device(c);
-  if (s != DG_OK) return s;
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  drop_graphs(c);
-  c->trace_cap = 0;
-  if ((s = alloc(c, c->trace, size_t(max_steps) * c->nrec * 3 * c->elem)) != DG_OK) return s;
-  c->trace_cap = max_steps;
-  return DG_OK;
+  try {
+    if (!c) return DG_EINVAL;
+    if (max_steps < 0) return fail(c, DG_EINVAL, "trace: negative capacity");
+    if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
+    if (c->nrec == 0) return fail(c, DG_ESTATE, "trace: no receivers set");
+    dg_status s = set_device(c);
+    if (s != DG_OK) return s;
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->trace_cap = 0;
+    if ((s = alloc(c, c->trace, size_t(max_steps) * c->nrec * 3 * c->elem)) != DG_OK) return s;
+    c->trace_cap = max_steps;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_trace_copy(dg_ctx* c, void* out, int64_t nrows) {
-  if (!c || !out) return DG_EINVAL;
-  if (nrows < 0 || nrows > c->trace_cap) return fail(c, DG_EINVAL, "trace: rows out of range");
-  dg_status s = set_device(c);
-  if (s != DG_OK) return s;
-  const size_t bytes = size_t(nrows) * c->nrec * 3 * c->elem;
-  if (bytes) DG_HIP(c, hipMemcpyAsync(out, c->trace.p, bytes, hipMemcpyDeviceToHost, c->stream));
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  return DG_OK;
+  try {
+    if (!c || !out) return DG_EINVAL;
+    if (nrows < 0 || nrows > c->trace_cap) return fail(c, DG_EINVAL, "trace: rows out of range");
+    dg_status s = set_device(c);
+    if (s != DG_OK) return s;
+    const size_t bytes = size_t(nrows) * c->nrec * 3 * c->elem;
+    if (bytes) DG_HIP(c, hipMemcpyAsync(out, c->trace.p, bytes, hipMemcpyDeviceToHost, c->stream));
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_advance(dg_ctx* c, double dt, int64_t nsteps) {
-  if (!c) return DG_EINVAL;
-  if (!std::isfinite(dt) || nsteps < 0) return fail(c, DG_EINVAL, "advance: bad dt or steps");
-  dg_status s = ready(c, true);
-  if (s != DG_OK) return s;
-  return advance_impl(c, dt, nsteps);
+  try {
+    if (!c) return DG_EINVAL;
+    if (!std::isfinite(dt) || nsteps < 0) return fail(c, DG_EINVAL, "advance: bad dt or steps");
+    dg_status s = ready(c, true);
+    if (s != DG_OK) return s;
+    return advance_impl(c, dt, nsteps);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_graph_advance(dg_ctx* c, double dt, int64_t nsteps) {
-  if (!c) return DG_EINVAL;
-  if (!std::isfinite(dt) || nsteps < 1) return fail(c, DG_EINVAL, "graph: bad dt or steps");
-  dg_status s = ready(c, true);
-  if (s != DG_OK) return s;
-  if (!c->stream) return fail(c, DG_ESTATE, "graph: the context needs its own stream");
-  const int cur0 = c->cur;
-  const int cur1 = int((cur0 + 5 * nsteps) & 1);
-  const dg_ctx::Graph* g = nullptr;
-  for (const auto& x : c->graphs)
-    if (x.dt == dt && x.nsteps == nsteps && x.cur == cur0) g = &x;
-  if (!g) {
-    hipGraph_t graph = nullptr;
-    // relaxed: other threads (other requests' set-up) keep calling HIP
-    DG_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-    s = advance_impl(c, dt, nsteps);
-    const hipError_t ec = hipStreamEndCapture(c->stream, &graph);
-    c->cur = cur0;   // capture recorded the launches without running them
-    if (s != DG_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return s;
+  try {
+    if (!c) return DG_EINVAL;
+    if (!std::isfinite(dt) || nsteps < 1) return fail(c, DG_EINVAL, "graph: bad dt or steps");
+    dg_status s = ready(c, true);
+    if (s != DG_OK) return s;
+    if (!c->stream) return fail(c, DG_ESTATE, "graph: the context needs its own stream");
+    const int cur0 = c->cur;
+    const int cur1 = int((cur0 + 5 * nsteps) & 1);
+    const dg_ctx::Graph* g = nullptr;
+    for (const auto& x : c->graphs)
+      if (x.dt == dt && x.nsteps == nsteps && x.cur == cur0) g = &x;
+    if (!g) {
+      hipGraph_t graph = nullptr;
+      // relaxed: other threads (other requests' set-up) keep calling HIP
+      DG_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+      s = advance_impl(c, dt, nsteps);
+      const hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+      c->cur = cur0;   // capture recorded the launches without running them
+      if (s != DG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+      }
+      if (ec != hipSuccess)
+        return fail(c, DG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess)
+        return fail(c, DG_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      c->graphs.push_back({dt, nsteps, cur0, exec});
+      g = &c->graphs.back();
     }
-    if (ec != hipSuccess)
-      return fail(c, DG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
-    hipGraphExec_t exec = nullptr;
-    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ei != hipSuccess)
-      return fail(c, DG_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
-    c->graphs.push_back({dt, nsteps, cur0, exec});
-    g = &c->graphs.back();
+    DG_HIP(c, hipGraphLaunch(g->exec, c->stream));
+    c->cur = cur1;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  DG_HIP(c, hipGraphLaunch(g->exec, c->stream));
-  c->cur = cur1;
-  return DG_OK;
 }
 
 dg_status dg_memory(const dg_ctx* c, uint64_t* bytes) {
-  if (!c || !bytes) return DG_EINVAL;
-  *bytes = c->allocated;
-  return DG_OK;
+  try {
+    if (!c || !bytes) return DG_EINVAL;
+    *bytes = c->allocated;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc, int32_t nrec,
                        int64_t trace_steps, uint64_t* bytes) {
-  if (!bytes || order < 1 || order > 7 || K < 1 || nsrc < 0 || nrec < 0 || trace_steps < 0)
-    return DG_EINVAL;
-  if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_FP32_BF16X3)
-    return DG_EINVAL;
-  if (precision == DG_FP32_BF16X3 && !dgh::mfma_supported(order)) return DG_EINVAL;
-  const uint64_t N = uint64_t(order), Np = (N + 1) * (N + 2) * (N + 3) / 6;
-  const uint64_t Nfp = (N + 1) * (N + 2) / 2, Nq = (N + 1) * (N + 1) * (N + 1), NF4 = 4 * Nfp;
-  const uint64_t NpP = 4 * ((Np + 3) / 4), QP = 32 * ((Nq + 31) / 32);
-  const uint64_t e = precision == DG_FP64 ? 8 : 4, k = uint64_t(K);
-  uint64_t b = 0;
-  b += (3 * Np * Np + Np * NF4 + Nq * Np + Np * Nq) * e;              // operators
-  b += (3 * Np * NpP + NF4 * NpP + Np * QP + QP * NpP) * e;           // transposed operators
-  b += NF4 * 4;                                                       // face masks
-  if (precision == DG_FP32_BF16X3) b += uint64_t(dgh::mfma_frag_count(order)) * 64 * 8 * 2;
-  else if (tiled_kernel(precision, order)) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 16;
-  b += k * (9 + 16) * e + k * 4 * 4 + k * 4 + 96 * Nfp * 4;          // geometry, tables
-  b += 3 * 9 * k * Np * e + 2 * sizeof(double);                      // q[2], res, clock
-  if (precision == DG_FP32_BF16X3 || tiled_kernel(precision, order))
-    b += k * NF4 * 4;                                                 // neighbour nodes
-  if (tiled_kernel(precision, order)) {
-    b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * 4;   // blocked material
-    b += (k + 15) / 16 * 4;                                           // tile order
+  try {
+    if (!bytes || order < 1 || order > 7 || K < 1 || nsrc < 0 || nrec < 0 || trace_steps < 0)
+      return DG_EINVAL;
+    if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_FP32_BF16X3)
+      return DG_EINVAL;
+    if (precision == DG_FP32_BF16X3 && !dgh::mfma_supported(order)) return DG_EINVAL;
+    const uint64_t N = uint64_t(order), Np = (N + 1) * (N + 2) * (N + 3) / 6;
+    const uint64_t Nfp = (N + 1) * (N + 2) / 2, Nq = (N + 1) * (N + 1) * (N + 1), NF4 = 4 * Nfp;
+    const uint64_t NpP = 4 * ((Np + 3) / 4), QP = 32 * ((Nq + 31) / 32);
+    const uint64_t e = precision == DG_FP64 ? 8 : 4, k = uint64_t(K);
+    uint64_t b = 0;
+    b += (3 * Np * Np + Np * NF4 + Nq * Np + Np * Nq) * e;              // operators
+    b += (3 * Np * NpP + NF4 * NpP + Np * QP + QP * NpP) * e;           // transposed operators
+    b += NF4 * 4;                                                       // face masks
+    if (precision == DG_FP32_BF16X3) b += uint64_t(dgh::mfma_frag_count(order)) * 64 * 8 * 2;
+    else if (tiled_kernel(precision, order)) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 16;
+    b += k * (9 + 16) * e + k * 4 * 4 + k * 4 + 96 * Nfp * 4;          // geometry, tables
+    b += 3 * 9 * k * Np * e + 2 * sizeof(double);                      // q[2], res, clock
+    if (precision == DG_FP32_BF16X3 || tiled_kernel(precision, order))
+      b += k * NF4 * 4;                                                 // neighbour nodes
+    if (tiled_kernel(precision, order)) {
+      b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * 4;   // blocked material
+      b += (k + 15) / 16 * 4;                                           // tile order
+    }
+    if (plain_material(precision, order)) b += 3 * k * Nq * e;          // 1/rho, lam, mu
+    b += 2 * k * Np * e;                                                // impedances
+    b += uint64_t(nsrc) * (8 + 3 * Np * e + 3 * 8);                     // sources
+    b += uint64_t(nrec) * (8 + Np * e) + uint64_t(trace_steps) * nrec * 3 * e;   // receivers
+    *bytes = b;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  if (plain_material(precision, order)) b += 3 * k * Nq * e;          // 1/rho, lam, mu
-  b += 2 * k * Np * e;                                                // impedances
-  b += uint64_t(nsrc) * (8 + 3 * Np * e + 3 * 8);                     // sources
-  b += uint64_t(nrec) * (8 + Np * e) + uint64_t(trace_steps) * nrec * 3 * e;   // receivers
-  *bytes = b;
-  return DG_OK;
 }
 
 dg_status dg_material_set_weights(dg_ctx* c, const double* irho_q, const double* lam_q,
                                   const double* mu_q, const double* zp_n, const double* zs_n) {
-  if (!c) return DG_EINVAL;
-  if (!c->has_mesh) return fail(c, DG_ESTATE, "weights: no mesh uploaded");
-  if (!irho_q || !lam_q || !mu_q || !zp_n || !zs_n) return fail(c, DG_EINVAL, "weights: null");
-  const int64_t K = c->mesh.K;
-  const size_t nq = size_t(K) * c->re.Nq, nn = size_t(K) * c->re.Np;
-  for (size_t i = 0; i < nq; ++i)
-    if (!std::isfinite(irho_q[i]) || !std::isfinite(lam_q[i]) || !std::isfinite(mu_q[i]))
-      return fail(c, DG_ENONFINITE, "weights: non-finite value");
-  for (size_t i = 0; i < nn; ++i) {
-    if (!std::isfinite(zp_n[i]) || !std::isfinite(zs_n[i]))
-      return fail(c, DG_ENONFINITE, "weights: non-finite impedance");
-    if (!(zp_n[i] > 0.0) || !(zs_n[i] > 0.0))
-      return fail(c, DG_EINVAL, "weights: impedances must be positive");
-  }
-  c->has_mat = false;
-  if (!device_ctx(c)) {
+  try {
+    if (!c) return DG_EINVAL;
+    if (!c->has_mesh) return fail(c, DG_ESTATE, "weights: no mesh uploaded");
+    if (!irho_q || !lam_q || !mu_q || !zp_n || !zs_n) return fail(c, DG_EINVAL, "weights: null");
+    const int64_t K = c->mesh.K;
+    const size_t nq = size_t(K) * c->re.Nq, nn = size_t(K) * c->re.Np;
+    for (size_t i = 0; i < nq; ++i)
+      if (!std::isfinite(irho_q[i]) || !std::isfinite(lam_q[i]) || !std::isfinite(mu_q[i]))
+        return fail(c, DG_ENONFINITE, "weights: non-finite value");
+    for (size_t i = 0; i < nn; ++i) {
+      if (!std::isfinite(zp_n[i]) || !std::isfinite(zs_n[i]))
+        return fail(c, DG_ENONFINITE, "weights: non-finite impedance");
+      if (!(zp_n[i] > 0.0) || !(zs_n[i] > 0.0))
+        return fail(c, DG_EINVAL, "weights: impedances must be positive");
+    }
+    c->has_mat = false;
+    if (!device_ctx(c)) {
+      c->has_mat = true;
+      return DG_OK;
+    }
+    dg_status s = set_device(c);
+    if (s != DG_OK) return s;
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    if (tiled_kernel(c->opt.precision, c->re.N)) {
+      const std::vector<double> blk = dgh::mfma_material(c->re.N, K, irho_q, lam_q, mu_q);
+      if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
+    }
+    if (plain_material(c->opt.precision, c->re.N)) {
+      if ((s = upload_real(c, c->irho, irho_q, nq)) != DG_OK) return s;
+      if ((s = upload_real(c, c->lam, lam_q, nq)) != DG_OK) return s;
+      if ((s = upload_real(c, c->mu, mu_q, nq)) != DG_OK) return s;
+    }
+    if ((s = upload_real(c, c->zp, zp_n, nn)) != DG_OK) return s;
+    if ((s = upload_real(c, c->zs, zs_n, nn)) != DG_OK) return s;
     c->has_mat = true;
+    drop_graphs(c);
+    if (!c->src.empty()) return upload_sources(c);
     return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  dg_status s = set_device(c);
-  if (s != DG_OK) return s;
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  if (tiled_kernel(c->opt.precision, c->re.N)) {
-    const std::vector<double> blk = dgh::mfma_material(c->re.N, K, irho_q, lam_q, mu_q);
-    if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
-  }
-  if (plain_material(c->opt.precision, c->re.N)) {
-    if ((s = upload_real(c, c->irho, irho_q, nq)) != DG_OK) return s;
-    if ((s = upload_real(c, c->lam, lam_q, nq)) != DG_OK) return s;
-    if ((s = upload_real(c, c->mu, mu_q, nq)) != DG_OK) return s;
-  }
-  if ((s = upload_real(c, c->zp, zp_n, nn)) != DG_OK) return s;
-  if ((s = upload_real(c, c->zs, zs_n, nn)) != DG_OK) return s;
-  c->has_mat = true;
-  drop_graphs(c);
-  if (!c->src.empty()) return upload_sources(c);
-  return DG_OK;
 }
 
 dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, int64_t every,
                              void* trace) {
-  if (!c || !trace) return DG_EINVAL;
-  if (!std::isfinite(t0) || !std::isfinite(dt) || nsteps < 1 || every < 1)
-    return fail(c, DG_EINVAL, "adjoint: bad t0, dt, step count or checkpoint interval");
-  dg_status s = ready(c, true);
-  if (s != DG_OK) return s;
-  if (c->opt.precision == DG_FP32_BF16X3)
-    return fail(c, DG_EINVAL, "adjoint: FP64 and FP32 contexts only");
-  if (c->nrec == 0) return fail(c, DG_ESTATE, "adjoint: no receivers set");
-  if ((s = adj_tables(c)) != DG_OK) return s;
-  const int64_t K = c->mesh.K, n = int64_t(9) * K * c->re.Np;
-  const int NF4 = 4 * c->re.Nfp, Nq = c->re.Nq;
-  const size_t S = size_t(n) * c->elem;
-  const int64_t nck = (nsteps + every - 1) / every;
-  const size_t tb = size_t(nsteps) * c->nrec * 3 * c->elem;
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  c->adj_ready = false;
-  struct Need {
-    DevBuf* b;
-    size_t bytes;
-  } need[] = {{&c->adj_ck, S * nck},
-              {&c->adj_seg, S * size_t(every)},
-              {&c->adj_y, S * 5},
-              {&c->adj_v, S * 6},
-              {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
-              {&c->adj_hb, size_t(K) * NF4 * 9 * c->elem},
-              {&c->adj_grad, size_t(K) * Nq * 3 * sizeof(double)},
-              {&c->adj_trace, tb}};
-  for (auto& x : need)
-    if (x.b->bytes != x.bytes && (s = alloc(c, *x.b, x.bytes)) != DG_OK) return s;
-  char* ck = static_cast<char*>(c->adj_ck.p);
-  char* tr = static_cast<char*>(c->adj_trace.p);
-  const size_t per = size_t(c->nrec) * 3 * c->elem;
-  for (int64_t i = 0; i < nsteps; ++i) {
-    if (i % every == 0)
-      DG_HIP(c, hipMemcpyAsync(ck + S * size_t(i / every), c->q[c->cur].p, S,
-                               hipMemcpyDeviceToDevice, c->stream));
-    if ((s = dg_step(c, t0 + double(i) * dt, dt)) != DG_OK) return s;
-    if ((s = launch_receivers(c, tr + per * size_t(i))) != DG_OK) return s;
+  try {
+    if (!c || !trace) return DG_EINVAL;
+    if (!std::isfinite(t0) || !std::isfinite(dt) || nsteps < 1 || every < 1)
+      return fail(c, DG_EINVAL, "adjoint: bad t0, dt, step count or checkpoint interval");
+    dg_status s = ready(c, true);
+    if (s != DG_OK) return s;
+    if (c->opt.precision == DG_FP32_BF16X3)
+      return fail(c, DG_EINVAL, "adjoint: FP64 and FP32 contexts only");
+    if (c->nrec == 0) return fail(c, DG_ESTATE, "adjoint: no receivers set");
+    if ((s = adj_tables(c)) != DG_OK) return s;
+    const int64_t K = c->mesh.K, n = int64_t(9) * K * c->re.Np;
+    const int NF4 = 4 * c->re.Nfp, Nq = c->re.Nq;
+    const size_t S = size_t(n) * c->elem;
+    const int64_t nck = (nsteps + every - 1) / every;
+    const size_t tb = size_t(nsteps) * c->nrec * 3 * c->elem;
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    c->adj_ready = false;
+    struct Need {
+      DevBuf* b;
+      size_t bytes;
+    } need[] = {{&c->adj_ck, S * nck},
+                {&c->adj_seg, S * size_t(every)},
+                {&c->adj_y, S * 5},
+                {&c->adj_v, S * 6},
+                {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
+                {&c->adj_hb, size_t(K) * NF4 * 9 * c->elem},
+                {&c->adj_grad, size_t(K) * Nq * 3 * sizeof(double)},
+                {&c->adj_trace, tb}};
+    for (auto& x : need)
+      if (x.b->bytes != x.bytes && (s = alloc(c, *x.b, x.bytes)) != DG_OK) return s;
+    char* ck = static_cast<char*>(c->adj_ck.p);
+    char* tr = static_cast<char*>(c->adj_trace.p);
+    const size_t per = size_t(c->nrec) * 3 * c->elem;
+    for (int64_t i = 0; i < nsteps; ++i) {
+      if (i % every == 0)
+        DG_HIP(c, hipMemcpyAsync(ck + S * size_t(i / every), c->q[c->cur].p, S,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      if ((s = dg_step(c, t0 + double(i) * dt, dt)) != DG_OK) return s;
+      if ((s = launch_receivers(c, tr + per * size_t(i))) != DG_OK) return s;
+    }
+    DG_HIP(c, copy_sync(c, trace, tr, tb, hipMemcpyDeviceToHost));
+    c->adj_t0 = t0;
+    c->adj_dt = dt;
+    c->adj_nsteps = nsteps;
+    c->adj_every = every;
+    c->adj_ready = true;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  DG_HIP(c, copy_sync(c, trace, tr, tb, hipMemcpyDeviceToHost));
-  c->adj_t0 = t0;
-  c->adj_dt = dt;
-  c->adj_nsteps = nsteps;
-  c->adj_every = every;
-  c->adj_ready = true;
-  return DG_OK;
 }
 
 dg_status dg_adjoint_backward(dg_ctx* c, const void* resid, double* grad) {
-  if (!c || !resid || !grad) return DG_EINVAL;
-  dg_status s = ready(c, true);
-  if (s != DG_OK) return s;
-  if (!c->adj_ready) return fail(c, DG_ESTATE, "adjoint: no checkpointed forward run");
-  const size_t tb = size_t(c->adj_nsteps) * c->nrec * 3 * c->elem;
-  DG_HIP(c, copy_sync(c, c->adj_trace.p, resid, tb, hipMemcpyHostToDevice));
-  // the sweep recomputes states in its own buffers: the context's state (the
-  // end of the forward run) is left as it is
-  if (c->elem == 8)
-    s = adj_backward_t<double>(c, static_cast<const double*>(c->adj_trace.p));
-  else
-    s = adj_backward_t<float>(c, static_cast<const float*>(c->adj_trace.p));
-  if (s != DG_OK) return s;
-  const size_t gb = size_t(c->mesh.K) * c->re.Nq * 3 * sizeof(double);
-  DG_HIP(c, copy_sync(c, grad, c->adj_grad.p, gb, hipMemcpyDeviceToHost));
-  return DG_OK;
+  try {
+    if (!c || !resid || !grad) return DG_EINVAL;
+    dg_status s = ready(c, true);
+    if (s != DG_OK) return s;
+    if (!c->adj_ready) return fail(c, DG_ESTATE, "adjoint: no checkpointed forward run");
+    const size_t tb = size_t(c->adj_nsteps) * c->nrec * 3 * c->elem;
+    DG_HIP(c, copy_sync(c, c->adj_trace.p, resid, tb, hipMemcpyHostToDevice));
+    // the sweep recomputes states in its own buffers: the context's state (the
+    // end of the forward run) is left as it is
+    if (c->elem == 8)
+      s = adj_backward_t<double>(c, static_cast<const double*>(c->adj_trace.p));
+    else
+      s = adj_backward_t<float>(c, static_cast<const float*>(c->adj_trace.p));
+    if (s != DG_OK) return s;
+    const size_t gb = size_t(c->mesh.K) * c->re.Nq * 3 * sizeof(double);
+    DG_HIP(c, copy_sync(c, grad, c->adj_grad.p, gb, hipMemcpyDeviceToHost));
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_synchronize(dg_ctx* c) {
-  if (!c) return DG_EINVAL;
-  dg_status s = set_device(c);
-  if (s != DG_OK) return s;
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  DG_HIP(c, hipGetLastError());
-  return DG_OK;
+  try {
+    if (!c) return DG_EINVAL;
+    dg_status s = set_device(c);
+    if (s != DG_OK) return s;
+    DG_HIP(c, hipStreamSynchronize(c->stream));
+    DG_HIP(c, hipGetLastError());
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_ref_operator(const dg_ctx* c, int32_t which, double* out) {
-  if (!c || !out) return DG_EINVAL;
-  const dgh::RefElement& re = c->re;
-  const std::vector<double>* src = nullptr;
-  switch (which) {
-    case 0: src = &re.Dr; break;
-    case 1: src = &re.Ds; break;
-    case 2: src = &re.Dt; break;
-    case 3: src = &re.LIFT; break;
-    case 4: src = &re.Vq; break;
-    case 5: src = &re.Pq; break;
-    case 6:
-      for (int i = 0; i < re.Np; ++i) {
-        out[i * 3 + 0] = re.r[i];
-        out[i * 3 + 1] = re.s[i];
-        out[i * 3 + 2] = re.t[i];
-      }
-      return DG_OK;
-    case 7:
-      for (int i = 0; i < re.Nq; ++i) {
-        out[i * 4 + 0] = re.rq[i];
-        out[i * 4 + 1] = re.sq[i];
-        out[i * 4 + 2] = re.tq[i];
-        out[i * 4 + 3] = re.wq[i];
-      }
-      return DG_OK;
-    default: return DG_EINVAL;
+  try {
+    if (!c || !out) return DG_EINVAL;
+    const dgh::RefElement& re = c->re;
+    const std::vector<double>* src = nullptr;
+    switch (which) {
+      case 0: src = &re.Dr; break;
+      case 1: src = &re.Ds; break;
+      case 2: src = &re.Dt; break;
+      case 3: src = &re.LIFT; break;
+      case 4: src = &re.Vq; break;
+      case 5: src = &re.Pq; break;
+      case 6:
+        for (int i = 0; i < re.Np; ++i) {
+          out[i * 3 + 0] = re.r[i];
+          out[i * 3 + 1] = re.s[i];
+          out[i * 3 + 2] = re.t[i];
+        }
+        return DG_OK;
+      case 7:
+        for (int i = 0; i < re.Nq; ++i) {
+          out[i * 4 + 0] = re.rq[i];
+          out[i * 4 + 1] = re.sq[i];
+          out[i * 4 + 2] = re.tq[i];
+          out[i * 4 + 3] = re.wq[i];
+        }
+        return DG_OK;
+      default: return DG_EINVAL;
+    }
+    std::memcpy(out, src->data(), src->size() * sizeof(double));
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  std::memcpy(out, src->data(), src->size() * sizeof(double));
-  return DG_OK;
 }
 
 dg_status dg_face_nodes(const dg_ctx* c, int32_t* fmask) {
-  if (!c || !fmask) return DG_EINVAL;
-  for (size_t i = 0; i < c->re.Fmask.size(); ++i) fmask[i] = c->re.Fmask[i];
-  return DG_OK;
+  try {
+    if (!c || !fmask) return DG_EINVAL;
+    for (size_t i = 0; i < c->re.Fmask.size(); ++i) fmask[i] = c->re.Fmask[i];
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_connectivity(const dg_ctx* c, int32_t* etoe, int32_t* etof, int32_t* nbnode) {
-  if (!c) return DG_EINVAL;
-  if (!c->has_mesh) return DG_ESTATE;
-  const dgh::MeshData& m = c->mesh;
-  const int Nfp = c->re.Nfp;
-  for (int64_t i = 0; i < m.K * 4; ++i) {
-    if (etoe) etoe[i] = m.EToE[i];
-    if (etof) etof[i] = m.EToF[i];
-    if (nbnode)
-      for (int j = 0; j < Nfp; ++j) nbnode[i * Nfp + j] = m.pat[size_t(m.EToP[i]) * Nfp + j];
+  try {
+    if (!c) return DG_EINVAL;
+    if (!c->has_mesh) return DG_ESTATE;
+    const dgh::MeshData& m = c->mesh;
+    const int Nfp = c->re.Nfp;
+    for (int64_t i = 0; i < m.K * 4; ++i) {
+      if (etoe) etoe[i] = m.EToE[i];
+      if (etof) etof[i] = m.EToF[i];
+      if (nbnode)
+        for (int j = 0; j < Nfp; ++j) nbnode[i * Nfp + j] = m.pat[size_t(m.EToP[i]) * Nfp + j];
+    }
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
   }
-  return DG_OK;
 }
 
 dg_status dg_tile_order(const dg_ctx* c, int32_t* out) {
-  if (!c || !out) return DG_EINVAL;
-  if (!c->has_mesh) return DG_ESTATE;
-  const std::vector<int32_t> t = dgh::tile_order(c->mesh, dgb::kTile, 8);
-  std::memcpy(out, t.data(), t.size() * sizeof(int32_t));
-  return DG_OK;
+  try {
+    if (!c || !out) return DG_EINVAL;
+    if (!c->has_mesh) return DG_ESTATE;
+    const std::vector<int32_t> t = dgh::tile_order(c->mesh, dgb::kTile, 8);
+    std::memcpy(out, t.data(), t.size() * sizeof(int32_t));
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 dg_status dg_geometry(const dg_ctx* c, double* geo, double* fgeo, double* J) {
-  if (!c) return DG_EINVAL;
-  if (!c->has_mesh) return DG_ESTATE;
-  const dgh::MeshData& m = c->mesh;
-  if (geo) std::memcpy(geo, m.geo.data(), m.geo.size() * sizeof(double));
-  if (fgeo) std::memcpy(fgeo, m.fgeo.data(), m.fgeo.size() * sizeof(double));
-  if (J) std::memcpy(J, m.J.data(), m.J.size() * sizeof(double));
-  return DG_OK;
+  try {
+    if (!c) return DG_EINVAL;
+    if (!c->has_mesh) return DG_ESTATE;
+    const dgh::MeshData& m = c->mesh;
+    if (geo) std::memcpy(geo, m.geo.data(), m.geo.size() * sizeof(double));
+    if (fgeo) std::memcpy(fgeo, m.fgeo.data(), m.fgeo.size() * sizeof(double));
+    if (J) std::memcpy(J, m.J.data(), m.J.size() * sizeof(double));
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 }  // extern "C"
