@@ -263,9 +263,18 @@ def order7_layered(args, steps=20):
     d = (states["bf16x3"] - states["fp64"]).reshape(9, -1)
     r = states["fp64"].reshape(9, -1)
     err = np.linalg.norm(d, axis=1) / np.linalg.norm(r, axis=1)
+    # matrix-core roofline: the dense contractions (D_r, D_s, D_t, LIFT, V_q,
+    # P_q over nine fields) of one element-stage, against the dense bf16 peak
+    # divided by the three products of a BF16x3 split product
+    Nfp, Nq = (N + 1) * (N + 2) // 2, (N + 1) ** 3
+    flop = 2 * 9 * (3 * Np * Np + Np * 4 * Nfp + 2 * Nq * Np)
+    achieved = flop * K / (res["bf16x3"]["ms_per_stage"] * 1e-3) / 1e12
+    peak = 2500.0 / 3.0
     return {"workload": f"N=7 (Np=120), {n}^3x6 = 82944 tets, 5 layers (interfaces inside "
                         f"elements, cp contrast 3x), smooth state, upwind, {steps} steps",
             "kernel": stage_kernel_name("bf16x3", N), "unit": "DOF-updates/s",
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak, "flop_per_element_stage": flop},
             "bf16x3": res["bf16x3"], "fp64_path": res["fp64"],
             "speedup_vs_fp64_path": res["bf16x3"]["value"] / res["fp64"]["value"],
             "rel_l2_vs_fp64_per_field": [float(x) for x in err]}
