@@ -108,11 +108,11 @@ def stage_kernel_name(precision, N):
     """The kernel one stage launches for this precision and order."""
     if precision == "bf16x3":
         return f"stage_bx<{N}>" if N <= 4 else f"stage_be<{N}>"
-    if precision == "fp32" and N <= 4:
-        return f"stage_bx<{N},f32>"
+    if precision == "fp32":
+        return f"stage_bx<{N},f32>" if N <= 4 else f"stage_be<{N},f32>"
     if N <= 4:
         return f"stage_cols<double,{N}>"
-    return f"stage_generic<{'double' if precision == 'fp64' else 'float'},{N}>"
+    return f"stage_generic<double,{N}>"
 
 
 def setup(args, precision, q0=None):

@@ -132,8 +132,11 @@ bool tiled_kernel(int32_t precision, int order) {
 bool plain_material(int32_t precision, int order) {
   return !(precision == DG_FP32_BF16X3 && order <= 4);
 }
+// Contexts whose stage runs on the matrix cores: BF16x3 and FP32 at every
+// order (the tiled kernel at orders 1-4, one element per workgroup at 5-7);
+// they read the neighbour-node table.
 bool tiled_mfma(const dg_ctx* c) {
-  return c->opt.precision == DG_FP32_BF16X3 || tiled_kernel(c->opt.precision, c->re.N);
+  return c->opt.precision == DG_FP32_BF16X3 || c->opt.precision == DG_FP32;
 }
 
 dg_status set_device(dg_ctx* c) {
@@ -345,7 +348,7 @@ hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res,
   return hipGetLastError();
 }
 
-template <int N>
+template <int N, bool F32>
 hipError_t launch_mfma_e(dg_ctx* c, const float* q_in, float* q_out, float* res, float* rhs_out,
                          double a, double b, double dt, int lsrk) {
   dgb::BeArgs A;
@@ -371,7 +374,7 @@ hipError_t launch_mfma_e(dg_ctx* c, const float* q_in, float* q_out, float* res,
   A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
   // one workgroup per element
   if (c->mesh.K > 0x7fffffff) return hipErrorInvalidValue;
-  dgb::stage_be<N><<<dim3(unsigned(c->mesh.K)), dim3(dgb::kThreads), 0, c->stream>>>(A);
+  dgb::stage_be<N, F32><<<dim3(unsigned(c->mesh.K)), dim3(dgb::kThreads), 0, c->stream>>>(A);
   return hipGetLastError();
 }
 
@@ -392,13 +395,16 @@ dg_status launch_mfma(dg_ctx* c, const void* q_in, void* q_out, void* res, void*
                     : launch_mfma_n<3, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
     case 4: e = f32 ? launch_mfma_n<4, true>(c, qi, qo, rs, ro, a, b, dt, lsrk)
                     : launch_mfma_n<4, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
-    case 5: e = launch_mfma_e<5>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
-    case 6: e = launch_mfma_e<6>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
-    case 7: e = launch_mfma_e<7>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 5: e = f32 ? launch_mfma_e<5, true>(c, qi, qo, rs, ro, a, b, dt, lsrk)
+                    : launch_mfma_e<5, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 6: e = f32 ? launch_mfma_e<6, true>(c, qi, qo, rs, ro, a, b, dt, lsrk)
+                    : launch_mfma_e<6, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
+    case 7: e = f32 ? launch_mfma_e<7, true>(c, qi, qo, rs, ro, a, b, dt, lsrk)
+                    : launch_mfma_e<7, false>(c, qi, qo, rs, ro, a, b, dt, lsrk); break;
     default: e = hipErrorInvalidValue;
   }
   if (e != hipSuccess)
-    return fail(c, DG_EDEVICE, std::string("BF16x3 stage launch: ") + hipGetErrorString(e));
+    return fail(c, DG_EDEVICE, std::string("matrix-core stage launch: ") + hipGetErrorString(e));
   return DG_OK;
 }
 
@@ -858,7 +864,7 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
           dg_destroy(c);
           return DG_ENOMEM;
         }
-      } else if (tiled_kernel(opt->precision, opt->order)) {
+      } else if (opt->precision == DG_FP32) {
         const std::vector<float> fr = dgh::mfma_fragments_f32(re);
         if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
           dg_destroy(c);
@@ -1476,10 +1482,10 @@ dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc
     b += (3 * Np * NpP + NF4 * NpP + Np * QP + QP * NpP) * e;           // transposed operators
     b += NF4 * 4;                                                       // face masks
     if (precision == DG_FP32_BF16X3) b += uint64_t(dgh::mfma_frag_count(order)) * 64 * 8 * 2;
-    else if (tiled_kernel(precision, order)) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 16;
+    else if (precision == DG_FP32) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 16;
     b += k * (9 + 16) * e + k * 4 * 4 + k * 4 + 96 * Nfp * 4;          // geometry, tables
     b += 3 * 9 * k * Np * e + 2 * sizeof(double);                      // q[2], res, clock
-    if (precision == DG_FP32_BF16X3 || tiled_kernel(precision, order))
+    if (precision == DG_FP32_BF16X3 || precision == DG_FP32)
       b += k * NF4 * 4;                                                 // neighbour nodes
     if (tiled_kernel(precision, order)) {
       b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * 4;   // blocked material

@@ -117,12 +117,48 @@ __device__ __forceinline__ void be_pipe(const BeArgs& A, int lane, Frag frag, BR
   }
 }
 
-template <int N>
+// FP32 variant (v_mfma_f32_16x16x4_f32, fragments in the layout of EFOrd):
+// K group s is 16 operator columns; lane (column e, group g) takes rows
+// 16 s + 4 j + g of column e as the B operand of the group's product j
+__device__ __forceinline__ void be_bread4(const float* buf, int s, int g, int e, float (&v)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = buf[(16 * s + 4 * j + g) * kCS + e];
+}
+
+template <int NS, int JS, typename Frag, typename BRead>
+__device__ __forceinline__ void be_pipe_f(const BeArgs& A, int lane, Frag frag, BRead bread,
+                                          f32x4 (&acc)[JS]) {
+  constexpr int NJ = NS * JS, P = kBePD < NJ ? kBePD : NJ;
+  const f32x4* fr = reinterpret_cast<const f32x4*>(A.frags);
+  f32x4 fa[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) fa[j] = fr[frag(j / JS, j % JS) * 64 + lane];
+  float vn[4], b[4];
+  bread(0, vn);
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int s = j / JS, i = j % JS;
+    if (i == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = vn[q];
+      if (s + 1 < NS) bread(s + 1, vn);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[i] = mma_f(fa[j % P][q], b[q], acc[i]);
+    if (j + P < NJ) fa[j % P] = fr[frag((j + P) / JS, (j + P) % JS) * 64 + lane];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int N, bool F32>
 __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
   using O = EOrd<N>;
+  using OF = EFOrd<N>;
   using L = BeLds<N>;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, Nq = O::Nq;
   constexpr int RT = O::RT, KN = O::KN, KF = O::KF, KQ = O::KQ, QT = O::QT;
+  static_assert(OF::RT == RT && OF::QT == QT && 16 * OF::KN <= L::NK && 16 * OF::KF <= L::FK &&
+                16 * OF::KQ <= 32 * KQ, "FP32 K groups within the zero-padded LDS rows");
   constexpr int NK = L::NK, FK = L::FK;
   constexpr int TW = (RT + 3) / 4;   // node tiles per wave (at most)
   constexpr int QW = (QT + 3) / 4;   // quadrature tiles per wave (at most)
@@ -205,10 +241,16 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
     f32x4 acc[3 * TW];
 #pragma unroll
     for (int i = 0; i < 3 * TW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    be_pipe<KN, 3 * TW>(
-        A, lane,
-        [&](int s, int i) { return O::OFF_D + (((i % 3) * RT + tn[i / 3]) * KN + s) * 2; },
-        [&](int s, float(&v)[8]) { be_bread(sq, s, g, e, v); }, acc);
+    if constexpr (F32)
+      be_pipe_f<OF::KN, 3 * TW>(
+          A, lane,
+          [&](int s, int i) { return OF::OFF_D + ((i % 3) * RT + tn[i / 3]) * OF::KN + s; },
+          [&](int s, float(&v)[4]) { be_bread4(sq, s, g, e, v); }, acc);
+    else
+      be_pipe<KN, 3 * TW>(
+          A, lane,
+          [&](int s, int i) { return O::OFF_D + (((i % 3) * RT + tn[i / 3]) * KN + s) * 2; },
+          [&](int s, float(&v)[8]) { be_bread(sq, s, g, e, v); }, acc);
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
       const int t = wave + 4 * i;
@@ -308,9 +350,14 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
         for (int j = 0; j < 4; ++j) acc[i][j] = sr[(16 * tn[i] + 4 * g + j) * kCS + e];
       }
     }
-    be_pipe<KF, TW>(
-        A, lane, [&](int s, int i) { return O::OFF_L + (tn[i] * KF + s) * 2; },
-        [&](int s, float(&v)[8]) { be_bread(sf, s, g, e, v); }, acc);
+    if constexpr (F32)
+      be_pipe_f<OF::KF, TW>(
+          A, lane, [&](int s, int i) { return OF::OFF_L + tn[i] * OF::KF + s; },
+          [&](int s, float(&v)[4]) { be_bread4(sf, s, g, e, v); }, acc);
+    else
+      be_pipe<KF, TW>(
+          A, lane, [&](int s, int i) { return O::OFF_L + (tn[i] * KF + s) * 2; },
+          [&](int s, float(&v)[8]) { be_bread(sf, s, g, e, v); }, acc);
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
       if (wave + 4 * i < RT) {
@@ -325,31 +372,8 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
   // weight-adjusted material operator: v rows times 1/rho, normal stresses
   // lam tr + 2 mu, shear stresses 2 mu
   {
-    bf16x8 bh[KN], bl[KN];
-#pragma unroll
-    for (int s = 0; s < KN; ++s) {
-      float v[8];
-      be_bread(sr, s, g, e, v);
-      split8(v, bh[s], bl[s]);
-    }
-    constexpr int NJ = QW * KN, P = kBePD < NJ ? kBePD : NJ;
-    auto frag = [&](int j) {
-      const int t = min(wave + 4 * (j / KN), QT - 1);
-      return O::OFF_V + (t * KN + j % KN) * 2;
-    };
-    u32x4 fh[P], fl[P];
-#pragma unroll
-    for (int j = 0; j < P; ++j) be_fload(A, frag(j), lane, fh[j], fl[j]);
-#pragma unroll
-    for (int u = 0; u < QW; ++u) {
-      f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < KN; ++s) {
-        const int j = u * KN + s;
-        w = mma3(fh[j % P], fl[j % P], bh[s], bl[s], w);
-        if (j + P < NJ) be_fload(A, frag(j + P), lane, fh[j % P], fl[j % P]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+    // the weight-adjusted material operator on tile u's V_q r (w) into sw
+    auto weigh = [&](int u, const f32x4& w) {
       const int t = wave + 4 * u;
       if (t < QT) {
 #pragma unroll
@@ -363,6 +387,62 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
           sw[p * kCS + e] = p < Nq ? v : 0.f;
         }
       }
+    };
+    if constexpr (F32) {
+      constexpr int KG = OF::KN;
+      float b[KG][4];
+#pragma unroll
+      for (int s = 0; s < KG; ++s) be_bread4(sr, s, g, e, b[s]);
+      constexpr int NJ = QW * KG, P = kBePD < NJ ? kBePD : NJ;
+      const f32x4* fr = reinterpret_cast<const f32x4*>(A.frags);
+      auto frag = [&](int j) {
+        const int t = min(wave + 4 * (j / KG), QT - 1);
+        return OF::OFF_V + t * KG + j % KG;
+      };
+      f32x4 fa[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) fa[j] = fr[frag(j) * 64 + lane];
+#pragma unroll
+      for (int u = 0; u < QW; ++u) {
+        f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KG; ++s) {
+          const int j = u * KG + s;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w = mma_f(fa[j % P][q], b[s][q], w);
+          if (j + P < NJ) fa[j % P] = fr[frag(j + P) * 64 + lane];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        weigh(u, w);
+      }
+    } else {
+      bf16x8 bh[KN], bl[KN];
+#pragma unroll
+      for (int s = 0; s < KN; ++s) {
+        float v[8];
+        be_bread(sr, s, g, e, v);
+        split8(v, bh[s], bl[s]);
+      }
+      constexpr int NJ = QW * KN, P = kBePD < NJ ? kBePD : NJ;
+      auto frag = [&](int j) {
+        const int t = min(wave + 4 * (j / KN), QT - 1);
+        return O::OFF_V + (t * KN + j % KN) * 2;
+      };
+      u32x4 fh[P], fl[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) be_fload(A, frag(j), lane, fh[j], fl[j]);
+#pragma unroll
+      for (int u = 0; u < QW; ++u) {
+        f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KN; ++s) {
+          const int j = u * KN + s;
+          w = mma3(fh[j % P], fl[j % P], bh[s], bl[s], w);
+          if (j + P < NJ) be_fload(A, frag(j + P), lane, fh[j % P], fl[j % P]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        weigh(u, w);
+      }
     }
   }
   __syncthreads();
@@ -373,9 +453,14 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
     f32x4 acc[TW];
 #pragma unroll
     for (int i = 0; i < TW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    be_pipe<KQ, TW>(
-        A, lane, [&](int s, int i) { return O::OFF_P + (tn[i] * KQ + s) * 2; },
-        [&](int s, float(&v)[8]) { be_bread(sw, s, g, e, v); }, acc);
+    if constexpr (F32)
+      be_pipe_f<OF::KQ, TW>(
+          A, lane, [&](int s, int i) { return OF::OFF_P + tn[i] * OF::KQ + s; },
+          [&](int s, float(&v)[4]) { be_bread4(sw, s, g, e, v); }, acc);
+    else
+      be_pipe<KQ, TW>(
+          A, lane, [&](int s, int i) { return O::OFF_P + (tn[i] * KQ + s) * 2; },
+          [&](int s, float(&v)[8]) { be_bread(sw, s, g, e, v); }, acc);
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
       const int t = wave + 4 * i;

@@ -110,3 +110,31 @@ struct FOrd {
 };
 
 }  // namespace dgb
+
+namespace dgb {
+
+// FP32 operator fragments of the orders 5-7 stage (v_mfma_f32_16x16x4_f32,
+// one element per workgroup, fields as the MFMA columns).  A K group is 16
+// operator columns: fragment (t, s) holds, for lane l, the float4 of rows
+// 16 t + l % 16 and columns 16 s + 4 j + l / 16 (j < 4), so that component
+// j is the A operand of the group's j-th 16x16x4 product.  Row tiles as in
+// EOrd; offsets in float4 units per 64 lanes.
+template <int N>
+struct EFOrd {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  static constexpr int NF4 = 4 * Nfp;
+  static constexpr int Nq = (N + 1) * (N + 1) * (N + 1);
+  static constexpr int RT = (Np + 15) / 16;         // node row tiles
+  static constexpr int QT = 2 * ((Nq + 31) / 32);   // quadrature row tiles (as EOrd)
+  static constexpr int KN = (Np + 15) / 16;         // K groups over nodes
+  static constexpr int KF = (NF4 + 15) / 16;        // K groups over face nodes
+  static constexpr int KQ = (Nq + 15) / 16;         // K groups over quadrature points
+  static constexpr int OFF_D = 0;                   // [3][RT][KN]
+  static constexpr int OFF_L = OFF_D + 3 * RT * KN; // [RT][KF]
+  static constexpr int OFF_V = OFF_L + RT * KF;     // V_q [QT][KN]
+  static constexpr int OFF_P = OFF_V + QT * KN;     // P_q [RT][KQ]
+  static constexpr int NFRAG = OFF_P + RT * KQ;
+};
+
+}  // namespace dgb

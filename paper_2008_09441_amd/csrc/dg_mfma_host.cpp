@@ -190,12 +190,43 @@ std::vector<uint16_t> mfma_fragments(const RefElement& re) {
   }
 }
 
+// FP32 fragments of the orders 5-7 stage in the layout of EFOrd
+template <int N>
+std::vector<float> build_frags_ef(const RefElement& re) {
+  using O = dgb::EFOrd<N>;
+  std::vector<float> out(size_t(O::NFRAG) * 64 * 4, 0.f);
+  auto put = [&](int frag, const std::vector<double>& M, int rows, int cols, int t, int s) {
+    for (int l = 0; l < 64; ++l)
+      for (int j = 0; j < 4; ++j) {
+        const int r = 16 * t + l % 16, k = 16 * s + 4 * j + l / 16;
+        out[(size_t(frag) * 64 + l) * 4 + j] =
+            (r < rows && k < cols) ? float(M[size_t(r) * cols + k]) : 0.f;
+      }
+  };
+  const int Np = O::Np, NF4 = O::NF4, Nq = O::Nq;
+  const std::vector<double>* D[3] = {&re.Dr, &re.Ds, &re.Dt};
+  for (int d = 0; d < 3; ++d)
+    for (int t = 0; t < O::RT; ++t)
+      for (int s = 0; s < O::KN; ++s)
+        put(O::OFF_D + (d * O::RT + t) * O::KN + s, *D[d], Np, Np, t, s);
+  for (int t = 0; t < O::RT; ++t)
+    for (int s = 0; s < O::KF; ++s) put(O::OFF_L + t * O::KF + s, re.LIFT, Np, NF4, t, s);
+  for (int t = 0; t < O::QT; ++t)
+    for (int s = 0; s < O::KN; ++s) put(O::OFF_V + t * O::KN + s, re.Vq, Nq, Np, t, s);
+  for (int t = 0; t < O::RT; ++t)
+    for (int s = 0; s < O::KQ; ++s) put(O::OFF_P + t * O::KQ + s, re.Pq, Np, Nq, t, s);
+  return out;
+}
+
 std::vector<float> mfma_fragments_f32(const RefElement& re) {
   switch (re.N) {
     case 1: return build_frags_f<1>(re);
     case 2: return build_frags_f<2>(re);
     case 3: return build_frags_f<3>(re);
-    default: return build_frags_f<4>(re);
+    case 4: return build_frags_f<4>(re);
+    case 5: return build_frags_ef<5>(re);
+    case 6: return build_frags_ef<6>(re);
+    default: return build_frags_ef<7>(re);
   }
 }
 
@@ -245,7 +276,10 @@ int mfma_f32_frag_count(int N) {
     case 1: return dgb::FOrd<1>::NF4S;
     case 2: return dgb::FOrd<2>::NF4S;
     case 3: return dgb::FOrd<3>::NF4S;
-    default: return dgb::FOrd<4>::NF4S;
+    case 4: return dgb::FOrd<4>::NF4S;
+    case 5: return dgb::EFOrd<5>::NFRAG * 64;
+    case 6: return dgb::EFOrd<6>::NFRAG * 64;
+    default: return dgb::EFOrd<7>::NFRAG * 64;
   }
 }
 

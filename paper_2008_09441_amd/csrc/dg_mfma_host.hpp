@@ -18,8 +18,9 @@ bool mfma_supported(int N);
 // lanes][8]
 std::vector<uint16_t> mfma_fragments(const RefElement& re);
 
-// FP32 operator fragments of the FP32 matrix-core stage (orders 1-4),
-// [NF4S][64 lanes][4] floats
+// FP32 operator fragments of the FP32 matrix-core stage: orders 1-4 in the
+// layout of FOrd ([NF4S][4] floats), orders 5-7 in that of EFOrd
+// ([NFRAG][64 lanes][4] floats)
 std::vector<float> mfma_fragments_f32(const RefElement& re);
 
 // Column-kernel operator pack: DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],
@@ -34,7 +35,7 @@ std::vector<double> mfma_material(int N, int64_t K, const double* irho, const do
 
 // fragment count and blocked-material floats per (tile, field) of order N
 int mfma_frag_count(int N);
-// float4 count of the FP32 fragments of order N (1-4)
+// float4 count of the FP32 fragments of order N (1-7)
 int mfma_f32_frag_count(int N);
 int mfma_mats(int N);
 

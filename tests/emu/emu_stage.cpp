@@ -188,7 +188,7 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
     return grid == -1 ? cols_dispatch<float>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk)
                       : cols_dispatch<double>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk);
   std::vector<uint16_t> fr = dgh::mfma_fragments(re);
-  if (N >= 5) {   // one element per workgroup
+  if (N >= 5) {   // one element per workgroup (grid 2: the FP32 kernel)
     dgb::BeArgs E{};
     float* qe = alloc<float>(9 * K * Np);
     std::memcpy(qe, q, sizeof(float) * 9 * K * Np);
@@ -203,12 +203,21 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
     E.fmask = dup(fme);
     E.irho = dupf(a); E.lam = dupf(b); E.mu = dupf(d);
     E.zp = dupf(zp); E.zs = dupf(zs);
-    E.frags = reinterpret_cast<const dgb::u32x4*>(dup(fr));
+    const bool fe = grid == 2;
+    if (fe) {
+      const std::vector<float> ff = dgh::mfma_fragments_f32(re);
+      E.frags = reinterpret_cast<const dgb::u32x4*>(dup(ff));
+    } else {
+      E.frags = reinterpret_cast<const dgb::u32x4*>(dup(fr));
+    }
     E.K = K; E.a = 0.f; E.b = 1.f; E.dt = 1.f; E.lsrk = lsrk; E.upwind = upwind;
     switch (N) {
-      case 5: run_grid(int(K), [=]() { dgb::stage_be<5>(E); }); break;
-      case 6: run_grid(int(K), [=]() { dgb::stage_be<6>(E); }); break;
-      default: run_grid(int(K), [=]() { dgb::stage_be<7>(E); }); break;
+      case 5: fe ? run_grid(int(K), [=]() { dgb::stage_be<5, true>(E); })
+                 : run_grid(int(K), [=]() { dgb::stage_be<5, false>(E); }); break;
+      case 6: fe ? run_grid(int(K), [=]() { dgb::stage_be<6, true>(E); })
+                 : run_grid(int(K), [=]() { dgb::stage_be<6, false>(E); }); break;
+      default: fe ? run_grid(int(K), [=]() { dgb::stage_be<7, true>(E); })
+                  : run_grid(int(K), [=]() { dgb::stage_be<7, false>(E); }); break;
     }
     for (int64_t i = 0; i < 9 * K * Np; ++i)
       out[i] = lsrk ? double(E.q_out[i]) - double(E.q_in[i]) : double(E.rhs_out[i]);

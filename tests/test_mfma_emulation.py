@@ -92,6 +92,16 @@ def test_fp32_matrix_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, 
     assert err.max() <= 2e-5
 
 
+@pytest.mark.parametrize("n,N,flux,lsrk", [(1, 5, "upwind", 0), (1, 6, "central", 0),
+                                           (1, 7, "upwind", 1), (1, 6, "upwind", 0)])
+def test_fp32_matrix_kernel_orders_5_to_7(emu_exe, tmp_path, n, N, flux, lsrk):
+    """The FP32 matrix-core kernel of orders 5-7 (one element per workgroup,
+    v_mfma_f32_16x16x4_f32), the last case on the odd-count mesh."""
+    err = _run(emu_exe, tmp_path, n, N, flux, grid=2, lsrk=lsrk, split=(flux == "upwind" and N == 6))
+    print("per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 2e-5
+
+
 def test_fp32_matrix_kernel_odd_element_count(emu_exe, tmp_path):
     err = _run(emu_exe, tmp_path, 2, 4, "upwind", grid=2, split=True)
     assert err.max() <= 2e-5
