@@ -206,8 +206,9 @@ hipError_t launch_generic(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* r
                           double a, double b, double dt, int lsrk) {
   const dgh::RefElement& re = c->re;
   dgk::StageArgs<T> A;
-  const T* ops = static_cast<const T*>(c->ops.p);
-  const size_t np2 = size_t(re.Np) * re.Np;
+  // the transposed pack DrT | DsT | DtT | LIFTT | VqT | PqT
+  const T* ops = static_cast<const T*>(c->opsT.p);
+  const size_t NpP = 4 * size_t((re.Np + 3) / 4), QP = 32 * size_t((re.Nq + 31) / 32);
   A.q_in = q_in;
   A.q_out = q_out;
   A.res = res;
@@ -223,12 +224,12 @@ hipError_t launch_generic(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* r
   A.mu = static_cast<const T*>(c->mu.p);
   A.zp = static_cast<const T*>(c->zp.p);
   A.zs = static_cast<const T*>(c->zs.p);
-  A.Dr = ops;
-  A.Ds = ops + np2;
-  A.Dt = ops + 2 * np2;
-  A.LIFT = ops + 3 * np2;
-  A.Vq = A.LIFT + size_t(re.Np) * 4 * re.Nfp;
-  A.Pq = A.Vq + size_t(re.Nq) * re.Np;
+  A.DrT = ops;
+  A.DsT = ops + size_t(re.Np) * NpP;
+  A.DtT = ops + 2 * size_t(re.Np) * NpP;
+  A.LIFTT = ops + 3 * size_t(re.Np) * NpP;
+  A.VqT = A.LIFTT + size_t(4 * re.Nfp) * NpP;
+  A.PqT = A.VqT + size_t(re.Np) * QP;
   A.K = c->mesh.K;
   A.a = T(a);
   A.b = T(b);
@@ -282,38 +283,28 @@ hipError_t launch_cols(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_stage_t(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_out,
-                          double a, double b, double dt, int lsrk) {
-  // FP32 at orders 1-4 runs on the matrix-core kernel (launch_mfma)
-  if constexpr (sizeof(T) == 8) {
-    switch (c->re.N) {
-      case 1: return launch_cols<T, 1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-      case 2: return launch_cols<T, 2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-      case 3: return launch_cols<T, 3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-      case 4: return launch_cols<T, 4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-      default: break;
-    }
-  }
+// FP64 contexts: the column kernel at orders 1-4, the generic kernel at 5-7
+// (FP32 and BF16x3 contexts run on the matrix cores, launch_mfma)
+hipError_t launch_stage_f64(const dg_ctx* c, const double* q_in, double* q_out, double* res,
+                            double* rhs_out, double a, double b, double dt, int lsrk) {
   switch (c->re.N) {
-    case 5: return launch_generic<T, 5>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 6: return launch_generic<T, 6>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 7: return launch_generic<T, 7>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 1: return launch_cols<double, 1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 2: return launch_cols<double, 2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 3: return launch_cols<double, 3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 4: return launch_cols<double, 4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 5: return launch_generic<double, 5>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 6: return launch_generic<double, 6>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 7: return launch_generic<double, 7>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     default: return hipErrorInvalidValue;
   }
 }
 
 dg_status launch_stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void* rhs_out,
                        double a, double b, double dt, int lsrk) {
-  hipError_t e;
-  if (c->elem == 8)
-    e = launch_stage_t<double>(c, static_cast<const double*>(q_in),
-                               static_cast<double*>(q_out), static_cast<double*>(res),
-                               static_cast<double*>(rhs_out), a, b, dt, lsrk);
-  else
-    e = launch_stage_t<float>(c, static_cast<const float*>(q_in), static_cast<float*>(q_out),
-                              static_cast<float*>(res), static_cast<float*>(rhs_out), a, b,
-                              dt, lsrk);
+  if (c->elem != 8) return fail(c, DG_EDEVICE, "stage launch: not an FP64 context");
+  const hipError_t e = launch_stage_f64(
+      c, static_cast<const double*>(q_in), static_cast<double*>(q_out),
+      static_cast<double*>(res), static_cast<double*>(rhs_out), a, b, dt, lsrk);
   if (e != hipSuccess) return fail(c, DG_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
   return DG_OK;
 }

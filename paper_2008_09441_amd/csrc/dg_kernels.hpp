@@ -71,13 +71,14 @@ struct StageArgs {
   const T* mu;
   const T* zp;        // [K][Np]
   const T* zs;
-  // operators
-  const T* Dr;        // [Np][Np]
-  const T* Ds;
-  const T* Dt;
-  const T* LIFT;      // [Np][4 Nfp]
-  const T* Vq;        // [Nq][Np]
-  const T* Pq;        // [Np][Nq]
+  // transposed operators (zero padded, NpP = 4 ceil(Np/4), QP = 32 ceil(Nq/32)),
+  // so that threads over output rows read consecutive entries:
+  const T* DrT;       // [Np][NpP]: DrT[m][n] = Dr[n][m]
+  const T* DsT;
+  const T* DtT;
+  const T* LIFTT;     // [4 Nfp][NpP]
+  const T* VqT;       // [Np][QP]
+  const T* PqT;       // [QP][NpP]
   int64_t K;
   T a, b, dt;
   int lsrk;           // 0: write rhs_out; 1: fused LSRK update
@@ -88,6 +89,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(kBlock) void stage_generic(StageArgs<T> A) {
   using O = Order<N>;
   constexpr int Np = O::Np, Nfp = O::Nfp, Nq = O::Nq, NF4 = O::NF4;
+  constexpr int NpP = 4 * ((Np + 3) / 4), QP = 32 * ((Nq + 31) / 32);
   constexpr int E = elems_per_block<T, N>();
   __shared__ __align__(16) unsigned char smem_raw[lds_bytes<T, N>()];
   T* sq = reinterpret_cast<T*>(smem_raw);   // [9][E][Np]
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void stage_generic(StageArgs<T> A) {
 #pragma unroll
     for (int f = 0; f < kNF; ++f) dq[0][f] = dq[1][f] = dq[2][f] = T(0);
     for (int m = 0; m < Np; ++m) {
-      const T dr = A.Dr[n * Np + m], ds = A.Ds[n * Np + m], dt = A.Dt[n * Np + m];
+      const T dr = A.DrT[m * NpP + n], ds = A.DsT[m * NpP + n], dt = A.DtT[m * NpP + n];
 #pragma unroll
       for (int f = 0; f < kNF; ++f) {
         const T v = sq[(f * E + e) * Np + m];
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void stage_generic(StageArgs<T> A) {
 #pragma unroll
     for (int f = 0; f < kNF; ++f) acc[f] = sr[(f * E + e) * Np + n];
     for (int j = 0; j < NF4; ++j) {
-      const T l = A.LIFT[n * NF4 + j];
+      const T l = A.LIFTT[j * NpP + n];
 #pragma unroll
       for (int f = 0; f < kNF; ++f) acc[f] += l * sb[(f * E + e) * NF4 + j];
     }
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void stage_generic(StageArgs<T> A) {
 #pragma unroll
     for (int f = 0; f < kNF; ++f) v[f] = T(0);
     for (int n = 0; n < Np; ++n) {
-      const T w = A.Vq[qp * Np + n];
+      const T w = A.VqT[n * QP + qp];
 #pragma unroll
       for (int f = 0; f < kNF; ++f) v[f] += w * sr[(f * E + e) * Np + n];
     }
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void stage_generic(StageArgs<T> A) {
 #pragma unroll
     for (int f = 0; f < kNF; ++f) acc[f] = T(0);
     for (int qp = 0; qp < Nq; ++qp) {
-      const T p = A.Pq[n * Nq + qp];
+      const T p = A.PqT[qp * NpP + n];
 #pragma unroll
       for (int f = 0; f < kNF; ++f) acc[f] += p * sb[(f * E + e) * Nq + qp];
     }
