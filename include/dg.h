@@ -53,11 +53,17 @@ typedef enum {
   DG_ENONFINITE = 5   /* non-finite input                              */
 } dg_status;
 
+/* DG_FP64: FP64 state and arithmetic (the column kernel at orders 1-4, the
+ * generic kernel at 5-7).  DG_FP32: FP32 state and arithmetic, with the
+ * dense contractions on the FP32 matrix cores (16x16x4 products).
+ * DG_FP32_BF16X3: FP32 state, the dense contractions as split products of
+ * bf16 hi/lo parts on the matrix cores with FP32 accumulation (three
+ * products each, about 2^-16 relative error per product). */
 typedef enum { DG_FP64 = 0, DG_FP32 = 1, DG_FP32_BF16X3 = 2 } dg_precision;
 typedef enum { DG_FLUX_UPWIND = 0, DG_FLUX_CENTRAL = 1 } dg_flux;
 
 typedef struct {
-  int32_t order;             /* N, 1..7 (DG_FP32_BF16X3: 1..4, else DG_EINVAL)   */
+  int32_t order;             /* N, 1..7 (else DG_EINVAL)                         */
   int32_t precision;         /* dg_precision                                     */
   int32_t flux;              /* dg_flux                                          */
   int32_t device;            /* HIP device ordinal; -1 = host-only (no GPU work) */
