@@ -480,15 +480,14 @@ def main():
         out["fp32_path"] = {"value": dofs * args.steps / sec32,
                             "ms_per_step": sec32 / args.steps * 1e3,
                             "kernel": stage_kernel_name("fp32", N)}
-        if N <= 4:
-            # FP32 matrix cores: dense contraction flops of an element-stage
-            # (D_r, D_s, D_t, LIFT, V_q, P_q over nine fields) per launch
-            Np, Nfp, Nq = (N + 1) * (N + 2) * (N + 3) // 6, (N + 1) * (N + 2) // 2, (N + 1) ** 3
-            flop = 2 * 9 * (3 * Np * Np + Np * 4 * Nfp + 2 * Nq * Np)
-            a32 = flop * K / (sec32 / (5 * args.steps)) / 1e12
-            out["fp32_path"]["roofline"] = {"bound": "mfma", "achieved": a32, "peak": 157.3,
-                                            "unit": "TFLOP/s", "frac": a32 / 157.3,
-                                            "flop_per_element_stage": flop}
+        # FP32 matrix cores: dense contraction flops of an element-stage
+        # (D_r, D_s, D_t, LIFT, V_q, P_q over nine fields) per launch
+        Np, Nfp, Nq = (N + 1) * (N + 2) * (N + 3) // 6, (N + 1) * (N + 2) // 2, (N + 1) ** 3
+        flop = 2 * 9 * (3 * Np * Np + Np * 4 * Nfp + 2 * Nq * Np)
+        a32 = flop * K / (sec32 / (5 * args.steps)) / 1e12
+        out["fp32_path"]["roofline"] = {"bound": "mfma", "achieved": a32, "peak": 157.3,
+                                        "unit": "TFLOP/s", "frac": a32 / 157.3,
+                                        "flop_per_element_stage": flop}
     if not args.no_fp64_reference and args.precision != "fp64":
         sec64, q64 = other_path("fp64")
         out["fp64_path"] = {"value": dofs * args.steps / sec64,
