@@ -1,5 +1,7 @@
-// Device kernels of the DG elastic-wave stage: generic LDS-staged kernel
-// (FP64 and FP32), templated on the order N.
+// Device kernels of the FP64 DG elastic-wave stage: the generic LDS-staged
+// kernel (orders 5-7), templated on the order N, and the column kernel
+// (orders 1-4) below.  FP32 and BF16x3 stages run on the matrix cores
+// (dg_bx.hpp, dg_be.hpp).
 //
 // One workgroup owns a block of E consecutive elements and runs the whole
 // stage for them in six phases separated by workgroup barriers:
@@ -300,7 +302,7 @@ __global__ void fill_kernel(T* p, int64_t n, T v) {
 namespace dgk {
 
 // --------------------------------------------------------------------------
-// Column kernel (orders 1-4, FP32 and FP64).  A workgroup of four waves owns
+// Column kernel (orders 1-4, FP64).  A workgroup of four waves owns
 // E = 7 CPL elements; lane l < 63 of every wave owns the output component
 // c = l / 7 of the CPL elements e = l % 7 + 7 p (p < CPL), and each wave owns
 // a block of operator rows, so that every dense contraction is a chain of
@@ -336,11 +338,6 @@ struct ColOrder {
 template <typename T>
 constexpr int col_sets() { return 1; }
 
-// FP32 stages the operators of the current phase in LDS (read as
-// wave-uniform broadcasts); FP64 reads them through the scalar cache
-template <typename T>
-constexpr bool ops_in_lds() { return sizeof(T) == 4; }
-
 template <typename T, int N>
 struct ColLayout {
   using O = Order<N>;
@@ -351,12 +348,10 @@ struct ColLayout {
   static constexpr int SR = 9 * E * O::Np;
   static constexpr int SW = 9 * E * kColQS;
   static constexpr int SG = E * 9;
-  // [sq | sg | union(sF, (sr | sw)) | operators of the current phase]
+  // [sq | sg | union(sF, (sr | sw))]; the operators are read through the
+  // scalar cache
   static constexpr int SU = SF > SR + SW ? SF : SR + SW;
-  static constexpr int OPS_C = (3 * O::Np + O::NF4) * ColOrder<N>::NpP;      // DrT|DsT|DtT|LIFTT
-  static constexpr int OPS_D = O::Np * ColOrder<N>::QP + ColOrder<N>::QP * ColOrder<N>::NpP;
-  static constexpr int SO = ops_in_lds<T>() ? (OPS_C > OPS_D ? OPS_C : OPS_D) : 0;
-  static constexpr int LDS_USED = (SQ + SG + SU + SO) * int(sizeof(T));
+  static constexpr int LDS_USED = (SQ + SG + SU) * int(sizeof(T));
   // Padded so that the workgroups one CU can hold (160 KiB of LDS) never use
   // more than 128 KiB together (at most 3 per CU at >40 KiB each, or 2 at
   // >53.3 KiB each): the largest per-CU LDS footprint any kernel of this
@@ -396,6 +391,7 @@ struct ColArgs {
 
 template <typename T, int N>
 __global__ __launch_bounds__(kBlock) void stage_cols(ColArgs<T> A) {
+  static_assert(sizeof(T) == 8, "the column kernel is the FP64 stage");
   using O = Order<N>;
   using CO = ColOrder<N>;
   using L = ColLayout<T, N>;
@@ -410,7 +406,6 @@ __global__ __launch_bounds__(kBlock) void stage_cols(ColArgs<T> A) {
   T* sF = su;                               // [9][E][NFS]     (phases B, C)
   T* sr = su;                               // [9][E][Np]      (phase D)
   T* sw = su + L::SR;                       // [9][E][QS]      (phase D)
-  T* so = su + L::SU;                       // operators of phase C / D (FP32)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -430,8 +425,6 @@ __global__ __launch_bounds__(kBlock) void stage_cols(ColArgs<T> A) {
   }
   for (int idx = tid; idx < E * 9; idx += kBlock)
     sg[idx] = (idx / 9 < ne) ? A.geo[e0 * 9 + idx] : T(0);
-  if (ops_in_lds<T>())   // DrT|DsT|DtT|LIFTT are contiguous
-    for (int idx = tid; idx < L::OPS_C; idx += kBlock) so[idx] = A.DrT[idx];
   __syncthreads();
 
   // B: face fluxes
@@ -497,10 +490,10 @@ __global__ __launch_bounds__(kBlock) void stage_cols(ColArgs<T> A) {
 
   // C: volume + lift for the wave's node rows, columns (ce + 7 p, cc)
   const int n0 = wave * RN;
-  const T* oDr = ops_in_lds<T>() ? so : A.DrT;
-  const T* oDs = ops_in_lds<T>() ? so + Np * NpP : A.DsT;
-  const T* oDt = ops_in_lds<T>() ? so + 2 * Np * NpP : A.DtT;
-  const T* oLf = ops_in_lds<T>() ? so + 3 * Np * NpP : A.LIFTT;
+  const T* oDr = A.DrT;
+  const T* oDs = A.DsT;
+  const T* oDt = A.DtT;
+  const T* oLf = A.LIFTT;
   T acc[CPL][RN];
 #pragma unroll
   for (int p = 0; p < CPL; ++p)
@@ -569,11 +562,9 @@ __global__ __launch_bounds__(kBlock) void stage_cols(ColArgs<T> A) {
       for (int i = 0; i < RN; ++i)
         if (n0 + i < Np) sr[(cc * E + ce + kColW * p) * Np + n0 + i] = acc[p][i];
   }
-  if (ops_in_lds<T>())   // VqT|PqT are contiguous
-    for (int idx = tid; idx < L::OPS_D; idx += kBlock) so[idx] = A.VqT[idx];
   __syncthreads();
-  const T* oVq = ops_in_lds<T>() ? so : A.VqT;
-  const T* oPq = ops_in_lds<T>() ? so + Np * QP : A.PqT;
+  const T* oVq = A.VqT;
+  const T* oPq = A.PqT;
 
   // D: quadrature chunks: V_q -> material -> P_q (accumulated in acc)
 #pragma unroll

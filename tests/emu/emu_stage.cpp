@@ -185,8 +185,8 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
   }
   for (int64_t i = 0; i < K * Np; ++i) { zp[i] = rho_n[i] * cp_n[i]; zs[i] = rho_n[i] * cs_n[i]; }
   if (grid < 0)
-    return grid == -1 ? cols_dispatch<float>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk)
-                      : cols_dispatch<double>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk);
+    return grid == -2 ? cols_dispatch<double>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk)
+                      : 3;
   std::vector<uint16_t> fr = dgh::mfma_fragments(re);
   if (N >= 5) {   // one element per workgroup (grid 2: the FP32 kernel)
     dgb::BeArgs E{};
@@ -260,7 +260,7 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
 }
 
 // input file: int32 N, flux_upwind, kernel (1: BF16x3 matrix-core kernel, 2:
-// FP32 matrix-core kernel; -1 / -2: column kernel in FP32 / FP64), lsrk; int64 K; then float64
+// FP32 matrix-core kernel; -2: the FP64 column kernel), lsrk; int64 K; then float64
 // vxyz[K*12], period[3], rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n
 // [K*Np each]; then float32 q[9*K*Np]
 int main(int argc, char** argv) {
