@@ -89,7 +89,7 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     p.add_argument("--no-order7", action="store_true",
                    help="skip the order-7 layered-media measurement")
-    p.add_argument("--adjoint-steps", type=int, default=100)
+    p.add_argument("--adjoint-steps", type=int, default=400)
     p.add_argument("--serving-requests", type=int, default=64)
     p.add_argument("--serving-rate", type=float, default=3.0, help="arrivals per second")
     p.add_argument("--serving-full", action="store_true",
@@ -354,7 +354,7 @@ def adjoint(args):
     B.dg_adjoint_backward(s.ctx, resid, g)
     t_bwd = time.perf_counter() - t0
     delta = rng.standard_normal(m.shape) * m
-    eps = 1e-3
+    eps = 1e-2   # FP32 misfits: a larger step keeps the quotient's rounding error down
     fd = (0.5 * np.sum((J(m + eps * delta) - d) ** 2)
           - 0.5 * np.sum((J(m - eps * delta) - d) ** 2)) / (2 * eps)
     an = float(np.sum(g * delta))
