@@ -806,6 +806,7 @@ dg_status exception_status() {
 extern "C" {
 
 dg_status dg_create(dg_ctx** out, const dg_options* opt) {
+  dg_ctx* c = nullptr;   // freed here if an exception escapes the set-up
   try {
     if (!out) return DG_EINVAL;
     *out = nullptr;
@@ -816,7 +817,7 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
       return DG_EINVAL;
     if (opt->flux != DG_FLUX_UPWIND && opt->flux != DG_FLUX_CENTRAL) return DG_EINVAL;
     if (opt->precision == DG_FP32_BF16X3 && !dgh::mfma_supported(opt->order)) return DG_EINVAL;
-    dg_ctx* c = new (std::nothrow) dg_ctx();
+    c = new (std::nothrow) dg_ctx();
     if (!c) return DG_ENOMEM;
     c->opt = *opt;
     c->elem = (opt->precision == DG_FP64) ? 8 : 4;
@@ -866,7 +867,10 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
     *out = c;
     return DG_OK;
   } catch (...) {
-    return exception_status();
+    const dg_status st = exception_status();
+    if (c) dg_destroy(c);
+    if (out) *out = nullptr;
+    return st;
   }
 }
 
