@@ -97,6 +97,7 @@ def parse():
     p.add_argument("--serving-precisions", default="fp32,bf16x3",
                    help="comma-separated precisions of the serving measurement")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-peaks", action="store_true", help="skip the copy and GEMM peak measurement")
     p.add_argument("--cpu-sample-n", type=int, default=12)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="before timing, run a fill, a sum and a copy of 256 MiB so that "
@@ -368,6 +369,43 @@ def adjoint(args):
             "rel_diff_vs_central_difference": abs(fd - an) / max(abs(fd), 1e-300)}
 
 
+def measured_peaks():
+    """The box's achievable rates, beside the published peaks the rooflines
+    use: a device-to-device copy of 2 GiB (bytes read plus written per
+    second) and a dense 8192^3 bf16 GEMM through torch (the library GEMM on
+    the matrix cores), each timed over ten repetitions with HIP events."""
+    import torch
+    st = torch.cuda.current_stream(0)
+
+    def timed(fn, reps=10):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    x = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    copy_gbps = 2 * x.numel() * 4 / timed(lambda: y.copy_(x)) / 1e9
+    del x, y
+    n = 8192
+    a = torch.randn(n, n, dtype=torch.bfloat16, device="cuda:0")
+    b = torch.randn(n, n, dtype=torch.bfloat16, device="cuda:0")
+    gemm_tflops = 2 * n ** 3 / timed(lambda: torch.matmul(a, b)) / 1e12
+    del a, b
+    torch.cuda.empty_cache()
+    return {"hbm_copy_GBps": copy_gbps, "bf16_gemm_TFLOPs": gemm_tflops,
+            "published": {"hbm_GBps": 8000.0, "bf16_dense_TFLOPs": 2500.0},
+            "method": "2 GiB device copy; 8192^3 bf16 torch.matmul; HIP events over 10 reps"}
+
+
 def cpu_baseline(args, N):
     """The oracle (FP64 NumPy, untuned) on a bounded sample: one LSRK(5,4)
     step on the n_s^3 x 6 periodic cube with the same order, media and
@@ -507,6 +545,10 @@ def main():
             out["serving" if prec == "fp32" else f"serving_{prec}"] = serving(args, prec)
     if not args.no_adjoint:
         out["adjoint"] = adjoint(args)
+    if not args.no_peaks:
+        out["peaks_measured"] = measured_peaks()
+        out["roofline"]["frac_of_measured_copy"] = (
+            out["roofline"]["achieved"] / out["peaks_measured"]["hbm_copy_GBps"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, N)
     print(json.dumps(out), flush=True)
