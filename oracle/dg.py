@@ -30,11 +30,19 @@ Semi-discrete operator, per element, in the order computed below:
 Time integration: LSRK(5,4) [CK94], five stages of
     res <- a_s res + dt F(q, t + c_s dt);   q <- q + b_s res.
 
-Pins (tests/test_oracle_pins.py, tests/test_oracle_physics.py): exact plane
-P and S waves, convergence order N+1, skew-symmetry (central) and
-negative-semidefiniteness (upwind) of the energy-weighted assembled operator,
-WADG reducing to the constant-coefficient operator in homogeneous media,
-momentum conservation, the LSRK stability polynomial and order.
+Pins (tests/test_oracle_pins.py, tests/test_oracle_physics.py,
+tests/test_oracle_riemann.py): exact plane P and S waves, convergence order
+N+1, skew-symmetry (central) and negative-semidefiniteness (upwind) of the
+energy-weighted assembled operator, also with the impedance jumping across
+every face, WADG reducing to the constant-coefficient operator in
+homogeneous media, momentum conservation, the LSRK stability polynomial and
+order.  Where Z- != Z+ the upwind flux is pinned by the Riemann problem it
+solves: the interface state is single-valued, each side's jump satisfies
+that side's wave relation, and normal incidence transmits the closed-form
+state.
+
+This module is test infrastructure: only the tests, the smoke check and the
+benchmark's CPU baseline use it.
 """
 from __future__ import annotations
 
@@ -141,9 +149,13 @@ class ElasticDG:
         r[8] = 0.5 * (dy[vx] + dx[vy])
         return r
 
-    def surface(self, q, elems):
-        """Steps 2-3: face flux at every face node, scaled and lifted."""
-        ref, m, mat = self.ref, self.mesh, self.mat
+    def face_flux(self, q, elems):
+        """Step 2: the numerical flux f[9, k, 4, Nfp] at every face node of
+        the elements `elems`, before the Fscale scaling: rows 0-2 are the
+        traction correction dt, rows 3-8 the Voigt components of
+        sym(dv (x) n).  (dv, dt) is the jump from this side's trace to the
+        state the face's Riemann problem leaves at the interface [WSG10]."""
+        m, mat = self.mesh, self.mat
         qf = q.reshape(NF, -1)
         iM = m.vmapM[elems]                                  # [k, 4, Nfp]
         iP = m.vmapP[elems]
@@ -185,9 +197,13 @@ class ElasticDG:
         f[6] = 0.5 * (dv[1] * nv[2] + dv[2] * nv[1])
         f[7] = 0.5 * (dv[0] * nv[2] + dv[2] * nv[0])
         f[8] = 0.5 * (dv[0] * nv[1] + dv[1] * nv[0])
-        f = f * m.Fscale[elems][None, :, :, None]
+        return f
+
+    def surface(self, q, elems):
+        """Step 3: the face flux scaled by Fscale and lifted to the nodes."""
+        f = self.face_flux(q, elems) * self.mesh.Fscale[elems][None, :, :, None]
         k = f.shape[1]
-        return f.reshape(NF, k, -1) @ ref.LIFT.T             # [9, k, Np]
+        return f.reshape(NF, k, -1) @ self.ref.LIFT.T        # [9, k, Np]
 
     def wadg(self, r, elems):
         """Step 4: weight-adjusted mass inverse."""

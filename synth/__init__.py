@@ -222,3 +222,23 @@ def split_tet_vertices(vx, k=0):
     out[k] = subs[0]
     return out
 
+
+
+def element_constant_params(K, seed=12):
+    """Per-element (rho, cp, cs) of element-constant media: rho ~ U[1, 3],
+    cp ~ U[2, 4], cs = cp / U[1.6, 2.0], one draw per element, so that the
+    material jumps across every face."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(1.0, 3.0, K)
+    cp = rng.uniform(2.0, 4.0, K)
+    cs = cp / rng.uniform(1.6, 2.0, K)
+    return rho, cp, cs
+
+
+def element_constant_samples(K, Nq, Np, seed=12):
+    """Element-constant media repeated at every quadrature point [K, Nq] and
+    every node [K, Np]: (rho_q, cp_q, cs_q, rho_n, cp_n, cs_n)."""
+    rho, cp, cs = element_constant_params(K, seed)
+    at_q = [np.repeat(a[:, None], Nq, axis=1) for a in (rho, cp, cs)]
+    at_n = [np.repeat(a[:, None], Np, axis=1) for a in (rho, cp, cs)]
+    return (*at_q, *at_n)

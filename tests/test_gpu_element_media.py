@@ -22,13 +22,8 @@ def _need_gpu():
 def _pair(n, N, precision):
     from paper_2008_09441_amd import B, Solver
     op = ElasticDG(n, N, synth.homogeneous_media, flux="upwind")
-    rng = np.random.default_rng(12)
-    rho = rng.uniform(1.0, 3.0, op.K)
-    cp = rng.uniform(2.0, 4.0, op.K)
-    cs = cp / rng.uniform(1.6, 2.0, op.K)
-    Nq = op.ref.Nq
-    arrs_q = [np.repeat(a[:, None], Nq, axis=1) for a in (rho, cp, cs)]
-    arrs_n = [np.repeat(a[:, None], op.Np, axis=1) for a in (rho, cp, cs)]
+    samples = synth.element_constant_samples(op.K, op.ref.Nq, op.Np, seed=12)
+    arrs_q, arrs_n = samples[:3], samples[3:]
     op.mat = material_from_samples(*arrs_q, *arrs_n)
     s = Solver(N, precision=precision, flux="upwind", device=0)
     s.upload_mesh(synth.kuhn_cube_vertices(n))

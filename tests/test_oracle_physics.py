@@ -3,6 +3,8 @@ waves, convergence order, the semi-discrete energy identity, homogeneous
 reductions, conservation, basis independence and the LSRK(5,4) stability
 polynomial.  Each pin fails for a plausible mistake (see
 test_oracle_mutations.py, which plants such mistakes and checks that)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -147,22 +149,47 @@ def test_plane_p_wave_order3_cube4_T05():
     assert err < 1e-2
 
 
-@pytest.mark.parametrize("wave", ["p", "s"])
-def test_convergence_order_N_plus_1(wave):
-    """Fully discrete plane waves at N=2, n = 2, 4, 8 to T = 0.1: observed
-    order close to N+1 = 3."""
+def _plane_wave_errors(wave, N, ns, T=0.1):
+    """Relative L2 error against the exact plane wave after LSRK(5,4) to T
+    at CFL 0.5, on the n^3 x 6 cubes of `ns` (homogeneous, upwind)."""
     fun = synth.plane_p_wave if wave == "p" else synth.plane_s_wave
     errs = []
-    T = 0.1
-    for n in (2, 4, 8):
-        op = ElasticDG(n, 2, synth.homogeneous_media)
+    for n in ns:
+        op = ElasticDG(n, N, synth.homogeneous_media)
         q0 = op.project_function(lambda x: fun(x, 0.0))
-        dt, ns = op.cfl_dt(T)
-        q = op.run(q0, 0.0, dt, ns)
+        dt, nst = op.cfl_dt(T)
+        q = op.run(q0, 0.0, dt, nst)
         qe = op.project_function(lambda x: fun(x, T))
         errs.append(np.sqrt(op.l2_sq(q - qe).sum() / op.l2_sq(qe).sum()))
-    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
-    assert rates[-1] > 2.6, (errs, rates)
+    return np.array(errs)
+
+
+@pytest.mark.parametrize("wave", ["p", "s"])
+def test_convergence_order_N_plus_1(wave):
+    """PA2 at N = 3: plane P and S waves on n = 2, 4, 8 to T = 0.1.  The
+    observed order between n = 4 and n = 8 is close to N + 1 = 4 (measured
+    3.79 for P, 3.77 for S); n = 2 is pre-asymptotic for the S wave."""
+    errs = _plane_wave_errors(wave, 3, (2, 4, 8))
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert rates[-1] >= 3.7, (errs, rates)
+    assert np.all(rates > 2.5), (errs, rates)
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(not os.environ.get("DG_SLOW_PINS"),
+                    reason="about 13 minutes per wave on 8 cores; set DG_SLOW_PINS=1")
+@pytest.mark.parametrize("wave", ["p", "s"])
+def test_convergence_order_N_plus_1_to_n16(wave):
+    """PA2 as stated, N = 3 and n = 2, 4, 8, 16 (24,576 tets at n = 16).
+    Measured errors: P 9.26e-2, 6.62e-3, 4.79e-4, 3.09e-5 (least-squares
+    slope 3.84, finest pair 3.95); S 7.34e-2, 1.10e-2, 8.03e-4, 5.93e-5
+    (slope over n = 4-16: 3.77)."""
+    errs = _plane_wave_errors(wave, 3, (2, 4, 8, 16))
+    h = 1.0 / np.array([2.0, 4.0, 8.0, 16.0])
+    fine = np.polyfit(np.log(h[1:]), np.log(errs[1:]), 1)[0]
+    assert fine >= 3.7, errs
+    if wave == "p":
+        assert np.polyfit(np.log(h), np.log(errs), 1)[0] >= 3.8, errs
 
 
 def test_basis_independence():
