@@ -184,6 +184,74 @@ class QuadNorm:
                 "rel_per_field_of_group": [float(x) for x in np.sqrt(e2 / grp)]}
 
 
+# Stated bounds of the reduced-precision paths against the FP64 GPU path on
+# the order-4 workload, in the energy measure of EnergyNorm.errors: each
+# field's error over the energy norm of the FP64 state, at any step count up
+# to 200 steps.
+ENERGY_BOUND = {"fp32": 1e-6, "bf16x3": 1e-5}
+
+
+class EnergyNorm:
+    """Errors measured in the elastic energy norm, which the solution keeps
+    (upwind: does not increase) at every step, so a bound stated in it holds
+    at any step count:
+
+        ||q||_E^2 = sum_k J_k sum_q w_q (rho |v|^2 + sigma : C^-1 : sigma)(x_q),
+        sigma : C^-1 : sigma = (sigma : sigma - lam / (3 lam + 2 mu) tr(sigma)^2) / (2 mu),
+
+    evaluated at the quadrature points (V_q applied to each field).  A
+    field's error is scaled the same way, rho e^2 for a velocity and
+    d_f e^2 / (2 mu) for a stress (d_f = 1 for normal, 2 for shear
+    components; an upper bound of its share since lam >= 0 here), and
+    divided by the energy norm of the reference state.  Evaluated on the GPU
+    in FP64 with torch (a measurement, not part of the path)."""
+
+    def __init__(self, s, rho_q, cp_q, cs_q):
+        import torch
+        from paper_2008_09441_amd import B
+        dev = torch.device("cuda:0")
+        self.Vq = torch.from_numpy(B.dg_ref_operator(s.ctx, 4)).to(dev)        # [Nq, Np]
+        w = torch.from_numpy(B.dg_ref_operator(s.ctx, 7)[:, 3].copy()).to(dev)
+        _, _, J = B.dg_geometry(s.ctx)
+        self.W = torch.from_numpy(J).to(dev)[:, None] * w[None, :]             # [K, Nq]
+        rho = torch.from_numpy(np.asarray(rho_q)).to(dev)
+        cp = torch.from_numpy(np.asarray(cp_q)).to(dev)
+        cs = torch.from_numpy(np.asarray(cs_q)).to(dev)
+        mu = rho * cs * cs
+        lam = rho * cp * cp - 2.0 * mu
+        self.rho = rho
+        self.inv2mu = 0.5 / mu
+        self.kappa = lam / (3.0 * lam + 2.0 * mu)
+
+    def _at_q(self, q, f):
+        import torch
+        return torch.from_numpy(np.ascontiguousarray(q[f], dtype=np.float64)).to(
+            self.Vq.device) @ self.Vq.T
+
+    def energy_sq(self, q):
+        v2 = sum(self._at_q(q, f) ** 2 for f in range(3))
+        s = [self._at_q(q, f) for f in range(3, 9)]
+        ss = s[0] ** 2 + s[1] ** 2 + s[2] ** 2 + 2.0 * (s[3] ** 2 + s[4] ** 2 + s[5] ** 2)
+        tr = s[0] + s[1] + s[2]
+        e = self.rho * v2 + self.inv2mu * (ss - self.kappa * tr * tr)
+        return float((self.W * e).sum())
+
+    def field_sq(self, e):
+        out = []
+        for f in range(9):
+            x = self._at_q(e, f) ** 2
+            wt = self.rho if f < 3 else self.inv2mu * (1.0 if f < 6 else 2.0)
+            out.append(float((self.W * wt * x).sum()))
+        return np.array(out)
+
+    def errors(self, q, ref, precision):
+        rel = np.sqrt(self.field_sq(q - ref) / self.energy_sq(ref))
+        bound = ENERGY_BOUND[precision]
+        return {"rel_per_field_of_energy": [float(x) for x in rel],
+                "max": float(rel.max()), "bound": bound,
+                "within_bound": bool(rel.max() <= bound)}
+
+
 def sources_receivers(args, steps=50):
     """The order-4 Kuhn cube of 24^3 x 6 tets with Fourier media, 4 Ricker
     point forces and 64 receivers: DOF-updates/s of the recorded run
@@ -312,12 +380,15 @@ def serving(args, precision="fp32"):
 
 
 def adjoint(args):
-    """Gradient of an L2 receiver misfit with respect to the weight-adjusted
-    material weights (1/rho, lam, mu at the quadrature points): order 4 on
+    """Gradient of an L2 receiver misfit with respect to the material fields
+    rho, lam, mu (at the quadrature points and at the nodes): order 4 on
     24^3 x 6 tets, smooth random media, 4 Ricker forces, 64 receivers,
-    checkpoint every 20 steps, FP32.  Times the checkpointed forward run and
-    the reverse sweep; the gradient is checked against a central difference
-    of the same GPU run along one random direction."""
+    checkpoint every 20 steps, FP32, upwind.  libdg returns dJ/dm for the
+    weight-adjusted weights m = (1/rho, lam, mu) and dJ/d(Zp, Zs) for the
+    flux impedances; the field gradient follows by the chain rule.  Times
+    the checkpointed forward run and the reverse sweep; the directional
+    derivative is checked against a central difference of the same GPU run
+    that perturbs the fields (weights and impedances recomputed)."""
     import synth
     from paper_2008_09441_amd import B, Solver
     n, N, steps, every = 24, 4, args.adjoint_steps, 20
@@ -326,8 +397,13 @@ def adjoint(args):
     xq, xn = s.quad_coords(), s.node_coords()
     rq, pq, sq = synth.fourier_media(xq, seed=77)
     rn, pn, sn = synth.fourier_media(xn, seed=77)
-    m = np.stack([1.0 / rq, rq * (pq ** 2 - 2 * sq ** 2), rq * sq ** 2])
-    zp, zs = rn * pn, rn * sn
+    P = [rq, rq * (pq ** 2 - 2 * sq ** 2), rq * sq ** 2, rn, rn * (pn ** 2 - 2 * sn ** 2),
+         rn * sn ** 2]
+
+    def weights(PP):
+        a, b, c, d_, e, f = PP
+        return np.stack([1.0 / a, b, c]), np.sqrt(d_ * (e + 2 * f)), np.sqrt(d_ * f)
+    m, zp, zs = weights(P)
     del xq, xn
     K, Np, _, Nq = s.sizes()
     rng = np.random.default_rng(5)
@@ -339,30 +415,38 @@ def adjoint(args):
     zero = np.zeros((9, K, Np), np.float32)
     tr = np.empty((steps, 64, 3), np.float32)
 
-    def J(mm):
-        B.dg_material_set_weights(s.ctx, mm[0], mm[1], mm[2], zp, zs)
+    def J(PP):
+        mm, zzp, zzs = weights(PP)
+        B.dg_material_set_weights(s.ctx, mm[0], mm[1], mm[2], zzp, zzs)
         s.set_state(zero)
         B.dg_adjoint_forward(s.ctx, 0.0, dt, steps, every, tr)
         return tr.astype(np.float64)
-    d = 0.5 * J(m)                                 # synthetic data: half the signal
+    d = 0.5 * J(P)                                 # synthetic data: half the signal
     s.set_state(zero)
     t0 = time.perf_counter()
     B.dg_adjoint_forward(s.ctx, 0.0, dt, steps, every, tr)
     t_fwd = time.perf_counter() - t0
     resid = (tr.astype(np.float64) - d).astype(np.float32)
     g = np.empty((3, K, Nq))
+    gz = np.empty((2, K, Np))
     t0 = time.perf_counter()
-    B.dg_adjoint_backward(s.ctx, resid, g)
+    B.dg_adjoint_backward(s.ctx, resid, g, gz)
     t_bwd = time.perf_counter() - t0
-    delta = rng.standard_normal(m.shape) * m
+    a_, b_, c_, d_, e_, f_ = P
+    gP = [-g[0] / a_ ** 2, g[1], g[2],
+          gz[0] * (e_ + 2 * f_) / (2 * zp) + gz[1] * f_ / (2 * zs),
+          gz[0] * d_ / (2 * zp), gz[0] * d_ / zp + gz[1] * d_ / (2 * zs)]
+    dP = [rng.standard_normal(p.shape) * p * 0.1 for p in P]
     eps = 1e-2   # FP32 misfits: a larger step keeps the quotient's rounding error down
-    fd = (0.5 * np.sum((J(m + eps * delta) - d) ** 2)
-          - 0.5 * np.sum((J(m - eps * delta) - d) ** 2)) / (2 * eps)
-    an = float(np.sum(g * delta))
+    fd = (0.5 * np.sum((J([p + eps * q for p, q in zip(P, dP)]) - d) ** 2)
+          - 0.5 * np.sum((J([p - eps * q for p, q in zip(P, dP)]) - d) ** 2)) / (2 * eps)
+    an = float(sum(np.sum(x * y) for x, y in zip(gP, dP)))
     s.close()
     dofs = 9 * K * Np * steps
     return {"workload": f"N={N}, {n}^3x6 = {K} tets, smooth random media, 4 Ricker forces, "
-                        f"64 receivers, {steps} LSRK steps, checkpoint every {every}, fp32",
+                        f"64 receivers, {steps} LSRK steps, checkpoint every {every}, fp32, "
+                        "upwind; gradient in rho, lam, mu at the quadrature points and nodes "
+                        "(weights and flux impedances)",
             "forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
             "adjoint_dof_updates_per_s": dofs / t_bwd,
             "directional_derivative": an, "central_difference": fd,
@@ -536,6 +620,19 @@ def main():
         out["l2_vs_fp64"] = {"norm": "quadrature L2 after warmup+steps", **norm.errors(q_lo, q64)}
         if "fp32_path" in out:
             out["fp32_path"]["l2_vs_fp64"] = norm.errors(q32, q64)
+        from paper_2008_09441_amd import Solver
+        sq = Solver(N, precision="fp64", flux="upwind", device=-1)   # host tables only
+        sq.upload_mesh(__import__("synth").kuhn_cube_vertices(n))
+        en = EnergyNorm(sq, *cache["media"][:3])
+        sq.close()
+        if args.precision in ENERGY_BOUND:
+            out["l2_vs_fp64"]["energy"] = en.errors(q_lo, q64, args.precision)
+            out["within_bound"] = out["l2_vs_fp64"]["energy"]["within_bound"]
+        if "fp32_path" in out:
+            out["fp32_path"]["l2_vs_fp64"]["energy"] = en.errors(q32, q64, "fp32")
+            out["fp32_path"]["within_bound"] = out["fp32_path"]["l2_vs_fp64"]["energy"]["within_bound"]
+        del en
+        torch.cuda.empty_cache()
     if not args.no_sources:
         out["sources_receivers"] = sources_receivers(args)
     if not args.no_order7:

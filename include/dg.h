@@ -219,10 +219,12 @@ dg_status dg_advance(dg_ctx* ctx, double dt, int64_t nsteps);
 dg_status dg_graph_advance(dg_ctx* ctx, double dt, int64_t nsteps);
 
 /* ---- Discrete adjoint ---------------------------------------------------
- * Gradient of a receiver misfit with respect to the weight-adjusted
- * material weights m = (1/rho, lam, mu) at the quadrature points, holding
- * the flux impedances fixed [CHW17, C18].  FP64 and FP32 contexts
- * (DG_EINVAL for DG_FP32_BF16X3). */
+ * Gradient of a receiver misfit with respect to the material: the
+ * weight-adjusted weights m = (1/rho, lam, mu) at the quadrature points
+ * [CHW17, C18] and, for the upwind flux, the impedances Zp = rho cp and
+ * Zs = rho cs at the nodes that the exact-Riemann flux reads [WSG10]; a
+ * gradient with respect to rho, lam, mu fields follows by the chain rule.
+ * FP64 and FP32 contexts (DG_EINVAL for DG_FP32_BF16X3). */
 
 /* Set the weights directly: 1/rho, lam, mu host [K][Nq], impedances Zp, Zs
  * host [K][Np] (all copied).  Errors: DG_ESTATE before the mesh,
@@ -236,8 +238,9 @@ dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const doubl
  * [nsteps][nrec][3], working precision).  Leaves the context at the end of
  * the run.  Needs receivers (DG_ESTATE).  Library-owned device memory:
  * ceil(nsteps/every) + every + 11 states plus two face-node work arrays
- * [K][4 Nfp][9] and the FP64 gradient [3][K][Nq], counted against the HBM
- * budget. */
+ * [K][4 Nfp][9] and the FP64 gradient [3][K][Nq] (upwind: also [K][4 Nfp][4]
+ * impedance terms and the FP64 gradient [2][K][Np]), counted against the
+ * HBM budget. */
 dg_status dg_adjoint_forward(dg_ctx* ctx, double t0, double dt, int64_t nsteps, int64_t every,
                              void* trace);
 
@@ -246,9 +249,13 @@ dg_status dg_adjoint_forward(dg_ctx* ctx, double t0, double dt, int64_t nsteps, 
  * discrete adjoint of every stage (transposed weight-adjusted inverse,
  * transposed volume, flux and LIFT operators, receiver adjoint), with the
  * states of each checkpoint interval recomputed from its checkpoint.
- * grad: host double [3][K][Nq] = dJ/d(1/rho, lam, mu).  The context's state
- * is not changed.  Synchronous. */
-dg_status dg_adjoint_backward(dg_ctx* ctx, const void* resid, double* grad);
+ * grad: host double [3][K][Nq] = dJ/d(1/rho, lam, mu) at the quadrature
+ * points.  grad_z: host double [2][K][Np] = dJ/d(Zp, Zs) at the nodes, or
+ * NULL to skip it (zero for the central flux, which reads no impedance).
+ * The context's state is not changed.  Synchronous.  DG_ESTATE when no
+ * forward run is recorded, or the mesh, material, sources or receivers
+ * changed since it. */
+dg_status dg_adjoint_backward(dg_ctx* ctx, const void* resid, double* grad, double* grad_z);
 
 /* Device bytes the context holds (the amount counted against its HBM
  * budget). */

@@ -1,19 +1,20 @@
 """Discrete adjoint of the oracle's LSRK(5,4) run with point sources and
 receivers, for tiny meshes.  Plain FP64 NumPy.
 
-Forward map.  The material weights m = (1/rho, lam, mu) at the quadrature
-points (shape [3, K, Nq]) enter only the weight-adjusted mass inverse W(m)
-[CHW17, C18]; the flux impedances are held fixed (with central fluxes the
-operator does not depend on them).  With R the raw operator (volume terms,
-face fluxes, LIFT) and s_raw the raw source vectors, one stage is
-    res_s = a_s res_{s-1} + dt W(m) (R y_{s-1} + s_raw g(t_s)),
+Forward map.  The material enters the operator in two places: the
+weights m = (1/rho, lam, mu) at the quadrature points (shape [3, K, Nq]) of
+the weight-adjusted mass inverse W(m) [CHW17, C18], and the impedances
+z = (Zp, Zs) = (rho cp, rho cs) at the nodes (shape [2, K, Np]) of the
+upwind flux inside the raw operator R(z) (with central fluxes R does not
+depend on z).  With s_raw the raw source vectors, one stage is
+    res_s = a_s res_{s-1} + dt W(m) (R(z) y_{s-1} + s_raw g(t_s)),
     y_s = y_{s-1} + b_s res_s             [CK94],
 and the receivers sample the velocity after every step, u_n = E q_n.
 
 Adjoint.  For a scalar J(u) with dJ/du = resid, the reverse sweep runs the
 stages backwards:
-    lres += b_s ly;  grad += dt d/dm <lres, W(m) r_s>;  ly += dt R^T W^T lres;
-    lres *= a_s,
+    lres += b_s ly;  grad_m += dt d/dm <lres, W(m) r_s>;  mu = W^T lres;
+    ly += dt R^T mu;  grad_z += dt d/dz <mu, R(z) y_{s-1}>;  lres *= a_s,
 with r_s = R y_{s-1} + s_raw g(t_s) and ly += E^T resid_n before step n is
 reversed.  R^T is the transpose of the assembled raw operator (built column
 by column from the oracle's own right-hand side), W^T and d/dm follow from
@@ -23,25 +24,41 @@ W(m) r = P_q[m-weighted V_q r]:
     d/d(1/rho) = sum_c (P_q^T l_c)(V_q r_c),  c = v_x, v_y, v_z,
     d/d lam    = tr(P_q^T l_s) tr(V_q r_s),
     d/d mu     = 2 sum_c (P_q^T l_c)(V_q r_c),  c = stress components.
+d/dz <mu, R(z) y> = d/dz sum over face nodes of (Fscale LIFT^T mu) . flux:
+each face node's flux depends on the four impedances it reads (its own
+node's and the neighbouring node's, P and S); the derivative with respect to
+each is taken by the complex-step method (Squire and Trapp, SIAM Review
+1998: for a function analytic in its argument, Im f(x + i h) / h with
+h = 1e-30 is its derivative to rounding, with no cancellation) and summed
+onto the node the face node reads it from.  A gradient with respect to
+rho, lam, mu fields follows by the chain rule through m and z.
 
-Pins (tests/test_oracle_adjoint.py): the gradient against central finite
-differences of J along random directions, for both fluxes, and a planted
-mistake (a dropped trace term) that the check catches.
+Pins (tests/test_oracle_adjoint.py): the gradients against central finite
+differences of J along random directions, for both fluxes: in m, in z, and
+in rho, lam, mu perturbed together with m and z recomputed from them; and
+planted mistakes (a dropped trace term, a dropped neighbour-side impedance
+term) that the checks catch.
+
+This module is test infrastructure: only the tests use it.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .dg import LSRK_A, LSRK_B, LSRK_C, ElasticDG
+from .dg import LSRK_A, LSRK_B, LSRK_C, ElasticDG, riemann_flux
 from .refelem import basis
 from .source import locate, receiver, ricker, source_vector
 
 
-def with_weights(op: ElasticDG, m):
-    """The operator with its weight-adjusted material replaced by m."""
+def with_weights(op: ElasticDG, m, z=None):
+    """The operator with its weight-adjusted material replaced by m and, if
+    given, its nodal impedances by z = (Zp, Zs)."""
     op.mat.irho_q = np.array(m[0], dtype=np.float64)
     op.mat.lam_q = np.array(m[1], dtype=np.float64)
     op.mat.mu_q = np.array(m[2], dtype=np.float64)
+    if z is not None:
+        op.mat.Zp_n = np.array(z[0], dtype=np.float64)
+        op.mat.Zs_n = np.array(z[1], dtype=np.float64)
     return op
 
 
@@ -97,9 +114,32 @@ def _dm(op, lam, r):
     return g
 
 
-def forward_trace(op, m, q0, t0, dt, nsteps, sources, receiver_points):
-    """Receiver velocities [nsteps, nrec, 3] of the run with weights m."""
-    with_weights(op, m)
+def _dz(op, mu, y):
+    """d/dz <mu, R(z) y> for the upwind flux: [2, K, Np] (Zp, Zs)."""
+    m, mat, ref = op.mesh, op.mat, op.ref
+    K, Np, Nfp = op.K, op.Np, ref.Nfp
+    gf = (mu @ ref.LIFT).reshape(9, K, 4, Nfp) * m.Fscale[None, :, :, None]
+    qf = y.reshape(9, -1)
+    iM, iP = m.vmapM, m.vmapP
+    qM, qP = qf[:, iM], qf[:, iP]
+    n = m.nrm[:, :, None, :]
+    Z = [mat.Zp_n.ravel()[iM], mat.Zp_n.ravel()[iP], mat.Zs_n.ravel()[iM], mat.Zs_n.ravel()[iP]]
+    h = 1e-30
+    out = np.zeros((2, K * Np))
+    # slot order of riemann_flux: ZpM, ZpP, ZsM, ZsP
+    for slot, (which, idx) in enumerate([(0, iM), (0, iP), (1, iM), (1, iP)]):
+        Zc = [z.astype(np.complex128) for z in Z]
+        Zc[slot] = Zc[slot] + 1j * h
+        f = riemann_flux(qM, qP, n, "upwind", tuple(Zc))
+        d = np.sum(gf * f.imag, axis=0) / h                 # [K, 4, Nfp]
+        np.add.at(out[which], idx.ravel(), d.ravel())
+    return out.reshape(2, K, Np)
+
+
+def forward_trace(op, m, q0, t0, dt, nsteps, sources, receiver_points, z=None):
+    """Receiver velocities [nsteps, nrec, 3] of the run with weights m (and
+    impedances z, if given)."""
+    with_weights(op, m, z)
     vecs = [source_vector(op, s["x"], np.asarray(s["d"], np.float64)) for s in sources]
     recs = [receiver(op, x) for x in receiver_points]
 
@@ -117,9 +157,11 @@ def forward_trace(op, m, q0, t0, dt, nsteps, sources, receiver_points):
     return tr
 
 
-def gradient(op, m, q0, t0, dt, nsteps, sources, receiver_points, resid, R=None):
-    """dJ/dm for dJ/d(trace) = resid [nsteps, nrec, 3]."""
-    with_weights(op, m)
+def gradient(op, m, q0, t0, dt, nsteps, sources, receiver_points, resid, R=None,
+             z=None, with_z=False):
+    """dJ/dm for dJ/d(trace) = resid [nsteps, nrec, 3]; with with_z, the pair
+    (dJ/dm, dJ/dz) with z = (Zp, Zs) at the nodes (zero for central fluxes)."""
+    with_weights(op, m, z)
     if R is None:
         R = raw_matrix(op)
     shp = (9, op.K, op.Np)
@@ -150,6 +192,7 @@ def gradient(op, m, q0, t0, dt, nsteps, sources, receiver_points, resid, R=None)
         qs.append(q)
     # reverse sweep
     grad = np.zeros((3, op.K, op.ref.Nq))
+    gradz = np.zeros((2, op.K, op.Np))
     ly = np.zeros(shp)
     for i in reversed(range(nsteps)):
         for r, (k, w) in enumerate(recs):
@@ -165,6 +208,9 @@ def gradient(op, m, q0, t0, dt, nsteps, sources, receiver_points, resid, R=None)
             lres = lres + b[s] * ly
             ts = t0 + (i + c[s]) * dt
             grad += dt * _dm(op, lres, raw_rhs(ys[s], ts))
-            ly = ly + dt * (R.T @ _wT(op, lres, m).ravel()).reshape(shp)
+            mu = _wT(op, lres, m)
+            ly = ly + dt * (R.T @ mu.ravel()).reshape(shp)
+            if with_z and op.flux == "upwind":
+                gradz += dt * _dz(op, mu, ys[s])
             lres = a[s] * lres
-    return grad
+    return (grad, gradz) if with_z else grad

@@ -101,6 +101,45 @@ def material_from_samples(rho_q, cp_q, cs_q, rho_n, cp_n, cs_n) -> Material:
                     Zp_n=rho_n * cp_n, Zs_n=rho_n * cs_n)
 
 
+def riemann_flux(qM, qP, n, flux, Z=None):
+    """The face flux of step 2 from the traces qM (own side) and qP
+    (neighbour) [9, ...], the outward normals n [..., 3] and, for the upwind
+    flux, the impedances Z = (ZpM, ZpP, ZsM, ZsP) at the same face nodes."""
+    nx, ny, nz = n[..., 0], n[..., 1], n[..., 2]
+
+    def traction(Q):
+        return np.stack([Q[3] * nx + Q[8] * ny + Q[7] * nz,
+                         Q[8] * nx + Q[4] * ny + Q[6] * nz,
+                         Q[7] * nx + Q[6] * ny + Q[5] * nz])
+    vM, vP = qM[0:3], qP[0:3]
+    tM, tP = traction(qM), traction(qP)
+    nv = np.stack([nx, ny, nz])                              # [3, ...]
+    jv = vP - vM
+    jt = tP - tM
+    if flux == "central":
+        dv = 0.5 * jv
+        dt = 0.5 * jt
+    else:
+        ZpM, ZpP, ZsM, ZsP = Z
+        jvn = np.sum(jv * nv, axis=0)
+        jtn = np.sum(jt * nv, axis=0)
+        jvt = jv - jvn * nv
+        jtt = jt - jtn * nv
+        dvn = (ZpP * jvn + jtn) / (ZpM + ZpP)
+        dvt = (ZsP * jvt + jtt) / (ZsM + ZsP)
+        dv = dvn * nv + dvt
+        dt = (ZpM * dvn) * nv + ZsM * dvt
+    f = np.empty((9,) + dv.shape[1:], dtype=dv.dtype)
+    f[0:3] = dt
+    f[3] = dv[0] * nv[0]
+    f[4] = dv[1] * nv[1]
+    f[5] = dv[2] * nv[2]
+    f[6] = 0.5 * (dv[1] * nv[2] + dv[2] * nv[1])
+    f[7] = 0.5 * (dv[0] * nv[2] + dv[2] * nv[0])
+    f[8] = 0.5 * (dv[0] * nv[1] + dv[1] * nv[0])
+    return f
+
+
 class ElasticDG:
     """Oracle DG operator on the periodic Kuhn cube of n^3 x 6 tetrahedra."""
 
@@ -159,45 +198,12 @@ class ElasticDG:
         qf = q.reshape(NF, -1)
         iM = m.vmapM[elems]                                  # [k, 4, Nfp]
         iP = m.vmapP[elems]
-        qM = qf[:, iM]                                       # [9, k, 4, Nfp]
-        qP = qf[:, iP]
         n = m.nrm[elems][:, :, None, :]                      # [k, 4, 1, 3]
-        nx, ny, nz = n[..., 0], n[..., 1], n[..., 2]
-
-        def traction(Q):
-            return np.stack([Q[3] * nx + Q[8] * ny + Q[7] * nz,
-                             Q[8] * nx + Q[4] * ny + Q[6] * nz,
-                             Q[7] * nx + Q[6] * ny + Q[5] * nz])
-        vM, vP = qM[0:3], qP[0:3]
-        tM, tP = traction(qM), traction(qP)
-        nv = np.stack([nx, ny, nz])                          # [3, k, 4, 1]
-        jv = vP - vM
-        jt = tP - tM
-        if self.flux == "central":
-            dv = 0.5 * jv
-            dt = 0.5 * jt
-        else:
-            ZpM = mat.Zp_n.ravel()[iM]
-            ZpP = mat.Zp_n.ravel()[iP]
-            ZsM = mat.Zs_n.ravel()[iM]
-            ZsP = mat.Zs_n.ravel()[iP]
-            jvn = np.sum(jv * nv, axis=0)
-            jtn = np.sum(jt * nv, axis=0)
-            jvt = jv - jvn * nv
-            jtt = jt - jtn * nv
-            dvn = (ZpP * jvn + jtn) / (ZpM + ZpP)
-            dvt = (ZsP * jvt + jtt) / (ZsM + ZsP)
-            dv = dvn * nv + dvt
-            dt = (ZpM * dvn) * nv + ZsM * dvt
-        f = np.empty_like(qM)
-        f[0:3] = dt
-        f[3] = dv[0] * nv[0]
-        f[4] = dv[1] * nv[1]
-        f[5] = dv[2] * nv[2]
-        f[6] = 0.5 * (dv[1] * nv[2] + dv[2] * nv[1])
-        f[7] = 0.5 * (dv[0] * nv[2] + dv[2] * nv[0])
-        f[8] = 0.5 * (dv[0] * nv[1] + dv[1] * nv[0])
-        return f
+        Z = None
+        if self.flux == "upwind":
+            Z = (mat.Zp_n.ravel()[iM], mat.Zp_n.ravel()[iP],
+                 mat.Zs_n.ravel()[iM], mat.Zs_n.ravel()[iP])
+        return riemann_flux(qf[:, iM], qf[:, iP], n, self.flux, Z)
 
     def surface(self, q, elems):
         """Step 3: the face flux scaled by Fscale and lifted to the nodes."""

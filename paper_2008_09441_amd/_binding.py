@@ -94,7 +94,7 @@ def _load():
         "dg_state_zero": ([P], I32),
         "dg_material_set_weights": ([P, P, P, P, P, P], I32),
         "dg_adjoint_forward": ([P, D, D, I64, I64, P], I32),
-        "dg_adjoint_backward": ([P, P, P], I32),
+        "dg_adjoint_backward": ([P, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -290,10 +290,15 @@ def dg_adjoint_forward(ctx, t0, dt, nsteps, every, trace):
                                       _ptr(trace)))
 
 
-def dg_adjoint_backward(ctx, resid, grad):
-    if grad.dtype != np.float64 or not grad.flags["C_CONTIGUOUS"]:
-        raise ValueError("grad must be a C-contiguous float64 host array")
-    check(ctx, lib.dg_adjoint_backward(ctx, _ptr(np.ascontiguousarray(resid)), _ptr(grad)))
+def dg_adjoint_backward(ctx, resid, grad, grad_z=None):
+    K, Np, _, Nq = dg_sizes(ctx)
+    for a, shape in ((grad, (3, K, Nq)), (grad_z, (2, K, Np))):
+        if a is None:
+            continue
+        if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"] or a.size != int(np.prod(shape)):
+            raise ValueError(f"gradients must be C-contiguous float64 host arrays of {shape}")
+    check(ctx, lib.dg_adjoint_backward(ctx, _ptr(np.ascontiguousarray(resid)), _ptr(grad),
+                                       _ptr(grad_z) if grad_z is not None else None))
 
 
 def dg_state_zero(ctx):

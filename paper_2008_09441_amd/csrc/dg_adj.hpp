@@ -16,7 +16,10 @@
 //            plus (d flux_nb / d q+)^T g_nb from the neighbour's face node
 //            that reads this node, with g = Fscale LIFT^T mu at face nodes.
 // The flux transpose is the reverse-mode derivative of the flux formula
-// written out step by step (rev_flux).
+// written out step by step (rev_flux).  With the upwind flux the operator
+// also depends on the impedances Zp, Zs at the nodes; their sensitivity
+// d/dZ <mu, R(Z) y> is differentiated by hand per face node (zgrad_faces)
+// and gathered onto the nodes (zgrad_nodes).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -395,6 +398,92 @@ __global__ __launch_bounds__(kAdjThreads) void volT_nodes(AdjArgs<T> A, const T*
     }
     for (int f = 0; f < 9; ++f) out[f * KNp + k * Np + n] = acc[f];
   }
+}
+
+// Impedance sensitivity of the upwind flux, pass 1: at every face node i,
+// the derivatives of phi_i = g_i . fl_i (g = LIFT^T mu at the face node, fl
+// the Fscale-scaled flux of the state y) with respect to the four
+// impedances the node reads, zb[i * 4 + {0, 1, 2, 3}] = d phi / d(ZpM, ZsM,
+// ZpP, ZsP).  Writing dv = dvn n + dvt and dt = ZpM dvn n + ZsM dvt,
+//   phi = dvn alpha + dvt . beta,  alpha = ZpM (h . n) + k . n,
+//   beta = ZsM h + k,
+// with h = fs g_{0..2} (traction rows) and k = fs S n, S the symmetric
+// tensor of the stress rows (off-diagonals halved), so that
+//   d/dZpM = dvn (h . n) - alpha dvn / (ZpM + ZpP),
+//   d/dZpP = alpha (jvn - dvn) / (ZpM + ZpP),
+//   d/dZsM = dvt . h - (beta . dvt) / (ZsM + ZsP),
+//   d/dZsP = beta . (jvt - dvt) / (ZsM + ZsP).
+template <typename T>
+__global__ void zgrad_faces(AdjArgs<T> A, const T* y, const T* gb, T* zb) {
+  const int Np = A.Np, Nfp = A.Nfp, NF4 = 4 * Nfp;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * NF4) return;
+  const int64_t k = i / NF4, KNp = A.K * Np;
+  const int j = int(i - k * NF4), face = j / Nfp, ii = j - face * Nfp;
+  const int vM = A.fmask[j];
+  const int64_t nb = A.etoe[k * 4 + face];
+  const int vP = A.pat[int(A.etop[k * 4 + face]) * Nfp + ii];
+  T qM[9], qP[9];
+  for (int f = 0; f < 9; ++f) {
+    qM[f] = y[f * KNp + k * Np + vM];
+    qP[f] = y[f * KNp + nb * Np + vP];
+  }
+  const T* fg = A.fgeo + (k * 4 + face) * 4;
+  const T nx = fg[0], ny = fg[1], nz = fg[2], fs = fg[3];
+  const T ZpM = A.zp[k * Np + vM], ZsM = A.zs[k * Np + vM];
+  const T ZpP = A.zp[nb * Np + vP], ZsP = A.zs[nb * Np + vP];
+  const T tMx = qM[3] * nx + qM[8] * ny + qM[7] * nz;
+  const T tMy = qM[8] * nx + qM[4] * ny + qM[6] * nz;
+  const T tMz = qM[7] * nx + qM[6] * ny + qM[5] * nz;
+  const T tPx = qP[3] * nx + qP[8] * ny + qP[7] * nz;
+  const T tPy = qP[8] * nx + qP[4] * ny + qP[6] * nz;
+  const T tPz = qP[7] * nx + qP[6] * ny + qP[5] * nz;
+  const T jvx = qP[0] - qM[0], jvy = qP[1] - qM[1], jvz = qP[2] - qM[2];
+  const T jtx = tPx - tMx, jty = tPy - tMy, jtz = tPz - tMz;
+  const T jvn = jvx * nx + jvy * ny + jvz * nz;
+  const T jtn = jtx * nx + jty * ny + jtz * nz;
+  const T sp = ZpM + ZpP, ss = ZsM + ZsP;
+  const T dvn = (ZpP * jvn + jtn) / sp;
+  const T jvtx = jvx - jvn * nx, jvty = jvy - jvn * ny, jvtz = jvz - jvn * nz;
+  const T dvtx = (ZsP * jvtx + (jtx - jtn * nx)) / ss;
+  const T dvty = (ZsP * jvty + (jty - jtn * ny)) / ss;
+  const T dvtz = (ZsP * jvtz + (jtz - jtn * nz)) / ss;
+  const T* g = gb + i * 9;
+  const T hx = fs * g[0], hy = fs * g[1], hz = fs * g[2];
+  const T kx = fs * (g[3] * nx + T(0.5) * (g[8] * ny + g[7] * nz));
+  const T ky = fs * (T(0.5) * g[8] * nx + g[4] * ny + T(0.5) * g[6] * nz);
+  const T kz = fs * (T(0.5) * (g[7] * nx + g[6] * ny) + g[5] * nz);
+  const T hn = hx * nx + hy * ny + hz * nz;
+  const T alpha = ZpM * hn + (kx * nx + ky * ny + kz * nz);
+  const T bx = ZsM * hx + kx, by = ZsM * hy + ky, bz = ZsM * hz + kz;
+  const T bdvt = bx * dvtx + by * dvty + bz * dvtz;
+  zb[i * 4 + 0] = dvn * hn - alpha * dvn / sp;
+  zb[i * 4 + 1] = (dvtx * hx + dvty * hy + dvtz * hz) - bdvt / ss;
+  zb[i * 4 + 2] = alpha * (jvn - dvn) / sp;
+  zb[i * 4 + 3] = (bx * (jvtx - dvtx) + by * (jvty - dvty) + bz * (jvtz - dvtz)) / ss;
+}
+
+// Impedance sensitivity, pass 2: onto every volume node n of element k,
+// gradz[{0: Zp, 1: Zs}][k][n] += s * (the own-side terms of the face nodes
+// on n, plus the neighbour-side terms of the neighbours' face nodes that
+// read n); one thread per (element, node)
+template <typename T>
+__global__ void zgrad_nodes(AdjArgs<T> A, const T* zb, double* gradz, double s) {
+  const int Np = A.Np, NF4 = 4 * A.Nfp;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= A.K * Np) return;
+  const int64_t k = i / Np;
+  const int n = int(i - k * Np);
+  double gp = 0.0, gs = 0.0;
+  for (int t = 0; t < 3; ++t) {
+    const int jf = A.invf[n * 3 + t];
+    if (jf < 0) continue;
+    const int64_t own = k * NF4 + jf, nbj = A.nbface[own];
+    gp += double(zb[own * 4 + 0]) + double(zb[nbj * 4 + 2]);
+    gs += double(zb[own * 4 + 1]) + double(zb[nbj * 4 + 3]);
+  }
+  gradz[i] += s * gp;
+  gradz[A.K * Np + i] += s * gs;
 }
 
 // receiver adjoint: l[c][k_r][n] += w_r[n] resid[r][c] for every receiver;

@@ -100,10 +100,13 @@ struct dg_ctx {
   DevBuf adj_v;             // ly, lres, mu, nu, r, res [6][9][K][Np]
   DevBuf adj_gb, adj_hb;    // face-node work [K][4 Nfp][9]
   DevBuf adj_grad;          // double [3][K][Nq]
+  DevBuf adj_zb;            // upwind: impedance terms per face node [K][4 Nfp][4]
+  DevBuf adj_gradz;         // upwind: double [2][K][Np]
   DevBuf adj_trace;         // [nsteps][nrec][3]
   bool adj_ready = false;
   double adj_t0 = 0.0, adj_dt = 0.0;
   int64_t adj_nsteps = 0, adj_every = 0;
+  int32_t adj_nrec = 0;     // receivers of the recorded forward run
 };
 
 namespace {
@@ -723,6 +726,13 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
   if ((s = fill_zero(c, lres, n)) != DG_OK) return s;
   dgk::fill_kernel<double><<<nblocks(3 * K * Nq), 256, 0, st>>>(grad, 3 * K * Nq, 0.0);
   DG_HIP(c, hipGetLastError());
+  const bool upwind = c->opt.flux == DG_FLUX_UPWIND;
+  T* zb = static_cast<T*>(c->adj_zb.p);
+  double* gradz = static_cast<double*>(c->adj_gradz.p);
+  if (upwind) {
+    dgk::fill_kernel<double><<<nblocks(2 * KNp), 256, 0, st>>>(gradz, 2 * KNp, 0.0);
+    DG_HIP(c, hipGetLastError());
+  }
   for (int64_t sg = nck - 1; sg >= 0; --sg) {
     const int64_t n0 = sg * every, n1 = std::min(n0 + every, nsteps);
     // step-start states of the segment, recomputed from its checkpoint
@@ -766,6 +776,11 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
         // and mu = W^T lres (one kernel); then ly += dt R^T mu
         dga::grad_wadgT<T><<<eg, et, lgw, st>>>(A, lres, r, grad, dt, mu);
         dga::liftT_faces<T><<<eg, et, l9, st>>>(A, mu, gb);
+        if (upwind) {
+          // and the impedance gradient dt d/dZ <mu, R(Z) y_q>
+          dga::zgrad_faces<T><<<nblocks(K * NF4), 256, 0, st>>>(A, ys + q * n, gb, zb);
+          dga::zgrad_nodes<T><<<nblocks(KNp), 256, 0, st>>>(A, zb, gradz, dt);
+        }
         dga::fluxT_faces<T><<<nblocks(K * NF4), 256, 0, st>>>(A, gb, hb);
         dga::volT_nodes<T><<<eg, et, l9, st>>>(A, mu, hb, nu);
         dga::axpby<T><<<nblocks(n), 256, 0, st>>>(ly, nu, dt, 1.0, n);
@@ -1012,6 +1027,7 @@ dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
     if (s != DG_OK) return s;
     if ((s = check(rho_n, cp_n, cs_n, nn)) != DG_OK) return s;
     c->has_mat = false;
+    c->adj_ready = false;
     if (!device_ctx(c)) {
       c->has_mat = true;
       return DG_OK;
@@ -1217,6 +1233,7 @@ dg_status dg_sources_set(dg_ctx* c, int32_t nsrc, const double* xyz, const doubl
     if (s != DG_OK) return s;
     DG_HIP(c, hipStreamSynchronize(c->stream));   // the old arrays may be in use
     drop_graphs(c);
+    c->adj_ready = false;
     c->src = std::move(src);
     return upload_sources(c);
   } catch (...) {
@@ -1272,6 +1289,7 @@ dg_status dg_receivers_set(dg_ctx* c, int32_t nrec, const double* xyz) {
     if (s != DG_OK) return s;
     DG_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
+    c->adj_ready = false;
     c->nrec = 0;
     c->trace_cap = 0;
     for (DevBuf* b : {&c->rec_elem, &c->rec_w, &c->rec_buf, &c->trace}) release(c, *b);
@@ -1515,6 +1533,7 @@ dg_status dg_material_set_weights(dg_ctx* c, const double* irho_q, const double*
         return fail(c, DG_EINVAL, "weights: impedances must be positive");
     }
     c->has_mat = false;
+    c->adj_ready = false;
     if (!device_ctx(c)) {
       c->has_mat = true;
       return DG_OK;
@@ -1559,6 +1578,7 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
     const size_t S = size_t(n) * c->elem;
     const int64_t nck = (nsteps + every - 1) / every;
     const size_t tb = size_t(nsteps) * c->nrec * 3 * c->elem;
+    const bool upwind = c->opt.flux == DG_FLUX_UPWIND;
     DG_HIP(c, hipStreamSynchronize(c->stream));
     c->adj_ready = false;
     struct Need {
@@ -1571,6 +1591,8 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
                 {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
                 {&c->adj_hb, size_t(K) * NF4 * 9 * c->elem},
                 {&c->adj_grad, size_t(K) * Nq * 3 * sizeof(double)},
+                {&c->adj_zb, upwind ? size_t(K) * NF4 * 4 * c->elem : 0},
+                {&c->adj_gradz, upwind ? size_t(K) * c->re.Np * 2 * sizeof(double) : 0},
                 {&c->adj_trace, tb}};
     for (auto& x : need)
       if (x.b->bytes != x.bytes && (s = alloc(c, *x.b, x.bytes)) != DG_OK) return s;
@@ -1589,6 +1611,7 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
     c->adj_dt = dt;
     c->adj_nsteps = nsteps;
     c->adj_every = every;
+    c->adj_nrec = c->nrec;
     c->adj_ready = true;
     return DG_OK;
   } catch (...) {
@@ -1596,13 +1619,18 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
   }
 }
 
-dg_status dg_adjoint_backward(dg_ctx* c, const void* resid, double* grad) {
+dg_status dg_adjoint_backward(dg_ctx* c, const void* resid, double* grad, double* grad_z) {
   try {
     if (!c || !resid || !grad) return DG_EINVAL;
     dg_status s = ready(c, true);
     if (s != DG_OK) return s;
-    if (!c->adj_ready) return fail(c, DG_ESTATE, "adjoint: no checkpointed forward run");
-    const size_t tb = size_t(c->adj_nsteps) * c->nrec * 3 * c->elem;
+    if (!c->adj_ready)
+      return fail(c, DG_ESTATE,
+                  "adjoint: no checkpointed forward run since the last change of mesh, "
+                  "material, sources or receivers");
+    if (c->adj_nrec != c->nrec)
+      return fail(c, DG_ESTATE, "adjoint: receivers changed since the forward run");
+    const size_t tb = size_t(c->adj_nsteps) * c->adj_nrec * 3 * c->elem;
     DG_HIP(c, copy_sync(c, c->adj_trace.p, resid, tb, hipMemcpyHostToDevice));
     // the sweep recomputes states in its own buffers: the context's state (the
     // end of the forward run) is left as it is
@@ -1613,6 +1641,14 @@ dg_status dg_adjoint_backward(dg_ctx* c, const void* resid, double* grad) {
     if (s != DG_OK) return s;
     const size_t gb = size_t(c->mesh.K) * c->re.Nq * 3 * sizeof(double);
     DG_HIP(c, copy_sync(c, grad, c->adj_grad.p, gb, hipMemcpyDeviceToHost));
+    if (grad_z) {
+      const size_t nz = size_t(c->mesh.K) * c->re.Np * 2;
+      if (c->opt.flux == DG_FLUX_UPWIND)
+        DG_HIP(c, copy_sync(c, grad_z, c->adj_gradz.p, nz * sizeof(double),
+                            hipMemcpyDeviceToHost));
+      else
+        std::fill(grad_z, grad_z + nz, 0.0);   // the central flux reads no impedance
+    }
     return DG_OK;
   } catch (...) {
     return exception_status();

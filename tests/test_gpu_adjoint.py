@@ -1,7 +1,12 @@
 """GPU discrete adjoint (dg_adjoint_forward / dg_adjoint_backward and the
 torch.autograd.Function over them) against the oracle's discrete adjoint
 (oracle/adjoint.py) and against central finite differences of the GPU
-forward run.  FP64: gradients within 1e-10 of the oracle's; FP32: 1e-3."""
+forward run.  FP64: gradients within 1e-10 of the oracle's; FP32: 1e-3.
+With the upwind flux the gradient includes the impedances Zp, Zs at the
+nodes; a gradient with respect to rho, lam, mu fields (at the quadrature
+points and nodes, with the weights and impedances recomputed from them) is
+checked against central differences of the GPU run that perturb the
+material."""
 import numpy as np
 import pytest
 
@@ -119,3 +124,113 @@ def test_autograd_function_gives_the_adjoint_gradient():
     J2 = 0.5 * ((receiver_traces(mm, s, zp, zs, q0, 0.0, dt, nsteps, every) - d) ** 2).sum()
     J2.backward()
     assert np.allclose(rho.grad.numpy(), -g[0] * m[0] ** 2, rtol=1e-10, atol=0)
+
+
+def test_backward_refuses_a_stale_forward_run():
+    """After dg_adjoint_forward, any change of material, sources or receivers
+    makes dg_adjoint_backward refuse with DG_ESTATE (the sweep would replay
+    the run with the new operator, or write a trace of the old size); the
+    autograd Function refuses the backward of a run that a later forward on
+    the same solver replaced."""
+    from paper_2008_09441_amd import B
+    from paper_2008_09441_amd.adjoint import receiver_traces
+    op, s, m, zp, zs, q0 = _setup("upwind", "fp64")
+    dt, nsteps, every = 0.01, 4, 2
+    resid = np.zeros((nsteps, len(RECS), 3))
+    g = np.empty(m.shape)
+    changes = [
+        lambda: B.dg_material_set_weights(s.ctx, m[0], m[1], m[2], zp, zs),
+        lambda: s.set_receivers(np.concatenate([RECS, RECS[:1]])),
+        lambda: s.set_sources(np.stack([x["x"] for x in SRC]), np.stack([x["d"] for x in SRC]),
+                              [x["f0"] for x in SRC], [x["t0"] for x in SRC], 1.0),
+    ]
+    for change in changes:
+        s.set_receivers(RECS)
+        s.set_state(q0)
+        tr = np.empty((nsteps, len(RECS), 3))
+        B.dg_adjoint_forward(s.ctx, 0.0, dt, nsteps, every, tr)
+        B.dg_adjoint_backward(s.ctx, resid, g)          # fresh run: accepted
+        change()
+        with pytest.raises(B.DGError) as ei:
+            B.dg_adjoint_backward(s.ctx, resid, g)
+        assert ei.value.status == B.DG_ESTATE
+    s.set_receivers(RECS)
+    mt = torch.tensor(m, requires_grad=True)
+    tr1 = receiver_traces(mt, s, zp, zs, q0, 0.0, dt, nsteps, every)
+    tr2 = receiver_traces(mt, s, zp, zs, q0, 0.0, dt, nsteps, every)
+    with pytest.raises(RuntimeError):
+        tr1.sum().backward()
+    tr2.sum().backward()                                  # the latest run: accepted
+    assert torch.isfinite(mt.grad).all()
+
+
+def _gpu_grad_z(s, m, zp, zs, q0, dt, nsteps, every, d):
+    from paper_2008_09441_amd import B
+    B.dg_material_set_weights(s.ctx, m[0], m[1], m[2], zp, zs)
+    s.set_state(q0)
+    tr = np.empty((nsteps, len(RECS), 3), dtype=s.dtype)
+    B.dg_adjoint_forward(s.ctx, 0.0, dt, nsteps, every, tr)
+    g = np.empty(m.shape)
+    gz = np.empty((2,) + zp.shape)
+    B.dg_adjoint_backward(s.ctx, (tr - d).astype(s.dtype), g, gz)
+    return tr.astype(np.float64), g, gz
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("fp32", 1e-3)])
+def test_impedance_gradient_matches_oracle(precision, bound):
+    print(f"case adjoint impedance gradient {precision}", flush=True)
+    op, s, m, zp, zs, q0 = _setup("upwind", precision)
+    z = np.stack([zp, zs])
+    dt, nsteps, every = 0.01, 12, 5
+    d = np.random.default_rng(25).standard_normal((nsteps, len(RECS), 3)) * 0.05
+    tr_ref = oadj.forward_trace(op, m, q0, 0.0, dt, nsteps, SRC, RECS, z)
+    g_ref, gz_ref = oadj.gradient(op, m, q0, 0.0, dt, nsteps, SRC, RECS, tr_ref - d,
+                                  z=z, with_z=True)
+    _, g, gz = _gpu_grad_z(s, m, zp, zs, q0, dt, nsteps, every, d)
+    gerr = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    zerr = np.linalg.norm(gz - gz_ref) / np.linalg.norm(gz_ref)
+    print("gradient m", gerr, "gradient z", zerr)
+    assert np.linalg.norm(gz_ref) > 0
+    assert gerr <= bound and zerr <= bound
+
+
+def test_central_flux_impedance_gradient_is_zero():
+    op, s, m, zp, zs, q0 = _setup("central", "fp64")
+    d = np.zeros((4, len(RECS), 3))
+    _, _, gz = _gpu_grad_z(s, m, zp, zs, q0, 0.01, 4, 2, d)
+    assert np.all(gz == 0.0)
+
+
+def test_gradient_in_material_fields_matches_central_differences_fp64():
+    """rho, lam, mu at the quadrature points and at the nodes, mapped by torch
+    to m = (1/rho, lam, mu) and (Zp, Zs) = (sqrt(rho (lam + 2 mu)),
+    sqrt(rho mu)); the autograd gradient against central differences of the
+    GPU run that perturb all six fields (impedances recomputed)."""
+    from paper_2008_09441_amd.adjoint import receiver_traces
+    op, s, m, zp, zs, q0 = _setup("upwind", "fp64")
+    rho_n = synth.fourier_media(op.mesh.x)[0]
+    P0 = [1.0 / m[0], m[1], m[2], rho_n, zp ** 2 / rho_n - 2.0 * zs ** 2 / rho_n,
+          zs ** 2 / rho_n]
+    dt, nsteps, every = 0.01, 10, 4
+    rng = np.random.default_rng(26)
+    d = torch.from_numpy(rng.standard_normal((nsteps, len(RECS), 3)) * 0.05)
+
+    def J_of(P):
+        rq, lq, mq, rn, ln, mn = P
+        mm = torch.stack([1.0 / rq, lq, mq])
+        zzp = torch.sqrt(rn * (ln + 2.0 * mn))
+        zzs = torch.sqrt(rn * mn)
+        tr = receiver_traces(mm, s, zzp, zzs, q0, 0.0, dt, nsteps, every)
+        return 0.5 * ((tr - d) ** 2).sum()
+    P = [torch.tensor(p, requires_grad=True) for p in P0]
+    J_of(P).backward()
+    for _ in range(3):
+        dP = [rng.standard_normal(p.shape) * p * 0.1 for p in P0]
+        an = sum(float((p.grad * torch.from_numpy(dp)).sum()) for p, dp in zip(P, dP))
+        eps = 1e-6
+        with torch.no_grad():
+            Jp = float(J_of([torch.tensor(p + eps * dp) for p, dp in zip(P0, dP)]))
+            Jm = float(J_of([torch.tensor(p - eps * dp) for p, dp in zip(P0, dP)]))
+        fd = (Jp - Jm) / (2 * eps)
+        print("fd", fd, "adjoint", an)
+        assert abs(fd - an) <= 1e-6 * abs(fd)

@@ -4,10 +4,14 @@ on the 24^3 x 6 cube (82,944 tets), smooth random media, 4 Ricker forces,
 initial state (the workload's 400 would make the 65 forward runs of this
 test take minutes).
 
-* FP64: the gradient of J = 1/2 |traces - d|^2 with respect to (1/rho, lam,
-  mu) at the quadrature points against central differences of the same GPU
-  run along 32 random directions, within 1e-6 relative (step 1e-5: the
-  quotient's truncation error ~1e-10, its rounding error ~1e-16 |J| / 1e-5);
+* FP64: the gradient of J = 1/2 |traces - d|^2 with respect to the
+  material fields rho, lam, mu at the quadrature points and at the nodes
+  (chained through the weights (1/rho, lam, mu) and the upwind flux's
+  impedances Zp = sqrt(rho (lam + 2 mu)), Zs = sqrt(rho mu)) against central
+  differences of the same GPU run, which perturb the fields and recompute
+  the weights and impedances, along 32 random directions, within 1e-6
+  relative (step 1e-5: the quotient's truncation error ~1e-10, its rounding
+  error ~1e-16 |J| / 1e-5);
 * FP32: the gradient against the FP64 one, within 1e-3 relative L2 (the
   bound of the small-mesh FP32 test)."""
 import math
@@ -44,14 +48,23 @@ def _context(precision, pb):
     xq, xn = s.quad_coords(), s.node_coords()
     rq, pq, sq = synth.fourier_media(xq, seed=77)
     rn, pn, sn = synth.fourier_media(xn, seed=77)
-    m = np.stack([1.0 / rq, rq * (pq ** 2 - 2 * sq ** 2), rq * sq ** 2])
-    zp, zs = rn * pn, rn * sn
+    # the material fields rho, lam, mu at the quadrature points and nodes
+    P = [rq, rq * (pq ** 2 - 2 * sq ** 2), rq * sq ** 2, rn, rn * (pn ** 2 - 2 * sn ** 2),
+         rn * sn ** 2]
+    m, (zp, zs) = _weights(P)
     B.dg_material_set_weights(s.ctx, m[0], m[1], m[2], zp, zs)
     s.set_sources(pb["src_x"], pb["src_d"], pb["f0"], pb["t0"], 1.0)
     s.set_receivers(pb["recs"])
     q0 = s.project_function(lambda x: synth.plane_p_wave(x, 0.1) + synth.plane_s_wave(x, 0.2)
                             + synth.gaussian_pulse(x, width=0.1))
-    return s, m, zp, zs, q0
+    return s, P, q0
+
+
+def _weights(P):
+    """m = (1/rho, lam, mu) at the quadrature points, (Zp, Zs) at the nodes."""
+    rq, lq, mq, rn, ln, mn = P
+    return (np.stack([1.0 / rq, lq, mq]),
+            (np.sqrt(rn * (ln + 2.0 * mn)), np.sqrt(rn * mn)))
 
 
 def _dt():
@@ -67,36 +80,48 @@ def _forward(s, m, zp, zs, q0):
     return tr.astype(np.float64)
 
 
-def _gradient(s, m, zp, zs, q0, d):
+def _gradient(s, P, q0, d):
+    """dJ/dP for the six material fields, by the chain rule from libdg's
+    dJ/dm and dJ/d(Zp, Zs)."""
     from paper_2008_09441_amd import B
+    m, (zp, zs) = _weights(P)
     tr = _forward(s, m, zp, zs, q0)
     g = np.empty(m.shape)
-    B.dg_adjoint_backward(s.ctx, (tr - d).astype(s.dtype), g)
-    return g
+    gz = np.empty((2,) + zp.shape)
+    B.dg_adjoint_backward(s.ctx, (tr - d).astype(s.dtype), g, gz)
+    rq, lq, mq, rn, ln, mn = P
+    return [-g[0] / rq ** 2, g[1], g[2],
+            gz[0] * (ln + 2 * mn) / (2 * zp) + gz[1] * mn / (2 * zs),
+            gz[0] * rn / (2 * zp),
+            gz[0] * rn / zp + gz[1] * rn / (2 * zs)]
 
 
 def test_config5_gradient_fp64_matches_central_differences_and_fp32():
     pb = _problem()
-    s, m, zp, zs, q0 = _context("fp64", pb)
+    s, P, q0 = _context("fp64", pb)
+    m, (zp, zs) = _weights(P)
     d = 0.5 * _forward(s, m, zp, zs, q0)          # synthetic data: half the signal
-    g = _gradient(s, m, zp, zs, q0, d)
+    g = _gradient(s, P, q0, d)
 
-    def J(mm):
-        return 0.5 * float(np.sum((_forward(s, mm, zp, zs, q0) - d) ** 2))
+    def J(PP):
+        mm, (zzp, zzs) = _weights(PP)
+        return 0.5 * float(np.sum((_forward(s, mm, zzp, zzs, q0) - d) ** 2))
     rng = pb["rng"]
     worst = 0.0
     for _ in range(32):
-        delta = rng.standard_normal(m.shape) * m
+        dP = [rng.standard_normal(p.shape) * p * 0.1 for p in P]
         eps = 1e-5   # truncation ~eps^2, rounding of J ~1e-16 |J| / eps
-        fd = (J(m + eps * delta) - J(m - eps * delta)) / (2 * eps)
-        an = float(np.sum(g * delta))
+        fd = (J([p + eps * dp for p, dp in zip(P, dP)])
+              - J([p - eps * dp for p, dp in zip(P, dP)])) / (2 * eps)
+        an = float(sum(np.sum(gi * dp) for gi, dp in zip(g, dP)))
         worst = max(worst, abs(fd - an) / abs(fd))
     print(f"32 directions: max |fd - adjoint| / |fd| = {worst:.2e}", flush=True)
     assert worst <= 1e-6
     s.close()
-    s32, m32, zp32, zs32, q032 = _context("fp32", pb)
-    g32 = _gradient(s32, m32, zp32, zs32, q032, d)
+    s32, P32, q032 = _context("fp32", pb)
+    g32 = _gradient(s32, P32, q032, d)
     s32.close()
-    rel = float(np.linalg.norm(g32 - g) / np.linalg.norm(g))
-    print(f"fp32 gradient vs fp64: {rel:.2e}", flush=True)
-    assert rel <= 1e-3
+    for i, (a, b) in enumerate(zip(g32, g)):
+        rel = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        print(f"fp32 gradient {i} vs fp64: {rel:.2e}", flush=True)
+        assert rel <= 1e-3

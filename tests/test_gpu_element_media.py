@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_common import rel_l2_per_field
+from gpu_common import assert_parity
 from oracle.dg import ElasticDG, material_from_samples
 
 pytestmark = pytest.mark.gpu
@@ -41,9 +41,7 @@ def test_rhs_element_constant_media(precision, tol):
     ref = op.rhs(q)
     dt = torch.float64 if precision == "fp64" else torch.float32
     got = s.rhs(torch.from_numpy(q).to("cuda:0", dt)).cpu().numpy()
-    err = rel_l2_per_field(got, ref)
-    print("per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= tol
+    assert_parity(got, ref, tol, f"element media rhs {precision}")
 
 
 def test_step_element_constant_media_fp64():
@@ -52,5 +50,4 @@ def test_step_element_constant_media_fp64():
     ref, _ = op.step(q0, np.zeros_like(q0), 1e-3)
     s.set_state(q0)
     s.step(0.0, 1e-3)
-    err = rel_l2_per_field(s.get_state(), ref)
-    assert err.max() <= 1e-12
+    assert_parity(s.get_state(), ref, 1e-12, "element media step fp64")

@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_common import make_pair, rel_l2_per_field
+from gpu_common import assert_parity, make_pair, rel_l2_per_field
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -49,25 +49,19 @@ def test_layered_order7_bf16x3_matches_oracle():
     # right-hand side of a random state: the stated bound
     q = synth.random_state(op.K, op.Np, seed=77).astype(np.float32).astype(np.float64)
     got = s.rhs(torch.from_numpy(q).to("cuda:0", torch.float32)).cpu().numpy()
-    err = rel_l2_per_field(got, op.rhs(q))
-    print("rhs (random state) per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-4
+    assert_parity(got, op.rhs(q), 1e-4, "rhs (random state) per-field rel L2")
     # right-hand side of a smooth state: the derivative sums cancel, so the
     # 2^-16 error of each split product is relative to sum |D_ij q_j| rather
     # than to |sum D_ij q_j|; at order 7 that ratio is ~10, hence 1e-3
     q0 = op.project_function(lambda x: _smooth(x, 0.15)).astype(np.float32).astype(np.float64)
     got = s.rhs(torch.from_numpy(q0).to("cuda:0", torch.float32)).cpu().numpy()
-    err = rel_l2_per_field(got, op.rhs(q0))
-    print("rhs (smooth state) per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-3
+    assert_parity(got, op.rhs(q0), 1e-3, "rhs (smooth state) per-field rel L2")
     # ten LSRK(5,4) steps of the smooth state: the stated bound on the state
     dt, steps = _dt(n, N), 10
     ref = op.run(q0, 0.0, dt, steps)
     s.set_state(q0)
     s.run(0.0, dt, steps)
-    err = rel_l2_per_field(s.get_state(), ref)
-    print(f"{steps} steps per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-4
+    assert_parity(s.get_state(), ref, 1e-4, f"{steps} steps per-field rel L2")
 
 
 def test_layered_order7_full_size_bf16x3_matches_fp64_gpu():
@@ -96,6 +90,4 @@ def test_layered_order7_full_size_bf16x3_matches_fp64_gpu():
         s.synchronize()
         print(f"{prec}: {(time.perf_counter() - t0) / (5 * steps) * 1e3:.3f} ms per stage", flush=True)
         out[prec] = s.get_state()
-    err = rel_l2_per_field(out["bf16x3"], out["fp64"])
-    print(f"{steps} steps per-field rel L2 (bf16x3 vs fp64 GPU):", np.array2string(err, precision=2))
-    assert err.max() <= 1e-4
+    assert_parity(out["bf16x3"], out["fp64"], 1e-4, f"{steps} steps per-field rel L2 (bf16x3 vs fp64 GPU)")

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_common import make_pair, rel_l2_per_field
+from gpu_common import assert_parity, make_pair, rel_l2_per_field
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -36,9 +36,7 @@ def test_rhs_fp64_matches_oracle(n, N, flux):
     q = synth.random_state(op.K, op.Np, seed=10 + N)
     ref = op.rhs(q)
     got = s.rhs(_dev(q, torch.float64)).cpu().numpy()
-    err = rel_l2_per_field(got, ref)
-    print("per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-12
+    assert_parity(got, ref, 1e-12, "per-field rel L2")
 
 
 @pytest.mark.parametrize("n,N", [(3, 3), (3, 4), (2, 7)])
@@ -48,9 +46,7 @@ def test_rhs_fp32_matches_oracle(n, N):
     q = synth.random_state(op.K, op.Np, seed=20 + N).astype(np.float32).astype(np.float64)
     ref = op.rhs(q)
     got = s.rhs(_dev(q, torch.float32)).cpu().numpy()
-    err = rel_l2_per_field(got, ref)
-    print("per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 2e-5
+    assert_parity(got, ref, 2e-5, "per-field rel L2")
 
 
 @pytest.mark.parametrize("N", [2, 4, 6])
@@ -67,16 +63,12 @@ def test_odd_element_count_fp64_fp32(N, precision, bound):
     q = synth.random_state(op.K, op.Np, seed=70 + N)
     if precision == "fp32":
         q = q.astype(np.float32).astype(np.float64)
-    err = rel_l2_per_field(s.rhs(_dev(q, dtype)).cpu().numpy(), op.rhs(q))
-    print("rhs per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= bound
+    assert_parity(s.rhs(_dev(q, dtype)).cpu().numpy(), op.rhs(q), bound, "rhs")
     dt = 1e-3
     ref, _ = op.step(q, np.zeros_like(q), dt)
     s.set_state(q)
     s.step(0.0, dt)
-    err = rel_l2_per_field(s.get_state(), ref)
-    print("one step per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= bound
+    assert_parity(s.get_state(), ref, bound, "one step")
 
 
 @pytest.mark.parametrize("n,N", [(3, 3), (3, 4)])
@@ -89,9 +81,7 @@ def test_one_lsrk_step_fp64_matches_oracle(n, N):
     s.set_state(q0)
     s.step(0.0, dt)
     got = s.get_state()
-    err = rel_l2_per_field(got, ref)
-    print("per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-12
+    assert_parity(got, ref, 1e-12, "per-field rel L2")
 
 
 def test_rhs_is_deterministic():
@@ -144,9 +134,7 @@ def test_rhs_bf16x3_matches_oracle(n, N, flux):
     q = synth.random_state(op.K, op.Np, seed=40 + N).astype(np.float32).astype(np.float64)
     ref = op.rhs(q)
     got = s.rhs(_dev(q, torch.float32)).cpu().numpy()
-    err = rel_l2_per_field(got, ref)
-    print("per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-4
+    assert_parity(got, ref, 1e-4, "per-field rel L2")
 
 
 def test_rhs_bf16x3_smooth_state():
@@ -156,12 +144,10 @@ def test_rhs_bf16x3_smooth_state():
     q = q.astype(np.float32).astype(np.float64)
     ref = op.rhs(q)
     got = s.rhs(_dev(q, torch.float32)).cpu().numpy()
-    err = rel_l2_per_field(got, ref)
-    print("bf16x3 per-field rel L2:", np.array2string(err, precision=2))
+    assert_parity(got, ref, 1e-4, "bf16x3")
     _, s32 = make_pair(4, 3, synth.fourier_media, "upwind", "fp32", oracle=False)
     err32 = rel_l2_per_field(s32.rhs(_dev(q, torch.float32)).cpu().numpy(), ref)
     print("fp32   per-field rel L2:", np.array2string(err32, precision=2))
-    assert err.max() <= 1e-4
 
 
 @pytest.mark.parametrize("n,N", [(3, 4), (4, 3), (3, 2), (2, 7)])
@@ -173,9 +159,7 @@ def test_one_lsrk_step_bf16x3_matches_oracle(n, N):
     s.set_state(q0)
     s.step(0.0, dt)
     got = s.get_state()
-    err = rel_l2_per_field(got, ref)
-    print("per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-5
+    assert_parity(got, ref, 1e-5, "per-field rel L2")
 
 
 @pytest.mark.parametrize("N", [2, 4, 5, 6, 7])
@@ -190,16 +174,12 @@ def test_bf16x3_odd_element_count(N):
     op, s = make_pair(2, N, synth.fourier_media, "upwind", "bf16x3", vertices=vx)
     assert op.K == 51
     q = synth.random_state(op.K, op.Np, seed=60 + N).astype(np.float32).astype(np.float64)
-    err = rel_l2_per_field(s.rhs(_dev(q, torch.float32)).cpu().numpy(), op.rhs(q))
-    print("rhs per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-4
+    assert_parity(s.rhs(_dev(q, torch.float32)).cpu().numpy(), op.rhs(q), 1e-4, "rhs per-field rel L2")
     dt = 1e-3
     ref, _ = op.step(q, np.zeros_like(q), dt)
     s.set_state(q)
     s.step(0.0, dt)
-    err = rel_l2_per_field(s.get_state(), ref)
-    print("one step per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-5
+    assert_parity(s.get_state(), ref, 1e-5, "one step per-field rel L2")
 
 
 def test_bf16x3_rejects_unsupported_order():

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_common import make_pair, rel_l2_per_field
+from gpu_common import assert_parity, make_pair, rel_l2_per_field
 from oracle.source import make_forcing, run_with_receivers
 
 pytestmark = pytest.mark.gpu
@@ -50,9 +50,7 @@ def test_rhs_with_sources_fp64():
     t = 0.17
     ref = op.rhs(q) + make_forcing(op, SOURCES)(t)
     got = s.rhs(torch.from_numpy(q).to("cuda:0"), t=t).cpu().numpy()
-    err = rel_l2_per_field(got, ref)
-    print("per-field rel L2:", np.array2string(err, precision=2))
-    assert err.max() <= 1e-12
+    assert_parity(got, ref, 1e-12, "per-field rel L2")
 
 
 @pytest.mark.parametrize("flux", ["upwind", "central"])
@@ -65,11 +63,10 @@ def test_run_record_fp64(flux):
     s.set_state(np.zeros((9, op.K, op.Np)))
     tr = s.run_record(0.0, dt, nsteps)
     q = s.get_state()
-    err = rel_l2_per_field(q, q_ref)
     terr = np.abs(tr - tr_ref).max() / np.abs(tr_ref).max()
-    print("state per-field rel L2:", np.array2string(err, precision=2), "trace", terr)
+    print("trace max rel", terr)
     assert np.abs(tr_ref).max() > 1e-4
-    assert err.max() <= 1e-12
+    assert_parity(q, q_ref, 1e-12, "state")
     assert terr <= 1e-11
 
 
