@@ -97,6 +97,8 @@ def parse():
     p.add_argument("--serving-precisions", default="fp32,bf16x3",
                    help="comma-separated precisions of the serving measurement")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-config1", action="store_true",
+                   help="skip the order-3 plane-wave latency and convergence measurement")
     p.add_argument("--no-peaks", action="store_true", help="skip the copy and GEMM peak measurement")
     p.add_argument("--cpu-sample-n", type=int, default=12)
     p.add_argument("--calibrate-copy", action="store_true",
@@ -349,33 +351,42 @@ def order7_layered(args, steps=20):
             "rel_l2_vs_fp64_per_field": [float(x) for x in err]}
 
 
-def serving(args, precision="fp32"):
+def serving(args, precision="fp32", batched=False, rate=None):
     """Continuous batching of independent solves: a seeded Poisson stream of
     requests (periodic Kuhn cubes, N in {3, 4, 5}, smooth random media, one
-    Ricker force with f0 in [5, 15], 16 receivers), admitted by HBM budget,
-    advanced by captured hipGraphs of 10 steps.  Latency = finish - arrival.
-    Default: 64 requests, n in [8, 24], 100-200 steps; --serving-full: the
-    full stream, 256 requests, n in [8, 32], 100-800 steps (progress on
-    stderr as requests complete)."""
+    Ricker force with f0 in [5, 15], 16 receivers), admitted by HBM budget.
+    Per-request mode: each request on its own stream, advanced by captured
+    hipGraphs of 10 steps.  Batched mode: the running requests of each order
+    advance together through one slot table, one launch per stage for the
+    whole group (dg_batch_advance), 10-step chunks.  Latency = finish -
+    arrival.  Default: 64 requests, n in [8, 24], 100-200 steps;
+    --serving-full: the full stream, 256 requests, n in [8, 32], 100-800
+    steps (progress on stderr as requests complete)."""
     from paper_2008_09441_amd.serving import Server, poisson_workload
+    rate = args.serving_rate if rate is None else rate
     if args.serving_full:
         nreq, n_range, steps = 256, (8, 32), (100, 800)
     else:
         nreq, n_range, steps = args.serving_requests, (8, 24), (100, 200)
-    reqs = poisson_workload(nreq, rate=args.serving_rate, n_range=n_range, orders=(3, 4, 5),
+    reqs = poisson_workload(nreq, rate=rate, n_range=n_range, orders=(3, 4, 5),
                             steps=steps, nrec=16, precision=precision, seed=2008)
-    srv = Server(hbm_budget=64 << 30, max_active=16, chunk=10, graphs=True, workers=4)
+    srv = Server(hbm_budget=64 << 30, max_active=16, chunk=10, graphs=True, workers=4,
+                 batched=batched)
 
     def progress(r):
         print(f"serving {precision}: request {r.rid} done, latency {r.latency:.2f} s",
               file=sys.stderr, flush=True)
     srv.run(reqs, on_result=progress if args.serving_full else None)
     st = dict(srv.stats)
-    st["workload"] = (f"{len(reqs)} Poisson requests at {args.serving_rate}/s, periodic "
+    if batched:
+        st["batch_chunks"] = srv.batch_launches
+    st["workload"] = (f"{len(reqs)} Poisson requests at {rate}/s, periodic "
                       f"n^3x6 Kuhn cubes n in [{n_range[0]},{n_range[1]}], N in {{3,4,5}}, "
                       f"{steps[0]}-{steps[1]} LSRK(5,4) steps, {precision}, smooth random media "
                       "(4 Fourier modes), 1 Ricker force (f0 in [5,15]), 16 receivers; 16 slots, "
-                      "64 GiB budget, 10-step captured graphs")
+                      "64 GiB budget, 10-step chunks, "
+                      + ("batched: one launch per stage per order over a slot table"
+                         if batched else "per-request captured graphs"))
     return st
 
 
@@ -453,6 +464,75 @@ def adjoint(args):
             "rel_diff_vs_central_difference": abs(fd - an) / max(abs(fd), 1e-300)}
 
 
+def config1(args):
+    """The order-3 plane-wave workload: n = 4 (384 tets), N = 3, rho = 1,
+    cp = 2, cs = 1, plane P wave along (1,1,0), upwind, LSRK(5,4) to T = 0.5
+    at CFL 0.5, FP64 on the GPU.  Too small for a roofline: reported as the
+    latency of a step (the 182-step run timed with HIP events after a
+    warm-up run) and as its error against the exact solution; plus the
+    convergence sweep n = 2, 4, 8, 16 at the same order to T = 0.1, with
+    the order fitted over the three finest meshes."""
+    import torch
+    import synth
+    from paper_2008_09441_amd import Solver
+
+    def run(n, T, timed=False):
+        s = Solver(3, precision="fp64", flux="upwind", device=0)
+        s.upload_mesh(synth.kuhn_cube_vertices(n))
+        s.upload_media(synth.homogeneous_media)
+        q0 = s.project_function(lambda x: synth.plane_p_wave(x, 0.0))
+        # dt from the CFL rule with h_min of the Kuhn cube (3 vol / max face area)
+        hmin = (1.0 / n) / math.sqrt(2.0)
+        nst = int(math.ceil(T / (0.5 * hmin / (2.0 * 16.0)) - 1e-12))
+        dt = T / nst
+        ms = None
+        if timed:
+            s.set_state(q0)
+            s.run(0.0, dt, nst)                      # warm-up run
+            st = torch.cuda.current_stream(0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.set_state(q0)
+            torch.cuda.synchronize()
+            e0.record(st)
+            s.run(0.0, dt, nst)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / nst
+        else:
+            s.set_state(q0)
+            s.run(0.0, dt, nst)
+        q = s.get_state()
+        qe = s.project_function(lambda x: synth.plane_p_wave(x, T))
+        norm = QuadNormOf(s)
+        err = math.sqrt(norm.sq(q - qe).sum() / norm.sq(qe).sum())
+        s.close()
+        return err, nst, ms
+    err, nst, ms = run(4, 0.5, timed=True)
+    sweep = [(n,) + run(n, 0.1)[:2] for n in (2, 4, 8, 16)]
+    errs = np.array([e for _, e, _ in sweep])
+    h = 1.0 / np.array([n for n, _, _ in sweep], dtype=np.float64)
+    slope = float(np.polyfit(np.log(h[1:]), np.log(errs[1:]), 1)[0])
+    return {"workload": "N=3, 4^3x6 = 384 tets, rho=1 cp=2 cs=1, plane P wave along (1,1,0), "
+                        "upwind, LSRK(5,4) to T=0.5 at CFL 0.5, fp64",
+            "steps": nst, "ms_per_step": ms, "us_per_stage": ms * 1e3 / 5,
+            "rel_l2_error_vs_exact": err,
+            "convergence": {"T": 0.1, "n": [n for n, _, _ in sweep],
+                            "rel_l2_error": [float(e) for e in errs],
+                            "steps": [k for _, _, k in sweep],
+                            "fitted_order_n4_to_16": slope}}
+
+
+class QuadNormOf(QuadNorm):
+    """The quadrature L2 norm of QuadNorm for an existing solver's mesh."""
+
+    def __init__(self, s):
+        from paper_2008_09441_amd import B
+        Vq = B.dg_ref_operator(s.ctx, 4)
+        w = B.dg_ref_operator(s.ctx, 7)[:, 3]
+        self.M = Vq.T @ (w[:, None] * Vq)
+        _, _, self.J = B.dg_geometry(s.ctx)
+
+
 def measured_peaks():
     """The box's achievable rates, beside the published peaks the rooflines
     use: a device-to-device copy of 2 GiB (bytes read plus written per
@@ -485,9 +565,16 @@ def measured_peaks():
     gemm_tflops = 2 * n ** 3 / timed(lambda: torch.matmul(a, b)) / 1e12
     del a, b
     torch.cuda.empty_cache()
-    return {"hbm_copy_GBps": copy_gbps, "bf16_gemm_TFLOPs": gemm_tflops,
+    from paper_2008_09441_amd import B
+    own_copy = B.dg_measure_copy(0, 2 << 30, 10)
+    own_mfma = B.dg_measure_mfma(0, 10)
+    return {"hbm_copy_GBps": own_copy, "mfma_bf16_TFLOPs": own_mfma,
+            "torch_copy_GBps": copy_gbps, "torch_bf16_gemm_TFLOPs": gemm_tflops,
             "published": {"hbm_GBps": 8000.0, "bf16_dense_TFLOPs": 2500.0},
-            "method": "2 GiB device copy; 8192^3 bf16 torch.matmul; HIP events over 10 reps"}
+            "method": "libdg dg_measure_copy (hand-written 16 B/lane copy of 2 GiB) and "
+                      "dg_measure_mfma (8 chains of v_mfma_f32_16x16x32_bf16 per wave); "
+                      "torch 2 GiB device copy and 8192^3 bf16 matmul beside them; "
+                      "HIP events over 10 reps"}
 
 
 def cpu_baseline(args, N):
@@ -633,6 +720,8 @@ def main():
             out["fp32_path"]["within_bound"] = out["fp32_path"]["l2_vs_fp64"]["energy"]["within_bound"]
         del en
         torch.cuda.empty_cache()
+    if not args.no_config1:
+        out["config1_plane_wave_order3"] = config1(args)
     if not args.no_sources:
         out["sources_receivers"] = sources_receivers(args)
     if not args.no_order7:
@@ -640,6 +729,14 @@ def main():
     if not args.no_serving:
         for prec in args.serving_precisions.split(","):
             out["serving" if prec == "fp32" else f"serving_{prec}"] = serving(args, prec)
+        out["serving_batched"] = serving(args, "fp32", batched=True)
+        # capacity: every request arrives within a fraction of a second, so
+        # the queue never empties and the rate is the server's, not the stream's
+        out["serving_saturated"] = {
+            "note": "arrivals at 1000/s: the rate is the capacity of the server",
+            "graphs_fp32": serving(args, "fp32", batched=False, rate=1000.0),
+            "batched_fp32": serving(args, "fp32", batched=True, rate=1000.0),
+            "batched_bf16x3": serving(args, "bf16x3", batched=True, rate=1000.0)}
     if not args.no_adjoint:
         out["adjoint"] = adjoint(args)
     if not args.no_peaks:

@@ -41,6 +41,7 @@ extern "C" {
 #endif
 
 typedef struct dg_ctx dg_ctx;
+typedef struct dg_batch dg_batch;
 
 /* No C++ exception crosses this interface: a host allocation failure inside
  * a call returns DG_ENOMEM, any other internal exception DG_EINVAL. */
@@ -218,6 +219,34 @@ dg_status dg_advance(dg_ctx* ctx, double dt, int64_t nsteps);
  * material or the mesh change. */
 dg_status dg_graph_advance(dg_ctx* ctx, double dt, int64_t nsteps);
 
+/* ---- Batched stepping (continuous batching of many solves) -------------
+ * Many independent contexts of one order and precision advanced together:
+ * each LSRK stage of the whole batch is one launch of the context's stage
+ * kernel over a slot table (every context owns a range of workgroups and
+ * runs the same per-tile arithmetic as alone, so each result is
+ * bit-identical alone and in a batch), followed by one source launch, and
+ * after each step one receiver launch, for all slots.  Each context steps
+ * on its own device clock with its own dt, exactly as dg_advance would, and
+ * may join or leave the batch between calls. */
+
+/* A batch object: a device slot table for up to max_slots contexts of
+ * `device` (allocated here, max_slots * a few hundred bytes).  DG_EINVAL
+ * for a bad device or max_slots outside 1 .. 65536, DG_ENOMEM. */
+dg_status dg_batch_create(dg_batch** out, int32_t device, int32_t max_slots);
+void dg_batch_destroy(dg_batch* b);   /* waits for the device first */
+
+/* nsteps LSRK(5,4) steps [CK94] of every context in ctxs[0..n): context i
+ * with time step dt[i] from its device clock, sources and receivers as in
+ * dg_advance.  All contexts: distinct, on the batch's device, same order,
+ * FP32 or DG_FP32_BF16X3, with mesh, material and state (DG_EINVAL /
+ * DG_ESTATE, reported in ctxs[0]'s dg_last_error).  Launches on `stream`
+ * (a hipStream_t; NULL: ctxs[0]'s stream); the caller orders the contexts'
+ * own streams against it (the serving loop creates every context of a batch
+ * on that stream).  Asynchronous.  The slot table is rewritten by every
+ * call; calls on one batch object are stream-ordered. */
+dg_status dg_batch_advance(dg_batch* b, void* stream, dg_ctx* const* ctxs, int32_t n,
+                           const double* dt, int64_t nsteps);
+
 /* ---- Discrete adjoint ---------------------------------------------------
  * Gradient of a receiver misfit with respect to the material: the
  * weight-adjusted weights m = (1/rho, lam, mu) at the quadrature points
@@ -299,6 +328,17 @@ dg_status dg_geometry(const dg_ctx* ctx, double* geo, double* fgeo, double* J);
  * face-neighbour tiles run close together on one XCD's L2.  A permutation
  * of 0 .. ceil(K/16) - 1.  DG_ESTATE before dg_mesh_upload. */
 dg_status dg_tile_order(const dg_ctx* ctx, int32_t* out);
+
+/* ---- Measured rates of the device (reference for rooflines) ------------
+ * dg_measure_copy: a hand-written streaming copy of `bytes` bytes (16 B per
+ * lane and access), bytes read plus bytes written per second, in GB/s.
+ * dg_measure_mfma: eight independent chains of v_mfma_f32_16x16x32_bf16 per
+ * wave, eight waves per SIMD, no memory traffic: the dense bf16 matrix-core
+ * rate in TFLOP/s.  Each is timed with HIP events over `reps` launches after
+ * a warm-up launch, on the null stream of `device`, with buffers allocated
+ * and freed here.  DG_EINVAL for bad arguments, DG_ENOMEM, DG_EDEVICE. */
+dg_status dg_measure_copy(int32_t device, int64_t bytes, int32_t reps, double* gbytes_per_s);
+dg_status dg_measure_mfma(int32_t device, int32_t reps, double* tflops);
 
 #ifdef __cplusplus
 }

@@ -23,12 +23,13 @@ EXPORTS = [
     "dg_create", "dg_destroy", "dg_last_error", "dg_sizes", "dg_mesh_upload",
     "dg_node_coords", "dg_quad_coords", "dg_material_upload", "dg_project",
     "dg_state_set", "dg_state_get", "dg_state_device_ptr", "dg_rhs", "dg_step",
+    "dg_batch_create", "dg_batch_destroy", "dg_batch_advance",
     "dg_run", "dg_synchronize", "dg_ref_operator", "dg_face_nodes",
     "dg_connectivity", "dg_geometry", "dg_tile_order", "dg_sources_set", "dg_receivers_set",
     "dg_receivers_sample", "dg_run_record", "dg_time_set", "dg_time_get",
     "dg_trace_reserve", "dg_trace_copy", "dg_advance", "dg_graph_advance", "dg_memory",
     "dg_footprint", "dg_state_zero", "dg_material_set_weights", "dg_adjoint_forward",
-    "dg_adjoint_backward",
+    "dg_adjoint_backward", "dg_measure_copy", "dg_measure_mfma",
 ]
 
 
@@ -95,6 +96,11 @@ def _load():
         "dg_material_set_weights": ([P, P, P, P, P, P], I32),
         "dg_adjoint_forward": ([P, D, D, I64, I64, P], I32),
         "dg_adjoint_backward": ([P, P, P, P], I32),
+        "dg_batch_create": ([ctypes.POINTER(P), I32, I32], I32),
+        "dg_batch_destroy": ([P], None),
+        "dg_batch_advance": ([P, P, P, I32, P, I64], I32),
+        "dg_measure_copy": ([I32, I64, I32, P], I32),
+        "dg_measure_mfma": ([I32, I32, P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -299,6 +305,49 @@ def dg_adjoint_backward(ctx, resid, grad, grad_z=None):
             raise ValueError(f"gradients must be C-contiguous float64 host arrays of {shape}")
     check(ctx, lib.dg_adjoint_backward(ctx, _ptr(np.ascontiguousarray(resid)), _ptr(grad),
                                        _ptr(grad_z) if grad_z is not None else None))
+
+
+def dg_batch_create(device, max_slots):
+    h = ctypes.c_void_p()
+    st = lib.dg_batch_create(ctypes.byref(h), int(device), int(max_slots))
+    if st != DG_OK:
+        raise DGError(st, "dg_batch_create failed")
+    return h
+
+
+def dg_batch_destroy(b):
+    lib.dg_batch_destroy(b)
+
+
+def _ctx_array(ctxs):
+    vals = [c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs]
+    return (ctypes.c_void_p * len(vals))(*vals)
+
+
+def dg_batch_advance(b, stream, ctxs, dts, nsteps):
+    """Advance the contexts ctxs (a list of dg_create handles) by nsteps steps
+    of their own time steps dts on `stream` (an int hipStream_t or None)."""
+    dts = np.ascontiguousarray(dts, dtype=np.float64)
+    if dts.shape != (len(ctxs),):
+        raise ValueError("one time step per context")
+    check(ctxs[0], lib.dg_batch_advance(b, stream or None, _ctx_array(ctxs), len(ctxs),
+                                        _ptr(dts), int(nsteps)))
+
+
+def dg_measure_copy(device, nbytes, reps=10):
+    v = ctypes.c_double()
+    st = lib.dg_measure_copy(int(device), int(nbytes), int(reps), ctypes.byref(v))
+    if st != DG_OK:
+        raise DGError(st, "dg_measure_copy failed")
+    return v.value
+
+
+def dg_measure_mfma(device, reps=10):
+    v = ctypes.c_double()
+    st = lib.dg_measure_mfma(int(device), int(reps), ctypes.byref(v))
+    if st != DG_OK:
+        raise DGError(st, "dg_measure_mfma failed")
+    return v.value
 
 
 def dg_state_zero(ctx):

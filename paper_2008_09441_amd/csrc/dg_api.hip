@@ -18,6 +18,8 @@
 #include "dg_bx.hpp"
 #include "dg_src.hpp"
 #include "dg_adj.hpp"
+#include "dg_batch.hpp"
+#include "dg_peaks.hpp"
 #include "dg_mfma_host.hpp"
 
 namespace {
@@ -45,6 +47,14 @@ struct DevBuf {
 };
 
 }  // namespace
+
+// a batch: the device slot table of dg_batch_advance and its host image
+struct dg_batch {
+  int device = 0;
+  int max_slots = 0;
+  void* table = nullptr;
+  std::vector<dgb::BatchSlot> host;
+};
 
 struct dg_ctx {
   dg_options opt{};
@@ -814,6 +824,199 @@ dg_status exception_status() {
     return DG_EINVAL;
   }
 }
+
+// ------------------------------------------------------------- batches ---
+// One launch per stage over many contexts (dg_batch.hpp): the slot table is
+// built on the host and written to device memory (the batch object's buffer,
+// or the library's static scratch array) by launches that carry it as
+// arguments, then each step runs five stage launches, five source launches
+// and one receiver launch for the whole batch.
+
+template <int N, bool F32>
+hipError_t launch_batch_stage(const dgb::BatchSlot* table, int n, int64_t grid, hipStream_t st,
+                              int par, double a, double b) {
+  if constexpr (N <= 4)
+    dgb::stage_bx_batch<N, F32><<<dim3(unsigned(grid)), dim3(dgb::kThreads), 0, st>>>(
+        table, n, par, float(a), float(b));
+  else
+    dgb::stage_be_batch<N, F32><<<dim3(unsigned(grid)), dim3(dgb::kThreads), 0, st>>>(
+        table, n, par, float(a), float(b));
+  return hipGetLastError();
+}
+
+hipError_t batch_stage(int N, bool f32, const dgb::BatchSlot* table, int n, int64_t grid,
+                       hipStream_t st, int par, double a, double b) {
+  switch (N) {
+#define DG_BATCH_CASE(NN)                                                                  \
+  case NN:                                                                                 \
+    return f32 ? launch_batch_stage<NN, true>(table, n, grid, st, par, a, b)              \
+               : launch_batch_stage<NN, false>(table, n, grid, st, par, a, b);
+    DG_BATCH_CASE(1)
+    DG_BATCH_CASE(2)
+    DG_BATCH_CASE(3)
+    DG_BATCH_CASE(4)
+    DG_BATCH_CASE(5)
+    DG_BATCH_CASE(6)
+    DG_BATCH_CASE(7)
+#undef DG_BATCH_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// the slot of context c (state buffers in the order of its current parity)
+dgb::BatchSlot batch_slot_of(const dg_ctx* c, double dt, int64_t first) {
+  dgb::BatchSlot S;
+  std::memset(&S, 0, sizeof(S));
+  const int Np = c->re.Np;
+  float* q0 = static_cast<float*>(c->q[c->cur].p);
+  float* q1 = static_cast<float*>(c->q[1 - c->cur].p);
+  float* res = static_cast<float*>(c->res.p);
+  if (c->re.N <= 4) {
+    dgb::BxArgs& A = S.k.bx;
+    A.q_in = q0;
+    A.q_out = q1;
+    A.res = res;
+    A.rhs_out = nullptr;
+    A.geo = static_cast<const float*>(c->geo.p);
+    A.fgeo = static_cast<const float*>(c->fgeo.p);
+    A.nbn = static_cast<const int32_t*>(c->nbn.p);
+    A.torder = static_cast<const int32_t*>(c->torder.p);
+    A.fmask = static_cast<const int32_t*>(c->fmask.p);
+    A.mat = static_cast<const float*>(c->matblk.p);
+    A.zp = static_cast<const float*>(c->zp.p);
+    A.zs = static_cast<const float*>(c->zs.p);
+    A.frags = static_cast<const dgb::u32x4*>(c->frags.p);
+    A.K = c->mesh.K;
+    A.dt = float(dt);
+    A.lsrk = 1;
+    A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+    S.nwg = (c->mesh.K + dgb::kTile - 1) / dgb::kTile;
+  } else {
+    dgb::BeArgs& A = S.k.be;
+    A.q_in = q0;
+    A.q_out = q1;
+    A.res = res;
+    A.rhs_out = nullptr;
+    A.geo = static_cast<const float*>(c->geo.p);
+    A.fgeo = static_cast<const float*>(c->fgeo.p);
+    A.nbn = static_cast<const int32_t*>(c->nbn.p);
+    A.fmask = static_cast<const int32_t*>(c->fmask.p);
+    A.irho = static_cast<const float*>(c->irho.p);
+    A.lam = static_cast<const float*>(c->lam.p);
+    A.mu = static_cast<const float*>(c->mu.p);
+    A.zp = static_cast<const float*>(c->zp.p);
+    A.zs = static_cast<const float*>(c->zs.p);
+    A.frags = static_cast<const dgb::u32x4*>(c->frags.p);
+    A.K = c->mesh.K;
+    A.dt = float(dt);
+    A.lsrk = 1;
+    A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+    S.nwg = c->mesh.K;
+  }
+  S.first = first;
+  S.q[0] = q0;
+  S.q[1] = q1;
+  S.res = res;
+  S.KNp = c->mesh.K * Np;
+  S.Np = Np;
+  S.nsrc = int(c->src.size());
+  S.src_elem = static_cast<const int64_t*>(c->src_elem.p);
+  S.src_w = static_cast<const float*>(c->src_w.p);
+  S.src_par = static_cast<const double*>(c->src_par.p);
+  S.nrec = c->nrec;
+  S.rec_elem = static_cast<const int64_t*>(c->rec_elem.p);
+  S.rec_w = static_cast<const float*>(c->rec_w.p);
+  S.trace = static_cast<float*>(c->trace.p);
+  S.trace_cap = c->trace_cap;
+  S.clk = static_cast<double*>(c->clk.p);
+  S.dt = dt;
+  return S;
+}
+
+// Checks the batch, builds its slot table in the host array `slots` and
+// writes it to the device array `table` (both with room for max_slots),
+// then advances every context by nsteps steps on the stream.  Errors are
+// reported on the first context.
+dg_status batch_advance_impl(void* table, dgb::BatchSlot* slots, int max_slots, void* stream,
+                             dg_ctx* const* cs, int n, const double* dt, int64_t nsteps) {
+  if (!cs || n < 1 || !cs[0]) return DG_EINVAL;
+  dg_ctx* c0 = cs[0];
+  if (!dt) return fail(c0, DG_EINVAL, "batch: null time steps");
+  if (n > max_slots)
+    return fail(c0, DG_EINVAL, "batch: " + std::to_string(n) + " contexts, more than the " +
+                                   std::to_string(max_slots) + " slots of the table");
+  if (nsteps < 0) return fail(c0, DG_EINVAL, "batch: negative step count");
+  for (int i = 0; i < n; ++i) {
+    dg_ctx* c = cs[i];
+    if (!c) return fail(c0, DG_EINVAL, "batch: null context");
+    for (int j = 0; j < i; ++j)
+      if (cs[j] == c) return fail(c0, DG_EINVAL, "batch: a context appears twice");
+    if (c->opt.device != c0->opt.device || c->re.N != c0->re.N ||
+        c->opt.precision != c0->opt.precision)
+      return fail(c0, DG_EINVAL, "batch: contexts differ in device, order or precision");
+    if (c->opt.precision != DG_FP32 && c->opt.precision != DG_FP32_BF16X3)
+      return fail(c0, DG_EINVAL, "batch: FP32 and BF16x3 contexts only");
+    if (!std::isfinite(dt[i])) return fail(c0, DG_EINVAL, "batch: non-finite time step");
+    dg_status s = ready(c, true);
+    if (s != DG_OK) return fail(c0, s, "batch: context " + std::to_string(i) + ": " + c->err);
+  }
+  dg_status s = set_device(c0);
+  if (s != DG_OK) return s;
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c0->stream;
+  int64_t pos = 0;
+  bool any_src = false, any_rec = false;
+  int max_np3 = 0, max_rec3 = 0;
+  for (int i = 0; i < n; ++i) {
+    slots[i] = batch_slot_of(cs[i], dt[i], pos);
+    pos += (slots[i].nwg + 7) / 8 * 8;
+    any_src = any_src || slots[i].nsrc > 0;
+    any_rec = any_rec || (slots[i].nrec > 0 && slots[i].trace_cap > 0);
+    max_np3 = std::max(max_np3, 3 * slots[i].Np);
+    max_rec3 = std::max(max_rec3, 3 * slots[i].nrec);
+  }
+  if (pos > 0x7fffffff) return fail(c0, DG_EINVAL, "batch: too many workgroups for one grid");
+  // the slot table, written by launches that carry it
+  const size_t words = size_t(n) * sizeof(dgb::BatchSlot) / 4;
+  static_assert(sizeof(dgb::BatchSlot) % 4 == 0, "whole words");
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(slots);
+  uint32_t* dst = static_cast<uint32_t*>(table);
+  for (size_t w0 = 0; w0 < words; w0 += dgb::kSlotWords) {
+    dgb::SlotChunk ch;
+    const int nw = int(std::min<size_t>(dgb::kSlotWords, words - w0));
+    std::memcpy(ch.w, src + w0, size_t(nw) * 4);
+    dgb::slot_write<<<1, 256, 0, st>>>(dst + w0, ch, nw);
+    DG_HIP(c0, hipGetLastError());
+  }
+  const dgb::BatchSlot* tab = static_cast<const dgb::BatchSlot*>(table);
+  const bool f32 = c0->opt.precision == DG_FP32;
+  const dim3 gsrc(unsigned((max_np3 + 255) / 256), unsigned(n));
+  const dim3 grec(unsigned((max_rec3 + 255) / 256), unsigned(n));
+  for (int64_t i = 0; i < nsteps; ++i) {
+    for (int stg = 0; stg < 5; ++stg) {
+      const int par = int((5 * i + stg) & 1);
+      const hipError_t e = batch_stage(c0->re.N, f32, tab, n, pos, st, par, kRkA[stg], kRkB[stg]);
+      if (e != hipSuccess)
+        return fail(c0, DG_EDEVICE, std::string("batch stage launch: ") + hipGetErrorString(e));
+      if (any_src) {
+        dgb::source_add_batch<<<gsrc, 256, 0, st>>>(tab, par, double(i) + kRkC[stg], kRkB[stg]);
+        DG_HIP(c0, hipGetLastError());
+      }
+    }
+    if (any_rec && max_rec3 > 0) {
+      dgb::receiver_sample_batch<<<grec, 256, 0, st>>>(tab, int((5 * (i + 1)) & 1), i);
+      DG_HIP(c0, hipGetLastError());
+    }
+  }
+  if (nsteps > 0) {
+    dgb::clock_advance_batch<<<unsigned((n + 63) / 64), 64, 0, st>>>(tab, n, nsteps);
+    DG_HIP(c0, hipGetLastError());
+  }
+  // five stages per step: the current buffer flips once per odd step count
+  if (nsteps & 1)
+    for (int i = 0; i < n; ++i) cs[i]->cur = 1 - cs[i]->cur;
+  return DG_OK;
+}
+
 
 }  // namespace
 
@@ -1756,6 +1959,120 @@ dg_status dg_geometry(const dg_ctx* c, double* geo, double* fgeo, double* J) {
   } catch (...) {
     return exception_status();
   }
+}
+
+dg_status dg_batch_create(dg_batch** out, int32_t device, int32_t max_slots) {
+  try {
+    if (!out || device < 0 || max_slots < 1 || max_slots > (1 << 16)) return DG_EINVAL;
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return DG_EDEVICE;
+    dg_batch* b = new dg_batch();
+    b->device = device;
+    b->max_slots = max_slots;
+    b->host.resize(size_t(max_slots));
+    if (hipMalloc(&b->table, size_t(max_slots) * sizeof(dgb::BatchSlot)) != hipSuccess) {
+      delete b;
+      return DG_ENOMEM;
+    }
+    *out = b;
+    return DG_OK;
+  } catch (...) {
+    return exception_status();
+  }
+}
+
+void dg_batch_destroy(dg_batch* b) {
+  if (!b) return;
+  if (b->table && hipSetDevice(b->device) == hipSuccess) {
+    (void)hipDeviceSynchronize();   // launches of the batch may still read the table
+    (void)hipFree(b->table);
+  }
+  delete b;
+}
+
+dg_status dg_batch_advance(dg_batch* b, void* stream, dg_ctx* const* ctxs, int32_t n,
+                           const double* dt, int64_t nsteps) {
+  try {
+    if (!b || !ctxs || n < 1 || !ctxs[0]) return DG_EINVAL;
+    if (ctxs[0]->opt.device != b->device)
+      return fail(ctxs[0], DG_EINVAL, "batch: contexts on another device than the batch");
+    return batch_advance_impl(b->table, b->host.data(), b->max_slots, stream, ctxs, n, dt,
+                              nsteps);
+  } catch (...) {
+    return exception_status();
+  }
+}
+
+dg_status dg_measure_copy(int32_t device, int64_t bytes, int32_t reps, double* gbytes_per_s) {
+  if (device < 0 || bytes < 16 || reps < 1 || !gbytes_per_s) return DG_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return DG_EDEVICE;
+  const int64_t n = bytes / 16;
+  void *src = nullptr, *dst = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  dg_status st = DG_OK;
+  int cus = 0;
+  float ms = 0.f;
+  if (hipMalloc(&src, size_t(n) * 16) != hipSuccess || hipMalloc(&dst, size_t(n) * 16) != hipSuccess) {
+    st = DG_ENOMEM;
+  } else if (hipMemset(src, 0, size_t(n) * 16) != hipSuccess ||
+             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) !=
+                 hipSuccess ||
+             hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    st = DG_EDEVICE;
+  } else {
+    const unsigned grid = unsigned(cus) * 16;
+    const auto* s4 = static_cast<const dgp::f32x4*>(src);
+    auto* d4 = static_cast<dgp::f32x4*>(dst);
+    dgp::copy16<<<grid, 256>>>(s4, d4, n);
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps; ++r) dgp::copy16<<<grid, 256>>>(s4, d4, n);
+    (void)hipEventRecord(e1, nullptr);
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+        ms <= 0.f)
+      st = DG_EDEVICE;
+    else
+      *gbytes_per_s = 2.0 * double(n) * 16.0 * reps / (double(ms) * 1e-3) / 1e9;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (src) (void)hipFree(src);
+  if (dst) (void)hipFree(dst);
+  return st;
+}
+
+dg_status dg_measure_mfma(int32_t device, int32_t reps, double* tflops) {
+  if (device < 0 || reps < 1 || !tflops) return DG_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return DG_EDEVICE;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return DG_EDEVICE;
+  const unsigned grid = unsigned(cus) * 8;   // eight waves per SIMD
+  const int iters = 2048;
+  float* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  dg_status st = DG_OK;
+  float ms = 0.f;
+  if (hipMalloc(&out, size_t(grid) * 256 * sizeof(float)) != hipSuccess) {
+    st = DG_ENOMEM;
+  } else if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    st = DG_EDEVICE;
+  } else {
+    dgp::mfma_loop<<<grid, 256>>>(out, iters);
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps; ++r) dgp::mfma_loop<<<grid, 256>>>(out, iters);
+    (void)hipEventRecord(e1, nullptr);
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+        ms <= 0.f) {
+      st = DG_EDEVICE;
+    } else {
+      const double flop = double(grid) * 4.0 * iters * 8.0 * 2.0 * 16 * 16 * 32 * reps;
+      *tflops = flop / (double(ms) * 1e-3) / 1e12;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (out) (void)hipFree(out);
+  return st;
 }
 
 }  // extern "C"

@@ -150,8 +150,11 @@ __device__ __forceinline__ void be_pipe_f(const BeArgs& A, int lane, Frag frag, 
   }
 }
 
+// The stage of one element: launch position bid of a grid of Gd positions
+// over the context's elements (Gd = K); the kernels below call it for a
+// single context or for one slot of a batch.
 template <int N, bool F32>
-__global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
+__device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_t bid) {
   using O = EOrd<N>;
   using OF = EFOrd<N>;
   using L = BeLds<N>;
@@ -176,7 +179,6 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int e = lane & 15, g = lane >> 4;
   // XCD-aware element order: each XCD takes one contiguous range of elements
-  const int64_t Gd = gridDim.x, bid = blockIdx.x;
   const int64_t xcd = bid & 7, per = Gd >> 3, rem8 = Gd & 7;
   const int64_t k = xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3);
   const int64_t K = A.K, KNp = K * Np;
@@ -480,6 +482,11 @@ __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
       }
     }
   }
+}
+
+template <int N, bool F32>
+__global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
+  stage_be_run<N, F32>(A, gridDim.x, blockIdx.x);
 }
 
 }  // namespace dgb

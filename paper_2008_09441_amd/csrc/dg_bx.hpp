@@ -600,8 +600,11 @@ struct TileMap {
   }
 };
 
+// The stage of one tile: launch position bid of a grid of G positions over
+// the context's tiles (G = ceil(K / 16)); the kernels below call it for a
+// single context or for one slot of a batch.
 template <int N, bool F32>
-__global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
+__device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t bid) {
   using O = BOrd<N>;
   using L = BLds<N>;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, RT = O::RT;
@@ -620,7 +623,6 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   // XCDs, so give each XCD one contiguous range of launch positions; the
   // host's tile order sweeps each range so that face neighbours run close
   // together (neighbour traces then mostly hit that XCD's L2)
-  const int64_t G = gridDim.x, bid = blockIdx.x;
   const int64_t xcd = bid & 7, per = G >> 3, rem8 = G & 7;
   const int64_t tile = A.torder[xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3)];
   const int64_t K = A.K;
@@ -883,6 +885,11 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
       }
     }
   }
+}
+
+template <int N, bool F32>
+__global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
+  stage_bx_run<N, F32>(A, gridDim.x, blockIdx.x);
 }
 
 }  // namespace dgb

@@ -574,6 +574,28 @@ std::vector<int32_t> tile_order(const MeshData& m, int tile, int parts) {
       return bx != by ? bx < by : x < y;
     });
   };
+  // Within a slab, strips of kStrip typical lengths across the sweep axis:
+  // the slab is swept strip by strip, so the tiles a sweep step covers (the
+  // strip's cross-section) are few and face neighbours along every axis
+  // inside a strip run a cross-section apart, within reach of the XCD's L2;
+  // only the neighbours across a strip boundary are far apart.
+  constexpr int kStrip = 8;
+  auto strip_sweep = [&](int64_t b, int64_t e, int du, int dv) {
+    double lu = 1e300, lv = 1e300;
+    for (int64_t i = b; i < e; ++i) {
+      lu = std::min(lu, c[size_t(ord[size_t(i)]) * 3 + du]);
+      lv = std::min(lv, c[size_t(ord[size_t(i)]) * 3 + dv]);
+    }
+    auto bucket = [&](int32_t t, int d, double lo) {
+      return int64_t(std::floor((c[size_t(t) * 3 + d] - lo) / h + 0.5));
+    };
+    std::stable_sort(ord.begin() + b, ord.begin() + e, [&](int32_t x, int32_t y) {
+      const int64_t sx = bucket(x, dv, lv) / kStrip, sy = bucket(y, dv, lv) / kStrip;
+      if (sx != sy) return sx < sy;
+      const int64_t ux = bucket(x, du, lu), uy = bucket(y, du, lu);
+      return ux != uy ? ux < uy : x < y;
+    });
+  };
   if (T == 0) return ord;
   const int a0 = longest(0, T, -1);
   sweep(0, T, a0);
@@ -583,7 +605,9 @@ std::vector<int32_t> tile_order(const MeshData& m, int tile, int parts) {
     const int64_t e = b + per + (x < rem ? 1 : 0);
     if (e - b < 2) continue;
     std::sort(ord.begin() + b, ord.begin() + e);   // element order within the slab
-    sweep(b, e, longest(b, e, a0));
+    const int du = longest(b, e, a0);               // sweep axis
+    const int dv = 3 - a0 - du;                     // strip axis
+    strip_sweep(b, e, du, dv);
   }
   return ord;
 }

@@ -20,6 +20,12 @@ receivers, run for a given number of LSRK(5,4) steps.  The server:
 * launches the next chunk of a request as soon as its previous one is
   done, so chunks of different requests overlap on the device, and new
   requests join between chunks (continuous batching);
+* or, in batched mode (``batched=True``), keeps one slot table per order
+  and precision (``dg_batch_advance``): all running requests of that order
+  advance together, each stage of the whole group being one launch over
+  the slots, with every request on its own dt and device clock; a chunk
+  runs the steps every member still needs at least, requests that finish
+  leave and newly prepared ones join at chunk boundaries;
 * on completion copies the receiver trace, frees the context and reports
   the request's latency (finish - arrival) and queueing delay.
 
@@ -111,6 +117,15 @@ class _Active:
     event: object = None
 
 
+def _collect(a: _Active):
+    """Receiver trace of a finished request, then its context is released
+    (worker thread: both wait for the request's stream)."""
+    tr = np.empty((a.req.nsteps, len(a.req.receivers), 3), dtype=a.solver.dtype)
+    B.dg_trace_copy(a.solver.ctx, tr, a.req.nsteps)
+    a.solver.close()
+    return tr
+
+
 def prepare(req: Request, stream, device=0):
     """Context of one request on its stream: mesh, media, source, receivers,
     trace, zero state, clock at 0.  Host-side work; safe on a worker thread."""
@@ -128,21 +143,65 @@ def prepare(req: Request, stream, device=0):
     return s
 
 
+@dataclass
+class _Group:
+    """Running requests of one order and precision in batched mode: their
+    contexts live on one stream and advance through one slot table; up to
+    `depth` chunks are queued on the stream at a time, so the device never
+    waits for the host between chunks."""
+    stream: object
+    batch: object
+    members: list
+    inflight: list
+
+
 class Server:
     """See the module docstring.  hbm_budget: device bytes the running
     requests may hold together; max_active: running requests at most;
     chunk: steps per launch; graphs: replay captured hipGraphs (else plain
-    launches)."""
+    launches); batched: advance the running requests of each order together
+    through dg_batch_advance (then `graphs` is not used)."""
 
     def __init__(self, hbm_budget=64 << 30, max_active=16, chunk=10, graphs=True,
-                 workers=4, device=0):
+                 workers=4, device=0, batched=False, depth=2):
         self.hbm_budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.chunk = int(chunk)
         self.graphs = graphs
+        self.batched = bool(batched)
+        self.depth = int(depth)
         self.workers = int(workers)
         self.device = device
         self.stats = {}
+        self._groups = {}
+        self.batch_launches = 0
+
+    def _group(self, req: Request):
+        import torch
+        key = (req.N, req.precision)
+        if key not in self._groups:
+            self._groups[key] = _Group(torch.cuda.Stream(device=self.device),
+                                       B.dg_batch_create(self.device, self.max_active), [], [])
+        return self._groups[key]
+
+    def _launch_group(self, g: _Group):
+        """Queue one chunk for the members that still have steps to queue:
+        the steps every one of them needs at least (at most `chunk`)."""
+        import torch
+        run = [a for a in g.members if a.done_steps < a.req.nsteps]
+        if not run:
+            return False
+        steps = min([self.chunk] + [a.req.nsteps - a.done_steps for a in run])
+        B.dg_batch_advance(g.batch, g.stream.cuda_stream, [a.solver.ctx for a in run],
+                           [a.req.dt for a in run], steps)
+        self.batch_launches += 1
+        ev = torch.cuda.Event()
+        ev.record(g.stream)
+        for a in run:
+            a.done_steps += steps
+            a.event = ev            # the chunk that holds the member's latest steps
+        g.inflight.append(ev)
+        return True
 
     def _launch_chunk(self, a: _Active):
         import torch
@@ -167,6 +226,7 @@ class Server:
                                  f"the whole budget {self.hbm_budget}")
         order = sorted(requests, key=lambda r: (r.arrival, r.rid))
         results = {}
+        finishing = {}                # future -> finished member (batched mode)
         waiting = []                  # arrived, not admitted
         preparing = {}                # future -> (req, stream, admitted)
         active = []
@@ -191,7 +251,8 @@ class Server:
                     waiting.pop(0)
                     used += fp
                     peak_used = max(peak_used, used)
-                    stream = torch.cuda.Stream(device=self.device)
+                    stream = (self._group(r).stream if self.batched
+                              else torch.cuda.Stream(device=self.device))
                     fut = pool.submit(prepare, r, stream, self.device)
                     preparing[fut] = (r, stream, now)
                     progressed = True
@@ -201,16 +262,14 @@ class Server:
                     a = _Active(r, fut.result(), stream, adm, started=clock() - start)
                     active.append(a)
                     peak_active = max(peak_active, len(active))
-                    self._launch_chunk(a)
-                    progressed = True
-                # next chunk for every request whose chunk is done
-                for a in list(active):
-                    if not a.event.query():
-                        continue
-                    progressed = True
-                    if a.done_steps < a.req.nsteps:
+                    if self.batched:
+                        self._group(r).members.append(a)   # joins at the next chunk
+                    else:
                         self._launch_chunk(a)
-                        continue
+                    progressed = True
+
+                def finish(a):
+                    nonlocal used
                     tr = np.empty((a.req.nsteps, len(a.req.receivers), 3),
                                   dtype=a.solver.dtype)
                     B.dg_trace_copy(a.solver.ctx, tr, a.req.nsteps)
@@ -223,12 +282,50 @@ class Server:
                         on_result(results[a.req.rid])
                     active.remove(a)
                     used -= a.req.footprint()
+                if self.batched:
+                    # retired chunks, finished members (their trace copy and
+                    # context release run on a worker, so that the group's
+                    # queued chunks keep the device busy), new chunks
+                    for g in self._groups.values():
+                        g.inflight = [e for e in g.inflight if not e.query()]
+                        for a in [a for a in g.members
+                                  if a.done_steps >= a.req.nsteps and a.event.query()]:
+                            g.members.remove(a)
+                            finishing[pool.submit(_collect, a)] = a
+                            progressed = True
+                        while len(g.inflight) < self.depth and self._launch_group(g):
+                            progressed = True
+                    for fut in [f for f in finishing if f.done()]:
+                        a = finishing.pop(fut)
+                        tr = fut.result()
+                        fin = clock() - start
+                        results[a.req.rid] = Result(a.req.rid, tr, a.req.arrival, a.admitted,
+                                                    a.started, fin, a.req.footprint(),
+                                                    a.req.dofs())
+                        if on_result is not None:
+                            on_result(results[a.req.rid])
+                        active.remove(a)
+                        used -= a.req.footprint()
+                        progressed = True
+                else:
+                    # next chunk for every request whose chunk is done
+                    for a in list(active):
+                        if not a.event.query():
+                            continue
+                        progressed = True
+                        if a.done_steps < a.req.nsteps:
+                            self._launch_chunk(a)
+                            continue
+                        finish(a)
                 if not progressed:
                     time.sleep(2e-4)
         finally:
             pool.shutdown(wait=True)
             for a in active:
                 a.solver.close()
+            for g in self._groups.values():
+                B.dg_batch_destroy(g.batch)
+            self._groups = {}
         end = clock() - start
         res = [results[r.rid] for r in requests]
         lat = np.array([x.latency for x in res])
@@ -241,6 +338,7 @@ class Server:
             "makespan_s": end - first,
             "dof_updates_per_s": float(sum(x.dofs for x in res) / (end - first)),
             "peak_active": peak_active,
+            "mode": "batched" if self.batched else ("graphs" if self.graphs else "plain"),
             "peak_footprint_bytes": peak_used,
             "hbm_budget_bytes": self.hbm_budget,
         }

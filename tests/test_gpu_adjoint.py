@@ -176,10 +176,11 @@ def _gpu_grad_z(s, m, zp, zs, q0, dt, nsteps, every, d):
     return tr.astype(np.float64), g, gz
 
 
-@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("fp32", 1e-3)])
-def test_impedance_gradient_matches_oracle(precision, bound):
-    print(f"case adjoint impedance gradient {precision}", flush=True)
-    op, s, m, zp, zs, q0 = _setup("upwind", precision)
+@pytest.mark.parametrize("precision,bound,n,N", [("fp64", 1e-10, 2, 2), ("fp32", 1e-3, 2, 2),
+                                                  ("fp64", 1e-10, 2, 3)])
+def test_impedance_gradient_matches_oracle(precision, bound, n, N):
+    print(f"case adjoint impedance gradient {precision} n={n} N={N}", flush=True)
+    op, s, m, zp, zs, q0 = _setup("upwind", precision, n=n, N=N)
     z = np.stack([zp, zs])
     dt, nsteps, every = 0.01, 12, 5
     d = np.random.default_rng(25).standard_normal((nsteps, len(RECS), 3)) * 0.05
@@ -201,13 +202,15 @@ def test_central_flux_impedance_gradient_is_zero():
     assert np.all(gz == 0.0)
 
 
-def test_gradient_in_material_fields_matches_central_differences_fp64():
+@pytest.mark.parametrize("N", [2, 4])
+def test_gradient_in_material_fields_matches_central_differences_fp64(N):
     """rho, lam, mu at the quadrature points and at the nodes, mapped by torch
     to m = (1/rho, lam, mu) and (Zp, Zs) = (sqrt(rho (lam + 2 mu)),
     sqrt(rho mu)); the autograd gradient against central differences of the
     GPU run that perturb all six fields (impedances recomputed)."""
     from paper_2008_09441_amd.adjoint import receiver_traces
-    op, s, m, zp, zs, q0 = _setup("upwind", "fp64")
+    print(f"case material-field gradient N={N}", flush=True)
+    op, s, m, zp, zs, q0 = _setup("upwind", "fp64", N=N)
     rho_n = synth.fourier_media(op.mesh.x)[0]
     P0 = [1.0 / m[0], m[1], m[2], rho_n, zp ** 2 / rho_n - 2.0 * zs ** 2 / rho_n,
           zs ** 2 / rho_n]

@@ -167,12 +167,14 @@ def test_sources_and_receivers_need_a_device_context():
         B.dg_destroy(ctx)
 
 
-@pytest.mark.parametrize("n", [4, 8])
+@pytest.mark.parametrize("n", [4, 8, 16])
 def test_tile_order_sweeps_slabs(n):
     # tile processing order of the matrix-core stage on the Kuhn cube: a
     # permutation; each of the eight launch ranges is one slab of hexahedron
-    # layers, swept so that face-neighbour tiles in the same range run at
-    # most two rows of tiles apart (except across the periodic seam)
+    # layers, swept strip by strip (strips 8 hexahedra wide), so that
+    # face-neighbour tiles in the same range run at most two strip
+    # cross-sections apart, except across a strip boundary or the periodic
+    # seam (at most one pair in 8 of the range's face pairs)
     s = _host(4, n)
     order = B.dg_tile_order(s.ctx)
     K = 6 * n ** 3
@@ -196,9 +198,9 @@ def test_tile_order_sweeps_slabs(n):
     ea = np.repeat(np.arange(K), 4)
     eb = etoe.reshape(-1)
     ta, tb = tile_of[ea], tile_of[eb]
-    # pairs across the periodic seam are the sweep's two ends
-    seam = (np.abs(ijk[ea] - ijk[eb]) == n - 1).any(1)
-    same = (part[ta] == part[tb]) & (ta != tb) & ~seam
-    row_tiles = -(-6 * n // 16)
+    same = (part[ta] == part[tb]) & (ta != tb)
     assert same.sum() > 0
-    assert np.abs(pos[ta[same]] - pos[tb[same]]).max() <= 2 * row_tiles
+    # a strip's cross-section: 8 hexahedra by the slab's layers, in tiles
+    cross = -(-6 * min(8, n) * max(1, n // 8) // 16)
+    near = np.abs(pos[ta[same]] - pos[tb[same]]) <= 2 * cross
+    assert near.mean() >= 7 / 8, near.mean()
