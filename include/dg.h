@@ -247,6 +247,18 @@ void dg_batch_destroy(dg_batch* b);   /* waits for the device first */
 dg_status dg_batch_advance(dg_batch* b, void* stream, dg_ctx* const* ctxs, int32_t n,
                            const double* dt, int64_t nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as dg_batch_advance, but the slot table lives in a static device array of
+ * the library (64 slots, 17,920 bytes per GPU, held until the process
+ * ends; its address is resolved once per device on the first call there).
+ * Calls no hipMalloc, hipFree or other allocating routine.  More than 64
+ * contexts: DG_EINVAL.  Every call on a GPU rewrites that GPU's one table,
+ * so calls that overlap on one GPU (from several host threads, or on
+ * streams not ordered against each other) race: order them. */
+dg_status dg_batch_advance_noalloc(void* stream, dg_ctx* const* ctxs, int32_t n,
+                                   const double* dt, int64_t nsteps);
+
 /* ---- Discrete adjoint ---------------------------------------------------
  * Gradient of a receiver misfit with respect to the material: the
  * weight-adjusted weights m = (1/rho, lam, mu) at the quadrature points

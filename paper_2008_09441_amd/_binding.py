@@ -23,7 +23,7 @@ EXPORTS = [
     "dg_create", "dg_destroy", "dg_last_error", "dg_sizes", "dg_mesh_upload",
     "dg_node_coords", "dg_quad_coords", "dg_material_upload", "dg_project",
     "dg_state_set", "dg_state_get", "dg_state_device_ptr", "dg_rhs", "dg_step",
-    "dg_batch_create", "dg_batch_destroy", "dg_batch_advance",
+    "dg_batch_create", "dg_batch_destroy", "dg_batch_advance", "dg_batch_advance_noalloc",
     "dg_run", "dg_synchronize", "dg_ref_operator", "dg_face_nodes",
     "dg_connectivity", "dg_geometry", "dg_tile_order", "dg_sources_set", "dg_receivers_set",
     "dg_receivers_sample", "dg_run_record", "dg_time_set", "dg_time_get",
@@ -99,6 +99,7 @@ def _load():
         "dg_batch_create": ([ctypes.POINTER(P), I32, I32], I32),
         "dg_batch_destroy": ([P], None),
         "dg_batch_advance": ([P, P, P, I32, P, I64], I32),
+        "dg_batch_advance_noalloc": ([P, P, I32, P, I64], I32),
         "dg_measure_copy": ([I32, I64, I32, P], I32),
         "dg_measure_mfma": ([I32, I32, P], I32),
     }
@@ -332,6 +333,16 @@ def dg_batch_advance(b, stream, ctxs, dts, nsteps):
         raise ValueError("one time step per context")
     check(ctxs[0], lib.dg_batch_advance(b, stream or None, _ctx_array(ctxs), len(ctxs),
                                         _ptr(dts), int(nsteps)))
+
+
+def dg_batch_advance_noalloc(stream, ctxs, dts, nsteps):
+    """dg_batch_advance without a batch object: the slot table lives in the
+    library's static device array (at most 64 contexts, no allocation)."""
+    dts = np.ascontiguousarray(dts, dtype=np.float64)
+    if dts.shape != (len(ctxs),):
+        raise ValueError("one time step per context")
+    check(ctxs[0], lib.dg_batch_advance_noalloc(stream or None, _ctx_array(ctxs), len(ctxs),
+                                                _ptr(dts), int(nsteps)))
 
 
 def dg_measure_copy(device, nbytes, reps=10):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -1017,6 +1018,14 @@ dg_status batch_advance_impl(void* table, dgb::BatchSlot* slots, int max_slots, 
   return DG_OK;
 }
 
+// The allocation-free variant's slot table: a static device array, one copy
+// per GPU, whose address each device resolves once (hipGetSymbolAddress) the
+// first time the entry point runs on it; host code uses only that address.
+constexpr int kBatchStaticSlots = 64;
+static __device__ __align__(256) unsigned char scratch[kBatchStaticSlots * sizeof(dgb::BatchSlot)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 }  // namespace
 
@@ -1998,6 +2007,39 @@ dg_status dg_batch_advance(dg_batch* b, void* stream, dg_ctx* const* ctxs, int32
       return fail(ctxs[0], DG_EINVAL, "batch: contexts on another device than the batch");
     return batch_advance_impl(b->table, b->host.data(), b->max_slots, stream, ctxs, n, dt,
                               nsteps);
+  } catch (...) {
+    return exception_status();
+  }
+}
+
+dg_status dg_batch_advance_noalloc(void* stream, dg_ctx* const* ctxs, int32_t n,
+                                   const double* dt, int64_t nsteps) {
+  try {
+    if (!ctxs || n < 1 || !ctxs[0]) return DG_EINVAL;
+    dg_ctx* c0 = ctxs[0];
+    if (n > kBatchStaticSlots)
+      return fail(c0, DG_EINVAL, "batch (no allocation): " + std::to_string(n) +
+                                     " contexts, at most " + std::to_string(kBatchStaticSlots));
+    dg_status s = set_device(c0);
+    if (s != DG_OK) return s;
+    const int dev = c0->opt.device;
+    if (dev >= kMaxDevices) return fail(c0, DG_EINVAL, "batch (no allocation): device index");
+    void* tab = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      if (!g_scratch_ptr[dev]) {
+        // with the device current: each GPU holds its own copy of the array
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+          return fail(c0, DG_EDEVICE, std::string("batch (no allocation): scratch address: ") +
+                                          hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+      }
+      tab = g_scratch_ptr[dev];
+    }
+    dgb::BatchSlot host[kBatchStaticSlots];
+    return batch_advance_impl(tab, host, kBatchStaticSlots, stream, ctxs, n, dt, nsteps);
   } catch (...) {
     return exception_status();
   }
