@@ -96,6 +96,8 @@ def parse():
                    help="serve the full stream (256 requests, n in [8,32], 100-800 steps)")
     p.add_argument("--serving-precisions", default="fp32,bf16x3",
                    help="comma-separated precisions of the serving measurement")
+    p.add_argument("--serving-batched", action="store_true",
+                   help="with --serving-full: batched stepping instead of per-request graphs")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-config1", action="store_true",
                    help="skip the order-3 plane-wave latency and convergence measurement")
@@ -702,6 +704,18 @@ def main():
         out["fp64_path"] = {"value": dofs * args.steps / sec64,
                             "ms_per_step": sec64 / args.steps * 1e3,
                             "kernel": stage_kernel_name("fp64", N)}
+        # the FP64 comparator against its own roofline: the dense
+        # contractions of an element-stage (D_r, D_s, D_t, LIFT, V_q, P_q over
+        # nine fields; 261,450 flop at order 4) against the 78.6 TFLOP/s FP64
+        # peak, and its FP64 algorithmic bytes against HBM
+        Np_, Nfp_, Nq_ = (N + 1) * (N + 2) * (N + 3) // 6, (N + 1) * (N + 2) // 2, (N + 1) ** 3
+        dense = 2 * 9 * (3 * Np_ * Np_ + Np_ * 4 * Nfp_ + 2 * Nq_ * Np_)
+        f64_stage = sec64 / (5 * args.steps)
+        a64 = dense * K / f64_stage / 1e12
+        out["fp64_path"]["roofline"] = {
+            "bound": "fp64", "achieved": a64, "peak": 78.6, "unit": "TFLOP/s",
+            "frac": a64 / 78.6, "flop_per_element_stage": dense,
+            "hbm_frac": alg_bytes_per_elem_stage(N, 8) * K / f64_stage / 8e12}
         out["speedup_vs_fp64_path"] = sec64 / sec
         norm = QuadNorm(args)
         out["l2_vs_fp64"] = {"norm": "quadrature L2 after warmup+steps", **norm.errors(q_lo, q64)}
@@ -726,7 +740,12 @@ def main():
         out["sources_receivers"] = sources_receivers(args)
     if not args.no_order7:
         out["order7_layered"] = order7_layered(args)
-    if not args.no_serving:
+    if not args.no_serving and args.serving_full:
+        # the full stream: one run per listed precision, per-request graphs
+        # (or batched with --serving-batched), at --serving-rate
+        for prec in args.serving_precisions.split(","):
+            out[f"serving_full_{prec}"] = serving(args, prec, batched=args.serving_batched)
+    elif not args.no_serving:
         for prec in args.serving_precisions.split(","):
             out["serving" if prec == "fp32" else f"serving_{prec}"] = serving(args, prec)
         out["serving_batched"] = serving(args, "fp32", batched=True)
