@@ -612,6 +612,11 @@ def cpu_baseline(args, N):
                       f"({sec:.1f} s)"}
 
 
+def progress(msg):
+    """One line on stderr as each measurement finishes (stdout keeps the JSON)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -645,6 +650,7 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    progress(f"{args.precision} path timed: {sec / args.steps * 1e3:.3f} ms per step")
 
     dofs = 9 * K * Np
     value = dofs * args.steps / sec
@@ -699,6 +705,7 @@ def main():
         out["fp32_path"]["roofline"] = {"bound": "mfma", "achieved": a32, "peak": 157.3,
                                         "unit": "TFLOP/s", "frac": a32 / 157.3,
                                         "flop_per_element_stage": flop}
+        progress("fp32 path timed")
     if not args.no_fp64_reference and args.precision != "fp64":
         sec64, q64 = other_path("fp64")
         out["fp64_path"] = {"value": dofs * args.steps / sec64,
@@ -717,6 +724,7 @@ def main():
             "frac": a64 / 78.6, "flop_per_element_stage": dense,
             "hbm_frac": alg_bytes_per_elem_stage(N, 8) * K / f64_stage / 8e12}
         out["speedup_vs_fp64_path"] = sec64 / sec
+        progress("fp64 path timed")
         norm = QuadNorm(args)
         out["l2_vs_fp64"] = {"norm": "quadrature L2 after warmup+steps", **norm.errors(q_lo, q64)}
         if "fp32_path" in out:
@@ -734,12 +742,16 @@ def main():
             out["fp32_path"]["within_bound"] = out["fp32_path"]["l2_vs_fp64"]["energy"]["within_bound"]
         del en
         torch.cuda.empty_cache()
+        progress("errors against the fp64 path computed")
     if not args.no_config1:
         out["config1_plane_wave_order3"] = config1(args)
+        progress("configuration 1 measured")
     if not args.no_sources:
         out["sources_receivers"] = sources_receivers(args)
+        progress("sources and receivers measured")
     if not args.no_order7:
         out["order7_layered"] = order7_layered(args)
+        progress("order 7 measured")
     if not args.no_serving and args.serving_full:
         # the full stream: one run per listed precision, per-request graphs
         # (or batched with --serving-batched), at --serving-rate
@@ -758,8 +770,10 @@ def main():
             "batched_bf16x3": serving(args, "bf16x3", batched=True, rate=1000.0)}
     if not args.no_adjoint:
         out["adjoint"] = adjoint(args)
+        progress("adjoint measured")
     if not args.no_peaks:
         out["peaks_measured"] = measured_peaks()
+        progress("peaks measured")
         out["roofline"]["frac_of_measured_copy"] = (
             out["roofline"]["achieved"] / out["peaks_measured"]["hbm_copy_GBps"])
     if not args.no_cpu_baseline:
