@@ -116,7 +116,7 @@ def stage_kernel_name(precision, N):
     if precision == "fp32":
         return f"stage_bx<{N},f32>" if N <= 4 else f"stage_be<{N},f32>"
     if N <= 4:
-        return f"stage_cols<double,{N}>"
+        return f"stage_bx_d<{N}>"
     return f"stage_generic<double,{N}>"
 
 

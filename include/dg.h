@@ -54,8 +54,9 @@ typedef enum {
   DG_ENONFINITE = 5   /* non-finite input                              */
 } dg_status;
 
-/* DG_FP64: FP64 state and arithmetic (the column kernel at orders 1-4, the
- * generic kernel at 5-7).  DG_FP32: FP32 state and arithmetic, with the
+/* DG_FP64: FP64 state and arithmetic (the dense contractions on the FP64
+ * matrix cores, 16x16x4 products, at orders 1-4; the generic kernel at 5-7).
+ * DG_FP32: FP32 state and arithmetic, with the
  * dense contractions on the FP32 matrix cores (16x16x4 products).
  * DG_FP32_BF16X3: FP32 state, the dense contractions as split products of
  * bf16 hi/lo parts on the matrix cores with FP32 accumulation (three

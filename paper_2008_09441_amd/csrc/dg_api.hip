@@ -136,12 +136,14 @@ dg_status fail(dg_ctx* c, dg_status s, const std::string& msg) {
 
 bool device_ctx(const dg_ctx* c) { return c->opt.device >= 0; }
 
-// The 16-element-tile matrix-core stage (dg_bx.hpp) runs BF16x3 and FP32 at
-// orders 1-4; it reads the blocked material, the neighbour-node table and
-// the tile order.  The [K][Nq] material is held by every other context and
-// by FP32 ones too (adjoint, sources).
+// The 16-element-tile matrix-core stage (dg_bx.hpp) runs every precision at
+// orders 1-4 (BF16x3, FP32 and FP64 products); it reads the blocked
+// material, the neighbour-node table and the tile order.  The [K][Nq]
+// material is held by every other context and by FP32 and FP64 ones too
+// (adjoint, sources).
 bool tiled_kernel(int32_t precision, int order) {
-  return order <= 4 && (precision == DG_FP32_BF16X3 || precision == DG_FP32);
+  return order <= 4 &&
+         (precision == DG_FP32_BF16X3 || precision == DG_FP32 || precision == DG_FP64);
 }
 bool plain_material(int32_t precision, int order) {
   return !(precision == DG_FP32_BF16X3 && order <= 4);
@@ -256,56 +258,47 @@ hipError_t launch_generic(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* r
   return hipGetLastError();
 }
 
-template <typename T, int N>
-hipError_t launch_cols(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_out, double a,
-                       double b, double dt, int lsrk) {
-  const dgh::RefElement& re = c->re;
-  dgk::ColArgs<T> A;
-  using CO = dgk::ColOrder<N>;
-  const T* ops = static_cast<const T*>(c->opsT.p);
-  const size_t dsz = size_t(re.Np) * CO::NpP;
+// FP64 stage on the matrix cores at orders 1-4: the tiled kernel with FP64
+// fragments and v_mfma_f64_16x16x4f64 (dg_bx.hpp)
+template <int N>
+hipError_t launch_mfma_d(const dg_ctx* c, const double* q_in, double* q_out, double* res,
+                         double* rhs_out, double a, double b, double dt, int lsrk) {
+  dgb::BxArgsT<double> A;
   A.q_in = q_in;
   A.q_out = q_out;
   A.res = res;
   A.rhs_out = rhs_out;
-  A.geo = static_cast<const T*>(c->geo.p);
-  A.fgeo = static_cast<const T*>(c->fgeo.p);
-  A.etoe = static_cast<const int32_t*>(c->etoe.p);
-  A.etop = static_cast<const uint8_t*>(c->etop.p);
-  A.pat = static_cast<const int32_t*>(c->pat.p);
+  A.geo = static_cast<const double*>(c->geo.p);
+  A.fgeo = static_cast<const double*>(c->fgeo.p);
+  A.nbn = static_cast<const int32_t*>(c->nbn.p);
+  A.torder = static_cast<const int32_t*>(c->torder.p);
   A.fmask = static_cast<const int32_t*>(c->fmask.p);
-  A.irho = static_cast<const T*>(c->irho.p);
-  A.lam = static_cast<const T*>(c->lam.p);
-  A.mu = static_cast<const T*>(c->mu.p);
-  A.zp = static_cast<const T*>(c->zp.p);
-  A.zs = static_cast<const T*>(c->zs.p);
-  A.DrT = ops;
-  A.DsT = ops + dsz;
-  A.DtT = ops + 2 * dsz;
-  A.LIFTT = ops + 3 * dsz;
-  A.VqT = A.LIFTT + size_t(4 * re.Nfp) * CO::NpP;
-  A.PqT = A.VqT + size_t(re.Np) * CO::QP;
+  A.mat = static_cast<const double*>(c->matblk.p);
+  A.zp = static_cast<const double*>(c->zp.p);
+  A.zs = static_cast<const double*>(c->zs.p);
+  A.frags = static_cast<const dgb::u32x4*>(c->frags.p);
   A.K = c->mesh.K;
-  A.a = T(a);
-  A.b = T(b);
-  A.dt = T(dt);
+  A.a = a;
+  A.b = b;
+  A.dt = dt;
   A.lsrk = lsrk;
   A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
-  constexpr int E = dgk::ColLayout<T, N>::E;
-  const int64_t nblk = (c->mesh.K + E - 1) / E;
-  dgk::stage_cols<T, N><<<dim3(unsigned(nblk)), dim3(dgk::kBlock), 0, c->stream>>>(A);
+  const int64_t tiles = (c->mesh.K + dgb::kTile - 1) / dgb::kTile;
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  dgb::stage_bx_d<N><<<dim3(unsigned(tiles)), dim3(dgb::kThreads), 0, c->stream>>>(A);
   return hipGetLastError();
 }
 
-// FP64 contexts: the column kernel at orders 1-4, the generic kernel at 5-7
-// (FP32 and BF16x3 contexts run on the matrix cores, launch_mfma)
+// FP64 contexts: the matrix-core tiled kernel at orders 1-4, the generic
+// kernel at 5-7 (FP32 and BF16x3 contexts run on the matrix cores at every
+// order, launch_mfma)
 hipError_t launch_stage_f64(const dg_ctx* c, const double* q_in, double* q_out, double* res,
                             double* rhs_out, double a, double b, double dt, int lsrk) {
   switch (c->re.N) {
-    case 1: return launch_cols<double, 1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 2: return launch_cols<double, 2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 3: return launch_cols<double, 3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 4: return launch_cols<double, 4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 1: return launch_mfma_d<1>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 2: return launch_mfma_d<2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 3: return launch_mfma_d<3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 4: return launch_mfma_d<4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 5: return launch_generic<double, 5>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 6: return launch_generic<double, 6>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 7: return launch_generic<double, 7>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
@@ -633,7 +626,7 @@ dga::AdjArgs<T> adj_args(const dg_ctx* c) {
   A.LIFT = ops + 3 * size_t(Np) * Np;
   A.Vq = A.LIFT + size_t(Np) * NF4;
   A.Pq = A.Vq + size_t(Nq) * Np;
-  // the transposed pack of the column kernel: DrT | DsT | DtT | LIFTT | VqT | PqT
+  // the transposed operator pack: DrT | DsT | DtT | LIFTT | VqT | PqT
   A.NpP = 4 * ((Np + 3) / 4);
   A.QP = 32 * ((Nq + 31) / 32);
   const T* opsT = static_cast<const T*>(c->opsT.p);
@@ -1069,7 +1062,7 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
       const dgh::RefElement& re = c->re;
       for (const auto* v : {&re.Dr, &re.Ds, &re.Dt, &re.LIFT, &re.Vq, &re.Pq})
         ops.insert(ops.end(), v->begin(), v->end());
-      // transposed, padded operators for the column kernel
+      // transposed, padded operators (generic FP64 kernel, adjoint)
       const std::vector<double> opsT = dgh::col_operators(re);
       if (upload_real(c, c->opsT, opsT.data(), opsT.size()) != DG_OK ||
           upload_real(c, c->ops, ops.data(), ops.size()) != DG_OK ||
@@ -1085,6 +1078,12 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
         }
       } else if (opt->precision == DG_FP32) {
         const std::vector<float> fr = dgh::mfma_fragments_f32(re);
+        if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
+          dg_destroy(c);
+          return DG_ENOMEM;
+        }
+      } else if (re.N <= 4) {   // FP64 on the matrix cores
+        const std::vector<double> fr = dgh::mfma_fragments_f64(re);
         if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
           dg_destroy(c);
           return DG_ENOMEM;
@@ -1175,7 +1174,7 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
     if ((s = upload_raw(c, c->etoe, md.EToE.data(), md.EToE.size())) != DG_OK) return s;
     if ((s = upload_raw(c, c->etop, md.EToP.data(), md.EToP.size())) != DG_OK) return s;
     if ((s = upload_raw(c, c->pat, md.pat.data(), md.pat.size())) != DG_OK) return s;
-    if (tiled_mfma(c)) {
+    if (tiled_mfma(c) || tiled_kernel(c->opt.precision, c->re.N)) {
       if (K * c->re.Np >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "mesh: K Np too large");
       const std::vector<int32_t> nbn = dgh::neighbour_nodes(c->re, md);
       if ((s = upload_raw(c, c->nbn, nbn.data(), nbn.size())) != DG_OK) return s;
@@ -1254,7 +1253,7 @@ dg_status dg_material_upload(dg_ctx* c, const double* rho_q, const double* cp_q,
     }
     if (tiled_kernel(c->opt.precision, c->re.N)) {
       const std::vector<double> blk =
-          dgh::mfma_material(c->re.N, K, a.data(), b.data(), d.data());
+          dgh::mfma_material(c->re.N, K, a.data(), b.data(), d.data(), c->opt.precision == DG_FP64);
       if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
     }
     if (plain_material(c->opt.precision, c->re.N)) {
@@ -1708,12 +1707,13 @@ dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc
     b += NF4 * 4;                                                       // face masks
     if (precision == DG_FP32_BF16X3) b += uint64_t(dgh::mfma_frag_count(order)) * 64 * 8 * 2;
     else if (precision == DG_FP32) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 16;
+    else if (order <= 4) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 32;   // FP64 fragments
     b += k * (9 + 16) * e + k * 4 * 4 + k * 4 + 96 * Nfp * 4;          // geometry, tables
     b += 3 * 9 * k * Np * e + 2 * sizeof(double);                      // q[2], res, clock
-    if (precision == DG_FP32_BF16X3 || precision == DG_FP32)
+    if (precision == DG_FP32_BF16X3 || precision == DG_FP32 || order <= 4)
       b += k * NF4 * 4;                                                 // neighbour nodes
     if (tiled_kernel(precision, order)) {
-      b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * 4;   // blocked material
+      b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * e;   // blocked material
       b += (k + 15) / 16 * 4;                                           // tile order
     }
     if (plain_material(precision, order)) b += 3 * k * Nq * e;          // 1/rho, lam, mu
@@ -1754,7 +1754,8 @@ dg_status dg_material_set_weights(dg_ctx* c, const double* irho_q, const double*
     if (s != DG_OK) return s;
     DG_HIP(c, hipStreamSynchronize(c->stream));
     if (tiled_kernel(c->opt.precision, c->re.N)) {
-      const std::vector<double> blk = dgh::mfma_material(c->re.N, K, irho_q, lam_q, mu_q);
+      const std::vector<double> blk =
+          dgh::mfma_material(c->re.N, K, irho_q, lam_q, mu_q, c->opt.precision == DG_FP64);
       if ((s = upload_real(c, c->matblk, blk.data(), blk.size())) != DG_OK) return s;
     }
     if (plain_material(c->opt.precision, c->re.N)) {

@@ -50,30 +50,42 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// four values of the working precision: the MFMA accumulator of a lane and
+// one lane's entry of an FP32 / FP64 operator fragment
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef f32x4 type; };
+template <> struct Vec4<double> { typedef f64x4 type; };
+template <typename T> using v4_t = typename Vec4<T>::type;
 
 constexpr int kThreads = 256;   // four waves
 constexpr int kTile = 16;       // elements per workgroup
 constexpr int kES = 17;         // LDS stride of a row of 16 element values (odd)
 
-struct BxArgs {
-  const float* q_in;     // [9][K][Np]
-  float* q_out;          // [9][K][Np] (LSRK mode)
-  float* res;            // [9][K][Np] (LSRK mode)
-  float* rhs_out;        // [9][K][Np] (rhs mode)
-  const float* geo;      // [K][9]: d(r,s,t)_i / d(x,y,z)_j at i*3+j
-  const float* fgeo;     // [K][4][4]: outward unit normal, Fscale
+// Arguments of the stage in working precision T (float: BF16x3 or FP32
+// matrix-core products; double: FP64 matrix-core products)
+template <typename T>
+struct BxArgsT {
+  const T* q_in;         // [9][K][Np]
+  T* q_out;              // [9][K][Np] (LSRK mode)
+  T* res;                // [9][K][Np] (LSRK mode)
+  T* rhs_out;            // [9][K][Np] (rhs mode)
+  const T* geo;          // [K][9]: d(r,s,t)_i / d(x,y,z)_j at i*3+j
+  const T* fgeo;         // [K][4][4]: outward unit normal, Fscale
   const int32_t* nbn;    // [K][4 Nfp]: neighbour volume node nb * Np + vP of each face node
   const int32_t* fmask;  // [4][Nfp]
   const int32_t* torder; // [ceil(K/16)]: tile processed at each launch position
-  const float* mat;      // [ceil(K/16)][3][MATS]: 1/rho, lam, mu blocked
-  const float* zp;       // [K][Np]
-  const float* zs;
-  const u32x4* frags;    // [NFRAG][64]
+  const T* mat;          // [ceil(K/16)][3][MATS]: 1/rho, lam, mu blocked
+  const T* zp;           // [K][Np]
+  const T* zs;
+  const u32x4* frags;    // BF16x3: [NFRAG][64] u32x4; FP32 / FP64: FOrd fragments of T
   int64_t K;
-  float a, b, dt;
+  T a, b, dt;
   int lsrk;              // 0: write rhs_out; 1: fused LSRK update
   int upwind;            // 1 upwind, 0 central
 };
+typedef BxArgsT<float> BxArgs;
 
 
 // Output component c (vx vy vz sxx syy szz syz sxz sxy) of the volume term
@@ -131,8 +143,8 @@ __device__ __forceinline__ void split8(const float* v, bf16x8& hi, bf16x8& lo) {
   }
 }
 
-// LDS use of one workgroup, in floats, and its padded allocation in bytes
-template <int N>
+// LDS use of one workgroup, in values of T, and its padded allocation in bytes
+template <int N, typename T = float>
 struct BLds {
   using O = BOrd<N>;
   static constexpr int SQ = 9 * O::Np * kES;             // q       [9][Np][17]
@@ -143,10 +155,10 @@ struct BLds {
   // the three-component wave keeps its V_q B operands (hi/lo, lane order)
   // in LDS behind the result rows during phase D
   static constexpr int RO = (SR + 3) & ~3;
-  static constexpr int SRL = 3 * O::SVQ * 2 * 64 * 4;
+  static constexpr int SRL = sizeof(T) == 4 ? 3 * O::SVQ * 2 * 64 * 4 : 0;
   static constexpr int SU = SF > RO + SRL ? SF : RO + SRL;
   static constexpr int OFF_U = (SQ + SG + SZ + 3) & ~3;  // 16-byte aligned union
-  static constexpr int USED = (OFF_U + SU) * 4;
+  static constexpr int USED = (OFF_U + SU) * int(sizeof(T));
   // Padded so that the workgroups one CU can hold (160 KiB of LDS) never use
   // more than 128 KiB together (at most 3 per CU at >40 KiB each, or 2 at
   // >53.3 KiB each).
@@ -242,18 +254,17 @@ __device__ __forceinline__ void vol_lift(const BxArgs& A, const float* sq, const
 // Material samples of chunk ch for this lane: m[f][u] holds quadrature
 // points 32 ch + 16 u + 4 g + j (j < 4) of field f (1/rho, lam, mu); only the
 // fields wave W uses are loaded
-template <int N, int W>
-__device__ __forceinline__ void mat_chunk(const BxArgs& A, int64_t tile, int lane, int ch,
-                                          f32x4 (&m)[3][2]) {
+template <int N, int W, typename T = float>
+__device__ __forceinline__ void mat_chunk(const BxArgsT<T>& A, int64_t tile, int lane, int ch,
+                                          v4_t<T> (&m)[3][2]) {
   using O = BOrd<N>;
   constexpr bool need[3] = {W == 0 || W == 1, W == 2, W != 0};
-  const f32x4* mat = reinterpret_cast<const f32x4*>(A.mat) + tile * 3 * (O::MATS / 4);
+  const v4_t<T>* mat = reinterpret_cast<const v4_t<T>*>(A.mat) + tile * 3 * (O::MATS / 4);
 #pragma unroll
   for (int f = 0; f < 3; ++f)
 #pragma unroll
     for (int u = 0; u < 2; ++u)
-      m[f][u] = need[f] ? mat[f * (O::MATS / 4) + (ch * 2 + u) * 64 + lane]
-                        : f32x4{0.f, 0.f, 0.f, 0.f};
+      m[f][u] = need[f] ? mat[f * (O::MATS / 4) + (ch * 2 + u) * 64 + lane] : v4_t<T>{0, 0, 0, 0};
 }
 
 // Phase D for wave W: V_q, material, P_q; the nodal result goes to sr.  m0
@@ -405,27 +416,35 @@ __device__ __forceinline__ void quad_proj(const BxArgs& A, int64_t tile, int lan
 __device__ __forceinline__ f32x4 mma_f(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f64x4 mma_f(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
-// Phase C of the FP32 kernel for wave W: acc[i][t] = rows 16 t + 4 g + j of
-// r_{comp i}, one K slot per lane and step (the order of FOrd); operator
-// fragments are fetched one group of four steps ahead.
-template <int N, int W>
-__device__ __forceinline__ void vol_lift_f(const BxArgs& A, const float* sq, const float* sg,
-                                           const float* sF, int lane,
-                                           f32x4 (&acc)[3][BOrd<N>::RT]) {
+// 1 / x: the hardware reciprocal (1 ulp) in FP32, a division in FP64
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+
+// Phase C of the FP32 / FP64 kernel for wave W: acc[i][t] = rows
+// 16 t + 4 g + j of r_{comp i}, one K slot per lane and step (the order of
+// FOrd); operator fragments are fetched one group of four steps ahead.
+template <int N, int W, typename T>
+__device__ __forceinline__ void vol_lift_f(const BxArgsT<T>& A, const T* sq, const T* sg,
+                                           const T* sF, int lane,
+                                           v4_t<T> (&acc)[3][BOrd<N>::RT]) {
   using O = FOrd<N>;
+  using V4 = v4_t<T>;
   constexpr int Np = O::Np, NF4 = O::NF4, RT = O::RT, NB = O::NB, SV = O::SV, SV4 = O::SV4;
   constexpr int NC = wave_ncomp(W);
   const int e = lane & 15, g = lane >> 4;
-  const f32x4* fr = reinterpret_cast<const f32x4*>(A.frags) + O::OFF_V;
-  float G[9];
+  const V4* fr = reinterpret_cast<const V4*>(A.frags) + O::OFF_V;
+  T G[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) G[i] = sg[e * 9 + i];
 #pragma unroll
   for (int i = 0; i < NC; ++i)
 #pragma unroll
-    for (int t = 0; t < RT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  f32x4 fc[RT], fn[RT];
+    for (int t = 0; t < RT; ++t) acc[i][t] = V4{0, 0, 0, 0};
+  V4 fc[RT], fn[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) fc[t] = fr[(t * SV4) * 64 + lane];
 #pragma unroll
@@ -439,18 +458,18 @@ __device__ __forceinline__ void vol_lift_f(const BxArgs& A, const float* sq, con
     for (int j = 0; j < 4; ++j) {
       const int s = 4 * q + j;
       if (s >= SV) break;
-      float b[NC];
+      T b[NC];
       if (s < 3 * NB) {
         // U_{c,d} at node 4 (s / 3) + g (clamped: beyond Np the operator is zero)
         const int d = s % 3, m = min(4 * (s / 3) + g, Np - 1);
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
           const int c = wave_comp(W, i);
-          float u = 0.f;
+          T u = 0;
 #pragma unroll
           for (int jj = 0; jj < 3; ++jj)
             if (comp_weight(c, jj) != 0.f)
-              u += G[d * 3 + jj] * comp_weight(c, jj) * sq[(comp_field(c, jj) * Np + m) * kES + e];
+              u += G[d * 3 + jj] * T(comp_weight(c, jj)) * sq[(comp_field(c, jj) * Np + m) * kES + e];
           b[i] = u;
         }
       } else {
@@ -473,27 +492,28 @@ __device__ __forceinline__ void vol_lift_f(const BxArgs& A, const float* sq, con
 // 16 t + 4 g + j), the pointwise weight-adjusted material operator, and
 // P_q with the weighted values as the B operand (K step (u, j) is point
 // 16 u + 4 g + j); the nodal result goes to sr.
-template <int N, int W>
-__device__ __forceinline__ void quad_proj_f(const BxArgs& A, int64_t tile, int lane,
-                                            const f32x4 (&acc)[3][BOrd<N>::RT],
-                                            const f32x4 (&m0)[3][2], float* sr) {
+template <int N, int W, typename T>
+__device__ __forceinline__ void quad_proj_f(const BxArgsT<T>& A, int64_t tile, int lane,
+                                            const v4_t<T> (&acc)[3][BOrd<N>::RT],
+                                            const v4_t<T> (&m0)[3][2], T* sr) {
   using O = FOrd<N>;
+  using V4 = v4_t<T>;
   constexpr int Np = O::Np, RT = O::RT, QT = O::QT, QC = O::QC;
   constexpr int NC = wave_ncomp(W);
   const int e = lane & 15, g = lane >> 4;
-  const f32x4* frq = reinterpret_cast<const f32x4*>(A.frags) + O::OFF_Q;
-  const f32x4* frp = reinterpret_cast<const f32x4*>(A.frags) + O::OFF_P;
-  f32x4 out[NC][RT];
+  const V4* frq = reinterpret_cast<const V4*>(A.frags) + O::OFF_Q;
+  const V4* frp = reinterpret_cast<const V4*>(A.frags) + O::OFF_P;
+  V4 out[NC][RT];
 #pragma unroll
   for (int i = 0; i < NC; ++i)
 #pragma unroll
-    for (int t = 0; t < RT; ++t) out[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  f32x4 m[3][2];
+    for (int t = 0; t < RT; ++t) out[i][t] = V4{0, 0, 0, 0};
+  V4 m[3][2];
 #pragma unroll
   for (int f = 0; f < 3; ++f) m[f][0] = m0[f][0], m[f][1] = m0[f][1];
 #pragma unroll
   for (int ch = 0; ch < QC; ++ch) {
-    f32x4 fv[2][RT], fp[RT][2];
+    V4 fv[2][RT], fp[RT][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int qt = 2 * ch + u < QT ? 2 * ch + u : QT - 1;
@@ -503,15 +523,15 @@ __device__ __forceinline__ void quad_proj_f(const BxArgs& A, int64_t tile, int l
         fp[t][u] = frp[(t * QT + qt) * 64 + lane];
       }
     }
-    f32x4 mn[3][2];
-    if (ch + 1 < QC) mat_chunk<N, W>(A, tile, lane, ch + 1, mn);
+    V4 mn[3][2];
+    if (ch + 1 < QC) mat_chunk<N, W, T>(A, tile, lane, ch + 1, mn);
     __builtin_amdgcn_sched_barrier(0);
-    f32x4 w[NC][2];
+    V4 w[NC][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
-        w[i][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        w[i][u] = V4{0, 0, 0, 0};
         if (2 * ch + u < QT) {
 #pragma unroll
           for (int t = 0; t < RT; ++t)
@@ -520,9 +540,9 @@ __device__ __forceinline__ void quad_proj_f(const BxArgs& A, int64_t tile, int l
         }
       }
     }
-    const f32x4* mi = m[0];
-    const f32x4* ml = m[1];
-    const f32x4* mm = m[2];
+    const V4* mi = m[0];
+    const V4* ml = m[1];
+    const V4* mm = m[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if constexpr (W == 0) {
@@ -530,15 +550,15 @@ __device__ __forceinline__ void quad_proj_f(const BxArgs& A, int64_t tile, int l
         w[1][u] *= mi[u];
       } else if constexpr (W == 1) {
         w[0][u] *= mi[u];
-        w[1][u] *= 2.f * mm[u];
+        w[1][u] *= T(2) * mm[u];
       } else if constexpr (W == 2) {
-        const f32x4 tr = w[0][u] + w[1][u] + w[2][u];
-        const f32x4 m2 = 2.f * mm[u];
+        const V4 tr = w[0][u] + w[1][u] + w[2][u];
+        const V4 m2 = T(2) * mm[u];
 #pragma unroll
         for (int i = 0; i < 3; ++i) w[i][u] = ml[u] * tr + m2 * w[i][u];
       } else {
-        w[0][u] *= 2.f * mm[u];
-        w[1][u] *= 2.f * mm[u];
+        w[0][u] *= T(2) * mm[u];
+        w[1][u] *= T(2) * mm[u];
       }
     }
 #pragma unroll
@@ -563,7 +583,7 @@ __device__ __forceinline__ void quad_proj_f(const BxArgs& A, int64_t tile, int l
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int n = 16 * t + 4 * g + j;
+        const int n = 16 * t + acc_row(sizeof(T) == 8, g, j);
         if (n < Np) sr[(wave_comp(W, i) * Np + n) * kES + e] = out[i][t][j];
       }
 }
@@ -603,17 +623,19 @@ struct TileMap {
 // The stage of one tile: launch position bid of a grid of G positions over
 // the context's tiles (G = ceil(K / 16)); the kernels below call it for a
 // single context or for one slot of a batch.
-template <int N, bool F32>
-__device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t bid) {
+template <int N, bool F32, typename T = float>
+__device__ __forceinline__ void stage_bx_run(const BxArgsT<T>& A, int64_t G, int64_t bid) {
+  static_assert(F32 || sizeof(T) == 4, "BF16x3 products work on FP32 data");
   using O = BOrd<N>;
-  using L = BLds<N>;
+  using L = BLds<N, T>;
+  using V4 = v4_t<T>;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, RT = O::RT;
-  __shared__ __align__(16) float smem[L::BYTES / 4];
-  float* sq = smem;               // [9][Np][17]
-  float* sg = sq + L::SQ;         // [16][9]
-  float* sz = sg + L::SG;         // [2][Np][17]: Z_p, Z_s of the tile's nodes
-  float* sF = smem + L::OFF_U;    // [9][NF4][17]  (phases B, C)
-  float* sr = sF;                 // [9][Np][17]   (phases D, E)
+  __shared__ __align__(16) T smem[L::BYTES / sizeof(T)];
+  T* sq = smem;                   // [9][Np][17]
+  T* sg = sq + L::SQ;             // [16][9]
+  T* sz = sg + L::SG;             // [2][Np][17]: Z_p, Z_s of the tile's nodes
+  T* sF = smem + L::OFF_U;        // [9][NF4][17]  (phases B, C)
+  T* sr = sF;                     // [9][Np][17]   (phases D, E)
   bf16x8* srl = reinterpret_cast<bf16x8*>(sF + L::RO);   // wave 2, phase D
 
   const int tid = threadIdx.x;
@@ -655,7 +677,7 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
   constexpr int IF = (TF + kThreads - 1) / kThreads;
   int vM[IF];
   bool ok[IF];
-  float fg[IF][4], qP[IF][9], zpP[IF], zsP[IF];
+  T fg[IF][4], qP[IF][9], zpP[IF], zsP[IF];
   unsigned nbi[IF];
   {
     // level 1: the face-node task tables (the gathers depend on nbn), the
@@ -663,7 +685,7 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
     // gathers.  Issue order matters: the load counter is in order, so the
     // gathers wait for nbn but not for the state loads.
     const int32_t* nbt = A.nbn + e0 * NF4;
-    const f32x4* fgt = reinterpret_cast<const f32x4*>(A.fgeo) + e0 * 4;
+    const V4* fgt = reinterpret_cast<const V4*>(A.fgeo) + e0 * 4;
     unsigned ecs[IF];
 #pragma unroll
     for (int it = 0; it < IF; ++it) {
@@ -674,22 +696,22 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
       ecs[it] = min(e, unsigned(ne - 1));   // a valid element of the tile
       nbi[it] = unsigned(nbt[ecs[it] * NF4 + jf]);
       vM[it] = A.fmask[jf];
-      const f32x4 g4 = fgt[ecs[it] * 4 + jf / Nfp];
+      const V4 g4 = fgt[ecs[it] * 4 + jf / Nfp];
 #pragma unroll
       for (int j = 0; j < 4; ++j) fg[it][j] = g4[j];
     }
     __builtin_amdgcn_sched_barrier(0);
-    const float* qt = A.q_in + e0 * Np;
-    float vm[TileMap<N>::MI > 0 ? TileMap<N>::MI : 1][9], vt[TileMap<N>::IT];
+    const T* qt = A.q_in + e0 * Np;
+    T vm[TileMap<N>::MI > 0 ? TileMap<N>::MI : 1][9], vt[TileMap<N>::IT];
 #pragma unroll
     for (int it = 0; it < TileMap<N>::MI; ++it)
 #pragma unroll
       for (int f = 0; f < 9; ++f) vm[it][f] = (qt + f * KNp)[tm.main_row(tid, it)];
 #pragma unroll
     for (int j = 0; j < TileMap<N>::IT; ++j) vt[j] = qt[tm.tail_field(tid, j) * KNp + tm.tail_row(tid, j)];
-    const float gv = tid < kTile * 9 && tid / 9 < ne ? A.geo[e0 * 9 + tid] : 0.f;
+    const T gv = tid < kTile * 9 && tid / 9 < ne ? A.geo[e0 * 9 + tid] : T(0);
     constexpr int IZ = (kTile * Np + kThreads - 1) / kThreads;
-    float zv[2][IZ];
+    T zv[2][IZ];
 #pragma unroll
     for (int it = 0; it < IZ; ++it) {
       const unsigned r = min(unsigned(tid + it * kThreads), unsigned(tm.rmax));
@@ -737,10 +759,10 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
       const int idx = tid + it * kThreads;
       const int e = min(idx / NF4, kTile - 1);
       const int jf = idx - (idx / NF4) * NF4;
-      float qM[9];
+      T qM[9];
 #pragma unroll
       for (int f = 0; f < 9; ++f) qM[f] = sq[(f * Np + vM[it]) * kES + e];
-      const float nx = fg[it][0], ny = fg[it][1], nz = fg[it][2], fs = fg[it][3];
+      const T nx = fg[it][0], ny = fg[it][1], nz = fg[it][2], fs = fg[it][3];
       // neighbour trace: from LDS when the neighbour is in the tile
       const unsigned rl = nbi[it] - unsigned(e0 * Np);
       const bool inT = rl < unsigned(kTile * Np);
@@ -750,52 +772,52 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
         const int ln = int((rc - en * Np) * kES + en);
 #pragma unroll
         for (int f = 0; f < 9; ++f) {
-          const float x = sq[f * Np * kES + ln];
+          const T x = sq[f * Np * kES + ln];
           qP[it][f] = inT ? x : qP[it][f];
         }
-        const float zpl = sz[ln], zsl = sz[Np * kES + ln];
+        const T zpl = sz[ln], zsl = sz[Np * kES + ln];
         zpP[it] = inT ? zpl : zpP[it];
         zsP[it] = inT ? zsl : zsP[it];
       }
-      const float* P = qP[it];
-      const float jtx = (P[3] - qM[3]) * nx + (P[8] - qM[8]) * ny + (P[7] - qM[7]) * nz;
-      const float jty = (P[8] - qM[8]) * nx + (P[4] - qM[4]) * ny + (P[6] - qM[6]) * nz;
-      const float jtz = (P[7] - qM[7]) * nx + (P[6] - qM[6]) * ny + (P[5] - qM[5]) * nz;
-      const float jvx = P[0] - qM[0], jvy = P[1] - qM[1], jvz = P[2] - qM[2];
-      float dvx, dvy, dvz, dtx, dty, dtz;
+      const T* P = qP[it];
+      const T jtx = (P[3] - qM[3]) * nx + (P[8] - qM[8]) * ny + (P[7] - qM[7]) * nz;
+      const T jty = (P[8] - qM[8]) * nx + (P[4] - qM[4]) * ny + (P[6] - qM[6]) * nz;
+      const T jtz = (P[7] - qM[7]) * nx + (P[6] - qM[6]) * ny + (P[5] - qM[5]) * nz;
+      const T jvx = P[0] - qM[0], jvy = P[1] - qM[1], jvz = P[2] - qM[2];
+      T dvx, dvy, dvz, dtx, dty, dtz;
       if (A.upwind) {
         const int lm = vM[it] * kES + e;
-        const float ZpM = sz[lm], ZsM = sz[Np * kES + lm], ZpP = zpP[it], ZsP = zsP[it];
-        const float jvn = jvx * nx + jvy * ny + jvz * nz;
-        const float jtn = jtx * nx + jty * ny + jtz * nz;
-        // hardware reciprocals (1 ulp): the impedance sums are positive
-        const float dvn = (ZpP * jvn + jtn) * __builtin_amdgcn_rcpf(ZpM + ZpP);
-        const float ivs = __builtin_amdgcn_rcpf(ZsM + ZsP);
-        const float dvtx = (ZsP * (jvx - jvn * nx) + (jtx - jtn * nx)) * ivs;
-        const float dvty = (ZsP * (jvy - jvn * ny) + (jty - jtn * ny)) * ivs;
-        const float dvtz = (ZsP * (jvz - jvn * nz) + (jtz - jtn * nz)) * ivs;
+        const T ZpM = sz[lm], ZsM = sz[Np * kES + lm], ZpP = zpP[it], ZsP = zsP[it];
+        const T jvn = jvx * nx + jvy * ny + jvz * nz;
+        const T jtn = jtx * nx + jty * ny + jtz * nz;
+        // reciprocals of the (positive) impedance sums: 1 ulp in FP32
+        const T dvn = (ZpP * jvn + jtn) * rcp_t(ZpM + ZpP);
+        const T ivs = rcp_t(ZsM + ZsP);
+        const T dvtx = (ZsP * (jvx - jvn * nx) + (jtx - jtn * nx)) * ivs;
+        const T dvty = (ZsP * (jvy - jvn * ny) + (jty - jtn * ny)) * ivs;
+        const T dvtz = (ZsP * (jvz - jvn * nz) + (jtz - jtn * nz)) * ivs;
         dvx = dvn * nx + dvtx;
         dvy = dvn * ny + dvty;
         dvz = dvn * nz + dvtz;
-        const float dtn = ZpM * dvn;
+        const T dtn = ZpM * dvn;
         dtx = dtn * nx + ZsM * dvtx;
         dty = dtn * ny + ZsM * dvty;
         dtz = dtn * nz + ZsM * dvtz;
       } else {
-        dvx = 0.5f * jvx; dvy = 0.5f * jvy; dvz = 0.5f * jvz;
-        dtx = 0.5f * jtx; dty = 0.5f * jty; dtz = 0.5f * jtz;
+        dvx = T(0.5) * jvx; dvy = T(0.5) * jvy; dvz = T(0.5) * jvz;
+        dtx = T(0.5) * jtx; dty = T(0.5) * jty; dtz = T(0.5) * jtz;
       }
-      const float z = ok[it] ? fs : 0.f;   // zero flux outside the tile
-      float fl[9];
+      const T z = ok[it] ? fs : T(0);   // zero flux outside the tile
+      T fl[9];
       fl[0] = z * dtx;
       fl[1] = z * dty;
       fl[2] = z * dtz;
       fl[3] = z * dvx * nx;
       fl[4] = z * dvy * ny;
       fl[5] = z * dvz * nz;
-      fl[6] = z * 0.5f * (dvy * nz + dvz * ny);
-      fl[7] = z * 0.5f * (dvx * nz + dvz * nx);
-      fl[8] = z * 0.5f * (dvx * ny + dvy * nx);
+      fl[6] = z * T(0.5) * (dvy * nz + dvz * ny);
+      fl[7] = z * T(0.5) * (dvx * nz + dvz * nx);
+      fl[8] = z * T(0.5) * (dvx * ny + dvy * nx);
       if (idx < TF) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) sF[(c * NF4 + jf) * kES + e] = fl[c];
@@ -805,14 +827,14 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
   __syncthreads();
 
   // C: volume + LIFT per wave
-  f32x4 acc[3][RT];
-  f32x4 m0[3][2];   // chunk-0 material, in flight during phase C
+  V4 acc[3][RT];
+  V4 m0[3][2];   // chunk-0 material, in flight during phase C
   if constexpr (F32) {
     switch (grp) {
-      case 0: mat_chunk<N, 0>(A, tile, lane, 0, m0); vol_lift_f<N, 0>(A, sq, sg, sF, lane, acc); break;
-      case 1: mat_chunk<N, 1>(A, tile, lane, 0, m0); vol_lift_f<N, 1>(A, sq, sg, sF, lane, acc); break;
-      case 2: mat_chunk<N, 2>(A, tile, lane, 0, m0); vol_lift_f<N, 2>(A, sq, sg, sF, lane, acc); break;
-      default: mat_chunk<N, 3>(A, tile, lane, 0, m0); vol_lift_f<N, 3>(A, sq, sg, sF, lane, acc); break;
+      case 0: mat_chunk<N, 0, T>(A, tile, lane, 0, m0); vol_lift_f<N, 0, T>(A, sq, sg, sF, lane, acc); break;
+      case 1: mat_chunk<N, 1, T>(A, tile, lane, 0, m0); vol_lift_f<N, 1, T>(A, sq, sg, sF, lane, acc); break;
+      case 2: mat_chunk<N, 2, T>(A, tile, lane, 0, m0); vol_lift_f<N, 2, T>(A, sq, sg, sF, lane, acc); break;
+      default: mat_chunk<N, 3, T>(A, tile, lane, 0, m0); vol_lift_f<N, 3, T>(A, sq, sg, sF, lane, acc); break;
     }
   } else {
     switch (grp) {
@@ -827,10 +849,10 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
   // D: quadrature and projection per wave
   if constexpr (F32) {
     switch (grp) {
-      case 0: quad_proj_f<N, 0>(A, tile, lane, acc, m0, sr); break;
-      case 1: quad_proj_f<N, 1>(A, tile, lane, acc, m0, sr); break;
-      case 2: quad_proj_f<N, 2>(A, tile, lane, acc, m0, sr); break;
-      default: quad_proj_f<N, 3>(A, tile, lane, acc, m0, sr); break;
+      case 0: quad_proj_f<N, 0, T>(A, tile, lane, acc, m0, sr); break;
+      case 1: quad_proj_f<N, 1, T>(A, tile, lane, acc, m0, sr); break;
+      case 2: quad_proj_f<N, 2, T>(A, tile, lane, acc, m0, sr); break;
+      default: quad_proj_f<N, 3, T>(A, tile, lane, acc, m0, sr); break;
     }
   } else {
     switch (grp) {
@@ -853,7 +875,7 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
   constexpr int EP = 3 * 64, EI = (kTile * Np + EP - 1) / EP;
   const int64_t t0 = e0 * Np;
   unsigned er[EI];
-  float rs[9][EI];
+  T rs[9][EI];
   if (grp != 2) {
     const int u = (grp > 2 ? grp - 1 : grp) * 64 +
                   int(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
@@ -874,9 +896,9 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
 #pragma unroll
       for (int f = 0; f < 9; ++f) {
         const int64_t fb = t0 + f * KNp;
-        const float rv = sr[f * Np * kES + li];
+        const T rv = sr[f * Np * kES + li];
         if (A.lsrk) {
-          const float rr = A.a * rs[f][it] + A.dt * rv;
+          const T rr = A.a * rs[f][it] + A.dt * rv;
           (A.res + fb)[er[it]] = rr;
           (A.q_out + fb)[er[it]] = sq[f * Np * kES + li] + A.b * rr;
         } else {
@@ -890,6 +912,14 @@ __device__ __forceinline__ void stage_bx_run(const BxArgs& A, int64_t G, int64_t
 template <int N, bool F32>
 __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   stage_bx_run<N, F32>(A, gridDim.x, blockIdx.x);
+}
+
+// FP64 stage on the matrix cores (v_mfma_f64_16x16x4f64): the FP32 kernel's
+// tiling in double precision.  At order 4 its LDS (124 KiB) holds one
+// workgroup per CU, whose waves may then use all 512 registers of a lane.
+template <int N>
+__global__ __launch_bounds__(kThreads, 1) void stage_bx_d(BxArgsT<double> A) {
+  stage_bx_run<N, true, double>(A, gridDim.x, blockIdx.x);
 }
 
 }  // namespace dgb

@@ -23,6 +23,11 @@
 
 namespace dgb {
 
+// Row of a 16-row accumulator tile held in item j (of 4) by the lanes of
+// group g = lane / 16: the f32 and bf16 16x16 products place rows 4 g + j
+// there, v_mfma_f64_16x16x4f64 places rows 4 j + g (measured on gfx950).
+constexpr int acc_row(bool f64, int g, int j) { return f64 ? 4 * j + g : 4 * g + j; }
+
 template <int N>
 struct BOrd {
   static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
@@ -85,9 +90,9 @@ namespace dgb {
 //  [Dr|Ds|Dt|LIFT], step s < 3 NB (NB = ceil(Np / 4) node blocks): node
 //      4 (s / 3) + g in reference direction s % 3; step s >= 3 NB: face
 //      node 4 (s - 3 NB) + g;
-//  V_q, quadrature tile u, step (t, j): node 16 t + 4 g + j (node tile t's
-//      accumulator row);
-//  P_q, node tile t, step (u, j): quadrature point 16 u + 4 g + j.
+//  V_q, quadrature tile u, step (t, j): node 16 t + acc_row(g, j) (node tile
+//      t's accumulator row; 4 g + j in FP32, 4 j + g in FP64);
+//  P_q, node tile t, step (u, j): quadrature point 16 u + acc_row(g, j).
 // Fragments hold four consecutive steps per lane (one float4): vol
 // [RT][SV4][64][4], V_q [QT][RT][64][4], P_q [RT][QT][64][4]; lane l of
 // tile t has operator row 16 t + l % 16.  Slots beyond the counts are zero.

@@ -1,7 +1,7 @@
-// Device kernels of the FP64 DG elastic-wave stage: the generic LDS-staged
-// kernel (orders 5-7), templated on the order N, and the column kernel
-// (orders 1-4) below.  FP32 and BF16x3 stages run on the matrix cores
-// (dg_bx.hpp, dg_be.hpp).
+// Device kernel of the FP64 DG elastic-wave stage at orders 5-7: the generic
+// LDS-staged kernel, templated on the order N.  Every precision at orders
+// 1-4, and FP32 and BF16x3 at 5-7, run on the matrix cores (dg_bx.hpp,
+// dg_be.hpp).
 //
 // One workgroup owns a block of E consecutive elements and runs the whole
 // stage for them in six phases separated by workgroup barriers:
@@ -295,365 +295,6 @@ template <typename T>
 __global__ void fill_kernel(T* p, int64_t n, T v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
-}
-
-}  // namespace dgk
-
-namespace dgk {
-
-// --------------------------------------------------------------------------
-// Column kernel (orders 1-4, FP64).  A workgroup of four waves owns
-// E = 7 CPL elements; lane l < 63 of every wave owns the output component
-// c = l / 7 of the CPL elements e = l % 7 + 7 p (p < CPL), and each wave owns
-// a block of operator rows, so that every dense contraction is a chain of
-// FMAs whose operator entry is the same for the whole wave (a scalar operand,
-// read through the scalar cache) and whose other factor is one LDS read per
-// column:
-//   A  stage q[9][E][Np] and the metric terms in LDS;
-//   B  face fluxes [9][E][4 Nfp] in LDS (one thread per element face node);
-//   C  r_c = sum_d D_d U_{c,d} + LIFT f_c with U_{c,d} = sum_j G_dj A_cj,
-//      (A_c0, A_c1, A_c2) the stress row of component c (div sigma) or the
-//      symmetrised velocity pattern (eps(v)); rows split over the waves;
-//   D  for each chunk of 32 quadrature points: V_q r (rows split over the
-//      waves), material weights (one thread per element point), P_q
-//      accumulation into each lane's node rows;
-//   E  stage update or right-hand side store, coalesced over [9][K][Np].
-// The operators are stored transposed and zero padded to whole row blocks
-// (NpP = 4 RN node rows, QP = multiple of 32 quadrature rows) so that the row
-// loops carry no bounds tests and their scalar loads can be issued together.
-constexpr int kColW = 7;      // elements per column set (7 x 9 components = 63 lanes)
-constexpr int kColQC = 32;    // quadrature points per chunk
-constexpr int kColQS = 33;    // LDS row stride of a chunk (odd: conflict-free column reads)
-
-template <int N>
-struct ColOrder {
-  using O = Order<N>;
-  static constexpr int RN = (O::Np + 3) / 4;          // node rows per wave
-  static constexpr int NpP = 4 * RN;                  // padded node rows
-  static constexpr int QP = ((O::Nq + kColQC - 1) / kColQC) * kColQC;
-  static constexpr int RQ = kColQC / 4;               // quadrature rows per wave and chunk
-};
-
-// one column set per lane (7 elements per workgroup)
-template <typename T>
-constexpr int col_sets() { return 1; }
-
-template <typename T, int N>
-struct ColLayout {
-  using O = Order<N>;
-  static constexpr int E = kColW * col_sets<T>();
-  static constexpr int SQ = 9 * E * O::Np;
-  static constexpr int NFS = O::NF4 + 1 - (O::NF4 & 1);   // odd row stride of the flux rows
-  static constexpr int SF = 9 * E * NFS;
-  static constexpr int SR = 9 * E * O::Np;
-  static constexpr int SW = 9 * E * kColQS;
-  static constexpr int SG = E * 9;
-  // [sq | sg | union(sF, (sr | sw))]; the operators are read through the
-  // scalar cache
-  static constexpr int SU = SF > SR + SW ? SF : SR + SW;
-  static constexpr int LDS_USED = (SQ + SG + SU) * int(sizeof(T));
-  // Padded so that the workgroups one CU can hold (160 KiB of LDS) never use
-  // more than 128 KiB together (at most 3 per CU at >40 KiB each, or 2 at
-  // >53.3 KiB each): the largest per-CU LDS footprint any kernel of this
-  // library has run with is kept below that.
-  static constexpr int FLOOR = LDS_USED <= 43690 ? 40976 : (LDS_USED <= 65536 ? 54630 : 0);
-  static constexpr int LDS = LDS_USED > FLOOR ? LDS_USED : FLOOR;
-};
-
-template <typename T>
-struct ColArgs {
-  const T* q_in;
-  T* q_out;
-  T* res;
-  T* rhs_out;
-  const T* geo;          // [K][9]
-  const T* fgeo;         // [K][4][4]
-  const int32_t* etoe;
-  const uint8_t* etop;
-  const int32_t* pat;
-  const int32_t* fmask;
-  const T* irho;         // [K][Nq]
-  const T* lam;
-  const T* mu;
-  const T* zp;           // [K][Np]
-  const T* zs;
-  const T* DrT;          // [Np][NpP]: DrT[m][n] = Dr[n][m], zero padded rows
-  const T* DsT;
-  const T* DtT;
-  const T* LIFTT;        // [4 Nfp][NpP]
-  const T* VqT;          // [Np][QP]
-  const T* PqT;          // [Nq][NpP]
-  int64_t K;
-  T a, b, dt;
-  int lsrk;
-  int upwind;
-};
-
-template <typename T, int N>
-__global__ __launch_bounds__(kBlock) void stage_cols(ColArgs<T> A) {
-  static_assert(sizeof(T) == 8, "the column kernel is the FP64 stage");
-  using O = Order<N>;
-  using CO = ColOrder<N>;
-  using L = ColLayout<T, N>;
-  constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, Nq = O::Nq;
-  constexpr int E = L::E, CPL = col_sets<T>();
-  constexpr int RN = CO::RN, NpP = CO::NpP, QP = CO::QP, RQ = CO::RQ;
-  constexpr int NFS = L::NFS, QS = kColQS;
-  __shared__ __align__(16) unsigned char smem_raw[L::LDS];
-  T* sq = reinterpret_cast<T*>(smem_raw);   // [9][E][Np]
-  T* sg = sq + L::SQ;                       // [E][9]
-  T* su = sg + L::SG;
-  T* sF = su;                               // [9][E][NFS]     (phases B, C)
-  T* sr = su;                               // [9][E][Np]      (phase D)
-  T* sw = su + L::SR;                       // [9][E][QS]      (phase D)
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t K = A.K;
-  const int64_t KNp = K * Np;
-  const int64_t e0 = int64_t(blockIdx.x) * E;
-  const int ne = int((K - e0) < E ? (K - e0) : E);
-  const bool col = lane < 9 * kColW;
-  const int ce = lane % kColW, cc = lane / kColW;   // column: element set offset, component
-
-  // A: stage q and metric terms
-  for (int idx = tid; idx < 9 * E * Np; idx += kBlock) {
-    const int f = idx / (E * Np);
-    const int rem = idx - f * E * Np;
-    sq[idx] = (rem / Np < ne) ? A.q_in[f * KNp + e0 * Np + rem] : T(0);
-  }
-  for (int idx = tid; idx < E * 9; idx += kBlock)
-    sg[idx] = (idx / 9 < ne) ? A.geo[e0 * 9 + idx] : T(0);
-  __syncthreads();
-
-  // B: face fluxes
-  for (int idx = tid; idx < E * NF4; idx += kBlock) {
-    const int el = idx / NF4, j = idx - el * NF4;
-    T fl[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) fl[c] = T(0);
-    if (el < ne) {
-      const int face = j / Nfp, i = j - face * Nfp;
-      const int64_t k = e0 + el;
-      const int vM = A.fmask[face * Nfp + i];
-      const int64_t nb = A.etoe[k * 4 + face];
-      const int vP = A.pat[int(A.etop[k * 4 + face]) * Nfp + i];
-      T qM[9], qP[9];
-#pragma unroll
-      for (int f = 0; f < 9; ++f) {
-        qM[f] = sq[(f * E + el) * Np + vM];
-        qP[f] = A.q_in[f * KNp + nb * Np + vP];
-      }
-      const T* fg = A.fgeo + (k * 4 + face) * 4;
-      const T nx = fg[0], ny = fg[1], nz = fg[2], fs = fg[3];
-      const T jtx = (qP[3] - qM[3]) * nx + (qP[8] - qM[8]) * ny + (qP[7] - qM[7]) * nz;
-      const T jty = (qP[8] - qM[8]) * nx + (qP[4] - qM[4]) * ny + (qP[6] - qM[6]) * nz;
-      const T jtz = (qP[7] - qM[7]) * nx + (qP[6] - qM[6]) * ny + (qP[5] - qM[5]) * nz;
-      const T jvx = qP[0] - qM[0], jvy = qP[1] - qM[1], jvz = qP[2] - qM[2];
-      T dvx, dvy, dvz, dtx, dty, dtz;
-      if (A.upwind) {
-        const T ZpM = A.zp[k * Np + vM], ZsM = A.zs[k * Np + vM];
-        const T ZpP = A.zp[nb * Np + vP], ZsP = A.zs[nb * Np + vP];
-        const T jvn = jvx * nx + jvy * ny + jvz * nz;
-        const T jtn = jtx * nx + jty * ny + jtz * nz;
-        const T dvn = (ZpP * jvn + jtn) / (ZpM + ZpP);
-        const T ivs = T(1) / (ZsM + ZsP);
-        const T dvtx = (ZsP * (jvx - jvn * nx) + (jtx - jtn * nx)) * ivs;
-        const T dvty = (ZsP * (jvy - jvn * ny) + (jty - jtn * ny)) * ivs;
-        const T dvtz = (ZsP * (jvz - jvn * nz) + (jtz - jtn * nz)) * ivs;
-        dvx = dvn * nx + dvtx;
-        dvy = dvn * ny + dvty;
-        dvz = dvn * nz + dvtz;
-        const T dtn = ZpM * dvn;
-        dtx = dtn * nx + ZsM * dvtx;
-        dty = dtn * ny + ZsM * dvty;
-        dtz = dtn * nz + ZsM * dvtz;
-      } else {
-        dvx = T(0.5) * jvx; dvy = T(0.5) * jvy; dvz = T(0.5) * jvz;
-        dtx = T(0.5) * jtx; dty = T(0.5) * jty; dtz = T(0.5) * jtz;
-      }
-      fl[0] = fs * dtx;
-      fl[1] = fs * dty;
-      fl[2] = fs * dtz;
-      fl[3] = fs * dvx * nx;
-      fl[4] = fs * dvy * ny;
-      fl[5] = fs * dvz * nz;
-      fl[6] = fs * T(0.5) * (dvy * nz + dvz * ny);
-      fl[7] = fs * T(0.5) * (dvx * nz + dvz * nx);
-      fl[8] = fs * T(0.5) * (dvx * ny + dvy * nx);
-    }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) sF[(c * E + el) * NFS + j] = fl[c];
-  }
-  __syncthreads();
-
-  // C: volume + lift for the wave's node rows, columns (ce + 7 p, cc)
-  const int n0 = wave * RN;
-  const T* oDr = A.DrT;
-  const T* oDs = A.DsT;
-  const T* oDt = A.DtT;
-  const T* oLf = A.LIFTT;
-  T acc[CPL][RN];
-#pragma unroll
-  for (int p = 0; p < CPL; ++p)
-#pragma unroll
-    for (int i = 0; i < RN; ++i) acc[p][i] = T(0);
-  if (col) {
-    // (A_c0, A_c1, A_c2): the stress row of component c (div sigma rows) or
-    // the symmetrised velocity pattern (eps(v) rows), as field index and weight
-    int fa0 = 0, fa1 = 0, fa2 = 0;
-    T wa0 = T(0), wa1 = T(0), wa2 = T(0);
-    switch (cc) {
-      case 0: fa0 = 3; fa1 = 8; fa2 = 7; wa0 = wa1 = wa2 = T(1); break;      // (sxx, sxy, sxz)
-      case 1: fa0 = 8; fa1 = 4; fa2 = 6; wa0 = wa1 = wa2 = T(1); break;      // (sxy, syy, syz)
-      case 2: fa0 = 7; fa1 = 6; fa2 = 5; wa0 = wa1 = wa2 = T(1); break;      // (sxz, syz, szz)
-      case 3: fa0 = 0; wa0 = T(1); break;                                     // (vx, 0, 0)
-      case 4: fa1 = 1; wa1 = T(1); break;                                     // (0, vy, 0)
-      case 5: fa2 = 2; wa2 = T(1); break;                                     // (0, 0, vz)
-      case 6: fa1 = 2; fa2 = 1; wa1 = wa2 = T(0.5); break;                    // (0, vz, vy)/2
-      case 7: fa0 = 2; fa2 = 0; wa0 = wa2 = T(0.5); break;                    // (vz, 0, vx)/2
-      default: fa0 = 1; fa1 = 0; wa0 = wa1 = T(0.5); break;                   // (vy, vx, 0)/2
-    }
-    T gm[CPL][9];
-    const T* q0[CPL];
-    const T* q1[CPL];
-    const T* q2[CPL];
-#pragma unroll
-    for (int p = 0; p < CPL; ++p) {
-      const int el = ce + kColW * p;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) gm[p][i] = sg[el * 9 + i];
-      q0[p] = sq + (fa0 * E + el) * Np;
-      q1[p] = sq + (fa1 * E + el) * Np;
-      q2[p] = sq + (fa2 * E + el) * Np;
-    }
-#pragma unroll 2
-    for (int m = 0; m < Np; ++m) {
-      const T* dr = oDr + m * NpP + n0;
-      const T* ds = oDs + m * NpP + n0;
-      const T* dt = oDt + m * NpP + n0;
-#pragma unroll
-      for (int p = 0; p < CPL; ++p) {
-        const T a0 = wa0 * q0[p][m], a1 = wa1 * q1[p][m], a2 = wa2 * q2[p][m];
-        const T ur = gm[p][0] * a0 + gm[p][1] * a1 + gm[p][2] * a2;
-        const T us = gm[p][3] * a0 + gm[p][4] * a1 + gm[p][5] * a2;
-        const T ut = gm[p][6] * a0 + gm[p][7] * a1 + gm[p][8] * a2;
-#pragma unroll
-        for (int i = 0; i < RN; ++i) acc[p][i] += dr[i] * ur + ds[i] * us + dt[i] * ut;
-      }
-    }
-#pragma unroll 2
-    for (int j = 0; j < NF4; ++j) {
-      const T* lf = oLf + j * NpP + n0;
-#pragma unroll
-      for (int p = 0; p < CPL; ++p) {
-        const T fv = sF[(cc * E + ce + kColW * p) * NFS + j];
-#pragma unroll
-        for (int i = 0; i < RN; ++i) acc[p][i] += lf[i] * fv;
-      }
-    }
-  }
-  __syncthreads();   // flux buffer and phase-C operators consumed
-  if (col) {
-#pragma unroll
-    for (int p = 0; p < CPL; ++p)
-#pragma unroll
-      for (int i = 0; i < RN; ++i)
-        if (n0 + i < Np) sr[(cc * E + ce + kColW * p) * Np + n0 + i] = acc[p][i];
-  }
-  __syncthreads();
-  const T* oVq = A.VqT;
-  const T* oPq = A.PqT;
-
-  // D: quadrature chunks: V_q -> material -> P_q (accumulated in acc)
-#pragma unroll
-  for (int p = 0; p < CPL; ++p)
-#pragma unroll
-    for (int i = 0; i < RN; ++i) acc[p][i] = T(0);
-  for (int qb = 0; qb < Nq; qb += kColQC) {
-    const int q0r = qb + wave * RQ;         // this wave's quadrature rows
-    if (col) {
-      T v[CPL][RQ];
-#pragma unroll
-      for (int p = 0; p < CPL; ++p)
-#pragma unroll
-        for (int i = 0; i < RQ; ++i) v[p][i] = T(0);
-#pragma unroll 2
-      for (int n = 0; n < Np; ++n) {
-        const T* vq = oVq + n * QP + q0r;
-#pragma unroll
-        for (int p = 0; p < CPL; ++p) {
-          const T rv = sr[(cc * E + ce + kColW * p) * Np + n];
-#pragma unroll
-          for (int i = 0; i < RQ; ++i) v[p][i] += vq[i] * rv;
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < CPL; ++p)
-#pragma unroll
-        for (int i = 0; i < RQ; ++i) sw[(cc * E + ce + kColW * p) * QS + wave * RQ + i] = v[p][i];
-    }
-    __syncthreads();
-    // material weights, one thread per (element, chunk point)
-    for (int idx = tid; idx < E * kColQC; idx += kBlock) {
-      const int el = idx / kColQC, pt = idx - el * kColQC;
-      const int qp = qb + pt;
-      if (el >= ne || qp >= Nq) continue;
-      const int64_t mi = (e0 + el) * Nq + qp;
-      const T ir = A.irho[mi], la = A.lam[mi], m2 = T(2) * A.mu[mi];
-      T* w = sw + el * QS + pt;              // field f at w[f * E * QS]
-      const T v3 = w[3 * E * QS], v4 = w[4 * E * QS], v5 = w[5 * E * QS];
-      const T tr = v3 + v4 + v5;
-      w[0] *= ir;
-      w[E * QS] *= ir;
-      w[2 * E * QS] *= ir;
-      w[3 * E * QS] = la * tr + m2 * v3;
-      w[4 * E * QS] = la * tr + m2 * v4;
-      w[5 * E * QS] = la * tr + m2 * v5;
-      w[6 * E * QS] *= m2;
-      w[7 * E * QS] *= m2;
-      w[8 * E * QS] *= m2;
-    }
-    __syncthreads();
-    if (col) {
-      // padded quadrature rows of P_q are zero, so the chunk runs in full
-#pragma unroll 2
-      for (int pt = 0; pt < kColQC; ++pt) {
-        const T* pq = oPq + (qb + pt) * NpP + n0;
-#pragma unroll
-        for (int p = 0; p < CPL; ++p) {
-          const T wv = sw[(cc * E + ce + kColW * p) * QS + pt];
-#pragma unroll
-          for (int i = 0; i < RN; ++i) acc[p][i] += pq[i] * wv;
-        }
-      }
-    }
-    __syncthreads();   // chunk buffer reused
-  }
-  // results to LDS (over r, which is consumed), then coalesced update
-  if (col) {
-#pragma unroll
-    for (int p = 0; p < CPL; ++p)
-#pragma unroll
-      for (int i = 0; i < RN; ++i)
-        if (n0 + i < Np) sr[(cc * E + ce + kColW * p) * Np + n0 + i] = acc[p][i];
-  }
-  __syncthreads();
-  for (int idx = tid; idx < 9 * E * Np; idx += kBlock) {
-    const int f = idx / (E * Np);
-    const int rem = idx - f * E * Np;
-    if (rem / Np >= ne) continue;
-    const int64_t gi = f * KNp + e0 * Np + rem;
-    const T r = sr[idx];
-    if (A.lsrk) {
-      const T rr = A.a * A.res[gi] + A.dt * r;
-      A.res[gi] = rr;
-      A.q_out[gi] = sq[idx] + A.b * rr;
-    } else {
-      A.rhs_out[gi] = r;
-    }
-  }
 }
 
 }  // namespace dgk

@@ -74,12 +74,14 @@ std::vector<uint16_t> build_frags(const RefElement& re) {
   return out;
 }
 
-// FP32 fragments of the FP32 matrix-core stage (FOrd), four steps per lane
-template <int N>
-std::vector<float> build_frags_f(const RefElement& re) {
+// Fragments of the FP32 / FP64 matrix-core stage (FOrd) in the working
+// precision V, four steps per lane
+template <int N, typename V>
+std::vector<V> build_frags_f(const RefElement& re) {
   using O = dgb::FOrd<N>;
   const int Np = O::Np, NF4 = O::NF4, Nq = O::Nq;
-  std::vector<float> out(size_t(O::NF4S) * 4, 0.f);
+  constexpr bool f64 = sizeof(V) == 8;   // accumulator row order of the FP64 product
+  std::vector<V> out(size_t(O::NF4S) * 4, V(0));
   const std::vector<double>* D[3] = {&re.Dr, &re.Ds, &re.Dt};
   for (int t = 0; t < O::RT; ++t)
     for (int q = 0; q < O::SV4; ++q)
@@ -96,23 +98,23 @@ std::vector<float> build_frags_f(const RefElement& re) {
               if (jf < NF4) v = re.LIFT[size_t(r) * NF4 + jf];
             }
           }
-          out[((size_t(O::OFF_V) + size_t(t * O::SV4 + q) * 64) + l) * 4 + j] = float(v);
+          out[((size_t(O::OFF_V) + size_t(t * O::SV4 + q) * 64) + l) * 4 + j] = V(v);
         }
   for (int u = 0; u < O::QT; ++u)
     for (int t = 0; t < O::RT; ++t)
       for (int l = 0; l < 64; ++l)
         for (int j = 0; j < 4; ++j) {
-          const int p = 16 * u + l % 16, n = 16 * t + 4 * (l / 16) + j;
+          const int p = 16 * u + l % 16, n = 16 * t + dgb::acc_row(f64, l / 16, j);
           const double v = (p < Nq && n < Np) ? re.Vq[size_t(p) * Np + n] : 0.0;
-          out[((size_t(O::OFF_Q) + size_t(u * O::RT + t) * 64) + l) * 4 + j] = float(v);
+          out[((size_t(O::OFF_Q) + size_t(u * O::RT + t) * 64) + l) * 4 + j] = V(v);
         }
   for (int t = 0; t < O::RT; ++t)
     for (int u = 0; u < O::QT; ++u)
       for (int l = 0; l < 64; ++l)
         for (int j = 0; j < 4; ++j) {
-          const int r = 16 * t + l % 16, p = 16 * u + 4 * (l / 16) + j;
+          const int r = 16 * t + l % 16, p = 16 * u + dgb::acc_row(f64, l / 16, j);
           const double v = (r < Np && p < Nq) ? re.Pq[size_t(r) * Nq + p] : 0.0;
-          out[((size_t(O::OFF_P) + size_t(t * O::QT + u) * 64) + l) * 4 + j] = float(v);
+          out[((size_t(O::OFF_P) + size_t(t * O::QT + u) * 64) + l) * 4 + j] = V(v);
         }
   return out;
 }
@@ -151,9 +153,9 @@ std::vector<uint16_t> build_frags_e(const RefElement& re) {
 
 template <int N>
 std::vector<double> build_material(int64_t K, const double* irho, const double* lam,
-                                   const double* mu) {
+                                   const double* mu, bool f64) {
   // [tile][field][chunk c][half u][lane l][4]: element 16 tile + l % 16,
-  // quadrature point 32 c + 16 u + 4 (l / 16) + j
+  // quadrature point 32 c + 16 u + acc_row(l / 16, j)
   using O = dgb::BOrd<N>;
   const int64_t ntiles = (K + 15) / 16;
   std::vector<double> blk(size_t(ntiles) * 3 * O::MATS, 0.0);
@@ -165,7 +167,7 @@ std::vector<double> build_material(int64_t K, const double* irho, const double* 
           for (int l = 0; l < 64; ++l)
             for (int j = 0; j < 4; ++j) {
               const int64_t k = 16 * tl + l % 16;
-              const int p = 32 * c + 16 * u + 4 * (l / 16) + j;
+              const int p = 32 * c + 16 * u + dgb::acc_row(f64, l / 16, j);
               if (k >= K || p >= O::Nq) continue;
               blk[(size_t(tl) * 3 + f) * O::MATS + ((size_t(c) * 2 + u) * 64 + l) * 4 + j] =
                   src[f][size_t(k) * O::Nq + p];
@@ -220,13 +222,23 @@ std::vector<float> build_frags_ef(const RefElement& re) {
 
 std::vector<float> mfma_fragments_f32(const RefElement& re) {
   switch (re.N) {
-    case 1: return build_frags_f<1>(re);
-    case 2: return build_frags_f<2>(re);
-    case 3: return build_frags_f<3>(re);
-    case 4: return build_frags_f<4>(re);
+    case 1: return build_frags_f<1, float>(re);
+    case 2: return build_frags_f<2, float>(re);
+    case 3: return build_frags_f<3, float>(re);
+    case 4: return build_frags_f<4, float>(re);
     case 5: return build_frags_ef<5>(re);
     case 6: return build_frags_ef<6>(re);
     default: return build_frags_ef<7>(re);
+  }
+}
+
+std::vector<double> mfma_fragments_f64(const RefElement& re) {
+  switch (re.N) {
+    case 1: return build_frags_f<1, double>(re);
+    case 2: return build_frags_f<2, double>(re);
+    case 3: return build_frags_f<3, double>(re);
+    case 4: return build_frags_f<4, double>(re);
+    default: return {};
   }
 }
 
@@ -250,12 +262,12 @@ std::vector<double> col_operators(const RefElement& re) {
 }
 
 std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
-                                  const double* mu) {
+                                  const double* mu, bool f64) {
   switch (N) {
-    case 1: return build_material<1>(K, irho, lam, mu);
-    case 2: return build_material<2>(K, irho, lam, mu);
-    case 3: return build_material<3>(K, irho, lam, mu);
-    default: return build_material<4>(K, irho, lam, mu);
+    case 1: return build_material<1>(K, irho, lam, mu, f64);
+    case 2: return build_material<2>(K, irho, lam, mu, f64);
+    case 3: return build_material<3>(K, irho, lam, mu, f64);
+    default: return build_material<4>(K, irho, lam, mu, f64);
   }
 }
 

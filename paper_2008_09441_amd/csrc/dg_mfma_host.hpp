@@ -23,15 +23,20 @@ std::vector<uint16_t> mfma_fragments(const RefElement& re);
 // ([NFRAG][64 lanes][4] floats)
 std::vector<float> mfma_fragments_f32(const RefElement& re);
 
-// Column-kernel operator pack: DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],
+// FP64 operator fragments of the FP64 matrix-core stage at orders 1-4 (the
+// layout of FOrd, [NF4S][4] doubles); empty at higher orders
+std::vector<double> mfma_fragments_f64(const RefElement& re);
+
+// Transposed operator pack (generic FP64 kernel, adjoint kernels): DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],
 // VqT [Np][QP], PqT [QP][NpP] (transposed, zero padded; NpP = 4 ceil(Np/4),
 // QP = 32 ceil(Nq/32)).
 std::vector<double> col_operators(const RefElement& re);
 
 // 1/rho, lam, mu at [K][Nq] -> blocked by 16-element tile in the lane order
-// of the kernel's quadrature phase, [ceil(K/16)][3][MATS] (zero padded)
+// of the kernel's quadrature phase, [ceil(K/16)][3][MATS] (zero padded);
+// f64: the accumulator row order of the FP64 product (acc_row)
 std::vector<double> mfma_material(int N, int64_t K, const double* irho, const double* lam,
-                                  const double* mu);
+                                  const double* mu, bool f64 = false);
 
 // fragment count and blocked-material floats per (tile, field) of order N
 int mfma_frag_count(int N);

@@ -1,5 +1,6 @@
-// Runs the stage kernels on the CPU, for tests (matrix-core dgb::stage_bx<N>
-// and dgb::stage_be<N>, column dgk::stage_cols<T, N>):
+// Runs the stage kernels on the CPU, for tests (the matrix-core kernels
+// dgb::stage_bx<N> in BF16x3 and FP32, dgb::stage_bx_d<N> in FP64, and
+// dgb::stage_be<N> in BF16x3 and FP32):
 // each workgroup is 256 host threads with real barriers; the 16x16x32 bf16
 // MFMA is emulated with its hardware lane layout (A: row lane%16, k 8(lane/16)+j;
 // B: column lane%16, k 8(lane/16)+j; D: column lane%16, row 4(lane/16)+j).
@@ -23,7 +24,7 @@ thread_local emu_dim3 threadIdx, blockIdx;
 emu_dim3 gridDim, blockDim;
 static std::unique_ptr<std::barrier<>> g_bar;
 static std::unique_ptr<std::barrier<>> g_wbar[4];
-struct Slot { emu_bf16x8 a[64], b[64]; float x[64], fa[64], fb[64]; };
+struct Slot { emu_bf16x8 a[64], b[64]; float x[64], fa[64], fb[64]; double da[64], db[64]; };
 static Slot g_slot[4];
 
 void __syncthreads() { g_bar->arrive_and_wait(); }
@@ -78,6 +79,26 @@ emu_f32x4 emu_mfma_16x16x4_f32(float a, float b, emu_f32x4 c, int, int, int) {
   return d;
 }
 
+// the 16x16x4 f64 product (A: row lane%16, k lane/16; B: column lane%16, k
+// lane/16; D: column lane%16, row 4 j + lane/16 -- the interleaved row order
+// measured on gfx950, unlike the f32 product's 4 (lane/16) + j)
+emu_f64x4 emu_mfma_16x16x4_f64(double a, double b, emu_f64x4 c, int, int, int) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  g_slot[w].da[lane] = a;
+  g_slot[w].db[lane] = b;
+  g_wbar[w]->arrive_and_wait();
+  emu_f64x4 d = c;
+  const int n = lane % 16;
+  for (int j = 0; j < 4; ++j) {
+    const int i = 4 * j + lane / 16;
+    double acc = c[j];
+    for (int k = 0; k < 4; ++k) acc += g_slot[w].da[i + 16 * k] * g_slot[w].db[n + 16 * k];
+    d[j] = acc;
+  }
+  g_wbar[w]->arrive_and_wait();
+  return d;
+}
+
 template <typename F>
 static void run_grid(int grid, F kern) {
   gridDim.x = grid; blockDim.x = 256;
@@ -120,55 +141,6 @@ static T* dupT(const std::vector<double>& v) {
   return p;
 }
 
-template <typename T, int N>
-static void run_cols(const dgh::RefElement& re, const dgh::MeshData& m, int64_t K,
-                     const std::vector<double>& irho, const std::vector<double>& lam,
-                     const std::vector<double>& mu, const std::vector<double>& zp,
-                     const std::vector<double>& zs, const float* q, double* out, int upwind,
-                     int lsrk) {
-  const int Np = re.Np;
-  dgk::ColArgs<T> A{};
-  std::vector<double> qd(q, q + 9 * K * Np);
-  A.q_in = dupT<T>(qd);
-  A.rhs_out = new T[9 * K * Np];
-  A.q_out = lsrk ? new T[9 * K * Np] : nullptr;
-  A.res = nullptr;
-  if (lsrk) { A.res = new T[9 * K * Np]; for (int64_t i = 0; i < 9 * K * Np; ++i) A.res[i] = T(0); }
-  A.geo = dupT<T>(m.geo); A.fgeo = dupT<T>(m.fgeo);
-  A.etoe = dup(m.EToE); A.etop = dup(m.EToP); A.pat = dup(m.pat);
-  std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
-  A.fmask = dup(fm);
-  A.irho = dupT<T>(irho); A.lam = dupT<T>(lam); A.mu = dupT<T>(mu);
-  A.zp = dupT<T>(zp); A.zs = dupT<T>(zs);
-  using CO = dgk::ColOrder<N>;
-  const std::vector<double> ops = dgh::col_operators(re);
-  const T* opsT = dupT<T>(ops);
-  const size_t dsz = size_t(Np) * CO::NpP;
-  A.DrT = opsT; A.DsT = opsT + dsz; A.DtT = opsT + 2 * dsz; A.LIFTT = opsT + 3 * dsz;
-  A.VqT = A.LIFTT + size_t(4 * re.Nfp) * CO::NpP; A.PqT = A.VqT + size_t(Np) * CO::QP;
-  A.K = K; A.a = T(0); A.b = T(1); A.dt = T(1); A.lsrk = lsrk; A.upwind = upwind;
-  constexpr int E = dgk::ColLayout<T, N>::E;
-  const int grid = int((K + E - 1) / E);
-  run_grid(grid, [=]() { dgk::stage_cols<T, N>(A); });
-  for (int64_t i = 0; i < 9 * K * Np; ++i)
-    out[i] = lsrk ? double(A.q_out[i]) - double(A.q_in[i]) : double(A.rhs_out[i]);
-}
-
-template <typename T>
-static int cols_dispatch(int N, const dgh::RefElement& re, const dgh::MeshData& m, int64_t K,
-                         const std::vector<double>& a, const std::vector<double>& b,
-                         const std::vector<double>& d, const std::vector<double>& zp,
-                         const std::vector<double>& zs, const float* q, double* out, int up,
-                         int lsrk) {
-  switch (N) {
-    case 1: run_cols<T, 1>(re, m, K, a, b, d, zp, zs, q, out, up, lsrk); return 0;
-    case 2: run_cols<T, 2>(re, m, K, a, b, d, zp, zs, q, out, up, lsrk); return 0;
-    case 3: run_cols<T, 3>(re, m, K, a, b, d, zp, zs, q, out, up, lsrk); return 0;
-    case 4: run_cols<T, 4>(re, m, K, a, b, d, zp, zs, q, out, up, lsrk); return 0;
-    default: return 3;
-  }
-}
-
 static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
                        const double* rho_q, const double* cp_q, const double* cs_q,
                        const double* rho_n, const double* cp_n, const double* cs_n,
@@ -184,9 +156,36 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
     d[i] = rho_q[i] * cs_q[i] * cs_q[i];
   }
   for (int64_t i = 0; i < K * Np; ++i) { zp[i] = rho_n[i] * cp_n[i]; zs[i] = rho_n[i] * cs_n[i]; }
-  if (grid < 0)
-    return grid == -2 ? cols_dispatch<double>(N, re, m, K, a, b, d, zp, zs, q, out, upwind, lsrk)
-                      : 3;
+  if (grid < 1 || grid > 3) return 3;
+  if (grid == 3) {   // FP64 matrix-core tiled kernel, orders 1-4
+    if (N > 4) return 3;
+    dgb::BxArgsT<double> D{};
+    std::vector<double> qd(q, q + 9 * K * Np);
+    D.q_in = dupT<double>(qd);
+    D.rhs_out = alloc<double>(9 * K * Np);
+    D.q_out = lsrk ? alloc<double>(9 * K * Np) : nullptr;
+    D.res = nullptr;
+    if (lsrk) { D.res = alloc<double>(9 * K * Np); for (int64_t i = 0; i < 9 * K * Np; ++i) D.res[i] = 0.0; }
+    D.geo = dupT<double>(m.geo); D.fgeo = dupT<double>(m.fgeo);
+    D.nbn = dup(dgh::neighbour_nodes(re, m));
+    D.torder = dup(dgh::tile_order(m, dgb::kTile, 8));
+    std::vector<int32_t> fmd(re.Fmask.begin(), re.Fmask.end());
+    D.fmask = dup(fmd);
+    D.mat = dupT<double>(dgh::mfma_material(N, K, a.data(), b.data(), d.data(), true));
+    D.zp = dupT<double>(zp); D.zs = dupT<double>(zs);
+    D.frags = reinterpret_cast<const dgb::u32x4*>(dup(dgh::mfma_fragments_f64(re)));
+    D.K = K; D.a = 0.0; D.b = 1.0; D.dt = 1.0; D.lsrk = lsrk; D.upwind = upwind;
+    const int tg = int((K + dgb::kTile - 1) / dgb::kTile);
+    switch (N) {
+      case 1: run_grid(tg, [=]() { dgb::stage_bx_d<1>(D); }); break;
+      case 2: run_grid(tg, [=]() { dgb::stage_bx_d<2>(D); }); break;
+      case 3: run_grid(tg, [=]() { dgb::stage_bx_d<3>(D); }); break;
+      default: run_grid(tg, [=]() { dgb::stage_bx_d<4>(D); }); break;
+    }
+    for (int64_t i = 0; i < 9 * K * Np; ++i)
+      out[i] = lsrk ? D.q_out[i] - D.q_in[i] : D.rhs_out[i];
+    return 0;
+  }
   std::vector<uint16_t> fr = dgh::mfma_fragments(re);
   if (N >= 5) {   // one element per workgroup (grid 2: the FP32 kernel)
     dgb::BeArgs E{};
@@ -260,7 +259,7 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
 }
 
 // input file: int32 N, flux_upwind, kernel (1: BF16x3 matrix-core kernel, 2:
-// FP32 matrix-core kernel; -2: the FP64 column kernel), lsrk; int64 K; then float64
+// FP32 matrix-core kernel, 3: FP64 matrix-core kernel), lsrk; int64 K; then float64
 // vxyz[K*12], period[3], rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n
 // [K*Np each]; then float32 q[9*K*Np]
 int main(int argc, char** argv) {

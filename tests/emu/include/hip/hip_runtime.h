@@ -21,6 +21,9 @@ emu_f32x4 emu_mfma_16x16x32_bf16(emu_bf16x8 a, emu_bf16x8 b, emu_f32x4 c, int, i
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16 emu_mfma_16x16x32_bf16
 emu_f32x4 emu_mfma_16x16x4_f32(float a, float b, emu_f32x4 c, int, int, int);
 #define __builtin_amdgcn_mfma_f32_16x16x4f32 emu_mfma_16x16x4_f32
+typedef double emu_f64x4 __attribute__((ext_vector_type(4)));
+emu_f64x4 emu_mfma_16x16x4_f64(double a, double b, emu_f64x4 c, int, int, int);
+#define __builtin_amdgcn_mfma_f64_16x16x4f64 emu_mfma_16x16x4_f64
 #define __align__(n) __attribute__((aligned(n)))
 #define __builtin_amdgcn_readfirstlane(x) (x)
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)

@@ -1,7 +1,7 @@
 """Parity at the full size of the order-4 heterogeneous workload: the
 periodic 48^3 x 6 Kuhn cube (663,552 tets), N = 4, Fourier media, in the
 launch configuration the benchmark times (the tiled matrix-core kernel with
-its XCD slab tile order for FP32 / BF16x3, the column kernel for FP64).
+its XCD slab tile order, in every precision).
 
 The oracle evaluates the right-hand side on a subset of elements, so the
 GPU result is compared element by element on about 2,000 sampled elements:

@@ -53,7 +53,7 @@ def test_rhs_fp32_matches_oracle(n, N):
 @pytest.mark.parametrize("precision,bound", [("fp64", 1e-12), ("fp32", 2e-5)])
 def test_odd_element_count_fp64_fp32(N, precision, bound):
     """The centroid-split Kuhn cube (K = 51, non-Kuhn element shapes) on the
-    FP64 column kernel and the FP32 matrix-core kernel (orders 1-4) and on
+    FP64 and FP32 matrix-core kernels (orders 1-4) and on
     the generic kernel (orders 5-7): right-hand side and one LSRK step
     against the oracle on the same mesh."""
     print(f"case odd K {precision} N={N}", flush=True)

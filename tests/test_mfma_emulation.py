@@ -1,6 +1,6 @@
 """CPU check of the stage kernel sources: the unchanged kernels (the BF16x3
-matrix-core kernels of orders 1-4 and 5-7, the FP32 matrix-core kernel and the
-FP64 column kernel) run on host threads
+and FP32 matrix-core kernels of orders 1-4 and 5-7, the FP64 matrix-core
+kernel of orders 1-4) run on host threads
 (tests/emu) built with AddressSanitizer, so any out-of-bounds index fails the
 test, and their results are compared with the FP64 oracle (BF16x3: 1e-4,
 FP32: 2e-5, FP64: 1e-12 per-field relative L2)."""
@@ -120,14 +120,17 @@ def test_stage_kernel_lsrk_mode(emu_exe, tmp_path, n, N):
 
 
 @pytest.mark.parametrize("n,N,flux", [(3, 1, "upwind"), (3, 2, "central"), (3, 3, "upwind"),
-                                      (3, 4, "upwind")])
-def test_column_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flux):
-    # the FP64 column kernel (FP32 runs on the matrix-core kernel at these orders)
-    err = _run(emu_exe, tmp_path, n, N, flux, grid=-2)
+                                      (3, 4, "upwind"), (2, 4, "central")])
+def test_fp64_matrix_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, N, flux):
+    """The FP64 matrix-core tiled kernel (orders 1-4, v_mfma_f64_16x16x4f64):
+    the tiling of the FP32 kernel in double precision, at the FP64 bound."""
+    err = _run(emu_exe, tmp_path, n, N, flux, grid=3)
     print("per-field rel L2:", np.array2string(err, precision=2))
     assert err.max() <= 1e-12
 
 
-def test_column_kernel_lsrk_mode(emu_exe, tmp_path):
-    err = _run(emu_exe, tmp_path, 2, 4, "upwind", grid=-2, lsrk=1)
+@pytest.mark.parametrize("lsrk,split", [(1, False), (0, True), (1, True)])
+def test_fp64_matrix_kernel_lsrk_and_odd_count(emu_exe, tmp_path, lsrk, split):
+    err = _run(emu_exe, tmp_path, 2, 4, "upwind", grid=3, lsrk=lsrk, split=split)
+    print("per-field rel L2:", np.array2string(err, precision=2))
     assert err.max() <= 1e-12
