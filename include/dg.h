@@ -279,7 +279,7 @@ dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const doubl
  * the receiver velocities after every step to trace (host
  * [nsteps][nrec][3], working precision).  Leaves the context at the end of
  * the run.  Needs receivers (DG_ESTATE).  Library-owned device memory:
- * ceil(nsteps/every) + every + 11 states plus two face-node work arrays
+ * ceil(nsteps/every) + 5 every + 6 states plus two face-node work arrays
  * [K][4 Nfp][9] and the FP64 gradient [3][K][Nq] (upwind: also [K][4 Nfp][4]
  * impedance terms and the FP64 gradient [2][K][Np]), counted against the
  * HBM budget. */

@@ -1,0 +1,591 @@
+// Tiled discrete adjoint of the FP32 stage at orders 1-4 on the matrix
+// cores (v_mfma_f32_16x16x4_f32).  One reverse stage is two kernels:
+//
+// adj_tile<N>: one workgroup per 16 consecutive elements (the MFMA columns).
+//   With y the stage input and l = a lres + b ly the adjoint of the stage's
+//   residual (written back to lres), it computes per element
+//     r  = R y + raw sources                 (volume terms, fluxes, LIFT),
+//     w  = V_q r,   p = P_q^T l              at the quadrature points,
+//     grad += s d/dm <l, W(m) r>             (d/d(1/rho) = sum_v p w,
+//                                             d/d lam = tr p tr w,
+//                                             d/d mu = 2 sum_s p w),
+//     mu = W^T l = V_q^T [weights . p],
+//     nu = volume^T mu = sum_d D_d^T (geometry-weighted mu),
+//     g  = LIFT^T mu at the face nodes,
+//   [CHW17, C18] for W(m) r = P_q[weights . V_q r], [HW08, Ch. 10] for R.
+//   Waves 0-2 each own one group of three components (velocities, normal
+//   stresses, shear stresses) from R y to nu and g; the material operator
+//   and the gradient terms then stay inside a wave except the stress sum of
+//   d/d mu, whose two partial sums meet in LDS.  Every product's B operand
+//   comes from LDS (y, fluxes, mu) or straight from the previous product's
+//   accumulators (the K orders of AOrd).  All waves compute the face fluxes;
+//   wave 3 also adds the stress term of the gradient.
+//
+// adj_nodes: one thread per volume node.  Adds the flux transposes of the
+//   face nodes on the node (its own side, plus the side of the neighbour's
+//   face node that reads it) to nu, and ly += s (nu + face terms); for the
+//   upwind flux also the impedance gradient (own-side and neighbour-side
+//   terms of the same face nodes), as the generic adjoint kernels do.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dg_adj_flux.hpp"
+#include "dg_bx_layout.hpp"
+
+namespace dgt {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+struct TileArgs {
+  const float* y;        // stage input [9][K][Np]
+  float* lres;           // [9][K][Np]: in the residual adjoint before this stage, out l
+  const float* ly;       // [9][K][Np]
+  float* nu;             // out: volume transpose of mu [9][K][Np]
+  float* gf;             // out: LIFT^T mu at the face nodes [9][K][4 Nfp]
+  double* grad;          // [3][K][Nq] += s d/dm <l, W(m) r>
+  const float* geo;      // [K][9]
+  const float* fgeo;     // [K][4][4]
+  const int32_t* nbn;    // [K][4 Nfp] neighbour node, flat (element * Np + node)
+  const int32_t* fmask;  // [4 Nfp] volume node of each face node
+  const float* mat;      // blocked material (1/rho, lam, mu) [ceil(K/16)][3][MATS]
+  const float* zp;       // [K][Np]
+  const float* zs;
+  const float* frags;    // [NG][64][4]
+  const int64_t* src_elem;  // point sources: element, raw response [nsrc][3][Np],
+  const float* src_w;       // Ricker parameters (f0, t0, amplitude)
+  const double* src_par;
+  int nsrc;
+  double ts;             // time of the stage (sources)
+  int64_t K;
+  float a, b;            // l = a lres + b ly
+  double s;              // gradient scale
+  int upwind;
+};
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ f4 mma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// volume-term map: output component c reads field vfield(c, j) with weight
+// vweight(c, j) times the metric term G_dj [HW08, Ch. 10]
+__host__ __device__ constexpr int vfield(int c, int j) {
+  return c == 0 ? (j == 0 ? 3 : j == 1 ? 8 : 7)
+       : c == 1 ? (j == 0 ? 8 : j == 1 ? 4 : 6)
+       : c == 2 ? (j == 0 ? 7 : j == 1 ? 6 : 5)
+       : c == 3 ? 0
+       : c == 4 ? 1
+       : c == 5 ? 2
+       : c == 6 ? (j == 1 ? 2 : 1)
+       : c == 7 ? (j == 0 ? 2 : 0)
+       : (j == 0 ? 1 : 0);
+}
+__host__ __device__ constexpr float vweight(int c, int j) {
+  return c < 3 ? 1.f : c < 6 ? (j == c - 3 ? 1.f : 0.f) : (j == c - 6 ? 0.f : 0.5f);
+}
+
+// Ricker wavelet value of source i at time t (the forward source term)
+__device__ inline double ricker(const double* par, int i, double t) {
+  const double x = 3.14159265358979323846 * par[3 * i] * (t - par[3 * i + 1]);
+  return par[3 * i + 2] * (1.0 - 2.0 * x * x) * exp(-x * x);
+}
+
+// Waves 0-2: everything from R y to nu and g for components 3W .. 3W + 2.
+template <int N, int W>
+__device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float* sy,
+                                           const float* sf, double* sg, const float (&G)[9]) {
+  using O = AOrd<N>;
+  constexpr int RT = O::RT, QT = O::QT, FT = O::FT, KN = O::KN, KF = O::KF, KF4 = O::KF4;
+  constexpr int Np = O::Np, Nq = O::Nq, NF4 = O::NF4, LN = 4 * KN, LFN = 4 * KF;
+  constexpr int C0 = 3 * W;
+  const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+  const int64_t K = A.K, KNp = K * Np;
+  const int64_t k = k0 + e;
+  const bool ok = k < K;
+  const int64_t kc = ok ? k : K - 1;
+  const f4* fr = reinterpret_cast<const f4*>(A.frags) + lane;
+  auto frag = [&](int grp) { return fr[grp * 64]; };
+
+  // the adjoint of the residual, l = a lres + b ly, at the rows this lane
+  // holds in the chained K order (node 16 t + 4 g + j); written back
+  float lv[3][RT][4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 16 * t + 4 * g + j;
+        const int64_t i = (C0 + c) * KNp + kc * Np + (n < Np ? n : Np - 1);
+        lv[c][t][j] = n < Np ? A.a * A.lres[i] + A.b * A.ly[i] : 0.f;
+      }
+
+  // r = R y: sum_d D_d (sum_j G_dj w(c, j) y_f(c, j)) + LIFT flux_c
+  f4 r[RT][3];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+  {
+    f4 fa[2][RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) fa[0][t] = frag(O::G_D + t * KN);
+#pragma unroll
+    for (int s = 0; s < KN; ++s) {
+      if (s + 1 < KN) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) fa[(s + 1) & 1][t] = frag(O::G_D + t * KN + s + 1);
+      }
+      const int m = 4 * s + g;
+      float z[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          float acc = 0.f;
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            if (vweight(C0 + c, j) != 0.f)
+              acc += vweight(C0 + c, j) * G[3 * d + j] * sy[(vfield(C0 + c, j) * LN + m) * 16 + e];
+          z[c][d] = acc;
+        }
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) r[t][c] = mma(fa[s & 1][t][d], z[c][d], r[t][c]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  {
+    f4 fa[2][RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) fa[0][t] = frag(O::G_L + t * KF4);
+#pragma unroll
+    for (int s4 = 0; s4 < KF4; ++s4) {
+      if (s4 + 1 < KF4) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) fa[(s4 + 1) & 1][t] = frag(O::G_L + t * KF4 + s4 + 1);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int s = 4 * s4 + i;
+        if (s < KF) {
+          float b[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) b[c] = sf[((C0 + c) * LFN + 4 * s + g) * 16 + e];
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r[t][c] = mma(fa[s4 & 1][t][i], b[c], r[t][c]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // raw point sources (velocity rows) of the elements in this tile
+  if (W == 0 && A.nsrc > 0) {
+    for (int i = 0; i < A.nsrc; ++i) {
+      if (A.src_elem[i] != k || !ok) continue;
+      const float f = float(ricker(A.src_par, i, A.ts));
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int n = 16 * t + 4 * g + j;
+            if (n < Np) r[t][c][j] += f * A.src_w[(i * 3 + c) * Np + n];
+          }
+    }
+  }
+  // write l back
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = 16 * t + 4 * g + j;
+          if (n < Np) A.lres[(C0 + c) * KNp + k * Np + n] = lv[c][t][j];
+        }
+  }
+  __syncthreads();   // (1) every wave is done with the fluxes: sg may be written
+
+  // per quadrature tile u: w = V_q r and p = P_q^T l, the gradient terms,
+  // the material, and mu += V_q^T [weights . p]
+  f4 mu[RT][3];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mu[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+  {
+    constexpr int MATS = 2 * ((QT + 1) / 2) * 64 * 4;   // BOrd<N>::MATS
+    const float* mb = A.mat + (k0 / 16) * 3 * MATS + lane * 4;
+    auto matv = [&](int f, int u) { return *reinterpret_cast<const f4*>(mb + f * MATS + u * 256); };
+    f4 fv[RT], fp[RT], fvt[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      fv[t] = frag(O::G_V + t);
+      fp[t] = frag(O::G_P + t);
+      fvt[t] = frag(O::G_VT + t);
+    }
+    f4 m0 = matv(W == 0 ? 0 : 2, 0), m1 = W == 1 ? matv(1, 0) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < QT; ++u) {
+      double* gr = A.grad + (W == 2 ? 0 : W) * K * Nq + kc * Nq;
+      double gold[4];
+      if (W < 2) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int p = 16 * u + 4 * g + j;
+          gold[j] = gr[p < Nq ? p : Nq - 1];
+        }
+      }
+      f4 w[3], p[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c] = p[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            w[c] = mma(fv[t][j], r[t][c][j], w[c]);
+            p[c] = mma(fp[t][j], lv[c][t][j], p[c]);
+          }
+        if (u + 1 < QT) {
+          fv[t] = frag(O::G_V + (u + 1) * RT + t);
+          fp[t] = frag(O::G_P + (u + 1) * RT + t);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      const f4 cm0 = m0, cm1 = m1;
+      if (u + 1 < QT) {
+        m0 = matv(W == 0 ? 0 : 2, u + 1);
+        if (W == 1) m1 = matv(1, u + 1);
+      }
+      // gradient terms at points 16 u + 4 g + j of element k
+      float uu[3][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int pt = 16 * u + 4 * g + j;
+        const bool live = ok && pt < Nq;
+        if (W == 0) {
+          const double g0 = double(p[0][j]) * double(w[0][j]) + double(p[1][j]) * double(w[1][j]) +
+                            double(p[2][j]) * double(w[2][j]);
+          if (live) gr[pt] = gold[j] + A.s * g0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) uu[c][j] = cm0[j] * p[c][j];
+        } else if (W == 1) {
+          const double g1 = (double(p[0][j]) + double(p[1][j]) + double(p[2][j])) *
+                            (double(w[0][j]) + double(w[1][j]) + double(w[2][j]));
+          if (live) gr[pt] = gold[j] + A.s * g1;
+          sg[(16 * u + 4 * g + j) * 16 + e] = double(p[0][j]) * double(w[0][j]) +
+                                              double(p[1][j]) * double(w[1][j]) +
+                                              double(p[2][j]) * double(w[2][j]);
+          const float tr = p[0][j] + p[1][j] + p[2][j];
+          const float m2 = 2.f * cm0[j];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) uu[c][j] = cm1[j] * tr + m2 * p[c][j];
+        } else {
+          sg[(16 * QT + 16 * u + 4 * g + j) * 16 + e] = double(p[0][j]) * double(w[0][j]) +
+                                                        double(p[1][j]) * double(w[1][j]) +
+                                                        double(p[2][j]) * double(w[2][j]);
+          const float m2 = 2.f * cm0[j];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) uu[c][j] = m2 * p[c][j];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) mu[t][c] = mma(fvt[t][j], uu[c][j], mu[t][c]);
+        if (u + 1 < QT) fvt[t] = frag(O::G_VT + (u + 1) * RT + t);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  __syncthreads();   // (2) y is no longer read: mu may overwrite it
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = 16 * t + 4 * g + j;
+      if (n < LN) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sy[((C0 + c) * LN + n) * 16 + e] = mu[t][c][j];
+      }
+    }
+  __syncthreads();   // (3) mu complete
+
+  // nu_f = sum_d D_d^T (sum over (c, j) with vfield(c, j) = f of
+  // vweight(c, j) G_dj mu_c), for the components f of this group
+  {
+    f4 o[RT][3];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+    f4 fa[2][RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) fa[0][t] = frag(O::G_DT + t * KN);
+#pragma unroll
+    for (int s = 0; s < KN; ++s) {
+      if (s + 1 < KN) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) fa[(s + 1) & 1][t] = frag(O::G_DT + t * KN + s + 1);
+      }
+      const int m = 4 * s + g;
+      float mv[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        bool used = false;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) used |= vweight(c, j) != 0.f && vfield(c, j) == C0 + f;
+        mv[c] = used ? sy[(c * LN + m) * 16 + e] : 0.f;
+      }
+      float z[3][3];
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          float acc = 0.f;
+#pragma unroll
+          for (int c = 0; c < 9; ++c)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              if (vweight(c, j) != 0.f && vfield(c, j) == C0 + f)
+                acc += vweight(c, j) * G[3 * d + j] * mv[c];
+          z[f][d] = acc;
+        }
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int f = 0; f < 3; ++f) o[t][f] = mma(fa[s & 1][t][d], z[f][d], o[t][f]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (ok) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int n = 16 * t + 4 * g + j;
+            if (n < Np) A.nu[(C0 + f) * KNp + k * Np + n] = o[t][f][j];
+          }
+    }
+  }
+  // g_c = LIFT^T mu_c at the face nodes, K from the mu accumulators
+  {
+    f4 fa[RT];
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) fa[t] = frag(O::G_LT + ft * RT + t);
+      f4 o[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) o[c] = mma(fa[t][j], mu[t][c][j], o[c]);
+      if (ok) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int jf = 16 * ft + 4 * g + j;
+            if (jf < NF4) A.gf[((C0 + c) * K + k) * NF4 + jf] = o[c][j];
+          }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
+  using O = AOrd<N>;
+  constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, Nq = O::Nq, QT = O::QT;
+  constexpr int LN = 4 * O::KN, LFN = 4 * O::KF;
+  constexpr int NT = (16 * NF4 + kThreads - 1) / kThreads;   // face-node tasks per thread
+  static_assert(LFN == NF4, "the face-node steps cover the face nodes exactly");
+  __shared__ __align__(16) float smem[O::BYTES / 4];
+  float* sy = smem;                                   // y, later mu
+  float* sf = smem + O::LY;                           // fluxes
+  double* sg = reinterpret_cast<double*>(smem + O::LY);   // stress sums (after the fluxes)
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t K = A.K, KNp = K * Np;
+  // XCD-aware tile order: each XCD takes one contiguous range of tiles
+  const int64_t Gd = gridDim.x, bid = blockIdx.x;
+  const int64_t xcd = bid & 7, per = Gd >> 3, rem8 = Gd & 7;
+  const int64_t tile = xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3);
+  const int64_t k0 = 16 * tile;
+
+  // the tile's y into LDS (rows past Np and elements past K are zero)
+  for (int i = tid; i < 9 * 16 * LN; i += kThreads) {
+    const int c = i / (16 * LN), rem = i - c * 16 * LN, e = rem / LN, m = rem - e * LN;
+    const int64_t k = k0 + e;
+    sy[(c * LN + m) * 16 + e] = (m < Np && k < K) ? A.y[c * KNp + k * Np + m] : 0.f;
+  }
+  // face-node tasks (element e, face node jf): the neighbour's state and
+  // impedances, then (after the barrier) the flux from the own side in LDS
+  float qP[NT][9], zpP[NT], zsP[NT];
+  int vMt[NT];
+  f4 fg[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int task = tid + kThreads * i;
+    const int tk = task < 16 * NF4 ? task : 16 * NF4 - 1;
+    const int e = tk / NF4, jf = tk - e * NF4;
+    const int64_t k = k0 + e < K ? k0 + e : K - 1;
+    const int64_t nb = A.nbn[k * NF4 + jf];
+    vMt[i] = A.fmask[jf];
+    fg[i] = reinterpret_cast<const f4*>(A.fgeo)[k * 4 + jf / Nfp];
+    zpP[i] = A.zp[nb];
+    zsP[i] = A.zs[nb];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) qP[i][f] = A.y[f * KNp + nb];
+  }
+  float G[9];
+  {
+    const int64_t k = k0 + (tid & 15) < K ? k0 + (tid & 15) : K - 1;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) G[i] = A.geo[k * 9 + i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int task = tid + kThreads * i;
+    if (task >= 16 * NF4) break;
+    const int e = task / NF4, jf = task - e * NF4;
+    const int64_t k = k0 + e < K ? k0 + e : K - 1;
+    const int vM = vMt[i];
+    float qM[9], fl[9];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) qM[f] = sy[(f * LN + vM) * 16 + e];
+    dga::flux<float>(qM, qP[i], fg[i][0], fg[i][1], fg[i][2], fg[i][3], A.zp[k * Np + vM],
+                     A.zs[k * Np + vM], zpP[i], zsP[i], A.upwind, fl);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) sf[(c * LFN + jf) * 16 + e] = fl[c];
+  }
+  __syncthreads();
+
+  if (wave == 0) {
+    tile_group<N, 0>(A, k0, sy, sf, sg, G);
+  } else if (wave == 1) {
+    tile_group<N, 1>(A, k0, sy, sf, sg, G);
+  } else if (wave == 2) {
+    tile_group<N, 2>(A, k0, sy, sf, sg, G);
+  } else {
+    __syncthreads();   // (1)
+    __syncthreads();   // (2): the partial stress sums are complete
+    // d/d mu = 2 (stress sum of the normal stresses + of the shear stresses)
+    const int lane = tid & 63;
+    for (int i = lane; i < 16 * Nq; i += 64) {
+      const int e = i / Nq, p = i - e * Nq;
+      const int64_t k = k0 + e;
+      if (k >= K) continue;
+      const double v = sg[(p)*16 + e] + sg[(16 * QT + p) * 16 + e];
+      A.grad[2 * K * Nq + k * Nq + p] += A.s * 2.0 * v;
+    }
+    __syncthreads();   // (3)
+  }
+}
+
+// The face terms of R^T mu and of the impedance gradient, gathered onto the
+// volume nodes, and ly += s (nu + face terms).
+struct NodeArgs {
+  const float* nu;        // [9][K][Np]
+  const float* gf;        // [9][K][4 Nfp]
+  const float* y;         // stage input [9][K][Np]
+  float* ly;              // [9][K][Np]
+  double* gradz;          // [2][K][Np] (upwind)
+  const float* fgeo;      // [K][4][4]
+  const float* zp;        // [K][Np]
+  const float* zs;
+  const int32_t* nbn;     // [K][4 Nfp] neighbour node (flat)
+  const int32_t* nbface;  // [K][4 Nfp] neighbour's face node (flat, element * 4 Nfp + j)
+  const int32_t* invf;    // [Np][3] face nodes on each volume node (-1 padded)
+  int64_t K;
+  int Np, Nfp;
+  double s;
+  int upwind;
+};
+
+__global__ __launch_bounds__(256) void adj_nodes(NodeArgs A) {
+  const int Np = A.Np, Nfp = A.Nfp, NF4 = 4 * Nfp;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t K = A.K, KNp = K * Np;
+  if (i >= KNp) return;
+  const int64_t k = i / Np;
+  const int n = int(i - k * Np);
+  float h[9];
+#pragma unroll
+  for (int f = 0; f < 9; ++f) h[f] = A.nu[f * KNp + i];
+  float qM[9];
+  if (A.upwind) {
+#pragma unroll
+    for (int f = 0; f < 9; ++f) qM[f] = A.y[f * KNp + i];
+  }
+  const float ZpM = A.zp[i], ZsM = A.zs[i];
+  double gp = 0.0, gs = 0.0;
+  for (int t = 0; t < 3; ++t) {
+    const int jf = A.invf[n * 3 + t];
+    if (jf < 0) continue;
+    const int64_t own = k * NF4 + jf, jn = A.nbface[own], nb = jn / NF4;
+    const int jfn = int(jn - nb * NF4);
+    const int64_t nP = A.nbn[own];
+    const float ZpP = A.zp[nP], ZsP = A.zs[nP];
+    const f4 fo = reinterpret_cast<const f4*>(A.fgeo)[k * 4 + jf / Nfp];
+    const f4 fn = reinterpret_cast<const f4*>(A.fgeo)[nb * 4 + jfn / Nfp];
+    float go[9], gn[9], a[9], b[9];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) {
+      go[f] = A.gf[(f * K + k) * NF4 + jf];
+      gn[f] = A.gf[(f * K + nb) * NF4 + jfn];
+    }
+    // own flux (this node on its "-" side), then the neighbour's flux at
+    // its face node jn, which reads this node as its "+" side
+    dga::rev_flux<float>(go, fo[0], fo[1], fo[2], fo[3], ZpM, ZsM, ZpP, ZsP, A.upwind, a, b);
+#pragma unroll
+    for (int f = 0; f < 9; ++f) h[f] += a[f];
+    dga::rev_flux<float>(gn, fn[0], fn[1], fn[2], fn[3], ZpP, ZsP, ZpM, ZsM, A.upwind, a, b);
+#pragma unroll
+    for (int f = 0; f < 9; ++f) h[f] += b[f];
+    if (A.upwind) {
+      float qP[9], zo[4], zn[4];
+#pragma unroll
+      for (int f = 0; f < 9; ++f) qP[f] = A.y[f * KNp + nP];
+      dga::zgrad_terms<float>(qM, qP, fo[0], fo[1], fo[2], fo[3], ZpM, ZsM, ZpP, ZsP, go, zo);
+      dga::zgrad_terms<float>(qP, qM, fn[0], fn[1], fn[2], fn[3], ZpP, ZsP, ZpM, ZsM, gn, zn);
+      gp += double(zo[0]) + double(zn[2]);
+      gs += double(zo[1]) + double(zn[3]);
+    }
+  }
+  const float sf = float(A.s);
+#pragma unroll
+  for (int f = 0; f < 9; ++f) A.ly[f * KNp + i] += sf * h[f];
+  if (A.upwind) {
+    A.gradz[i] += A.s * gp;
+    A.gradz[KNp + i] += A.s * gs;
+  }
+}
+
+}  // namespace dgt

@@ -10,6 +10,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dg.h"
@@ -19,6 +20,7 @@
 #include "dg_bx.hpp"
 #include "dg_src.hpp"
 #include "dg_adj.hpp"
+#include "dg_adjt.hpp"
 #include "dg_batch.hpp"
 #include "dg_peaks.hpp"
 #include "dg_mfma_host.hpp"
@@ -106,13 +108,13 @@ struct dg_ctx {
   // discrete adjoint: tables, checkpoints and work arrays
   DevBuf adj_nbface, adj_invf;
   DevBuf adj_ck;            // checkpoints [nck][9][K][Np]
-  DevBuf adj_seg;           // step-start states of one segment [every][9][K][Np]
-  DevBuf adj_y;             // stage inputs [5][9][K][Np]
+  DevBuf adj_seg;           // stage inputs of one segment [every][5][9][K][Np]
   DevBuf adj_v;             // ly, lres, mu, nu, r, res [6][9][K][Np]
   DevBuf adj_gb, adj_hb;    // face-node work [K][4 Nfp][9]
   DevBuf adj_grad;          // double [3][K][Nq]
   DevBuf adj_zb;            // upwind: impedance terms per face node [K][4 Nfp][4]
   DevBuf adj_gradz;         // upwind: double [2][K][Np]
+  DevBuf adj_frag;          // FP32 orders 1-4: fragments of the tiled adjoint kernel
   DevBuf adj_trace;         // [nsteps][nrec][3]
   bool adj_ready = false;
   double adj_t0 = 0.0, adj_dt = 0.0;
@@ -154,6 +156,9 @@ bool plain_material(int32_t precision, int order) {
 bool tiled_mfma(const dg_ctx* c) {
   return c->opt.precision == DG_FP32_BF16X3 || c->opt.precision == DG_FP32;
 }
+// FP32 contexts of orders 1-4 run the reverse stage on the tiled adjoint
+// kernel (matrix cores); the others on the generic adjoint kernels
+bool adj_tiled(const dg_ctx* c) { return c->opt.precision == DG_FP32 && c->re.N <= 4; }
 
 dg_status set_device(dg_ctx* c) {
   if (!device_ctx(c)) return fail(c, DG_EDEVICE, "host-only context: no device work");
@@ -655,49 +660,87 @@ dg_status adj_tables(dg_ctx* c) {
   if (c->adj_nbface.p) return DG_OK;
   const dgh::RefElement& re = c->re;
   const dgh::MeshData& m = c->mesh;
-  const int Nfp = re.Nfp, NF4 = 4 * Nfp, Np = re.Np;
+  const int NF4 = 4 * re.Nfp;
   if (m.K * NF4 >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "adjoint: mesh too large");
-  std::vector<int32_t> nbf(size_t(m.K) * NF4), invf(size_t(Np) * 3, -1);
-  for (int64_t k = 0; k < m.K; ++k)
-    for (int f = 0; f < 4; ++f) {
-      const int64_t nb = m.EToE[k * 4 + f];
-      const int fn = m.EToF[k * 4 + f];
-      for (int i = 0; i < Nfp; ++i) {
-        const int vP = m.pat[size_t(m.EToP[k * 4 + f]) * Nfp + i];
-        int jn = -1;
-        for (int i2 = 0; i2 < Nfp; ++i2)
-          if (re.Fmask[fn * Nfp + i2] == vP) jn = fn * Nfp + i2;
-        if (jn < 0) return fail(c, DG_EINVAL, "adjoint: face tables inconsistent");
-        nbf[size_t(k) * NF4 + f * Nfp + i] = int32_t(nb * NF4 + jn);
-      }
-    }
-  for (int j = 0; j < NF4; ++j) {
-    const int n = re.Fmask[j];
-    int s = 0;
-    while (s < 3 && invf[n * 3 + s] >= 0) ++s;
-    if (s == 3) return fail(c, DG_EINVAL, "adjoint: node on more than three faces");
-    invf[n * 3 + s] = j;
-  }
+  std::vector<int32_t> nbf, invf;
+  std::string err;
+  if (!dgh::adjoint_face_tables(re, m, nbf, invf, err)) return fail(c, DG_EINVAL, err);
   dg_status st;
+  if (adj_tiled(c)) {
+    const std::vector<float> fr = dgh::adj_fragments_f32(re);
+    if ((st = upload_raw(c, c->adj_frag, fr.data(), fr.size())) != DG_OK) return st;
+  }
   if ((st = upload_raw(c, c->adj_nbface, nbf.data(), nbf.size())) != DG_OK) return st;
   return upload_raw(c, c->adj_invf, invf.data(), invf.size());
 }
 
-// one LSRK(5,4) step from qin into qout through the temporaries t0, t1 and
-// residual res (sources at host time t)
-dg_status full_step(dg_ctx* c, const void* qin, void* qout, void* t0, void* t1, void* res,
-                    double t, double dt) {
-  const int64_t n = int64_t(9) * c->mesh.K * c->re.Np;
-  dg_status s = fill_zero(c, res, n);
-  if (s != DG_OK) return s;
-  const void* in = qin;
-  void* outs[5] = {t0, t1, t0, t1, qout};
-  for (int st = 0; st < 5; ++st) {
-    if ((s = stage(c, in, outs[st], res, nullptr, kRkA[st], kRkB[st], dt, 1)) != DG_OK) return s;
-    if ((s = launch_sources(c, res, outs[st], t + kRkC[st] * dt, dt, kRkB[st] * dt)) != DG_OK)
-      return s;
-    in = outs[st];
+// one reverse stage on the tiled adjoint kernels (FP32, orders 1-4): lres
+// = a lres + b ly, the gradient terms, then ly += dt R^T W^T lres and the
+// impedance gradient
+template <int N>
+void launch_adj_tile(dg_ctx* c, const dgt::TileArgs& A) {
+  const unsigned tiles = unsigned((A.K + 15) / 16);
+  hipLaunchKernelGGL(dgt::adj_tile<N>, dim3(tiles), dim3(dgt::kThreads), 0, c->stream, A);
+}
+
+dg_status adj_stage_tiled(dg_ctx* c, const float* y, float* lres, float* ly, float* nu,
+                          double* grad, double* gradz, float a, float b, double dt, double ts) {
+  const int64_t K = c->mesh.K;
+  const int Np = c->re.Np;
+  dgt::TileArgs A{};
+  A.y = y;
+  A.lres = lres;
+  A.ly = ly;
+  A.nu = nu;
+  A.gf = static_cast<float*>(c->adj_gb.p);
+  A.grad = grad;
+  A.geo = static_cast<const float*>(c->geo.p);
+  A.fgeo = static_cast<const float*>(c->fgeo.p);
+  A.nbn = static_cast<const int32_t*>(c->nbn.p);
+  A.fmask = static_cast<const int32_t*>(c->fmask.p);
+  A.mat = static_cast<const float*>(c->matblk.p);
+  A.zp = static_cast<const float*>(c->zp.p);
+  A.zs = static_cast<const float*>(c->zs.p);
+  A.frags = static_cast<const float*>(c->adj_frag.p);
+  A.src_elem = static_cast<const int64_t*>(c->src_elem.p);
+  A.src_w = static_cast<const float*>(c->src_wraw.p);
+  A.src_par = static_cast<const double*>(c->src_par.p);
+  A.nsrc = int(c->src.size());
+  A.ts = ts;
+  A.K = K;
+  A.a = a;
+  A.b = b;
+  A.s = dt;
+  A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+  if (!A.nbn || !A.mat || !A.frags || !A.fmask)
+    return fail(c, DG_ESTATE, "adjoint: tiled kernel tables missing");
+  switch (c->re.N) {
+    case 1: launch_adj_tile<1>(c, A); break;
+    case 2: launch_adj_tile<2>(c, A); break;
+    case 3: launch_adj_tile<3>(c, A); break;
+    case 4: launch_adj_tile<4>(c, A); break;
+    default: return fail(c, DG_EINVAL, "adjoint: no tiled kernel at this order");
   }
+  DG_HIP(c, hipGetLastError());
+  dgt::NodeArgs B{};
+  B.nu = nu;
+  B.gf = A.gf;
+  B.y = y;
+  B.ly = ly;
+  B.gradz = gradz;
+  B.fgeo = A.fgeo;
+  B.zp = A.zp;
+  B.zs = A.zs;
+  B.nbn = A.nbn;
+  B.nbface = static_cast<const int32_t*>(c->adj_nbface.p);
+  B.invf = static_cast<const int32_t*>(c->adj_invf.p);
+  B.K = K;
+  B.Np = Np;
+  B.Nfp = c->re.Nfp;
+  B.s = dt;
+  B.upwind = A.upwind;
+  hipLaunchKernelGGL(dgt::adj_nodes, dim3(nblocks(K * Np)), dim3(256), 0, c->stream, B);
+  DG_HIP(c, hipGetLastError());
   return DG_OK;
 }
 
@@ -708,7 +751,6 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
   const dga::AdjArgs<T> A = adj_args<T>(c);
   T* ck = static_cast<T*>(c->adj_ck.p);
   T* seg = static_cast<T*>(c->adj_seg.p);
-  T* ys = static_cast<T*>(c->adj_y.p);
   T* v = static_cast<T*>(c->adj_v.p);
   T *ly = v, *lres = v + n, *mu = v + 2 * n, *nu = v + 3 * n, *r = v + 4 * n, *res = v + 5 * n;
   T* gb = static_cast<T*>(c->adj_gb.p);
@@ -739,13 +781,24 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
   }
   for (int64_t sg = nck - 1; sg >= 0; --sg) {
     const int64_t n0 = sg * every, n1 = std::min(n0 + every, nsteps);
-    // step-start states of the segment, recomputed from its checkpoint
+    // the stage inputs y_0 .. y_4 of every step of the segment, recomputed
+    // from its checkpoint by the forward stages (so bit for bit those of the
+    // forward run); step i's inputs at seg + (i - n0) 5 n
     DG_HIP(c, hipMemcpyAsync(seg, ck + sg * n, n * sizeof(T), hipMemcpyDeviceToDevice, st));
-    for (int64_t i = n0; i + 1 < n1; ++i)
-      if ((s = full_step(c, seg + (i - n0) * n, seg + (i - n0 + 1) * n, ys, ys + n, res,
-                         t0 + double(i) * dt, dt)) != DG_OK)
-        return s;
+    for (int64_t i = n0; i < n1; ++i) {
+      T* y = seg + (i - n0) * 5 * n;
+      const double ti = t0 + double(i) * dt;
+      if ((s = fill_zero(c, res, n)) != DG_OK) return s;
+      for (int q = 0; q < 5 && (q < 4 || i + 1 < n1); ++q) {
+        T* out = q < 4 ? y + (q + 1) * n : y + 5 * n;   // stage 5: the next step's y_0
+        if ((s = stage(c, y + q * n, out, res, nullptr, kRkA[q], kRkB[q], dt, 1)) != DG_OK)
+          return s;
+        if ((s = launch_sources(c, res, out, ti + kRkC[q] * dt, dt, kRkB[q] * dt)) != DG_OK)
+          return s;
+      }
+    }
     for (int64_t i = n1 - 1; i >= n0; --i) {
+      const T* ys = seg + (i - n0) * 5 * n;
       // misfit sensitivity of the trace row of step i (state after step i)
       if (c->nrec > 0) {
         dga::receiver_adjoint<T><<<nblocks(3 * Np), 256, 0, st>>>(
@@ -753,18 +806,18 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
             static_cast<const T*>(c->rec_w.p), c->nrec, Np, KNp);
         DG_HIP(c, hipGetLastError());
       }
-      // the step's stage inputs y_0 .. y_4
       const double ti = t0 + double(i) * dt;
-      DG_HIP(c, hipMemcpyAsync(ys, seg + (i - n0) * n, n * sizeof(T), hipMemcpyDeviceToDevice,
-                               st));
-      if ((s = fill_zero(c, res, n)) != DG_OK) return s;
-      for (int q = 0; q < 4; ++q) {
-        if ((s = stage(c, ys + q * n, ys + (q + 1) * n, res, nullptr, kRkA[q], kRkB[q], dt, 1)) !=
-            DG_OK)
-          return s;
-        if ((s = launch_sources(c, res, ys + (q + 1) * n, ti + kRkC[q] * dt, dt, kRkB[q] * dt)) !=
-            DG_OK)
-          return s;
+      if constexpr (std::is_same_v<T, float>) {
+        if (adj_tiled(c)) {
+          // the residual scaling of the stage after (a_{q+1}; for q = 4 the
+          // a_0 = 0 of the next step's first stage) is applied here
+          for (int q = 4; q >= 0; --q)
+            if ((s = adj_stage_tiled(c, ys + q * n, lres, ly, nu, grad, gradz,
+                                     float(kRkA[q == 4 ? 0 : q + 1]), float(kRkB[q]), dt,
+                                     ti + kRkC[q] * dt)) != DG_OK)
+              return s;
+          continue;
+        }
       }
       for (int q = 4; q >= 0; --q) {
         const double ts = ti + kRkC[q] * dt;
@@ -1111,7 +1164,7 @@ void dg_destroy(dg_ctx* c) {
                       &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
                       &c->res, &c->frags, &c->matblk, &c->nbn, &c->torder, &c->src_elem, &c->src_w,
                       &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf, &c->src_wraw,
-                      &c->adj_nbface, &c->adj_invf, &c->adj_ck, &c->adj_seg, &c->adj_y,
+                      &c->adj_nbface, &c->adj_invf, &c->adj_ck, &c->adj_seg,
                       &c->adj_v, &c->adj_gb, &c->adj_hb,
                       &c->adj_grad, &c->adj_trace})
       release(c, *b);
@@ -1158,7 +1211,7 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
     drop_graphs(c);
     for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf,
                       &c->trace, &c->src_wraw, &c->adj_nbface, &c->adj_invf, &c->adj_ck,
-                      &c->adj_seg, &c->adj_y, &c->adj_v, &c->adj_gb, &c->adj_hb,
+                      &c->adj_seg, &c->adj_v, &c->adj_gb, &c->adj_hb,
                       &c->adj_grad, &c->adj_trace})
       release(c, *b);
     c->adj_ready = false;
@@ -1791,20 +1844,19 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
     const size_t S = size_t(n) * c->elem;
     const int64_t nck = (nsteps + every - 1) / every;
     const size_t tb = size_t(nsteps) * c->nrec * 3 * c->elem;
-    const bool upwind = c->opt.flux == DG_FLUX_UPWIND;
+    const bool upwind = c->opt.flux == DG_FLUX_UPWIND, tiled = adj_tiled(c);
     DG_HIP(c, hipStreamSynchronize(c->stream));
     c->adj_ready = false;
     struct Need {
       DevBuf* b;
       size_t bytes;
     } need[] = {{&c->adj_ck, S * nck},
-                {&c->adj_seg, S * size_t(every)},
-                {&c->adj_y, S * 5},
+                {&c->adj_seg, S * size_t(every) * 5},
                 {&c->adj_v, S * 6},
                 {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
-                {&c->adj_hb, size_t(K) * NF4 * 9 * c->elem},
+                {&c->adj_hb, tiled ? 0 : size_t(K) * NF4 * 9 * c->elem},
                 {&c->adj_grad, size_t(K) * Nq * 3 * sizeof(double)},
-                {&c->adj_zb, upwind ? size_t(K) * NF4 * 4 * c->elem : 0},
+                {&c->adj_zb, upwind && !tiled ? size_t(K) * NF4 * 4 * c->elem : 0},
                 {&c->adj_gradz, upwind ? size_t(K) * c->re.Np * 2 * sizeof(double) : 0},
                 {&c->adj_trace, tb}};
     for (auto& x : need)

@@ -143,3 +143,60 @@ struct EFOrd {
 };
 
 }  // namespace dgb
+
+namespace dgt {
+
+// Sizes, FP32 operator fragments and LDS use of the tiled discrete-adjoint
+// kernel of order N (orders 1-4, v_mfma_f32_16x16x4_f32).  The 16 elements
+// of a tile are the MFMA columns; lane l = 16 g + e holds column e, supplies
+// K slot g of every 4-slot step and holds rows 4 g + j (j < 4) of each
+// 16-row accumulator tile.  Fragment groups are one float4 per lane (four
+// steps, or the three reference directions of one step), [group][64][4];
+// for lane l, r = l % 16 and k = l / 16:
+//   D   (t, s), item d < 3: D_d[16 t + r][4 s + k]   (item 3 zero)
+//   L   (t, s4), item i:    LIFT[16 t + r][4 (4 s4 + i) + k]
+//   V   (u, t), item j:     V_q[16 u + r][16 t + 4 k + j]
+//   P   (u, t), item j:     P_q[16 t + 4 k + j][16 u + r]     (P_q^T)
+//   VT  (u, t), item j:     V_q[16 u + 4 k + j][16 t + r]     (V_q^T)
+//   DT  (t, s), item d < 3: D_d[4 s + k][16 t + r]            (D_d^T)
+//   LT  (f, t), item j:     LIFT[16 t + 4 k + j][16 f + r]    (LIFT^T)
+// t: node tiles, u: quadrature tiles, f: face-node tiles.  The node index
+// 16 t + 4 k + j of V, P and LT (and the point index of VT) is the row that
+// lane group k holds in item j of an accumulator tile, so those products
+// take their B operand straight from the previous product's accumulators.
+// Entries beyond Np, Nq or 4 Nfp are zero.
+template <int N>
+struct AOrd {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  static constexpr int NF4 = 4 * Nfp;
+  static constexpr int Nq = (N + 1) * (N + 1) * (N + 1);
+  static constexpr int RT = (Np + 15) / 16;    // node tiles
+  static constexpr int QT = (Nq + 15) / 16;    // quadrature tiles
+  static constexpr int FT = (NF4 + 15) / 16;   // face-node tiles
+  static constexpr int KN = (Np + 3) / 4;      // 4-slot steps over the nodes
+  static constexpr int KF = (NF4 + 3) / 4;     // 4-slot steps over the face nodes
+  static constexpr int KF4 = (KF + 3) / 4;
+  static constexpr int G_D = 0;
+  static constexpr int G_L = G_D + RT * KN;
+  static constexpr int G_V = G_L + RT * KF4;
+  static constexpr int G_P = G_V + QT * RT;
+  static constexpr int G_VT = G_P + QT * RT;
+  static constexpr int G_DT = G_VT + QT * RT;
+  static constexpr int G_LT = G_DT + RT * KN;
+  static constexpr int NG = G_LT + FT * RT;    // fragment groups
+  // LDS, in floats: the stage input y (later mu = W^T l) [9][4 KN][16]; the
+  // face fluxes [9][4 KF][16], later the two partial stress sums of the
+  // gradient, double [2][16 QT][16]
+  static constexpr int LY = 9 * 4 * KN * 16;
+  static constexpr int LF = 9 * 4 * KF * 16;
+  static constexpr int LG = 2 * 2 * 16 * QT * 16;
+  static constexpr int LU = LF > LG ? LF : LG;
+  static constexpr int USED = (LY + LU) * 4;
+  // padded as the stage kernels are: the workgroups one CU holds never use
+  // more than 128 KiB of LDS together
+  static constexpr int FLOOR = USED <= 43690 ? 40976 : (USED <= 65536 ? 54630 : 0);
+  static constexpr int BYTES = USED > FLOOR ? USED : FLOOR;
+};
+
+}  // namespace dgt

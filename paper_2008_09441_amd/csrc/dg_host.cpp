@@ -529,6 +529,40 @@ std::vector<int32_t> neighbour_nodes(const RefElement& re, const MeshData& m) {
   return out;
 }
 
+bool adjoint_face_tables(const RefElement& re, const MeshData& m, std::vector<int32_t>& nbface,
+                         std::vector<int32_t>& invf, std::string& err) {
+  const int Nfp = re.Nfp, NF4 = 4 * Nfp, Np = re.Np;
+  nbface.assign(size_t(m.K) * NF4, 0);
+  invf.assign(size_t(Np) * 3, -1);
+  for (int64_t k = 0; k < m.K; ++k)
+    for (int f = 0; f < 4; ++f) {
+      const int64_t nb = m.EToE[k * 4 + f];
+      const int fn = m.EToF[k * 4 + f];
+      for (int i = 0; i < Nfp; ++i) {
+        const int vP = m.pat[size_t(m.EToP[k * 4 + f]) * Nfp + i];
+        int jn = -1;
+        for (int i2 = 0; i2 < Nfp; ++i2)
+          if (re.Fmask[fn * Nfp + i2] == vP) jn = fn * Nfp + i2;
+        if (jn < 0) {
+          err = "adjoint: face tables inconsistent";
+          return false;
+        }
+        nbface[size_t(k) * NF4 + f * Nfp + i] = int32_t(nb * NF4 + jn);
+      }
+    }
+  for (int j = 0; j < NF4; ++j) {
+    const int n = re.Fmask[j];
+    int s = 0;
+    while (s < 3 && invf[n * 3 + s] >= 0) ++s;
+    if (s == 3) {
+      err = "adjoint: node on more than three faces";
+      return false;
+    }
+    invf[n * 3 + s] = j;
+  }
+  return true;
+}
+
 std::vector<int32_t> tile_order(const MeshData& m, int tile, int parts) {
   const int64_t K = m.K, T = (K + tile - 1) / tile;
   std::vector<double> c(size_t(T) * 3, 0.0);

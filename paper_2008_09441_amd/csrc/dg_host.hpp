@@ -63,6 +63,13 @@ bool build_mesh(const RefElement& re, int64_t K, const double* vxyz,
 // of each element is paired with, [K][4 Nfp] (requires K Np < 2^31).
 std::vector<int32_t> neighbour_nodes(const RefElement& re, const MeshData& m);
 
+// Tables of the adjoint's flux transpose: for every face node, the
+// neighbour's face node that reads it (flat nb * 4 Nfp + j', [K][4 Nfp]),
+// and for every volume node the face nodes on it ([Np][3], -1 padded).
+// Returns false with err set when the face tables are inconsistent.
+bool adjoint_face_tables(const RefElement& re, const MeshData& m, std::vector<int32_t>& nbface,
+                         std::vector<int32_t>& invf, std::string& err);
+
 // Processing order of the tiles of `tile` consecutive elements, for a launch
 // whose workgroups are dealt to `parts` caches (XCDs) in contiguous ranges
 // of launch positions: the tiles are sorted into `parts` slabs along the

@@ -283,6 +283,62 @@ int mfma_frag_count(int N) {
   }
 }
 
+namespace {
+
+// FP32 operator fragments of the tiled adjoint kernel (the layout of
+// dgt::AOrd<N>): [NG][64 lanes][4]
+template <int N>
+std::vector<float> build_adj_frags(const RefElement& re) {
+  using O = dgt::AOrd<N>;
+  const int Np = O::Np, NF4 = O::NF4, Nq = O::Nq;
+  std::vector<float> out(size_t(O::NG) * 64 * 4, 0.f);
+  const double* Dd[3] = {re.Dr.data(), re.Ds.data(), re.Dt.data()};
+  // operator entries, zero outside the matrix
+  auto D = [&](int d, int i, int j) { return i < Np && j < Np ? Dd[d][size_t(i) * Np + j] : 0.0; };
+  auto L = [&](int i, int j) { return i < Np && j < NF4 ? re.LIFT[size_t(i) * NF4 + j] : 0.0; };
+  auto V = [&](int p, int n) { return p < Nq && n < Np ? re.Vq[size_t(p) * Np + n] : 0.0; };
+  auto P = [&](int n, int p) { return n < Np && p < Nq ? re.Pq[size_t(n) * Nq + p] : 0.0; };
+  auto put = [&](int grp, int l, int item, double v) {
+    out[(size_t(grp) * 64 + l) * 4 + item] = float(v);
+  };
+  for (int l = 0; l < 64; ++l) {
+    const int r = l % 16, k = l / 16;
+    for (int t = 0; t < O::RT; ++t)
+      for (int s = 0; s < O::KN; ++s)
+        for (int d = 0; d < 3; ++d) {
+          put(O::G_D + t * O::KN + s, l, d, D(d, 16 * t + r, 4 * s + k));
+          put(O::G_DT + t * O::KN + s, l, d, D(d, 4 * s + k, 16 * t + r));
+        }
+    for (int t = 0; t < O::RT; ++t)
+      for (int s4 = 0; s4 < O::KF4; ++s4)
+        for (int i = 0; i < 4; ++i)
+          if (4 * s4 + i < O::KF) put(O::G_L + t * O::KF4 + s4, l, i, L(16 * t + r, 4 * (4 * s4 + i) + k));
+    for (int u = 0; u < O::QT; ++u)
+      for (int t = 0; t < O::RT; ++t)
+        for (int j = 0; j < 4; ++j) {
+          put(O::G_V + u * O::RT + t, l, j, V(16 * u + r, 16 * t + 4 * k + j));
+          put(O::G_P + u * O::RT + t, l, j, P(16 * t + 4 * k + j, 16 * u + r));
+          put(O::G_VT + u * O::RT + t, l, j, V(16 * u + 4 * k + j, 16 * t + r));
+        }
+    for (int f = 0; f < O::FT; ++f)
+      for (int t = 0; t < O::RT; ++t)
+        for (int j = 0; j < 4; ++j) put(O::G_LT + f * O::RT + t, l, j, L(16 * t + 4 * k + j, 16 * f + r));
+  }
+  return out;
+}
+
+}  // namespace
+
+std::vector<float> adj_fragments_f32(const RefElement& re) {
+  switch (re.N) {
+    case 1: return build_adj_frags<1>(re);
+    case 2: return build_adj_frags<2>(re);
+    case 3: return build_adj_frags<3>(re);
+    case 4: return build_adj_frags<4>(re);
+    default: return {};
+  }
+}
+
 int mfma_f32_frag_count(int N) {
   switch (N) {
     case 1: return dgb::FOrd<1>::NF4S;
