@@ -103,17 +103,24 @@ __device__ inline void rev_flux(const T* g, T nx, T ny, T nz, T fs, T ZpM, T ZsM
 // zgrad_terms gives these four for one face node from its two states,
 // normal, Fscale, impedances and g; zgrad_faces applies it at every face
 // node.
+// the velocity jump jv = vP - vM and traction jump jt = t(P) - t(M) of a
+// face node (t = sigma n, Voigt xx yy zz yz xz xy), j[0..5] = (jv, jt)
 template <typename T>
-__device__ inline void zgrad_terms(const T* qM, const T* qP, T nx, T ny, T nz, T fs, T ZpM,
-                                   T ZsM, T ZpP, T ZsP, const T* g, T* z) {
-  const T tMx = qM[3] * nx + qM[8] * ny + qM[7] * nz;
-  const T tMy = qM[8] * nx + qM[4] * ny + qM[6] * nz;
-  const T tMz = qM[7] * nx + qM[6] * ny + qM[5] * nz;
-  const T tPx = qP[3] * nx + qP[8] * ny + qP[7] * nz;
-  const T tPy = qP[8] * nx + qP[4] * ny + qP[6] * nz;
-  const T tPz = qP[7] * nx + qP[6] * ny + qP[5] * nz;
-  const T jvx = qP[0] - qM[0], jvy = qP[1] - qM[1], jvz = qP[2] - qM[2];
-  const T jtx = tPx - tMx, jty = tPy - tMy, jtz = tPz - tMz;
+__device__ inline void face_jumps(const T* qM, const T* qP, T nx, T ny, T nz, T* j) {
+  j[0] = qP[0] - qM[0];
+  j[1] = qP[1] - qM[1];
+  j[2] = qP[2] - qM[2];
+  j[3] = (qP[3] - qM[3]) * nx + (qP[8] - qM[8]) * ny + (qP[7] - qM[7]) * nz;
+  j[4] = (qP[8] - qM[8]) * nx + (qP[4] - qM[4]) * ny + (qP[6] - qM[6]) * nz;
+  j[5] = (qP[7] - qM[7]) * nx + (qP[6] - qM[6]) * ny + (qP[5] - qM[5]) * nz;
+}
+
+// the same four derivatives from the face node's jumps (face_jumps)
+template <typename T>
+__device__ inline void zgrad_from_jumps(const T* jmp, T nx, T ny, T nz, T fs, T ZpM, T ZsM,
+                                        T ZpP, T ZsP, const T* g, T* z) {
+  const T jvx = jmp[0], jvy = jmp[1], jvz = jmp[2];
+  const T jtx = jmp[3], jty = jmp[4], jtz = jmp[5];
   const T jvn = jvx * nx + jvy * ny + jvz * nz;
   const T jtn = jtx * nx + jty * ny + jtz * nz;
   const T sp = ZpM + ZpP, ss = ZsM + ZsP;
@@ -134,6 +141,14 @@ __device__ inline void zgrad_terms(const T* qM, const T* qP, T nx, T ny, T nz, T
   z[1] = (dvtx * hx + dvty * hy + dvtz * hz) - bdvt / ss;
   z[2] = alpha * (jvn - dvn) / sp;
   z[3] = (bx * (jvtx - dvtx) + by * (jvty - dvty) + bz * (jvtz - dvtz)) / ss;
+}
+
+template <typename T>
+__device__ inline void zgrad_terms(const T* qM, const T* qP, T nx, T ny, T nz, T fs, T ZpM,
+                                   T ZsM, T ZpP, T ZsP, const T* g, T* z) {
+  T jmp[6];
+  face_jumps(qM, qP, nx, ny, nz, jmp);
+  zgrad_from_jumps(jmp, nx, ny, nz, fs, ZpM, ZsM, ZpP, ZsP, g, z);
 }
 
 }  // namespace dga

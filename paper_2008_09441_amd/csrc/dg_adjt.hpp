@@ -21,11 +21,15 @@
 //   accumulators (the K orders of AOrd).  All waves compute the face fluxes;
 //   wave 3 also adds the stress term of the gradient.
 //
+//   For the upwind flux it also keeps the velocity and traction jumps of
+//   every face node (the state the impedance gradient needs).
+//
 // adj_nodes: one thread per volume node.  Adds the flux transposes of the
 //   face nodes on the node (its own side, plus the side of the neighbour's
 //   face node that reads it) to nu, and ly += s (nu + face terms); for the
 //   upwind flux also the impedance gradient (own-side and neighbour-side
-//   terms of the same face nodes), as the generic adjoint kernels do.
+//   terms of the same face nodes, from their jumps), as the generic adjoint
+//   kernels do.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -43,7 +47,8 @@ struct TileArgs {
   float* lres;           // [9][K][Np]: in the residual adjoint before this stage, out l
   const float* ly;       // [9][K][Np]
   float* nu;             // out: volume transpose of mu [9][K][Np]
-  float* gf;             // out: LIFT^T mu at the face nodes [9][K][4 Nfp]
+  float* gf;             // out: LIFT^T mu at the face nodes [K][4 Nfp][9]
+  float* jmp;            // out (upwind): face-node jumps (jv, jt) [K][4 Nfp][8]
   double* grad;          // [3][K][Nq] += s d/dm <l, W(m) r>
   const float* geo;      // [K][9]
   const float* fgeo;     // [K][4][4]
@@ -96,10 +101,11 @@ __device__ inline double ricker(const double* par, int i, double t) {
 // Waves 0-2: everything from R y to nu and g for components 3W .. 3W + 2.
 template <int N, int W>
 __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float* sy,
-                                           const float* sf, double* sg, const float (&G)[9]) {
+                                           const float* sf, double* sg, const float (&G)[9],
+                                           const float (&lv)[3][AOrd<N>::RT][4]) {
   using O = AOrd<N>;
   constexpr int RT = O::RT, QT = O::QT, FT = O::FT, KN = O::KN, KF = O::KF, KF4 = O::KF4;
-  constexpr int Np = O::Np, Nq = O::Nq, NF4 = O::NF4, LN = 4 * KN, LFN = 4 * KF;
+  constexpr int Np = O::Np, Nq = O::Nq, NF4 = O::NF4, LN = 4 * KN, LFN = 4 * KF, CS = O::CS;
   constexpr int C0 = 3 * W;
   const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
   const int64_t K = A.K, KNp = K * Np;
@@ -109,20 +115,6 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
   const f4* fr = reinterpret_cast<const f4*>(A.frags) + lane;
   auto frag = [&](int grp) { return fr[grp * 64]; };
 
-  // the adjoint of the residual, l = a lres + b ly, at the rows this lane
-  // holds in the chained K order (node 16 t + 4 g + j); written back
-  float lv[3][RT][4];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = 16 * t + 4 * g + j;
-        const int64_t i = (C0 + c) * KNp + kc * Np + (n < Np ? n : Np - 1);
-        lv[c][t][j] = n < Np ? A.a * A.lres[i] + A.b * A.ly[i] : 0.f;
-      }
-
   // r = R y: sum_d D_d (sum_j G_dj w(c, j) y_f(c, j)) + LIFT flux_c
   f4 r[RT][3];
 #pragma unroll
@@ -130,14 +122,17 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[t][c] = f4{0.f, 0.f, 0.f, 0.f};
   {
-    f4 fa[2][RT];
+    // fragments two steps ahead
+    f4 fa[3][RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) fa[0][t] = frag(O::G_D + t * KN);
+    for (int s = 0; s < 2 && s < KN; ++s)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) fa[s][t] = frag(O::G_D + t * KN + s);
 #pragma unroll
     for (int s = 0; s < KN; ++s) {
-      if (s + 1 < KN) {
+      if (s + 2 < KN) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) fa[(s + 1) & 1][t] = frag(O::G_D + t * KN + s + 1);
+        for (int t = 0; t < RT; ++t) fa[(s + 2) % 3][t] = frag(O::G_D + t * KN + s + 2);
       }
       const int m = 4 * s + g;
       float z[3][3];
@@ -149,7 +144,7 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
 #pragma unroll
           for (int j = 0; j < 3; ++j)
             if (vweight(C0 + c, j) != 0.f)
-              acc += vweight(C0 + c, j) * G[3 * d + j] * sy[(vfield(C0 + c, j) * LN + m) * 16 + e];
+              acc += vweight(C0 + c, j) * G[3 * d + j] * sy[(vfield(C0 + c, j) * LN + m) * CS + e];
           z[c][d] = acc;
         }
 #pragma unroll
@@ -157,7 +152,7 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) r[t][c] = mma(fa[s & 1][t][d], z[c][d], r[t][c]);
+          for (int c = 0; c < 3; ++c) r[t][c] = mma(fa[s % 3][t][d], z[c][d], r[t][c]);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -177,7 +172,7 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
         if (s < KF) {
           float b[3];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) b[c] = sf[((C0 + c) * LFN + 4 * s + g) * 16 + e];
+          for (int c = 0; c < 3; ++c) b[c] = sf[((C0 + c) * LFN + 4 * s + g) * CS + e];
 #pragma unroll
           for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -188,9 +183,15 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
     }
   }
   // raw point sources (velocity rows) of the elements in this tile
+  int64_t sel[8];
   if (W == 0 && A.nsrc > 0) {
     for (int i = 0; i < A.nsrc; ++i) {
-      if (A.src_elem[i] != k || !ok) continue;
+      if (i % 8 == 0) {
+        // the elements of the next eight sources, loaded together
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sel[q] = i + q < A.nsrc ? A.src_elem[i + q] : -1;
+      }
+      if (sel[i % 8] != k || !ok) continue;
       const float f = float(ricker(A.src_par, i, A.ts));
 #pragma unroll
       for (int c = 0; c < 3; ++c)
@@ -321,7 +322,7 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
       const int n = 16 * t + 4 * g + j;
       if (n < LN) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sy[((C0 + c) * LN + n) * 16 + e] = mu[t][c][j];
+        for (int c = 0; c < 3; ++c) sy[((C0 + c) * LN + n) * CS + e] = mu[t][c][j];
       }
     }
   __syncthreads();   // (3) mu complete
@@ -334,14 +335,16 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int c = 0; c < 3; ++c) o[t][c] = f4{0.f, 0.f, 0.f, 0.f};
-    f4 fa[2][RT];
+    f4 fa[3][RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) fa[0][t] = frag(O::G_DT + t * KN);
+    for (int s = 0; s < 2 && s < KN; ++s)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) fa[s][t] = frag(O::G_DT + t * KN + s);
 #pragma unroll
     for (int s = 0; s < KN; ++s) {
-      if (s + 1 < KN) {
+      if (s + 2 < KN) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) fa[(s + 1) & 1][t] = frag(O::G_DT + t * KN + s + 1);
+        for (int t = 0; t < RT; ++t) fa[(s + 2) % 3][t] = frag(O::G_DT + t * KN + s + 2);
       }
       const int m = 4 * s + g;
       float mv[9];
@@ -352,7 +355,7 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
         for (int f = 0; f < 3; ++f)
 #pragma unroll
           for (int j = 0; j < 3; ++j) used |= vweight(c, j) != 0.f && vfield(c, j) == C0 + f;
-        mv[c] = used ? sy[(c * LN + m) * 16 + e] : 0.f;
+        mv[c] = used ? sy[(c * LN + m) * CS + e] : 0.f;
       }
       float z[3][3];
 #pragma unroll
@@ -373,7 +376,7 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
-          for (int f = 0; f < 3; ++f) o[t][f] = mma(fa[s & 1][t][d], z[f][d], o[t][f]);
+          for (int f = 0; f < 3; ++f) o[t][f] = mma(fa[s % 3][t][d], z[f][d], o[t][f]);
       __builtin_amdgcn_sched_barrier(0);
     }
     if (ok) {
@@ -390,11 +393,15 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
   }
   // g_c = LIFT^T mu_c at the face nodes, K from the mu accumulators
   {
-    f4 fa[RT];
+    f4 fa[2][RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) fa[0][t] = frag(O::G_LT + t);
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) {
+      if (ft + 1 < FT) {
 #pragma unroll
-      for (int t = 0; t < RT; ++t) fa[t] = frag(O::G_LT + ft * RT + t);
+        for (int t = 0; t < RT; ++t) fa[(ft + 1) & 1][t] = frag(O::G_LT + (ft + 1) * RT + t);
+      }
       f4 o[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) o[c] = f4{0.f, 0.f, 0.f, 0.f};
@@ -403,25 +410,47 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) o[c] = mma(fa[t][j], mu[t][c][j], o[c]);
+          for (int c = 0; c < 3; ++c) o[c] = mma(fa[ft & 1][t][j], mu[t][c][j], o[c]);
       if (ok) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < 4; ++j) {
+          const int jf = 16 * ft + 4 * g + j;
+          if (jf < NF4) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int jf = 16 * ft + 4 * g + j;
-            if (jf < NF4) A.gf[((C0 + c) * K + k) * NF4 + jf] = o[c][j];
+            for (int c = 0; c < 3; ++c) A.gf[(k * NF4 + jf) * 9 + C0 + c] = o[c][j];
           }
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
+// l = a lres + b ly for components c0 .. c0 + 2 of element k0 + e at the
+// rows the lane holds in the chained K order (node 16 t + 4 g + j)
+template <int N>
+__device__ __forceinline__ void load_l(const TileArgs& A, int64_t k0, int c0,
+                                       float (&lv)[3][AOrd<N>::RT][4]) {
+  using O = AOrd<N>;
+  constexpr int Np = O::Np;
+  const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+  const int64_t KNp = A.K * Np, kc = k0 + e < A.K ? k0 + e : A.K - 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int t = 0; t < O::RT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 16 * t + 4 * g + j;
+        const int64_t i = (c0 + c) * KNp + kc * Np + (n < Np ? n : Np - 1);
+        lv[c][t][j] = n < Np ? A.a * A.lres[i] + A.b * A.ly[i] : 0.f;
+      }
+}
+
 template <int N>
 __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
   using O = AOrd<N>;
-  constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, Nq = O::Nq, QT = O::QT;
+  constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, Nq = O::Nq, QT = O::QT, CS = O::CS;
   constexpr int LN = 4 * O::KN, LFN = 4 * O::KF;
   constexpr int NT = (16 * NF4 + kThreads - 1) / kThreads;   // face-node tasks per thread
   static_assert(LFN == NF4, "the face-node steps cover the face nodes exactly");
@@ -438,11 +467,25 @@ __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
   const int64_t tile = xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3);
   const int64_t k0 = 16 * tile;
 
-  // the tile's y into LDS (rows past Np and elements past K are zero)
-  for (int i = tid; i < 9 * 16 * LN; i += kThreads) {
-    const int c = i / (16 * LN), rem = i - c * 16 * LN, e = rem / LN, m = rem - e * LN;
-    const int64_t k = k0 + e;
-    sy[(c * LN + m) * 16 + e] = (m < Np && k < K) ? A.y[c * KNp + k * Np + m] : 0.f;
+  // the tile's y into LDS (rows past Np and elements past K are zero): all
+  // of a thread's loads are issued before the first store
+  {
+    constexpr int NY = (9 * 16 * LN + kThreads - 1) / kThreads;
+    float yv[NY];
+#pragma unroll
+    for (int r = 0; r < NY; ++r) {
+      const int i = tid + kThreads * r;
+      const int c = i / (16 * LN), rem = i - c * 16 * LN, e = rem / LN, m = rem - e * LN;
+      const int64_t k = k0 + e;
+      const bool live = i < 9 * 16 * LN && m < Np && k < K;
+      yv[r] = live ? A.y[c * KNp + k * Np + m] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < NY; ++r) {
+      const int i = tid + kThreads * r;
+      const int c = i / (16 * LN), rem = i - c * 16 * LN, e = rem / LN, m = rem - e * LN;
+      if (i < 9 * 16 * LN) sy[(c * LN + m) * CS + e] = yv[r];
+    }
   }
   // face-node tasks (element e, face node jf): the neighbour's state and
   // impedances, then (after the barrier) the flux from the own side in LDS
@@ -469,6 +512,9 @@ __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) G[i] = A.geo[k * 9 + i];
   }
+  // the group waves' l (loaded at the start of their phases: issued here,
+  // beside the neighbour gathers, it cost registers that then spilled)
+  float lv[3][O::RT][4];
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
@@ -479,33 +525,58 @@ __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
     const int vM = vMt[i];
     float qM[9], fl[9];
 #pragma unroll
-    for (int f = 0; f < 9; ++f) qM[f] = sy[(f * LN + vM) * 16 + e];
+    for (int f = 0; f < 9; ++f) qM[f] = sy[(f * LN + vM) * CS + e];
     dga::flux<float>(qM, qP[i], fg[i][0], fg[i][1], fg[i][2], fg[i][3], A.zp[k * Np + vM],
                      A.zs[k * Np + vM], zpP[i], zsP[i], A.upwind, fl);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) sf[(c * LFN + jf) * 16 + e] = fl[c];
+    for (int c = 0; c < 9; ++c) sf[(c * LFN + jf) * CS + e] = fl[c];
+    if (A.upwind && k0 + e < K) {
+      float jm[6];
+      dga::face_jumps<float>(qM, qP[i], fg[i][0], fg[i][1], fg[i][2], jm);
+      f4* jo = reinterpret_cast<f4*>(A.jmp + (k * NF4 + jf) * 8);
+      jo[0] = f4{jm[0], jm[1], jm[2], jm[3]};
+      jo[1] = f4{jm[4], jm[5], 0.f, 0.f};
+    }
   }
   __syncthreads();
 
   if (wave == 0) {
-    tile_group<N, 0>(A, k0, sy, sf, sg, G);
+    load_l<N>(A, k0, 0, lv);
+    tile_group<N, 0>(A, k0, sy, sf, sg, G, lv);
   } else if (wave == 1) {
-    tile_group<N, 1>(A, k0, sy, sf, sg, G);
+    load_l<N>(A, k0, 3, lv);
+    tile_group<N, 1>(A, k0, sy, sf, sg, G, lv);
   } else if (wave == 2) {
-    tile_group<N, 2>(A, k0, sy, sf, sg, G);
+    load_l<N>(A, k0, 6, lv);
+    tile_group<N, 2>(A, k0, sy, sf, sg, G, lv);
   } else {
     __syncthreads();   // (1)
     __syncthreads();   // (2): the partial stress sums are complete
-    // d/d mu = 2 (stress sum of the normal stresses + of the shear stresses)
+    __syncthreads();   // (3): nothing writes them any more
+    // d/d mu = 2 (stress sum of the normal stresses + of the shear stresses),
+    // while the other waves run their last products; in batches whose loads
+    // are all issued before the first store
     const int lane = tid & 63;
-    for (int i = lane; i < 16 * Nq; i += 64) {
-      const int e = i / Nq, p = i - e * Nq;
-      const int64_t k = k0 + e;
-      if (k >= K) continue;
-      const double v = sg[(p)*16 + e] + sg[(16 * QT + p) * 16 + e];
-      A.grad[2 * K * Nq + k * Nq + p] += A.s * 2.0 * v;
+    double* g2 = A.grad + 2 * K * Nq;
+    constexpr int NB = 16, NI = (16 * Nq + 63) / 64;
+#pragma unroll
+    for (int r0 = 0; r0 < NI; r0 += NB) {
+      double old[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const int i = lane + 64 * (r0 + r);
+        const int e = i / Nq, p = i - e * Nq;
+        const bool live = r0 + r < NI && i < 16 * Nq && k0 + e < K;
+        old[r] = live ? g2[(k0 + e) * Nq + p] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const int i = lane + 64 * (r0 + r);
+        const int e = i / Nq, p = i - e * Nq;
+        if (r0 + r < NI && i < 16 * Nq && k0 + e < K)
+          g2[(k0 + e) * Nq + p] = old[r] + A.s * 2.0 * (sg[p * 16 + e] + sg[(16 * QT + p) * 16 + e]);
+      }
     }
-    __syncthreads();   // (3)
   }
 }
 
@@ -513,8 +584,8 @@ __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
 // volume nodes, and ly += s (nu + face terms).
 struct NodeArgs {
   const float* nu;        // [9][K][Np]
-  const float* gf;        // [9][K][4 Nfp]
-  const float* y;         // stage input [9][K][Np]
+  const float* gf;        // [K][4 Nfp][9]
+  const float* jmp;       // [K][4 Nfp][8] face-node jumps (upwind)
   float* ly;              // [9][K][Np]
   double* gradz;          // [2][K][Np] (upwind)
   const float* fgeo;      // [K][4][4]
@@ -539,11 +610,6 @@ __global__ __launch_bounds__(256) void adj_nodes(NodeArgs A) {
   float h[9];
 #pragma unroll
   for (int f = 0; f < 9; ++f) h[f] = A.nu[f * KNp + i];
-  float qM[9];
-  if (A.upwind) {
-#pragma unroll
-    for (int f = 0; f < 9; ++f) qM[f] = A.y[f * KNp + i];
-  }
   const float ZpM = A.zp[i], ZsM = A.zs[i];
   double gp = 0.0, gs = 0.0;
   for (int t = 0; t < 3; ++t) {
@@ -558,8 +624,8 @@ __global__ __launch_bounds__(256) void adj_nodes(NodeArgs A) {
     float go[9], gn[9], a[9], b[9];
 #pragma unroll
     for (int f = 0; f < 9; ++f) {
-      go[f] = A.gf[(f * K + k) * NF4 + jf];
-      gn[f] = A.gf[(f * K + nb) * NF4 + jfn];
+      go[f] = A.gf[own * 9 + f];
+      gn[f] = A.gf[jn * 9 + f];
     }
     // own flux (this node on its "-" side), then the neighbour's flux at
     // its face node jn, which reads this node as its "+" side
@@ -570,11 +636,14 @@ __global__ __launch_bounds__(256) void adj_nodes(NodeArgs A) {
 #pragma unroll
     for (int f = 0; f < 9; ++f) h[f] += b[f];
     if (A.upwind) {
-      float qP[9], zo[4], zn[4];
-#pragma unroll
-      for (int f = 0; f < 9; ++f) qP[f] = A.y[f * KNp + nP];
-      dga::zgrad_terms<float>(qM, qP, fo[0], fo[1], fo[2], fo[3], ZpM, ZsM, ZpP, ZsP, go, zo);
-      dga::zgrad_terms<float>(qP, qM, fn[0], fn[1], fn[2], fn[3], ZpP, ZsP, ZpM, ZsM, gn, zn);
+      const f4* jo = reinterpret_cast<const f4*>(A.jmp + own * 8);
+      const f4* jq = reinterpret_cast<const f4*>(A.jmp + jn * 8);
+      const f4 o0 = jo[0], o1 = jo[1], q0 = jq[0], q1 = jq[1];
+      const float jmo[6] = {o0[0], o0[1], o0[2], o0[3], o1[0], o1[1]};
+      const float jmn[6] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1]};
+      float zo[4], zn[4];
+      dga::zgrad_from_jumps<float>(jmo, fo[0], fo[1], fo[2], fo[3], ZpM, ZsM, ZpP, ZsP, go, zo);
+      dga::zgrad_from_jumps<float>(jmn, fn[0], fn[1], fn[2], fn[3], ZpP, ZsP, ZpM, ZsM, gn, zn);
       gp += double(zo[0]) + double(zn[2]);
       gs += double(zo[1]) + double(zn[3]);
     }

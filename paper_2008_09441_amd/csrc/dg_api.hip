@@ -113,6 +113,7 @@ struct dg_ctx {
   DevBuf adj_gb, adj_hb;    // face-node work [K][4 Nfp][9]
   DevBuf adj_grad;          // double [3][K][Nq]
   DevBuf adj_zb;            // upwind: impedance terms per face node [K][4 Nfp][4]
+                            // (tiled adjoint: face-node jumps [K][4 Nfp][8])
   DevBuf adj_gradz;         // upwind: double [2][K][Np]
   DevBuf adj_frag;          // FP32 orders 1-4: fragments of the tiled adjoint kernel
   DevBuf adj_trace;         // [nsteps][nrec][3]
@@ -693,6 +694,7 @@ dg_status adj_stage_tiled(dg_ctx* c, const float* y, float* lres, float* ly, flo
   A.ly = ly;
   A.nu = nu;
   A.gf = static_cast<float*>(c->adj_gb.p);
+  A.jmp = static_cast<float*>(c->adj_zb.p);
   A.grad = grad;
   A.geo = static_cast<const float*>(c->geo.p);
   A.fgeo = static_cast<const float*>(c->fgeo.p);
@@ -725,7 +727,7 @@ dg_status adj_stage_tiled(dg_ctx* c, const float* y, float* lres, float* ly, flo
   dgt::NodeArgs B{};
   B.nu = nu;
   B.gf = A.gf;
-  B.y = y;
+  B.jmp = A.jmp;
   B.ly = ly;
   B.gradz = gradz;
   B.fgeo = A.fgeo;
@@ -1856,7 +1858,7 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
                 {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
                 {&c->adj_hb, tiled ? 0 : size_t(K) * NF4 * 9 * c->elem},
                 {&c->adj_grad, size_t(K) * Nq * 3 * sizeof(double)},
-                {&c->adj_zb, upwind && !tiled ? size_t(K) * NF4 * 4 * c->elem : 0},
+                {&c->adj_zb, upwind ? size_t(K) * NF4 * (tiled ? 8 : 4) * c->elem : 0},
                 {&c->adj_gradz, upwind ? size_t(K) * c->re.Np * 2 * sizeof(double) : 0},
                 {&c->adj_trace, tb}};
     for (auto& x : need)

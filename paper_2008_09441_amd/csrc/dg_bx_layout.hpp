@@ -185,11 +185,13 @@ struct AOrd {
   static constexpr int G_DT = G_VT + QT * RT;
   static constexpr int G_LT = G_DT + RT * KN;
   static constexpr int NG = G_LT + FT * RT;    // fragment groups
-  // LDS, in floats: the stage input y (later mu = W^T l) [9][4 KN][16]; the
-  // face fluxes [9][4 KF][16], later the two partial stress sums of the
-  // gradient, double [2][16 QT][16]
-  static constexpr int LY = 9 * 4 * KN * 16;
-  static constexpr int LF = 9 * 4 * KF * 16;
+  // LDS, in floats: the stage input y (later mu = W^T l) [9][4 KN][CS]; the
+  // face fluxes [9][4 KF][CS], later the two partial stress sums of the
+  // gradient, double [2][16 QT][16]; rows of CS = 17 floats (16 elements,
+  // padded so that row-wise and column-wise accesses spread over the banks)
+  static constexpr int CS = 17;
+  static constexpr int LY = 9 * 4 * KN * CS;
+  static constexpr int LF = 9 * 4 * KF * CS;
   static constexpr int LG = 2 * 2 * 16 * QT * 16;
   static constexpr int LU = LF > LG ? LF : LG;
   static constexpr int USED = (LY + LU) * 4;

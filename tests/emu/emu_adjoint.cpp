@@ -71,6 +71,7 @@ int main(int argc, char** argv) {
   float* lyd = dup(ly);
   float* nu = alloc<float>(n9);
   float* gf = alloc<float>(size_t(9) * K * NF4);
+  float* jmp = alloc<float>(size_t(8) * K * NF4);
   double* grad = alloc<double>(size_t(3) * K * Nq);
   double* gradz = alloc<double>(size_t(2) * K * Np);
   for (int64_t i = 0; i < 3 * K * Nq; ++i) grad[i] = 0.0;
@@ -78,7 +79,7 @@ int main(int argc, char** argv) {
   std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
 
   dgt::TileArgs A{};
-  A.y = yd; A.lres = lr; A.ly = lyd; A.nu = nu; A.gf = gf; A.grad = grad;
+  A.y = yd; A.lres = lr; A.ly = lyd; A.nu = nu; A.gf = gf; A.jmp = jmp; A.grad = grad;
   A.geo = dupf(m.geo); A.fgeo = dupf(m.fgeo);
   A.nbn = dup(dgh::neighbour_nodes(re, m));
   A.fmask = dup(fm);
@@ -98,7 +99,7 @@ int main(int argc, char** argv) {
     default: run_grid(tiles, [=]() { dgt::adj_tile<4>(A); }); break;
   }
   dgt::NodeArgs B{};
-  B.nu = nu; B.gf = gf; B.y = yd; B.ly = lyd; B.gradz = gradz;
+  B.nu = nu; B.gf = gf; B.jmp = jmp; B.ly = lyd; B.gradz = gradz;
   B.fgeo = A.fgeo; B.zp = A.zp; B.zs = A.zs; B.nbn = A.nbn;
   B.nbface = dup(nbface); B.invf = dup(invf);
   B.K = K; B.Np = Np; B.Nfp = re.Nfp; B.s = sc[2]; B.upwind = upwind;
