@@ -55,7 +55,7 @@ typedef enum {
 } dg_status;
 
 /* DG_FP64: FP64 state and arithmetic (the dense contractions on the FP64
- * matrix cores, 16x16x4 products, at orders 1-4; the generic kernel at 5-7).
+ * matrix cores, 16x16x4 products, at every order).
  * DG_FP32: FP32 state and arithmetic, with the
  * dense contractions on the FP32 matrix cores (16x16x4 products).
  * DG_FP32_BF16X3: FP32 state, the dense contractions as split products of
@@ -279,10 +279,11 @@ dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const doubl
  * the receiver velocities after every step to trace (host
  * [nsteps][nrec][3], working precision).  Leaves the context at the end of
  * the run.  Needs receivers (DG_ESTATE).  Library-owned device memory:
- * ceil(nsteps/every) + 5 every + 6 states plus two face-node work arrays
- * [K][4 Nfp][9] and the FP64 gradient [3][K][Nq] (upwind: also [K][4 Nfp][4]
- * impedance terms and the FP64 gradient [2][K][Np]), counted against the
- * HBM budget. */
+ * ceil(nsteps/every) + 5 every + 6 states plus face-node work arrays
+ * ([K][4 Nfp][9], two of them on the generic adjoint kernels) and the FP64
+ * gradient [3][K][Nq] (upwind: also [K][4 Nfp][4] impedance terms, [K][4
+ * Nfp][8] face jumps on the tiled FP32 kernels of orders 1-4, and the FP64
+ * gradient [2][K][Np]), counted against the HBM budget. */
 dg_status dg_adjoint_forward(dg_ctx* ctx, double t0, double dt, int64_t nsteps, int64_t every,
                              void* trace);
 

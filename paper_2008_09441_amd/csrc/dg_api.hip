@@ -151,9 +151,9 @@ bool tiled_kernel(int32_t precision, int order) {
 bool plain_material(int32_t precision, int order) {
   return !(precision == DG_FP32_BF16X3 && order <= 4);
 }
-// Contexts whose stage runs on the matrix cores: BF16x3 and FP32 at every
-// order (the tiled kernel at orders 1-4, one element per workgroup at 5-7);
-// they read the neighbour-node table.
+// FP32 and BF16x3 contexts (launch_mfma: the tiled kernel at orders 1-4, one
+// element per workgroup at 5-7); FP64 contexts run the FP64 matrix-core
+// kernels through launch_stage.
 bool tiled_mfma(const dg_ctx* c) {
   return c->opt.precision == DG_FP32_BF16X3 || c->opt.precision == DG_FP32;
 }
@@ -223,47 +223,6 @@ dg_status upload_raw(dg_ctx* c, DevBuf& b, const U* src, size_t n) {
 }
 
 // ---------------------------------------------------------------- launch --
-template <typename T, int N>
-hipError_t launch_generic(const dg_ctx* c, const T* q_in, T* q_out, T* res, T* rhs_out,
-                          double a, double b, double dt, int lsrk) {
-  const dgh::RefElement& re = c->re;
-  dgk::StageArgs<T> A;
-  // the transposed pack DrT | DsT | DtT | LIFTT | VqT | PqT
-  const T* ops = static_cast<const T*>(c->opsT.p);
-  const size_t NpP = 4 * size_t((re.Np + 3) / 4), QP = 32 * size_t((re.Nq + 31) / 32);
-  A.q_in = q_in;
-  A.q_out = q_out;
-  A.res = res;
-  A.rhs_out = rhs_out;
-  A.geo = static_cast<const T*>(c->geo.p);
-  A.fgeo = static_cast<const T*>(c->fgeo.p);
-  A.etoe = static_cast<const int32_t*>(c->etoe.p);
-  A.etop = static_cast<const uint8_t*>(c->etop.p);
-  A.pat = static_cast<const int32_t*>(c->pat.p);
-  A.fmask = static_cast<const int32_t*>(c->fmask.p);
-  A.irho = static_cast<const T*>(c->irho.p);
-  A.lam = static_cast<const T*>(c->lam.p);
-  A.mu = static_cast<const T*>(c->mu.p);
-  A.zp = static_cast<const T*>(c->zp.p);
-  A.zs = static_cast<const T*>(c->zs.p);
-  A.DrT = ops;
-  A.DsT = ops + size_t(re.Np) * NpP;
-  A.DtT = ops + 2 * size_t(re.Np) * NpP;
-  A.LIFTT = ops + 3 * size_t(re.Np) * NpP;
-  A.VqT = A.LIFTT + size_t(4 * re.Nfp) * NpP;
-  A.PqT = A.VqT + size_t(re.Np) * QP;
-  A.K = c->mesh.K;
-  A.a = T(a);
-  A.b = T(b);
-  A.dt = T(dt);
-  A.lsrk = lsrk;
-  A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
-  constexpr int E = dgk::elems_per_block<T, N>();
-  const int64_t nblk = (c->mesh.K + E - 1) / E;
-  dgk::stage_generic<T, N><<<dim3(unsigned(nblk)), dim3(dgk::kBlock), 0, c->stream>>>(A);
-  return hipGetLastError();
-}
-
 // FP64 stage on the matrix cores at orders 1-4: the tiled kernel with FP64
 // fragments and v_mfma_f64_16x16x4f64 (dg_bx.hpp)
 template <int N>
@@ -295,9 +254,40 @@ hipError_t launch_mfma_d(const dg_ctx* c, const double* q_in, double* q_out, dou
   return hipGetLastError();
 }
 
-// FP64 contexts: the matrix-core tiled kernel at orders 1-4, the generic
-// kernel at 5-7 (FP32 and BF16x3 contexts run on the matrix cores at every
-// order, launch_mfma)
+// FP64 stage on the matrix cores at orders 5-7: one element per workgroup
+// with FP64 fragments and v_mfma_f64_16x16x4f64 (dg_be.hpp)
+template <int N>
+hipError_t launch_be_d(const dg_ctx* c, const double* q_in, double* q_out, double* res,
+                       double* rhs_out, double a, double b, double dt, int lsrk) {
+  dgb::BeArgsT<double> A;
+  A.q_in = q_in;
+  A.q_out = q_out;
+  A.res = res;
+  A.rhs_out = rhs_out;
+  A.geo = static_cast<const double*>(c->geo.p);
+  A.fgeo = static_cast<const double*>(c->fgeo.p);
+  A.nbn = static_cast<const int32_t*>(c->nbn.p);
+  A.fmask = static_cast<const int32_t*>(c->fmask.p);
+  A.irho = static_cast<const double*>(c->irho.p);
+  A.lam = static_cast<const double*>(c->lam.p);
+  A.mu = static_cast<const double*>(c->mu.p);
+  A.zp = static_cast<const double*>(c->zp.p);
+  A.zs = static_cast<const double*>(c->zs.p);
+  A.frags = static_cast<const dgb::u32x4*>(c->frags.p);
+  A.K = c->mesh.K;
+  A.a = a;
+  A.b = b;
+  A.dt = dt;
+  A.lsrk = lsrk;
+  A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+  if (c->mesh.K > 0x7fffffff) return hipErrorInvalidValue;
+  dgb::stage_be_d<N><<<dim3(unsigned(c->mesh.K)), dim3(dgb::kThreads), 0, c->stream>>>(A);
+  return hipGetLastError();
+}
+
+// FP64 contexts: the matrix-core kernels in double precision (the tiled
+// kernel at orders 1-4, one element per workgroup at 5-7), as FP32 and
+// BF16x3 contexts run on the matrix cores at every order (launch_mfma)
 hipError_t launch_stage_f64(const dg_ctx* c, const double* q_in, double* q_out, double* res,
                             double* rhs_out, double a, double b, double dt, int lsrk) {
   switch (c->re.N) {
@@ -305,9 +295,9 @@ hipError_t launch_stage_f64(const dg_ctx* c, const double* q_in, double* q_out, 
     case 2: return launch_mfma_d<2>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 3: return launch_mfma_d<3>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     case 4: return launch_mfma_d<4>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 5: return launch_generic<double, 5>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 6: return launch_generic<double, 6>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
-    case 7: return launch_generic<double, 7>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 5: return launch_be_d<5>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 6: return launch_be_d<6>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
+    case 7: return launch_be_d<7>(c, q_in, q_out, res, rhs_out, a, b, dt, lsrk);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1137,7 +1127,7 @@ dg_status dg_create(dg_ctx** out, const dg_options* opt) {
           dg_destroy(c);
           return DG_ENOMEM;
         }
-      } else if (re.N <= 4) {   // FP64 on the matrix cores
+      } else {   // FP64 on the matrix cores
         const std::vector<double> fr = dgh::mfma_fragments_f64(re);
         if (upload_raw(c, c->frags, fr.data(), fr.size()) != DG_OK) {
           dg_destroy(c);
@@ -1229,7 +1219,7 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
     if ((s = upload_raw(c, c->etoe, md.EToE.data(), md.EToE.size())) != DG_OK) return s;
     if ((s = upload_raw(c, c->etop, md.EToP.data(), md.EToP.size())) != DG_OK) return s;
     if ((s = upload_raw(c, c->pat, md.pat.data(), md.pat.size())) != DG_OK) return s;
-    if (tiled_mfma(c) || tiled_kernel(c->opt.precision, c->re.N)) {
+    {   // every stage kernel gathers through the neighbour-node table
       if (K * c->re.Np >= (int64_t(1) << 31)) return fail(c, DG_EINVAL, "mesh: K Np too large");
       const std::vector<int32_t> nbn = dgh::neighbour_nodes(c->re, md);
       if ((s = upload_raw(c, c->nbn, nbn.data(), nbn.size())) != DG_OK) return s;
@@ -1762,11 +1752,10 @@ dg_status dg_footprint(int32_t order, int32_t precision, int64_t K, int32_t nsrc
     b += NF4 * 4;                                                       // face masks
     if (precision == DG_FP32_BF16X3) b += uint64_t(dgh::mfma_frag_count(order)) * 64 * 8 * 2;
     else if (precision == DG_FP32) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 16;
-    else if (order <= 4) b += uint64_t(dgh::mfma_f32_frag_count(order)) * 32;   // FP64 fragments
+    else b += uint64_t(dgh::mfma_f32_frag_count(order)) * 32;   // FP64 fragments
     b += k * (9 + 16) * e + k * 4 * 4 + k * 4 + 96 * Nfp * 4;          // geometry, tables
     b += 3 * 9 * k * Np * e + 2 * sizeof(double);                      // q[2], res, clock
-    if (precision == DG_FP32_BF16X3 || precision == DG_FP32 || order <= 4)
-      b += k * NF4 * 4;                                                 // neighbour nodes
+    b += k * NF4 * 4;                                                   // neighbour nodes
     if (tiled_kernel(precision, order)) {
       b += ((k + 15) / 16) * 3 * uint64_t(dgh::mfma_mats(order)) * e;   // blocked material
       b += (k + 15) / 16 * 4;                                           // tile order

@@ -21,6 +21,9 @@
 //      stresses is gathered across the lanes of a row), into LDS;
 //   7  P_q (rows split by wave), then the right-hand side store or the
 //      LSRK(5,4) stage update [CK94] straight from the accumulators.
+// The FP32 variant (stage_be<N, true>) runs the same phases on
+// v_mfma_f32_16x16x4_f32 with FP32 fragments (EFOrd), and stage_be_d<N> in
+// double precision on v_mfma_f64_16x16x4f64.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -32,29 +35,34 @@ namespace dgb {
 
 constexpr int kCS = 17;   // LDS row stride of a [rows][16 columns] buffer
 
-struct BeArgs {
-  const float* q_in;     // [9][K][Np]
-  float* q_out;          // [9][K][Np] (LSRK mode)
-  float* res;            // [9][K][Np] (LSRK mode)
-  float* rhs_out;        // [9][K][Np] (rhs mode)
-  const float* geo;      // [K][9]: d(r,s,t)_i / d(x,y,z)_j at i*3+j
-  const float* fgeo;     // [K][4][4]: outward unit normal, Fscale
+// kernel arguments in the working precision T (float; double for the FP64
+// matrix-core kernel)
+template <typename T>
+struct BeArgsT {
+  const T* q_in;         // [9][K][Np]
+  T* q_out;              // [9][K][Np] (LSRK mode)
+  T* res;                // [9][K][Np] (LSRK mode)
+  T* rhs_out;            // [9][K][Np] (rhs mode)
+  const T* geo;          // [K][9]: d(r,s,t)_i / d(x,y,z)_j at i*3+j
+  const T* fgeo;         // [K][4][4]: outward unit normal, Fscale
   const int32_t* nbn;    // [K][4 Nfp]: neighbour volume node nb * Np + vP of each face node
   const int32_t* fmask;  // [4][Nfp]
-  const float* irho;     // [K][Nq]
-  const float* lam;      // [K][Nq]
-  const float* mu;       // [K][Nq]
-  const float* zp;       // [K][Np]
-  const float* zs;
+  const T* irho;         // [K][Nq]
+  const T* lam;          // [K][Nq]
+  const T* mu;           // [K][Nq]
+  const T* zp;           // [K][Np]
+  const T* zs;
   const u32x4* frags;    // [NFRAG][64]
   int64_t K;
-  float a, b, dt;
+  T a, b, dt;
   int lsrk;              // 0: write rhs_out; 1: fused LSRK update
   int upwind;            // 1 upwind, 0 central
 };
+typedef BeArgsT<float> BeArgs;
 
-// LDS use of one workgroup, in floats, and its padded allocation in bytes
-template <int N>
+// LDS use of one workgroup, in elements of T, and its padded allocation in
+// bytes
+template <int N, typename T = float>
 struct BeLds {
   using O = EOrd<N>;
   static constexpr int NK = 32 * O::KN, FK = 32 * O::KF, QK = 32 * O::KQ;
@@ -65,11 +73,12 @@ struct BeLds {
   static constexpr int SW = QK * kCS;                 // weighted V_q r [QK][17] (phases 6-7)
   static constexpr int OFF_U = ((SQ + SR) + 3) & ~3;
   static constexpr int SU = SD + SF > SW ? SD + SF : SW;
-  static constexpr int USED = (OFF_U + SU) * 4;
+  static constexpr int USED = (OFF_U + SU) * int(sizeof(T));
   // Padded so that the workgroups one CU can hold (160 KiB of LDS) never use
-  // more than 128 KiB together (at most 3 per CU at >40 KiB each, or 2 at
-  // >53.3 KiB each).
-  static constexpr int FLOOR = USED <= 43690 ? 40976 : (USED <= 65536 ? 54630 : 0);
+  // more than 128 KiB together (at most 3 per CU at >40 KiB each, 2 at
+  // >53.3 KiB each, or 1 at >80 KiB each).
+  static constexpr int FLOOR =
+      USED <= 43690 ? 40976 : USED <= 65536 ? 54630 : USED <= 81920 ? 81936 : 0;
   static constexpr int BYTES = USED > FLOOR ? USED : FLOOR;
 };
 
@@ -120,20 +129,21 @@ __device__ __forceinline__ void be_pipe(const BeArgs& A, int lane, Frag frag, BR
 // FP32 variant (v_mfma_f32_16x16x4_f32, fragments in the layout of EFOrd):
 // K group s is 16 operator columns; lane (column e, group g) takes rows
 // 16 s + 4 j + g of column e as the B operand of the group's product j
-__device__ __forceinline__ void be_bread4(const float* buf, int s, int g, int e, float (&v)[4]) {
+template <typename T>
+__device__ __forceinline__ void be_bread4(const T* buf, int s, int g, int e, T (&v)[4]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) v[j] = buf[(16 * s + 4 * j + g) * kCS + e];
 }
 
-template <int NS, int JS, typename Frag, typename BRead>
-__device__ __forceinline__ void be_pipe_f(const BeArgs& A, int lane, Frag frag, BRead bread,
-                                          f32x4 (&acc)[JS]) {
+template <int NS, int JS, typename T, typename Frag, typename BRead>
+__device__ __forceinline__ void be_pipe_f(const BeArgsT<T>& A, int lane, Frag frag, BRead bread,
+                                          v4_t<T> (&acc)[JS]) {
   constexpr int NJ = NS * JS, P = kBePD < NJ ? kBePD : NJ;
-  const f32x4* fr = reinterpret_cast<const f32x4*>(A.frags);
-  f32x4 fa[P];
+  const v4_t<T>* fr = reinterpret_cast<const v4_t<T>*>(A.frags);
+  v4_t<T> fa[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) fa[j] = fr[frag(j / JS, j % JS) * 64 + lane];
-  float vn[4], b[4];
+  T vn[4], b[4];
   bread(0, vn);
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
@@ -153,11 +163,14 @@ __device__ __forceinline__ void be_pipe_f(const BeArgs& A, int lane, Frag frag, 
 // The stage of one element: launch position bid of a grid of Gd positions
 // over the context's elements (Gd = K); the kernels below call it for a
 // single context or for one slot of a batch.
-template <int N, bool F32>
-__device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_t bid) {
+template <int N, bool F32, typename T = float>
+__device__ __forceinline__ void stage_be_run(const BeArgsT<T>& A, int64_t Gd, int64_t bid) {
+  static_assert(F32 || sizeof(T) == 4, "the BF16x3 kernel works in FP32");
+  using V4 = v4_t<T>;
+  constexpr bool D64 = sizeof(T) == 8;   // accumulator rows as acc_row(D64, g, j)
   using O = EOrd<N>;
   using OF = EFOrd<N>;
-  using L = BeLds<N>;
+  using L = BeLds<N, T>;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, Nq = O::Nq;
   constexpr int RT = O::RT, KN = O::KN, KF = O::KF, KQ = O::KQ, QT = O::QT;
   static_assert(OF::RT == RT && OF::QT == QT && 16 * OF::KN <= L::NK && 16 * OF::KF <= L::FK &&
@@ -167,12 +180,12 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
   constexpr int QW = (QT + 3) / 4;   // quadrature tiles per wave (at most)
   constexpr int ML = (QW + 3) / 4;   // material loads per lane and field
   static_assert(NF4 <= kThreads && NK <= kThreads && FK <= kThreads, "one item per thread");
-  __shared__ __align__(16) float smem[L::BYTES / 4];
-  float* sq = smem;                  // [NK][17]: q, columns = fields
-  float* sr = smem + L::SQ;          // [NK][17]: r, columns = components
-  float* sd = smem + L::OFF_U;       // [3][Np][17]
-  float* sf = sd + L::SD;            // [FK][17]
-  float* sw = smem + L::OFF_U;       // [QK][17]  (over sd, sf)
+  __shared__ __align__(16) T smem[L::BYTES / sizeof(T)];
+  T* sq = smem;                  // [NK][17]: q, columns = fields
+  T* sr = smem + L::SQ;          // [NK][17]: r, columns = components
+  T* sd = smem + L::OFF_U;       // [3][Np][17]
+  T* sf = sd + L::SD;            // [FK][17]
+  T* sw = smem + L::OFF_U;       // [QK][17]  (over sd, sf)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -196,8 +209,8 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
   const int jf = ft ? tid : NF4 - 1;
   const int vM = A.fmask[jf];
   const unsigned nbi = unsigned(A.nbn[k * NF4 + jf]);
-  const f32x4 fg = reinterpret_cast<const f32x4*>(A.fgeo)[k * 4 + jf / Nfp];
-  float qv[16];
+  const V4 fg = reinterpret_cast<const V4*>(A.fgeo)[k * 4 + jf / Nfp];
+  T qv[16];
   {
     const int n = tid < NK ? tid : NK - 1;
     const unsigned nc = unsigned(n < Np ? n : Np - 1);
@@ -206,7 +219,7 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
   }
   // material: lane l holds quadrature point 16 t + l % 16 of the wave's
   // quadrature tile t = wave + 4 (4 m + l / 16), for m < ML
-  float mt[3][ML];
+  T mt[3][ML];
 #pragma unroll
   for (int m = 0; m < ML; ++m) {
     const int t = min(wave + 4 * (4 * m + g), QT - 1);
@@ -215,50 +228,50 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
     mt[1][m] = (A.lam + k * Nq)[p];
     mt[2][m] = (A.mu + k * Nq)[p];
   }
-  // residual of component e at the lane's output rows 16 t + 4 g + j (read
+  // residual of component e at the lane's output rows 16 t + acc_row(g, j) (read
   // from the state in right-hand-side mode, where it is not used)
   const int ec = e < 9 ? e : 8;
-  float rv[TW][4];
+  T rv[TW][4];
   {
-    const float* rb = (A.lsrk ? A.res : A.q_in) + ec * KNp + k * Np;
+    const T* rb = (A.lsrk ? A.res : A.q_in) + ec * KNp + k * Np;
 #pragma unroll
     for (int i = 0; i < TW; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) rv[i][j] = rb[min(16 * tn[i] + 4 * g + j, Np - 1)];
+      for (int j = 0; j < 4; ++j) rv[i][j] = rb[min(16 * tn[i] + acc_row(D64, g, j), Np - 1)];
   }
   __builtin_amdgcn_sched_barrier(0);
-  const float zpM = A.zp[k * Np + vM], zsM = A.zs[k * Np + vM];
-  const float zpP = A.zp[nbi], zsP = A.zs[nbi];
-  float qP[9];
+  const T zpM = A.zp[k * Np + vM], zsM = A.zs[k * Np + vM];
+  const T zpP = A.zp[nbi], zsP = A.zs[nbi];
+  T qP[9];
 #pragma unroll
   for (int f = 0; f < 9; ++f) qP[f] = (A.q_in + f * KNp)[nbi];
   if (tid < NK) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) sq[tid * kCS + c] = (c < 9 && tid < Np) ? qv[c] : 0.f;
+    for (int c = 0; c < 16; ++c) sq[tid * kCS + c] = (c < 9 && tid < Np) ? qv[c] : T(0);
   }
   __syncthreads();
 
   // 2: D_d q for the wave's node tiles (target i = 3 tile + d)
   {
-    f32x4 acc[3 * TW];
+    V4 acc[3 * TW];
 #pragma unroll
-    for (int i = 0; i < 3 * TW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 3 * TW; ++i) acc[i] = V4{T(0), T(0), T(0), T(0)};
     if constexpr (F32)
       be_pipe_f<OF::KN, 3 * TW>(
           A, lane,
           [&](int s, int i) { return OF::OFF_D + ((i % 3) * RT + tn[i / 3]) * OF::KN + s; },
-          [&](int s, float(&v)[4]) { be_bread4(sq, s, g, e, v); }, acc);
+          [&](int s, T(&v)[4]) { be_bread4(sq, s, g, e, v); }, acc);
     else
       be_pipe<KN, 3 * TW>(
           A, lane,
           [&](int s, int i) { return O::OFF_D + (((i % 3) * RT + tn[i / 3]) * KN + s) * 2; },
-          [&](int s, float(&v)[8]) { be_bread(sq, s, g, e, v); }, acc);
+          [&](int s, T(&v)[8]) { be_bread(sq, s, g, e, v); }, acc);
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
       const int t = wave + 4 * i;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int n = 16 * t + 4 * g + j;
+        const int n = 16 * t + acc_row(D64, g, j);
         if (t < RT && n < Np) {
 #pragma unroll
           for (int d = 0; d < 3; ++d) sd[(d * Np + n) * kCS + e] = acc[3 * i + d][j];
@@ -269,39 +282,40 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
 
   // 3: face fluxes, exact-Riemann upwind or central [WSG10], scaled by Fscale
   if (tid < FK) {
-    float fl[9];
+    T fl[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) fl[c] = 0.f;
+    for (int c = 0; c < 9; ++c) fl[c] = T(0);
     if (ft) {
-      float qM[9];
+      T qM[9];
 #pragma unroll
       for (int f = 0; f < 9; ++f) qM[f] = sq[vM * kCS + f];
-      const float nx = fg[0], ny = fg[1], nz = fg[2], fs = fg[3];
-      const float* P = qP;
-      const float jtx = (P[3] - qM[3]) * nx + (P[8] - qM[8]) * ny + (P[7] - qM[7]) * nz;
-      const float jty = (P[8] - qM[8]) * nx + (P[4] - qM[4]) * ny + (P[6] - qM[6]) * nz;
-      const float jtz = (P[7] - qM[7]) * nx + (P[6] - qM[6]) * ny + (P[5] - qM[5]) * nz;
-      const float jvx = P[0] - qM[0], jvy = P[1] - qM[1], jvz = P[2] - qM[2];
-      float dvx, dvy, dvz, dtx, dty, dtz;
+      const T nx = fg[0], ny = fg[1], nz = fg[2], fs = fg[3];
+      const T* P = qP;
+      const T jtx = (P[3] - qM[3]) * nx + (P[8] - qM[8]) * ny + (P[7] - qM[7]) * nz;
+      const T jty = (P[8] - qM[8]) * nx + (P[4] - qM[4]) * ny + (P[6] - qM[6]) * nz;
+      const T jtz = (P[7] - qM[7]) * nx + (P[6] - qM[6]) * ny + (P[5] - qM[5]) * nz;
+      const T jvx = P[0] - qM[0], jvy = P[1] - qM[1], jvz = P[2] - qM[2];
+      T dvx, dvy, dvz, dtx, dty, dtz;
       if (A.upwind) {
-        const float jvn = jvx * nx + jvy * ny + jvz * nz;
-        const float jtn = jtx * nx + jty * ny + jtz * nz;
-        // hardware reciprocals (1 ulp): the impedance sums are positive
-        const float dvn = (zpP * jvn + jtn) * __builtin_amdgcn_rcpf(zpM + zpP);
-        const float ivs = __builtin_amdgcn_rcpf(zsM + zsP);
-        const float dvtx = (zsP * (jvx - jvn * nx) + (jtx - jtn * nx)) * ivs;
-        const float dvty = (zsP * (jvy - jvn * ny) + (jty - jtn * ny)) * ivs;
-        const float dvtz = (zsP * (jvz - jvn * nz) + (jtz - jtn * nz)) * ivs;
+        const T jvn = jvx * nx + jvy * ny + jvz * nz;
+        const T jtn = jtx * nx + jty * ny + jtz * nz;
+        // reciprocals (FP32: the hardware one, 1 ulp; FP64: a division): the
+        // impedance sums are positive
+        const T dvn = (zpP * jvn + jtn) * rcp_t(zpM + zpP);
+        const T ivs = rcp_t(zsM + zsP);
+        const T dvtx = (zsP * (jvx - jvn * nx) + (jtx - jtn * nx)) * ivs;
+        const T dvty = (zsP * (jvy - jvn * ny) + (jty - jtn * ny)) * ivs;
+        const T dvtz = (zsP * (jvz - jvn * nz) + (jtz - jtn * nz)) * ivs;
         dvx = dvn * nx + dvtx;
         dvy = dvn * ny + dvty;
         dvz = dvn * nz + dvtz;
-        const float dtn = zpM * dvn;
+        const T dtn = zpM * dvn;
         dtx = dtn * nx + zsM * dvtx;
         dty = dtn * ny + zsM * dvty;
         dtz = dtn * nz + zsM * dvtz;
       } else {
-        dvx = 0.5f * jvx; dvy = 0.5f * jvy; dvz = 0.5f * jvz;
-        dtx = 0.5f * jtx; dty = 0.5f * jty; dtz = 0.5f * jtz;
+        dvx = T(0.5) * jvx; dvy = T(0.5) * jvy; dvz = T(0.5) * jvz;
+        dtx = T(0.5) * jtx; dty = T(0.5) * jty; dtz = T(0.5) * jtz;
       }
       fl[0] = fs * dtx;
       fl[1] = fs * dty;
@@ -309,62 +323,62 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
       fl[3] = fs * dvx * nx;
       fl[4] = fs * dvy * ny;
       fl[5] = fs * dvz * nz;
-      fl[6] = fs * 0.5f * (dvy * nz + dvz * ny);
-      fl[7] = fs * 0.5f * (dvx * nz + dvz * nx);
-      fl[8] = fs * 0.5f * (dvx * ny + dvy * nx);
+      fl[6] = fs * T(0.5) * (dvy * nz + dvz * ny);
+      fl[7] = fs * T(0.5) * (dvx * nz + dvz * nx);
+      fl[8] = fs * T(0.5) * (dvx * ny + dvy * nx);
     }
 #pragma unroll
-    for (int c = 0; c < 16; ++c) sf[tid * kCS + c] = c < 9 ? fl[c] : 0.f;
+    for (int c = 0; c < 16; ++c) sf[tid * kCS + c] = c < 9 ? fl[c] : T(0);
   }
   __syncthreads();
 
   // 4: chain rule, r_c(n) = sum_d sum_j G_dj w(c, j) (D_d q_{f(c,j)})(n),
   // one node row per thread (rows past Np and columns past 8 are zero)
   if (tid < NK) {
-    float G[9];
+    T G[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) G[i] = A.geo[k * 9 + i];
     const int n = tid < Np ? tid : Np - 1;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      float r = 0.f;
+      T r = T(0);
       if (c < 9) {
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
           for (int j = 0; j < 3; ++j)
-            if (comp_weight(c, j) != 0.f)
+            if (comp_weight(c, j) != T(0))
               r += G[d * 3 + j] * comp_weight(c, j) * sd[(d * Np + n) * kCS + comp_field(c, j)];
       }
-      sr[tid * kCS + c] = tid < Np ? r : 0.f;
+      sr[tid * kCS + c] = tid < Np ? r : T(0);
     }
   }
   __syncthreads();
 
   // 5: r += LIFT f for the wave's node tiles, in place
   {
-    f32x4 acc[TW];
+    V4 acc[TW];
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
-      acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      acc[i] = V4{T(0), T(0), T(0), T(0)};
       if (wave + 4 * i < RT) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = sr[(16 * tn[i] + 4 * g + j) * kCS + e];
+        for (int j = 0; j < 4; ++j) acc[i][j] = sr[(16 * tn[i] + acc_row(D64, g, j)) * kCS + e];
       }
     }
     if constexpr (F32)
       be_pipe_f<OF::KF, TW>(
           A, lane, [&](int s, int i) { return OF::OFF_L + tn[i] * OF::KF + s; },
-          [&](int s, float(&v)[4]) { be_bread4(sf, s, g, e, v); }, acc);
+          [&](int s, T(&v)[4]) { be_bread4(sf, s, g, e, v); }, acc);
     else
       be_pipe<KF, TW>(
           A, lane, [&](int s, int i) { return O::OFF_L + (tn[i] * KF + s) * 2; },
-          [&](int s, float(&v)[8]) { be_bread(sf, s, g, e, v); }, acc);
+          [&](int s, T(&v)[8]) { be_bread(sf, s, g, e, v); }, acc);
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
       if (wave + 4 * i < RT) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) sr[(16 * tn[i] + 4 * g + j) * kCS + e] = acc[i][j];
+        for (int j = 0; j < 4; ++j) sr[(16 * tn[i] + acc_row(D64, g, j)) * kCS + e] = acc[i][j];
       }
     }
   }
@@ -375,38 +389,38 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
   // lam tr + 2 mu, shear stresses 2 mu
   {
     // the weight-adjusted material operator on tile u's V_q r (w) into sw
-    auto weigh = [&](int u, const f32x4& w) {
+    auto weigh = [&](int u, const V4& w) {
       const int t = wave + 4 * u;
       if (t < QT) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int p = 16 * t + 4 * g + j;
-          const int src = ((u & 3) << 4) + 4 * g + j;   // holder of point p
-          const float ir = __shfl(mt[0][u >> 2], src), la = __shfl(mt[1][u >> 2], src);
-          const float m2 = 2.f * __shfl(mt[2][u >> 2], src);
-          const float tr = __shfl(w[j], 16 * g + 3) + __shfl(w[j], 16 * g + 4) + __shfl(w[j], 16 * g + 5);
-          const float v = e < 3 ? ir * w[j] : e < 6 ? la * tr + m2 * w[j] : e < 9 ? m2 * w[j] : 0.f;
-          sw[p * kCS + e] = p < Nq ? v : 0.f;
+          const int p = 16 * t + acc_row(D64, g, j);
+          const int src = ((u & 3) << 4) + acc_row(D64, g, j);   // holder of point p
+          const T ir = __shfl(mt[0][u >> 2], src), la = __shfl(mt[1][u >> 2], src);
+          const T m2 = T(2) * __shfl(mt[2][u >> 2], src);
+          const T tr = __shfl(w[j], 16 * g + 3) + __shfl(w[j], 16 * g + 4) + __shfl(w[j], 16 * g + 5);
+          const T v = e < 3 ? ir * w[j] : e < 6 ? la * tr + m2 * w[j] : e < 9 ? m2 * w[j] : T(0);
+          sw[p * kCS + e] = p < Nq ? v : T(0);
         }
       }
     };
     if constexpr (F32) {
       constexpr int KG = OF::KN;
-      float b[KG][4];
+      T b[KG][4];
 #pragma unroll
       for (int s = 0; s < KG; ++s) be_bread4(sr, s, g, e, b[s]);
       constexpr int NJ = QW * KG, P = kBePD < NJ ? kBePD : NJ;
-      const f32x4* fr = reinterpret_cast<const f32x4*>(A.frags);
+      const V4* fr = reinterpret_cast<const V4*>(A.frags);
       auto frag = [&](int j) {
         const int t = min(wave + 4 * (j / KG), QT - 1);
         return OF::OFF_V + t * KG + j % KG;
       };
-      f32x4 fa[P];
+      V4 fa[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) fa[j] = fr[frag(j) * 64 + lane];
 #pragma unroll
       for (int u = 0; u < QW; ++u) {
-        f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
+        V4 w = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
           const int j = u * KG + s;
@@ -421,7 +435,7 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
       bf16x8 bh[KN], bl[KN];
 #pragma unroll
       for (int s = 0; s < KN; ++s) {
-        float v[8];
+        T v[8];
         be_bread(sr, s, g, e, v);
         split8(v, bh[s], bl[s]);
       }
@@ -435,7 +449,7 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
       for (int j = 0; j < P; ++j) be_fload(A, frag(j), lane, fh[j], fl[j]);
 #pragma unroll
       for (int u = 0; u < QW; ++u) {
-        f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
+        V4 w = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int s = 0; s < KN; ++s) {
           const int j = u * KN + s;
@@ -452,27 +466,27 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
   // 7: P_q for the wave's node tiles, then the store or stage update of
   // component e at nodes 16 t + 4 g + j
   {
-    f32x4 acc[TW];
+    V4 acc[TW];
 #pragma unroll
-    for (int i = 0; i < TW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < TW; ++i) acc[i] = V4{T(0), T(0), T(0), T(0)};
     if constexpr (F32)
       be_pipe_f<OF::KQ, TW>(
           A, lane, [&](int s, int i) { return OF::OFF_P + tn[i] * OF::KQ + s; },
-          [&](int s, float(&v)[4]) { be_bread4(sw, s, g, e, v); }, acc);
+          [&](int s, T(&v)[4]) { be_bread4(sw, s, g, e, v); }, acc);
     else
       be_pipe<KQ, TW>(
           A, lane, [&](int s, int i) { return O::OFF_P + (tn[i] * KQ + s) * 2; },
-          [&](int s, float(&v)[8]) { be_bread(sw, s, g, e, v); }, acc);
+          [&](int s, T(&v)[8]) { be_bread(sw, s, g, e, v); }, acc);
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
       const int t = wave + 4 * i;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int n = 16 * t + 4 * g + j;
+        const int n = 16 * t + acc_row(D64, g, j);
         if (t < RT && e < 9 && n < Np) {
           const int64_t gi = ec * KNp + k * Np + n;
           if (A.lsrk) {
-            const float rr = A.a * rv[i][j] + A.dt * acc[i][j];
+            const T rr = A.a * rv[i][j] + A.dt * acc[i][j];
             A.res[gi] = rr;
             A.q_out[gi] = sq[n * kCS + ec] + A.b * rr;
           } else {
@@ -487,6 +501,14 @@ __device__ __forceinline__ void stage_be_run(const BeArgs& A, int64_t Gd, int64_
 template <int N, bool F32>
 __global__ __launch_bounds__(kThreads, 2) void stage_be(BeArgs A) {
   stage_be_run<N, F32>(A, gridDim.x, blockIdx.x);
+}
+
+// FP64 on the matrix cores (v_mfma_f64_16x16x4f64, FP64 fragments in the
+// layout of EFOrd): the kernel above in double precision; its LDS (twice
+// that of FP32) leaves one workgroup per CU at orders 6 and 7
+template <int N>
+__global__ __launch_bounds__(kThreads, 1) void stage_be_d(BeArgsT<double> A) {
+  stage_be_run<N, true, double>(A, gridDim.x, blockIdx.x);
 }
 
 }  // namespace dgb

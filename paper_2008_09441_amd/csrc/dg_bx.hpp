@@ -160,9 +160,10 @@ struct BLds {
   static constexpr int OFF_U = (SQ + SG + SZ + 3) & ~3;  // 16-byte aligned union
   static constexpr int USED = (OFF_U + SU) * int(sizeof(T));
   // Padded so that the workgroups one CU can hold (160 KiB of LDS) never use
-  // more than 128 KiB together (at most 3 per CU at >40 KiB each, or 2 at
-  // >53.3 KiB each).
-  static constexpr int FLOOR = USED <= 43690 ? 40976 : (USED <= 65536 ? 54630 : 0);
+  // more than 128 KiB together (at most 3 per CU at >40 KiB each, 2 at
+  // >53.3 KiB each, or 1 at >80 KiB each).
+  static constexpr int FLOOR =
+      USED <= 43690 ? 40976 : USED <= 65536 ? 54630 : USED <= 81920 ? 81936 : 0;
   static constexpr int BYTES = USED > FLOOR ? USED : FLOOR;
 };
 

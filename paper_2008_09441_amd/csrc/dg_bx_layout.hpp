@@ -197,7 +197,8 @@ struct AOrd {
   static constexpr int USED = (LY + LU) * 4;
   // padded as the stage kernels are: the workgroups one CU holds never use
   // more than 128 KiB of LDS together
-  static constexpr int FLOOR = USED <= 43690 ? 40976 : (USED <= 65536 ? 54630 : 0);
+  static constexpr int FLOOR =
+      USED <= 43690 ? 40976 : USED <= 65536 ? 54630 : USED <= 81920 ? 81936 : 0;
   static constexpr int BYTES = USED > FLOOR ? USED : FLOOR;
 };
 

@@ -192,17 +192,18 @@ std::vector<uint16_t> mfma_fragments(const RefElement& re) {
   }
 }
 
-// FP32 fragments of the orders 5-7 stage in the layout of EFOrd
-template <int N>
-std::vector<float> build_frags_ef(const RefElement& re) {
+// FP32 (V = float) or FP64 (V = double) fragments of the orders 5-7 stage in
+// the layout of EFOrd
+template <int N, typename V>
+std::vector<V> build_frags_ef(const RefElement& re) {
   using O = dgb::EFOrd<N>;
-  std::vector<float> out(size_t(O::NFRAG) * 64 * 4, 0.f);
+  std::vector<V> out(size_t(O::NFRAG) * 64 * 4, V(0));
   auto put = [&](int frag, const std::vector<double>& M, int rows, int cols, int t, int s) {
     for (int l = 0; l < 64; ++l)
       for (int j = 0; j < 4; ++j) {
         const int r = 16 * t + l % 16, k = 16 * s + 4 * j + l / 16;
         out[(size_t(frag) * 64 + l) * 4 + j] =
-            (r < rows && k < cols) ? float(M[size_t(r) * cols + k]) : 0.f;
+            (r < rows && k < cols) ? V(M[size_t(r) * cols + k]) : V(0);
       }
   };
   const int Np = O::Np, NF4 = O::NF4, Nq = O::Nq;
@@ -226,9 +227,9 @@ std::vector<float> mfma_fragments_f32(const RefElement& re) {
     case 2: return build_frags_f<2, float>(re);
     case 3: return build_frags_f<3, float>(re);
     case 4: return build_frags_f<4, float>(re);
-    case 5: return build_frags_ef<5>(re);
-    case 6: return build_frags_ef<6>(re);
-    default: return build_frags_ef<7>(re);
+    case 5: return build_frags_ef<5, float>(re);
+    case 6: return build_frags_ef<6, float>(re);
+    default: return build_frags_ef<7, float>(re);
   }
 }
 
@@ -238,7 +239,9 @@ std::vector<double> mfma_fragments_f64(const RefElement& re) {
     case 2: return build_frags_f<2, double>(re);
     case 3: return build_frags_f<3, double>(re);
     case 4: return build_frags_f<4, double>(re);
-    default: return {};
+    case 5: return build_frags_ef<5, double>(re);
+    case 6: return build_frags_ef<6, double>(re);
+    default: return build_frags_ef<7, double>(re);
   }
 }
 

@@ -23,15 +23,16 @@ std::vector<uint16_t> mfma_fragments(const RefElement& re);
 // ([NFRAG][64 lanes][4] floats)
 std::vector<float> mfma_fragments_f32(const RefElement& re);
 
-// FP64 operator fragments of the FP64 matrix-core stage at orders 1-4 (the
-// layout of FOrd, [NF4S][4] doubles); empty at higher orders
+// FP64 operator fragments of the FP64 matrix-core stage: orders 1-4 in the
+// layout of FOrd ([NF4S][4] doubles), orders 5-7 in that of EFOrd
+// ([NFRAG][64 lanes][4] doubles)
 std::vector<double> mfma_fragments_f64(const RefElement& re);
 
 // FP32 operator fragments of the tiled adjoint kernel of orders 1-4 (the
 // layout of dgt::AOrd, [NG][64 lanes][4] floats); empty at higher orders
 std::vector<float> adj_fragments_f32(const RefElement& re);
 
-// Transposed operator pack (generic FP64 kernel, adjoint kernels): DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],
+// Transposed operator pack (the generic adjoint kernels): DrT | DsT | DtT [Np][NpP], LIFTT [4 Nfp][NpP],
 // VqT [Np][QP], PqT [QP][NpP] (transposed, zero padded; NpP = 4 ceil(Np/4),
 // QP = 32 ceil(Nq/32)).
 std::vector<double> col_operators(const RefElement& re);

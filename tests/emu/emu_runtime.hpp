@@ -17,7 +17,7 @@ thread_local emu_dim3 threadIdx, blockIdx;
 emu_dim3 gridDim, blockDim;
 static std::unique_ptr<std::barrier<>> g_bar;
 static std::unique_ptr<std::barrier<>> g_wbar[4];
-struct Slot { emu_bf16x8 a[64], b[64]; float x[64], fa[64], fb[64]; double da[64], db[64]; };
+struct Slot { emu_bf16x8 a[64], b[64]; float x[64], fa[64], fb[64]; double da[64], db[64], xd[64]; };
 static Slot g_slot[4];
 
 void __syncthreads() { g_bar->arrive_and_wait(); }
@@ -49,6 +49,15 @@ float emu_shfl(float v, int src, int) {
   g_slot[w].x[lane] = v;
   g_wbar[w]->arrive_and_wait();
   const float r = g_slot[w].x[src & 63];
+  g_wbar[w]->arrive_and_wait();
+  return r;
+}
+
+double emu_shfl_d(double v, int src, int) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  g_slot[w].xd[lane] = v;
+  g_wbar[w]->arrive_and_wait();
+  const double r = g_slot[w].xd[src & 63];
   g_wbar[w]->arrive_and_wait();
   return r;
 }

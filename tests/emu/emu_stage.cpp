@@ -1,6 +1,6 @@
 // Runs the stage kernels on the CPU, for tests (the matrix-core kernels
-// dgb::stage_bx<N> in BF16x3 and FP32, dgb::stage_bx_d<N> in FP64, and
-// dgb::stage_be<N> in BF16x3 and FP32):
+// dgb::stage_bx<N> in BF16x3 and FP32, dgb::stage_bx_d<N> in FP64,
+// dgb::stage_be<N> in BF16x3 and FP32, and dgb::stage_be_d<N> in FP64):
 // each workgroup is 256 host threads with real barriers; the 16x16x32 bf16
 // MFMA is emulated with its hardware lane layout (A: row lane%16, k 8(lane/16)+j;
 // B: column lane%16, k 8(lane/16)+j; D: column lane%16, row 4(lane/16)+j).
@@ -14,7 +14,6 @@
 #include <cstring>
 #include <cstdlib>
 #include <cmath>
-#include "dg_kernels.hpp"
 #include "dg_be.hpp"
 #include "dg_bx.hpp"
 #include "dg_host.hpp"
@@ -44,8 +43,32 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
   }
   for (int64_t i = 0; i < K * Np; ++i) { zp[i] = rho_n[i] * cp_n[i]; zs[i] = rho_n[i] * cs_n[i]; }
   if (grid < 1 || grid > 3) return 3;
+  if (grid == 3 && N >= 5) {   // FP64 matrix-core kernel, orders 5-7
+    dgb::BeArgsT<double> E{};
+    std::vector<double> qd(q, q + 9 * K * Np);
+    E.q_in = dupT<double>(qd);
+    E.rhs_out = alloc<double>(9 * K * Np);
+    E.q_out = lsrk ? alloc<double>(9 * K * Np) : nullptr;
+    E.res = nullptr;
+    if (lsrk) { E.res = alloc<double>(9 * K * Np); for (int64_t i = 0; i < 9 * K * Np; ++i) E.res[i] = 0.0; }
+    E.geo = dupT<double>(m.geo); E.fgeo = dupT<double>(m.fgeo);
+    E.nbn = dup(dgh::neighbour_nodes(re, m));
+    std::vector<int32_t> fmd(re.Fmask.begin(), re.Fmask.end());
+    E.fmask = dup(fmd);
+    E.irho = dupT<double>(a); E.lam = dupT<double>(b); E.mu = dupT<double>(d);
+    E.zp = dupT<double>(zp); E.zs = dupT<double>(zs);
+    E.frags = reinterpret_cast<const dgb::u32x4*>(dup(dgh::mfma_fragments_f64(re)));
+    E.K = K; E.a = 0.0; E.b = 1.0; E.dt = 1.0; E.lsrk = lsrk; E.upwind = upwind;
+    switch (N) {
+      case 5: run_grid(int(K), [=]() { dgb::stage_be_d<5>(E); }); break;
+      case 6: run_grid(int(K), [=]() { dgb::stage_be_d<6>(E); }); break;
+      default: run_grid(int(K), [=]() { dgb::stage_be_d<7>(E); }); break;
+    }
+    for (int64_t i = 0; i < 9 * K * Np; ++i)
+      out[i] = lsrk ? E.q_out[i] - E.q_in[i] : E.rhs_out[i];
+    return 0;
+  }
   if (grid == 3) {   // FP64 matrix-core tiled kernel, orders 1-4
-    if (N > 4) return 3;
     dgb::BxArgsT<double> D{};
     std::vector<double> qd(q, q + 9 * K * Np);
     D.q_in = dupT<double>(qd);
@@ -146,7 +169,7 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
 }
 
 // input file: int32 N, flux_upwind, kernel (1: BF16x3 matrix-core kernel, 2:
-// FP32 matrix-core kernel, 3: FP64 matrix-core kernel), lsrk; int64 K; then float64
+// FP32 matrix-core kernel, 3: FP64 matrix-core kernel, every order), lsrk; int64 K; then float64
 // vxyz[K*12], period[3], rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n
 // [K*Np each]; then float32 q[9*K*Np]
 int main(int argc, char** argv) {

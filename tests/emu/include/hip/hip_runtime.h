@@ -43,4 +43,6 @@ inline long min(long a, long b) { return a < b ? a : b; }
 inline unsigned min(unsigned a, unsigned b) { return a < b ? a : b; }
 #define __builtin_amdgcn_rcpf(x) (1.f / (x))
 float emu_shfl(float v, int src, int width);
+double emu_shfl_d(double v, int src, int width);
 inline float __shfl(float v, int src, int width = 64) { return emu_shfl(v, src, width); }
+inline double __shfl(double v, int src, int width = 64) { return emu_shfl_d(v, src, width); }

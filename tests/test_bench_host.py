@@ -23,7 +23,7 @@ def test_kernel_names():
     assert bench.stage_kernel_name("fp32", 3) == "stage_bx<3,f32>"
     assert bench.stage_kernel_name("fp32", 6) == "stage_be<6,f32>"
     assert bench.stage_kernel_name("fp64", 4) == "stage_bx_d<4>"
-    assert bench.stage_kernel_name("fp64", 5) == "stage_generic<double,5>"
+    assert bench.stage_kernel_name("fp64", 5) == "stage_be_d<5>"
 
 
 def test_algorithmic_bytes_per_element_stage():

@@ -53,8 +53,8 @@ def test_rhs_fp32_matches_oracle(n, N):
 @pytest.mark.parametrize("precision,bound", [("fp64", 1e-12), ("fp32", 2e-5)])
 def test_odd_element_count_fp64_fp32(N, precision, bound):
     """The centroid-split Kuhn cube (K = 51, non-Kuhn element shapes) on the
-    FP64 and FP32 matrix-core kernels (orders 1-4) and on
-    the generic kernel (orders 5-7): right-hand side and one LSRK step
+    FP64 and FP32 matrix-core kernels (the tiled kernels at orders 1-4, one
+    element per workgroup at 5-7): right-hand side and one LSRK step
     against the oracle on the same mesh."""
     print(f"case odd K {precision} N={N}", flush=True)
     vx = synth.split_tet_vertices(synth.kuhn_cube_vertices(2))

@@ -1,6 +1,6 @@
 """CPU check of the stage kernel sources: the unchanged kernels (the BF16x3
 and FP32 matrix-core kernels of orders 1-4 and 5-7, the FP64 matrix-core
-kernel of orders 1-4) run on host threads
+kernels of orders 1-4 and 5-7) run on host threads
 (tests/emu) built with AddressSanitizer, so any out-of-bounds index fails the
 test, and their results are compared with the FP64 oracle (BF16x3: 1e-4,
 FP32: 2e-5, FP64: 1e-12 per-field relative L2)."""
@@ -132,5 +132,18 @@ def test_fp64_matrix_kernel_source_in_bounds_and_accurate(emu_exe, tmp_path, n, 
 @pytest.mark.parametrize("lsrk,split", [(1, False), (0, True), (1, True)])
 def test_fp64_matrix_kernel_lsrk_and_odd_count(emu_exe, tmp_path, lsrk, split):
     err = _run(emu_exe, tmp_path, 2, 4, "upwind", grid=3, lsrk=lsrk, split=split)
+    print("per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("n,N,flux,lsrk,split", [(1, 5, "upwind", 0, False),
+                                                 (1, 6, "central", 1, False),
+                                                 (1, 7, "upwind", 0, False),
+                                                 (1, 6, "upwind", 0, True)])
+def test_fp64_matrix_kernel_orders_5_to_7(emu_exe, tmp_path, n, N, flux, lsrk, split):
+    """The FP64 matrix-core kernel of orders 5-7 (one element per workgroup,
+    v_mfma_f64_16x16x4f64 with its measured accumulator row order), at the
+    FP64 bound; the last case on the odd-count mesh."""
+    err = _run(emu_exe, tmp_path, n, N, flux, grid=3, lsrk=lsrk, split=split)
     print("per-field rel L2:", np.array2string(err, precision=2))
     assert err.max() <= 1e-12
