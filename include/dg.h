@@ -279,7 +279,8 @@ dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const doubl
  * the receiver velocities after every step to trace (host
  * [nsteps][nrec][3], working precision).  Leaves the context at the end of
  * the run.  Needs receivers (DG_ESTATE).  Library-owned device memory:
- * ceil(nsteps/every) + 5 every + 6 states plus face-node work arrays
+ * ceil(nsteps/every) + 5 every + 6 states (FP32 at orders 1-4: 10 every + 6,
+ * the replay also keeping R y of every stage input) plus face-node work arrays
  * ([K][4 Nfp][9], two of them on the generic adjoint kernels) and the FP64
  * gradient [3][K][Nq] (upwind: also [K][4 Nfp][4] impedance terms, [K][4
  * Nfp][8] face jumps on the tiled FP32 kernels of orders 1-4, and the FP64

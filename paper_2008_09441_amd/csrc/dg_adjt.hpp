@@ -1,10 +1,13 @@
 // Tiled discrete adjoint of the FP32 stage at orders 1-4 on the matrix
 // cores (v_mfma_f32_16x16x4_f32).  One reverse stage is two kernels:
 //
-// adj_tile<N>: one workgroup per 16 consecutive elements (the MFMA columns).
-//   With y the stage input and l = a lres + b ly the adjoint of the stage's
-//   residual (written back to lres), it computes per element
-//     r  = R y + raw sources                 (volume terms, fluxes, LIFT),
+// adj_tile<N, RIN>: one workgroup per 16 consecutive elements (the MFMA
+//   columns).  With y the stage input and l = a lres + b ly the adjoint of
+//   the stage's residual (written back to lres), it computes per element
+//     r  = R y + raw sources                 (volume terms, fluxes, LIFT;
+//                                             with RIN, R y is an input: the
+//                                             replay's forward stage stores
+//                                             it, dgb::stage_bx_r),
 //     w  = V_q r,   p = P_q^T l              at the quadrature points,
 //     grad += s d/dm <l, W(m) r>             (d/d(1/rho) = sum_v p w,
 //                                             d/d lam = tr p tr w,
@@ -18,8 +21,9 @@
 //   and the gradient terms then stay inside a wave except the stress sum of
 //   d/d mu, whose two partial sums meet in LDS.  Every product's B operand
 //   comes from LDS (y, fluxes, mu) or straight from the previous product's
-//   accumulators (the K orders of AOrd).  All waves compute the face fluxes;
-//   wave 3 also adds the stress term of the gradient.
+//   accumulators (the K orders of AOrd).  All waves compute the face fluxes
+//   (with RIN only the face jumps); wave 3 also adds the stress term of the
+//   gradient.
 //
 //   For the upwind flux it also keeps the velocity and traction jumps of
 //   every face node (the state the impedance gradient needs).
@@ -44,6 +48,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 struct TileArgs {
   const float* y;        // stage input [9][K][Np]
+  const float* r;        // adj_tile<N, true>: its raw right-hand side R y [9][K][Np]
   float* lres;           // [9][K][Np]: in the residual adjoint before this stage, out l
   const float* ly;       // [9][K][Np]
   float* nu;             // out: volume transpose of mu [9][K][Np]
@@ -99,7 +104,7 @@ __device__ inline double ricker(const double* par, int i, double t) {
 }
 
 // Waves 0-2: everything from R y to nu and g for components 3W .. 3W + 2.
-template <int N, int W>
+template <int N, int W, bool RIN>
 __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float* sy,
                                            const float* sf, double* sg, const float (&G)[9],
                                            const float (&lv)[3][AOrd<N>::RT][4]) {
@@ -121,6 +126,19 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (RIN) {
+    // R y given (stored by the forward stage that produced this stage's
+    // output), at the chained rows
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = 16 * t + 4 * g + j;
+          r[t][c][j] = n < Np ? A.r[(C0 + c) * KNp + kc * Np + (n < Np ? n : Np - 1)] : 0.f;
+        }
+  } else {
   {
     // fragments two steps ahead
     f4 fa[3][RT];
@@ -181,6 +199,7 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
       }
       __builtin_amdgcn_sched_barrier(0);
     }
+  }
   }
   // raw point sources (velocity rows) of the elements in this tile
   int64_t sel[8];
@@ -447,7 +466,7 @@ __device__ __forceinline__ void load_l(const TileArgs& A, int64_t k0, int c0,
       }
 }
 
-template <int N>
+template <int N, bool RIN>
 __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
   using O = AOrd<N>;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF4 = O::NF4, Nq = O::Nq, QT = O::QT, CS = O::CS;
@@ -467,45 +486,6 @@ __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
   const int64_t tile = xcd * per + (xcd < rem8 ? xcd : rem8) + (bid >> 3);
   const int64_t k0 = 16 * tile;
 
-  // the tile's y into LDS (rows past Np and elements past K are zero): all
-  // of a thread's loads are issued before the first store
-  {
-    constexpr int NY = (9 * 16 * LN + kThreads - 1) / kThreads;
-    float yv[NY];
-#pragma unroll
-    for (int r = 0; r < NY; ++r) {
-      const int i = tid + kThreads * r;
-      const int c = i / (16 * LN), rem = i - c * 16 * LN, e = rem / LN, m = rem - e * LN;
-      const int64_t k = k0 + e;
-      const bool live = i < 9 * 16 * LN && m < Np && k < K;
-      yv[r] = live ? A.y[c * KNp + k * Np + m] : 0.f;
-    }
-#pragma unroll
-    for (int r = 0; r < NY; ++r) {
-      const int i = tid + kThreads * r;
-      const int c = i / (16 * LN), rem = i - c * 16 * LN, e = rem / LN, m = rem - e * LN;
-      if (i < 9 * 16 * LN) sy[(c * LN + m) * CS + e] = yv[r];
-    }
-  }
-  // face-node tasks (element e, face node jf): the neighbour's state and
-  // impedances, then (after the barrier) the flux from the own side in LDS
-  float qP[NT][9], zpP[NT], zsP[NT];
-  int vMt[NT];
-  f4 fg[NT];
-#pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const int task = tid + kThreads * i;
-    const int tk = task < 16 * NF4 ? task : 16 * NF4 - 1;
-    const int e = tk / NF4, jf = tk - e * NF4;
-    const int64_t k = k0 + e < K ? k0 + e : K - 1;
-    const int64_t nb = A.nbn[k * NF4 + jf];
-    vMt[i] = A.fmask[jf];
-    fg[i] = reinterpret_cast<const f4*>(A.fgeo)[k * 4 + jf / Nfp];
-    zpP[i] = A.zp[nb];
-    zsP[i] = A.zs[nb];
-#pragma unroll
-    for (int f = 0; f < 9; ++f) qP[i][f] = A.y[f * KNp + nb];
-  }
   float G[9];
   {
     const int64_t k = k0 + (tid & 15) < K ? k0 + (tid & 15) : K - 1;
@@ -515,40 +495,115 @@ __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
   // the group waves' l (loaded at the start of their phases: issued here,
   // beside the neighbour gathers, it cost registers that then spilled)
   float lv[3][O::RT][4];
-  __syncthreads();
+  if constexpr (RIN) {
+    // R y is given: only the upwind flux's face-node jumps are needed here,
+    // from the own and the neighbour's state gathered straight from HBM
+    if (A.upwind) {
+      float qM[NT][9], qP[NT][9];
+      f4 fg[NT];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const int task = tid + kThreads * i;
-    if (task >= 16 * NF4) break;
-    const int e = task / NF4, jf = task - e * NF4;
-    const int64_t k = k0 + e < K ? k0 + e : K - 1;
-    const int vM = vMt[i];
-    float qM[9], fl[9];
+      for (int i = 0; i < NT; ++i) {
+        const int task = tid + kThreads * i;
+        const int tk = task < 16 * NF4 ? task : 16 * NF4 - 1;
+        const int e = tk / NF4, jf = tk - e * NF4;
+        const int64_t k = k0 + e < K ? k0 + e : K - 1;
+        const int64_t nb = A.nbn[k * NF4 + jf];
+        const int64_t own = k * Np + A.fmask[jf];
+        fg[i] = reinterpret_cast<const f4*>(A.fgeo)[k * 4 + jf / Nfp];
 #pragma unroll
-    for (int f = 0; f < 9; ++f) qM[f] = sy[(f * LN + vM) * CS + e];
-    dga::flux<float>(qM, qP[i], fg[i][0], fg[i][1], fg[i][2], fg[i][3], A.zp[k * Np + vM],
-                     A.zs[k * Np + vM], zpP[i], zsP[i], A.upwind, fl);
+        for (int f = 0; f < 9; ++f) {
+          qM[i][f] = A.y[f * KNp + own];
+          qP[i][f] = A.y[f * KNp + nb];
+        }
+      }
 #pragma unroll
-    for (int c = 0; c < 9; ++c) sf[(c * LFN + jf) * CS + e] = fl[c];
-    if (A.upwind && k0 + e < K) {
-      float jm[6];
-      dga::face_jumps<float>(qM, qP[i], fg[i][0], fg[i][1], fg[i][2], jm);
-      f4* jo = reinterpret_cast<f4*>(A.jmp + (k * NF4 + jf) * 8);
-      jo[0] = f4{jm[0], jm[1], jm[2], jm[3]};
-      jo[1] = f4{jm[4], jm[5], 0.f, 0.f};
+      for (int i = 0; i < NT; ++i) {
+        const int task = tid + kThreads * i;
+        const int e = task / NF4, jf = task - e * NF4;
+        if (task < 16 * NF4 && k0 + e < K) {
+          float jm[6];
+          dga::face_jumps<float>(qM[i], qP[i], fg[i][0], fg[i][1], fg[i][2], jm);
+          f4* jo = reinterpret_cast<f4*>(A.jmp + ((k0 + e) * NF4 + jf) * 8);
+          jo[0] = f4{jm[0], jm[1], jm[2], jm[3]};
+          jo[1] = f4{jm[4], jm[5], 0.f, 0.f};
+        }
+      }
     }
+  } else {
+    // the tile's y into LDS (rows past Np and elements past K are zero): all
+    // of a thread's loads are issued before the first store
+    {
+      constexpr int NY = (9 * 16 * LN + kThreads - 1) / kThreads;
+      float yv[NY];
+  #pragma unroll
+      for (int r = 0; r < NY; ++r) {
+        const int i = tid + kThreads * r;
+        const int c = i / (16 * LN), rem = i - c * 16 * LN, e = rem / LN, m = rem - e * LN;
+        const int64_t k = k0 + e;
+        const bool live = i < 9 * 16 * LN && m < Np && k < K;
+        yv[r] = live ? A.y[c * KNp + k * Np + m] : 0.f;
+      }
+  #pragma unroll
+      for (int r = 0; r < NY; ++r) {
+        const int i = tid + kThreads * r;
+        const int c = i / (16 * LN), rem = i - c * 16 * LN, e = rem / LN, m = rem - e * LN;
+        if (i < 9 * 16 * LN) sy[(c * LN + m) * CS + e] = yv[r];
+      }
+    }
+    // face-node tasks (element e, face node jf): the neighbour's state and
+    // impedances, then (after the barrier) the flux from the own side in LDS
+    float qP[NT][9], zpP[NT], zsP[NT];
+    int vMt[NT];
+    f4 fg[NT];
+  #pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int task = tid + kThreads * i;
+      const int tk = task < 16 * NF4 ? task : 16 * NF4 - 1;
+      const int e = tk / NF4, jf = tk - e * NF4;
+      const int64_t k = k0 + e < K ? k0 + e : K - 1;
+      const int64_t nb = A.nbn[k * NF4 + jf];
+      vMt[i] = A.fmask[jf];
+      fg[i] = reinterpret_cast<const f4*>(A.fgeo)[k * 4 + jf / Nfp];
+      zpP[i] = A.zp[nb];
+      zsP[i] = A.zs[nb];
+  #pragma unroll
+      for (int f = 0; f < 9; ++f) qP[i][f] = A.y[f * KNp + nb];
+    }
+    __syncthreads();
+  #pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int task = tid + kThreads * i;
+      if (task >= 16 * NF4) break;
+      const int e = task / NF4, jf = task - e * NF4;
+      const int64_t k = k0 + e < K ? k0 + e : K - 1;
+      const int vM = vMt[i];
+      float qM[9], fl[9];
+  #pragma unroll
+      for (int f = 0; f < 9; ++f) qM[f] = sy[(f * LN + vM) * CS + e];
+      dga::flux<float>(qM, qP[i], fg[i][0], fg[i][1], fg[i][2], fg[i][3], A.zp[k * Np + vM],
+                       A.zs[k * Np + vM], zpP[i], zsP[i], A.upwind, fl);
+  #pragma unroll
+      for (int c = 0; c < 9; ++c) sf[(c * LFN + jf) * CS + e] = fl[c];
+      if (A.upwind && k0 + e < K) {
+        float jm[6];
+        dga::face_jumps<float>(qM, qP[i], fg[i][0], fg[i][1], fg[i][2], jm);
+        f4* jo = reinterpret_cast<f4*>(A.jmp + (k * NF4 + jf) * 8);
+        jo[0] = f4{jm[0], jm[1], jm[2], jm[3]};
+        jo[1] = f4{jm[4], jm[5], 0.f, 0.f};
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   if (wave == 0) {
     load_l<N>(A, k0, 0, lv);
-    tile_group<N, 0>(A, k0, sy, sf, sg, G, lv);
+    tile_group<N, 0, RIN>(A, k0, sy, sf, sg, G, lv);
   } else if (wave == 1) {
     load_l<N>(A, k0, 3, lv);
-    tile_group<N, 1>(A, k0, sy, sf, sg, G, lv);
+    tile_group<N, 1, RIN>(A, k0, sy, sf, sg, G, lv);
   } else if (wave == 2) {
     load_l<N>(A, k0, 6, lv);
-    tile_group<N, 2>(A, k0, sy, sf, sg, G, lv);
+    tile_group<N, 2, RIN>(A, k0, sy, sf, sg, G, lv);
   } else {
     __syncthreads();   // (1)
     __syncthreads();   // (2): the partial stress sums are complete

@@ -116,6 +116,8 @@ struct dg_ctx {
                             // (tiled adjoint: face-node jumps [K][4 Nfp][8])
   DevBuf adj_gradz;         // upwind: double [2][K][Np]
   DevBuf adj_frag;          // FP32 orders 1-4: fragments of the tiled adjoint kernel
+  DevBuf adj_r;             // FP32 orders 1-4: R y of every stage input of a segment,
+                            // [every][5][9][K][Np] (stored by the replay)
   DevBuf adj_trace;         // [nsteps][nrec][3]
   bool adj_ready = false;
   double adj_t0 = 0.0, adj_dt = 0.0;
@@ -312,9 +314,9 @@ dg_status launch_stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void
   return DG_OK;
 }
 
-template <int N, bool F32>
+template <int N, bool F32, bool RST = false>
 hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res, float* rhs_out,
-                         double a, double b, double dt, int lsrk) {
+                         double a, double b, double dt, int lsrk, float* r_out = nullptr) {
   dgb::BxArgs A;
   A.q_in = q_in;
   A.q_out = q_out;
@@ -338,7 +340,11 @@ hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res,
   // one workgroup per tile of 16 elements
   const int64_t tiles = (c->mesh.K + dgb::kTile - 1) / dgb::kTile;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  dgb::stage_bx<N, F32><<<dim3(unsigned(tiles)), dim3(dgb::kThreads), 0, c->stream>>>(A);
+  A.r_out = r_out;
+  if constexpr (RST)
+    dgb::stage_bx_r<N><<<dim3(unsigned(tiles)), dim3(dgb::kThreads), 0, c->stream>>>(A);
+  else
+    dgb::stage_bx<N, F32><<<dim3(unsigned(tiles)), dim3(dgb::kThreads), 0, c->stream>>>(A);
   return hipGetLastError();
 }
 
@@ -671,15 +677,36 @@ dg_status adj_tables(dg_ctx* c) {
 template <int N>
 void launch_adj_tile(dg_ctx* c, const dgt::TileArgs& A) {
   const unsigned tiles = unsigned((A.K + 15) / 16);
-  hipLaunchKernelGGL(dgt::adj_tile<N>, dim3(tiles), dim3(dgt::kThreads), 0, c->stream, A);
+  hipLaunchKernelGGL((dgt::adj_tile<N, true>), dim3(tiles), dim3(dgt::kThreads), 0, c->stream, A);
 }
 
-dg_status adj_stage_tiled(dg_ctx* c, const float* y, float* lres, float* ly, float* nu,
-                          double* grad, double* gradz, float a, float b, double dt, double ts) {
+// one FP32 stage of the replay (fused LSRK update) that also stores R q_in
+dg_status stage_raw(dg_ctx* c, const void* q_in, void* q_out, void* res, void* r_out, double a,
+                    double b, double dt) {
+  const float* qi = static_cast<const float*>(q_in);
+  float* qo = static_cast<float*>(q_out);
+  float* rs = static_cast<float*>(res);
+  float* ro = static_cast<float*>(r_out);
+  hipError_t e;
+  switch (c->re.N) {
+    case 1: e = launch_mfma_n<1, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro); break;
+    case 2: e = launch_mfma_n<2, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro); break;
+    case 3: e = launch_mfma_n<3, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro); break;
+    case 4: e = launch_mfma_n<4, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro); break;
+    default: return fail(c, DG_EINVAL, "adjoint: no tiled kernel at this order");
+  }
+  if (e != hipSuccess) return fail(c, DG_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
+  return DG_OK;
+}
+
+dg_status adj_stage_tiled(dg_ctx* c, const float* y, const float* r, float* lres, float* ly,
+                          float* nu, double* grad, double* gradz, float a, float b, double dt,
+                          double ts) {
   const int64_t K = c->mesh.K;
   const int Np = c->re.Np;
   dgt::TileArgs A{};
   A.y = y;
+  A.r = r;
   A.lres = lres;
   A.ly = ly;
   A.nu = nu;
@@ -704,7 +731,7 @@ dg_status adj_stage_tiled(dg_ctx* c, const float* y, float* lres, float* ly, flo
   A.b = b;
   A.s = dt;
   A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
-  if (!A.nbn || !A.mat || !A.frags || !A.fmask)
+  if (!A.nbn || !A.mat || !A.frags || !A.fmask || !A.r)
     return fail(c, DG_ESTATE, "adjoint: tiled kernel tables missing");
   switch (c->re.N) {
     case 1: launch_adj_tile<1>(c, A); break;
@@ -745,6 +772,11 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
   T* seg = static_cast<T*>(c->adj_seg.p);
   T* v = static_cast<T*>(c->adj_v.p);
   T *ly = v, *lres = v + n, *mu = v + 2 * n, *nu = v + 3 * n, *r = v + 4 * n, *res = v + 5 * n;
+  // tiled FP32 adjoint: R y of every stage input of a segment, and a
+  // scratch output for the segment's last stage (mu is not used there)
+  const bool tiled = adj_tiled(c);
+  T* rr = static_cast<T*>(c->adj_r.p);
+  T* res2 = mu;
   T* gb = static_cast<T*>(c->adj_gb.p);
   T* hb = static_cast<T*>(c->adj_hb.p);
   double* grad = static_cast<double*>(c->adj_grad.p);
@@ -781,9 +813,15 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
       T* y = seg + (i - n0) * 5 * n;
       const double ti = t0 + double(i) * dt;
       if ((s = fill_zero(c, res, n)) != DG_OK) return s;
-      for (int q = 0; q < 5 && (q < 4 || i + 1 < n1); ++q) {
-        T* out = q < 4 ? y + (q + 1) * n : y + 5 * n;   // stage 5: the next step's y_0
-        if ((s = stage(c, y + q * n, out, res, nullptr, kRkA[q], kRkB[q], dt, 1)) != DG_OK)
+      // the tiled adjoint also takes R y of every stage input, which the
+      // replay's FP32 stage stores as it goes (all five stages then)
+      for (int q = 0; q < 5 && (q < 4 || i + 1 < n1 || tiled); ++q) {
+        T* out = q < 4 ? y + (q + 1) * n : (i + 1 < n1 ? y + 5 * n : res2);
+        if (tiled) {
+          if ((s = stage_raw(c, y + q * n, out, res, rr + ((i - n0) * 5 + q) * n, kRkA[q],
+                             kRkB[q], dt)) != DG_OK)
+            return s;
+        } else if ((s = stage(c, y + q * n, out, res, nullptr, kRkA[q], kRkB[q], dt, 1)) != DG_OK)
           return s;
         if ((s = launch_sources(c, res, out, ti + kRkC[q] * dt, dt, kRkB[q] * dt)) != DG_OK)
           return s;
@@ -804,9 +842,9 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
           // the residual scaling of the stage after (a_{q+1}; for q = 4 the
           // a_0 = 0 of the next step's first stage) is applied here
           for (int q = 4; q >= 0; --q)
-            if ((s = adj_stage_tiled(c, ys + q * n, lres, ly, nu, grad, gradz,
-                                     float(kRkA[q == 4 ? 0 : q + 1]), float(kRkB[q]), dt,
-                                     ti + kRkC[q] * dt)) != DG_OK)
+            if ((s = adj_stage_tiled(c, ys + q * n, rr + ((i - n0) * 5 + q) * n, lres, ly, nu,
+                                     grad, gradz, float(kRkA[q == 4 ? 0 : q + 1]),
+                                     float(kRkB[q]), dt, ti + kRkC[q] * dt)) != DG_OK)
               return s;
           continue;
         }
@@ -1156,9 +1194,9 @@ void dg_destroy(dg_ctx* c) {
                       &c->irho, &c->lam, &c->mu, &c->zp, &c->zs, &c->q[0], &c->q[1],
                       &c->res, &c->frags, &c->matblk, &c->nbn, &c->torder, &c->src_elem, &c->src_w,
                       &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf, &c->src_wraw,
-                      &c->adj_nbface, &c->adj_invf, &c->adj_ck, &c->adj_seg,
-                      &c->adj_v, &c->adj_gb, &c->adj_hb,
-                      &c->adj_grad, &c->adj_trace})
+                      &c->adj_nbface, &c->adj_invf, &c->adj_ck, &c->adj_seg, &c->adj_r,
+                      &c->adj_v, &c->adj_gb, &c->adj_hb, &c->adj_grad, &c->adj_zb,
+                      &c->adj_gradz, &c->adj_frag, &c->adj_trace})
       release(c, *b);
   }
   delete c;
@@ -1203,8 +1241,8 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
     drop_graphs(c);
     for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf,
                       &c->trace, &c->src_wraw, &c->adj_nbface, &c->adj_invf, &c->adj_ck,
-                      &c->adj_seg, &c->adj_v, &c->adj_gb, &c->adj_hb,
-                      &c->adj_grad, &c->adj_trace})
+                      &c->adj_seg, &c->adj_r, &c->adj_v, &c->adj_gb, &c->adj_hb,
+                      &c->adj_grad, &c->adj_zb, &c->adj_gradz, &c->adj_frag, &c->adj_trace})
       release(c, *b);
     c->adj_ready = false;
     c->trace_cap = 0;
@@ -1843,6 +1881,7 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
       size_t bytes;
     } need[] = {{&c->adj_ck, S * nck},
                 {&c->adj_seg, S * size_t(every) * 5},
+                {&c->adj_r, tiled ? S * size_t(every) * 5 : 0},
                 {&c->adj_v, S * 6},
                 {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
                 {&c->adj_hb, tiled ? 0 : size_t(K) * NF4 * 9 * c->elem},

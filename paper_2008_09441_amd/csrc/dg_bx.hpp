@@ -84,6 +84,7 @@ struct BxArgsT {
   T a, b, dt;
   int lsrk;              // 0: write rhs_out; 1: fused LSRK update
   int upwind;            // 1 upwind, 0 central
+  T* r_out;              // stage_bx_r: the raw right-hand side R q [9][K][Np]
 };
 typedef BxArgsT<float> BxArgs;
 
@@ -488,6 +489,29 @@ __device__ __forceinline__ void vol_lift_f(const BxArgsT<T>& A, const T* sq, con
   }
 }
 
+// The raw right-hand side R q (volume terms and LIFT, before the mass
+// inverse) of wave W's components from its phase-C accumulators, rows
+// 16 t + 4 g + j of element column e, to r_out (FP32 only)
+template <int N, int W>
+__device__ __forceinline__ void store_raw(const BxArgs& A, int64_t e0, int ne, int lane,
+                                          const f32x4 (&acc)[3][BOrd<N>::RT]) {
+  using O = BOrd<N>;
+  constexpr int Np = O::Np, RT = O::RT, NC = wave_ncomp(W);
+  const int e = lane & 15, g = lane >> 4;
+  if (e >= ne) return;
+  const int64_t KNp = A.K * Np;
+  float* out = A.r_out + (e0 + e) * Np;
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 16 * t + 4 * g + j;
+        if (n < Np) out[wave_comp(W, i) * KNp + n] = acc[i][t][j];
+      }
+}
+
 // Phase D of the FP32 kernel for wave W: per chunk of two quadrature tiles,
 // V_q with the node accumulators as the B operand (K step (t, j) is row
 // 16 t + 4 g + j), the pointwise weight-adjusted material operator, and
@@ -624,9 +648,10 @@ struct TileMap {
 // The stage of one tile: launch position bid of a grid of G positions over
 // the context's tiles (G = ceil(K / 16)); the kernels below call it for a
 // single context or for one slot of a batch.
-template <int N, bool F32, typename T = float>
+template <int N, bool F32, typename T = float, bool RST = false>
 __device__ __forceinline__ void stage_bx_run(const BxArgsT<T>& A, int64_t G, int64_t bid) {
   static_assert(F32 || sizeof(T) == 4, "BF16x3 products work on FP32 data");
+  static_assert(!RST || (F32 && sizeof(T) == 4), "R q is stored by the FP32 kernel");
   using O = BOrd<N>;
   using L = BLds<N, T>;
   using V4 = v4_t<T>;
@@ -837,6 +862,14 @@ __device__ __forceinline__ void stage_bx_run(const BxArgsT<T>& A, int64_t G, int
       case 2: mat_chunk<N, 2, T>(A, tile, lane, 0, m0); vol_lift_f<N, 2, T>(A, sq, sg, sF, lane, acc); break;
       default: mat_chunk<N, 3, T>(A, tile, lane, 0, m0); vol_lift_f<N, 3, T>(A, sq, sg, sF, lane, acc); break;
     }
+    if constexpr (RST) {
+      switch (grp) {
+        case 0: store_raw<N, 0>(A, e0, ne, lane, acc); break;
+        case 1: store_raw<N, 1>(A, e0, ne, lane, acc); break;
+        case 2: store_raw<N, 2>(A, e0, ne, lane, acc); break;
+        default: store_raw<N, 3>(A, e0, ne, lane, acc); break;
+      }
+    }
   } else {
     switch (grp) {
       case 0: mat_chunk<N, 0>(A, tile, lane, 0, m0); vol_lift<N, 0>(A, sq, sg, sF, lane, acc); break;
@@ -913,6 +946,14 @@ __device__ __forceinline__ void stage_bx_run(const BxArgsT<T>& A, int64_t G, int
 template <int N, bool F32>
 __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
   stage_bx_run<N, F32>(A, gridDim.x, blockIdx.x);
+}
+
+// The FP32 stage that also stores the raw right-hand side R q of its input
+// (r_out): the replay of a checkpoint interval in the discrete adjoint,
+// whose reverse stage needs R y of every stage input
+template <int N>
+__global__ __launch_bounds__(kThreads, 2) void stage_bx_r(BxArgs A) {
+  stage_bx_run<N, true, float, true>(A, gridDim.x, blockIdx.x);
 }
 
 // FP64 stage on the matrix cores (v_mfma_f64_16x16x4f64): the FP32 kernel's

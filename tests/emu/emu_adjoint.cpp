@@ -1,12 +1,14 @@
-// Runs one reverse stage of the tiled FP32 adjoint (dgt::adj_tile<N> and
+// Runs one reverse stage of the tiled FP32 adjoint (dgt::adj_tile<N, rin> and
 // dgt::adj_nodes, orders 1-4) on the CPU, for tests: each workgroup is 256
 // host threads with real barriers and emulated matrix-core products (see
 // emu_runtime.hpp).  Built with AddressSanitizer by the test, so any
 // out-of-bounds access of the kernel source shows up on the CPU.
 //
-// input file: int32 N, flux_upwind; int64 K; float64 vxyz[K*12], period[3],
+// input file: int32 N, flux_upwind, rin; int64 K; float64 vxyz[K*12], period[3],
 // rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n [K*Np each]; float32
-// y, lres, ly [9*K*Np each]; float64 a, b, dt, ts; int32 nsrc; per source
+// y, lres, ly [9*K*Np each]; with rin, float32 R y [9*K*Np] (the kernel
+// variant that takes R y instead of computing it); float64 a, b, dt, ts;
+// int32 nsrc; per source
 // int64 element, float32 raw response [3*Np], float64 (f0, t0, amplitude).
 // output file: float64 lres (= a lres + b ly), ly, grad [3*K*Nq], gradz
 // [2*K*Np] after the stage (grad and gradz accumulated from zero).
@@ -27,9 +29,9 @@ int main(int argc, char** argv) {
   if (argc != 3) { fprintf(stderr, "usage: emu_adjoint in.bin out.bin\n"); return 2; }
   FILE* f = fopen(argv[1], "rb");
   if (!f) return 2;
-  int32_t hdr[2]; int64_t K;
-  if (fread(hdr, 4, 2, f) != 2 || fread(&K, 8, 1, f) != 1) return 2;
-  const int N = hdr[0], upwind = hdr[1];
+  int32_t hdr[3]; int64_t K;
+  if (fread(hdr, 4, 3, f) != 3 || fread(&K, 8, 1, f) != 1) return 2;
+  const int N = hdr[0], upwind = hdr[1], rin = hdr[2];
   if (N < 1 || N > 4) return 3;
   const int Np = dgh::num_nodes(N), Nq = dgh::num_quad(N);
   auto rd = [&](size_t n) { std::vector<double> v(n); if (fread(v.data(), 8, n, f) != n) exit(2); return v; };
@@ -39,6 +41,7 @@ int main(int argc, char** argv) {
   auto rn = rd(K * Np), pn = rd(K * Np), sn = rd(K * Np);
   const size_t n9 = size_t(9) * K * Np;
   auto y = rdf(n9), lres = rdf(n9), ly = rdf(n9);
+  std::vector<float> rraw = rin ? rdf(n9) : std::vector<float>();
   auto sc = rd(4);
   int32_t nsrc = 0;
   if (fread(&nsrc, 4, 1, f) != 1) return 2;
@@ -79,7 +82,7 @@ int main(int argc, char** argv) {
   std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
 
   dgt::TileArgs A{};
-  A.y = yd; A.lres = lr; A.ly = lyd; A.nu = nu; A.gf = gf; A.jmp = jmp; A.grad = grad;
+  A.y = yd; A.r = rin ? dup(rraw) : nullptr; A.lres = lr; A.ly = lyd; A.nu = nu; A.gf = gf; A.jmp = jmp; A.grad = grad;
   A.geo = dupf(m.geo); A.fgeo = dupf(m.fgeo);
   A.nbn = dup(dgh::neighbour_nodes(re, m));
   A.fmask = dup(fm);
@@ -92,11 +95,20 @@ int main(int argc, char** argv) {
   A.nsrc = nsrc; A.ts = sc[3];
   A.K = K; A.a = float(sc[0]); A.b = float(sc[1]); A.s = sc[2]; A.upwind = upwind;
   const int tiles = int((K + 15) / 16);
-  switch (N) {
-    case 1: run_grid(tiles, [=]() { dgt::adj_tile<1>(A); }); break;
-    case 2: run_grid(tiles, [=]() { dgt::adj_tile<2>(A); }); break;
-    case 3: run_grid(tiles, [=]() { dgt::adj_tile<3>(A); }); break;
-    default: run_grid(tiles, [=]() { dgt::adj_tile<4>(A); }); break;
+  if (rin) {
+    switch (N) {
+      case 1: run_grid(tiles, [=]() { dgt::adj_tile<1, true>(A); }); break;
+      case 2: run_grid(tiles, [=]() { dgt::adj_tile<2, true>(A); }); break;
+      case 3: run_grid(tiles, [=]() { dgt::adj_tile<3, true>(A); }); break;
+      default: run_grid(tiles, [=]() { dgt::adj_tile<4, true>(A); }); break;
+    }
+  } else {
+    switch (N) {
+      case 1: run_grid(tiles, [=]() { dgt::adj_tile<1, false>(A); }); break;
+      case 2: run_grid(tiles, [=]() { dgt::adj_tile<2, false>(A); }); break;
+      case 3: run_grid(tiles, [=]() { dgt::adj_tile<3, false>(A); }); break;
+      default: run_grid(tiles, [=]() { dgt::adj_tile<4, false>(A); }); break;
+    }
   }
   dgt::NodeArgs B{};
   B.nu = nu; B.gf = gf; B.jmp = jmp; B.ly = lyd; B.gradz = gradz;

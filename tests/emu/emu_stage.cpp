@@ -42,7 +42,7 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
     d[i] = rho_q[i] * cs_q[i] * cs_q[i];
   }
   for (int64_t i = 0; i < K * Np; ++i) { zp[i] = rho_n[i] * cp_n[i]; zs[i] = rho_n[i] * cs_n[i]; }
-  if (grid < 1 || grid > 3) return 3;
+  if (grid < 1 || grid > 4) return 3;
   if (grid == 3 && N >= 5) {   // FP64 matrix-core kernel, orders 5-7
     dgb::BeArgsT<double> E{};
     std::vector<double> qd(q, q + 9 * K * Np);
@@ -147,15 +147,36 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
   A.fmask = dup(fm);
   A.mat = dupf(dgh::mfma_material(N, K, a.data(), b.data(), d.data()));
   A.zp = dupf(zp); A.zs = dupf(zs);
-  const bool f32 = grid == 2;   // FP32 matrix-core kernel
+  const bool f32 = grid == 2 || grid == 4;   // FP32 matrix-core kernel
+  float* rraw = nullptr;
+  if (grid == 4) {   // the FP32 kernel that also stores R q: output R q
+    if (N > 4) return 3;
+    rraw = alloc<float>(9 * K * Np);
+    A.r_out = rraw;
+    if (!lsrk) { A.res = alloc<float>(9 * K * Np); A.q_out = alloc<float>(9 * K * Np); }
+    for (int64_t i = 0; i < 9 * K * Np; ++i) A.res[i] = 0.f;
+    A.lsrk = 1;
+  }
   if (f32) {
     const std::vector<float> ff = dgh::mfma_fragments_f32(re);
     A.frags = reinterpret_cast<const dgb::u32x4*>(dup(ff));
   } else {
     A.frags = reinterpret_cast<const dgb::u32x4*>(dup(fr));
   }
-  A.K = K; A.a = 0.f; A.b = 1.f; A.dt = 1.f; A.lsrk = lsrk; A.upwind = upwind;
+  A.K = K; A.a = 0.f; A.b = 1.f; A.dt = 1.f; A.upwind = upwind;
+  if (!rraw) A.lsrk = lsrk;
+  const bool rst = rraw != nullptr;
   grid = int((K + dgb::kTile - 1) / dgb::kTile);   // one workgroup per element tile
+  if (rst) {
+    switch (N) {
+      case 1: run_grid(grid, [=]() { dgb::stage_bx_r<1>(A); }); break;
+      case 2: run_grid(grid, [=]() { dgb::stage_bx_r<2>(A); }); break;
+      case 3: run_grid(grid, [=]() { dgb::stage_bx_r<3>(A); }); break;
+      default: run_grid(grid, [=]() { dgb::stage_bx_r<4>(A); }); break;
+    }
+    for (int64_t i = 0; i < 9 * K * Np; ++i) out[i] = double(rraw[i]);
+    return 0;
+  }
   switch (N) {
     case 1: f32 ? run<1, true>(A, grid) : run<1, false>(A, grid); break;
     case 2: f32 ? run<2, true>(A, grid) : run<2, false>(A, grid); break;
@@ -169,7 +190,8 @@ static int emu_rhs(int N, int64_t K, const double* vxyz, const double* period,
 }
 
 // input file: int32 N, flux_upwind, kernel (1: BF16x3 matrix-core kernel, 2:
-// FP32 matrix-core kernel, 3: FP64 matrix-core kernel, every order), lsrk; int64 K; then float64
+// FP32 matrix-core kernel, 3: FP64 matrix-core kernel, every order, 4: the
+// FP32 kernel that also stores R q, whose R q is the output), lsrk; int64 K; then float64
 // vxyz[K*12], period[3], rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n
 // [K*Np each]; then float32 q[9*K*Np]
 int main(int argc, char** argv) {

@@ -53,7 +53,7 @@ def rel_l2_per_field(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
-def _case(exe, tmp_path, n, N, flux, split=False, nsrc=0):
+def _case(exe, tmp_path, n, N, flux, split=False, nsrc=0, rin=False):
     vx = synth.kuhn_cube_vertices(n)
     mesh = None
     if split:   # one element split at its centroid: an odd element count
@@ -70,13 +70,15 @@ def _case(exe, tmp_path, n, N, flux, split=False, nsrc=0):
     for i in range(nsrc):
         srcs.append(dict(k=int(rng.integers(K)), w=rng.standard_normal((3, Np)).astype(np.float32),
                          f0=float(rng.uniform(2, 6)), t0=0.15, amp=float(rng.uniform(0.5, 2))))
-    parts = [np.array([N, 1 if flux == "upwind" else 0], np.int32).tobytes(),
+    parts = [np.array([N, 1 if flux == "upwind" else 0, 1 if rin else 0], np.int32).tobytes(),
              np.array([K], np.int64).tobytes(), vx.astype(np.float64).tobytes(),
              np.ones(3).tobytes()]
     for arr in synth.fourier_media(op.mesh.xq) + synth.fourier_media(op.mesh.x):
         parts.append(np.ascontiguousarray(arr, np.float64).tobytes())
-    parts += [y.tobytes(), lres.tobytes(), ly.tobytes(), np.array([a, b, dt, ts]).tobytes(),
-              np.array([nsrc], np.int32).tobytes()]
+    parts += [y.tobytes(), lres.tobytes(), ly.tobytes()]
+    if rin:   # R y as the replay's FP32 stage would store it
+        parts.append(op.rhs_raw(y.astype(np.float64)).astype(np.float32).tobytes())
+    parts += [np.array([a, b, dt, ts]).tobytes(), np.array([nsrc], np.int32).tobytes()]
     for s in srcs:
         parts += [np.array([s["k"]], np.int64).tobytes(), s["w"].tobytes(),
                   np.array([s["f0"], s["t0"], s["amp"]]).tobytes()]
@@ -120,14 +122,18 @@ def _check(errs):
     assert errs.get("gradz", 0.0) <= 1e-4
 
 
+@pytest.mark.parametrize("rin", [False, True])
 @pytest.mark.parametrize("n,N,flux", [(1, 1, "upwind"), (2, 1, "central"), (2, 2, "upwind"),
                                       (1, 3, "central"), (1, 4, "upwind")])
-def test_adjoint_tile_kernels_in_bounds_and_match_the_oracle(emu_adj, tmp_path, n, N, flux):
-    _check(_case(emu_adj, tmp_path, n, N, flux))
+def test_adjoint_tile_kernels_in_bounds_and_match_the_oracle(emu_adj, tmp_path, n, N, flux, rin):
+    """Both variants: R y computed in the kernel, and R y given (the
+    library's, which the replay's forward stage stores)."""
+    _check(_case(emu_adj, tmp_path, n, N, flux, rin=rin))
 
 
+@pytest.mark.parametrize("rin", [False, True])
 @pytest.mark.parametrize("n,N,flux,nsrc", [(2, 3, "upwind", 2), (1, 4, "central", 1)])
-def test_adjoint_tile_kernels_odd_count_and_sources(emu_adj, tmp_path, n, N, flux, nsrc):
+def test_adjoint_tile_kernels_odd_count_and_sources(emu_adj, tmp_path, n, N, flux, nsrc, rin):
     """An odd element count (one element split at its centroid, non-Kuhn
     shapes, a ragged last tile) with point sources inside the tiles."""
-    _check(_case(emu_adj, tmp_path, n, N, flux, split=True, nsrc=nsrc))
+    _check(_case(emu_adj, tmp_path, n, N, flux, split=True, nsrc=nsrc, rin=rin))

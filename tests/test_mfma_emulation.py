@@ -38,7 +38,7 @@ def emu_exe(tmp_path_factory):
     return exe
 
 
-def _run(exe, tmp_path, n, N, flux="upwind", grid=1, lsrk=0, split=False):
+def _run(exe, tmp_path, n, N, flux="upwind", grid=1, lsrk=0, split=False, raw=False):
     vx = synth.kuhn_cube_vertices(n)
     mesh = None
     if split:   # one element split at its centroid: K = 6 n^3 + 3 (odd)
@@ -60,7 +60,7 @@ def _run(exe, tmp_path, n, N, flux="upwind", grid=1, lsrk=0, split=False):
                        timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     got = np.fromfile(fout, np.float64).reshape(9, op.K, op.Np)
-    ref = op.rhs(q.astype(np.float64))
+    ref = op.rhs_raw(q.astype(np.float64)) if raw else op.rhs(q.astype(np.float64))
     return rel_l2_per_field(got, ref)
 
 
@@ -147,3 +147,14 @@ def test_fp64_matrix_kernel_orders_5_to_7(emu_exe, tmp_path, n, N, flux, lsrk, s
     err = _run(emu_exe, tmp_path, n, N, flux, grid=3, lsrk=lsrk, split=split)
     print("per-field rel L2:", np.array2string(err, precision=2))
     assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("n,N,flux,split", [(2, 1, "upwind", False), (3, 2, "central", False),
+                                            (3, 3, "upwind", False), (2, 4, "upwind", True)])
+def test_fp32_matrix_kernel_stores_the_raw_rhs(emu_exe, tmp_path, n, N, flux, split):
+    """stage_bx_r<N>, the FP32 kernel of the adjoint's replay: besides its
+    stage it stores R q (volume terms and LIFT before the mass inverse),
+    checked against the oracle's raw right-hand side."""
+    err = _run(emu_exe, tmp_path, n, N, flux, grid=4, split=split, raw=True)
+    print("per-field rel L2:", np.array2string(err, precision=2))
+    assert err.max() <= 2e-5
