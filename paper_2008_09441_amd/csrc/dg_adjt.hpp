@@ -103,6 +103,38 @@ __device__ inline double ricker(const double* par, int i, double t) {
   return par[3 * i + 2] * (1.0 - 2.0 * x * x) * exp(-x * x);
 }
 
+// The node held by lane group g in item j of node tile t: the chained K
+// order 16 t + 4 g + j, except (packed, PK) for the last tile, whose nodes
+// 16 t + g sit in item 0 (-1: no node)
+template <int N, bool PK>
+__device__ __forceinline__ int chained_node(int t, int g, int j) {
+  using O = AOrd<N>;
+  if (PK && t == O::RT - 1) return j == 0 && g < O::VLAST ? 16 * t + g : -1;
+  const int n = 16 * t + 4 * g + j;
+  return n < O::Np ? n : -1;
+}
+
+// l = a lres + b ly for components c0 .. c0 + 2 of element k0 + e at the
+// rows the lane holds in the chained K order (chained_node)
+template <int N, bool PK>
+__device__ __forceinline__ void load_l(const TileArgs& A, int64_t k0, int c0,
+                                       float (&lv)[3][AOrd<N>::RT][4]) {
+  using O = AOrd<N>;
+  constexpr int Np = O::Np;
+  const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+  const int64_t KNp = A.K * Np, kc = k0 + e < A.K ? k0 + e : A.K - 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int t = 0; t < O::RT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = chained_node<N, PK>(t, g, j);
+        const int64_t i = (c0 + c) * KNp + kc * Np + (n >= 0 ? n : 0);
+        lv[c][t][j] = n >= 0 ? A.a * A.lres[i] + A.b * A.ly[i] : 0.f;
+      }
+}
+
 // Waves 0-2: everything from R y to nu and g for components 3W .. 3W + 2.
 template <int N, int W, bool RIN>
 __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float* sy,
@@ -112,6 +144,7 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
   constexpr int RT = O::RT, QT = O::QT, FT = O::FT, KN = O::KN, KF = O::KF, KF4 = O::KF4;
   constexpr int Np = O::Np, Nq = O::Nq, NF4 = O::NF4, LN = 4 * KN, LFN = 4 * KF, CS = O::CS;
   constexpr int C0 = 3 * W;
+  constexpr bool PK = RIN && O::PACK;   // the last node tile packed in one step
   const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
   const int64_t K = A.K, KNp = K * Np;
   const int64_t k = k0 + e;
@@ -135,8 +168,8 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
       for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int n = 16 * t + 4 * g + j;
-          r[t][c][j] = n < Np ? A.r[(C0 + c) * KNp + kc * Np + (n < Np ? n : Np - 1)] : 0.f;
+          const int n = chained_node<N, PK>(t, g, j);
+          r[t][c][j] = n >= 0 ? A.r[(C0 + c) * KNp + kc * Np + n] : 0.f;
         }
   } else {
   {
@@ -218,8 +251,8 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
         for (int t = 0; t < RT; ++t)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const int n = 16 * t + 4 * g + j;
-            if (n < Np) r[t][c][j] += f * A.src_w[(i * 3 + c) * Np + n];
+            const int n = chained_node<N, PK>(t, g, j);
+            if (n >= 0) r[t][c][j] += f * A.src_w[(i * 3 + c) * Np + n];
           }
     }
   }
@@ -231,8 +264,8 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
       for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int n = 16 * t + 4 * g + j;
-          if (n < Np) A.lres[(C0 + c) * KNp + k * Np + n] = lv[c][t][j];
+          const int n = chained_node<N, PK>(t, g, j);
+          if (n >= 0) A.lres[(C0 + c) * KNp + k * Np + n] = lv[c][t][j];
         }
   }
   __syncthreads();   // (1) every wave is done with the fluxes: sg may be written
@@ -251,8 +284,12 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
     f4 fv[RT], fp[RT], fvt[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
-      fv[t] = frag(O::G_V + t);
-      fp[t] = frag(O::G_P + t);
+      if (!PK || t < RT - 1) {
+        fv[t] = frag(O::G_V + t);
+        fp[t] = frag(O::G_P + t);
+      } else {
+        fv[t] = frag(O::G_VX);   // item 0: V_q, item 1: P_q of the packed tile
+      }
       fvt[t] = frag(O::G_VT + t);
     }
     f4 m0 = matv(W == 0 ? 0 : 2, 0), m1 = W == 1 ? matv(1, 0) : f4{0.f, 0.f, 0.f, 0.f};
@@ -272,16 +309,25 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
       for (int c = 0; c < 3; ++c) w[c] = p[c] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int t = 0; t < RT; ++t) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
+        if (PK && t == RT - 1) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            w[c] = mma(fv[t][j], r[t][c][j], w[c]);
-            p[c] = mma(fp[t][j], lv[c][t][j], p[c]);
+            w[c] = mma(fv[t][0], r[t][c][0], w[c]);
+            p[c] = mma(fv[t][1], lv[c][t][0], p[c]);
           }
-        if (u + 1 < QT) {
-          fv[t] = frag(O::G_V + (u + 1) * RT + t);
-          fp[t] = frag(O::G_P + (u + 1) * RT + t);
+          if (u + 1 < QT) fv[t] = frag(O::G_VX + u + 1);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              w[c] = mma(fv[t][j], r[t][c][j], w[c]);
+              p[c] = mma(fp[t][j], lv[c][t][j], p[c]);
+            }
+          if (u + 1 < QT) {
+            fv[t] = frag(O::G_V + (u + 1) * RT + t);
+            fp[t] = frag(O::G_P + (u + 1) * RT + t);
+          }
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -445,27 +491,6 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
   }
 }
 
-// l = a lres + b ly for components c0 .. c0 + 2 of element k0 + e at the
-// rows the lane holds in the chained K order (node 16 t + 4 g + j)
-template <int N>
-__device__ __forceinline__ void load_l(const TileArgs& A, int64_t k0, int c0,
-                                       float (&lv)[3][AOrd<N>::RT][4]) {
-  using O = AOrd<N>;
-  constexpr int Np = O::Np;
-  const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
-  const int64_t KNp = A.K * Np, kc = k0 + e < A.K ? k0 + e : A.K - 1;
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int t = 0; t < O::RT; ++t)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = 16 * t + 4 * g + j;
-        const int64_t i = (c0 + c) * KNp + kc * Np + (n < Np ? n : Np - 1);
-        lv[c][t][j] = n < Np ? A.a * A.lres[i] + A.b * A.ly[i] : 0.f;
-      }
-}
-
 template <int N, bool RIN>
 __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
   using O = AOrd<N>;
@@ -596,13 +621,13 @@ __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
   }
 
   if (wave == 0) {
-    load_l<N>(A, k0, 0, lv);
+    load_l<N, RIN && AOrd<N>::PACK>(A, k0, 0, lv);
     tile_group<N, 0, RIN>(A, k0, sy, sf, sg, G, lv);
   } else if (wave == 1) {
-    load_l<N>(A, k0, 3, lv);
+    load_l<N, RIN && AOrd<N>::PACK>(A, k0, 3, lv);
     tile_group<N, 1, RIN>(A, k0, sy, sf, sg, G, lv);
   } else if (wave == 2) {
-    load_l<N>(A, k0, 6, lv);
+    load_l<N, RIN && AOrd<N>::PACK>(A, k0, 6, lv);
     tile_group<N, 2, RIN>(A, k0, sy, sf, sg, G, lv);
   } else {
     __syncthreads();   // (1)

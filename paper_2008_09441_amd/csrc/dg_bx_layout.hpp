@@ -184,7 +184,15 @@ struct AOrd {
   static constexpr int G_VT = G_P + QT * RT;
   static constexpr int G_DT = G_VT + QT * RT;
   static constexpr int G_LT = G_DT + RT * KN;
-  static constexpr int NG = G_LT + FT * RT;    // fragment groups
+  // With R y and l read from memory (adj_tile<N, true>), the nodes of the
+  // last node tile, when they fit one 4-slot step (VLAST <= 4: orders 1, 3
+  // and 4), go in a single step, lane group k holding node 16 (RT - 1) + k:
+  //   VX  (u), item 0:      V_q[16 u + r][16 (RT - 1) + k]
+  //            item 1:      P_q[16 (RT - 1) + k][16 u + r]   (items 2, 3 zero)
+  static constexpr int VLAST = Np - 16 * (RT - 1);
+  static constexpr bool PACK = VLAST <= 4;
+  static constexpr int G_VX = G_LT + FT * RT;
+  static constexpr int NG = G_VX + (PACK ? QT : 0);   // fragment groups
   // LDS, in floats: the stage input y (later mu = W^T l) [9][4 KN][CS]; the
   // face fluxes [9][4 KF][CS], later the two partial stress sums of the
   // gradient, double [2][16 QT][16]; rows of CS = 17 floats (16 elements,

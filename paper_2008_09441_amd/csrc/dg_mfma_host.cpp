@@ -326,6 +326,13 @@ std::vector<float> build_adj_frags(const RefElement& re) {
     for (int f = 0; f < O::FT; ++f)
       for (int t = 0; t < O::RT; ++t)
         for (int j = 0; j < 4; ++j) put(O::G_LT + f * O::RT + t, l, j, L(16 * t + 4 * k + j, 16 * f + r));
+    if (O::PACK) {
+      const int n = 16 * (O::RT - 1) + k;   // zero past Np (k >= VLAST)
+      for (int u = 0; u < O::QT; ++u) {
+        put(O::G_VX + u, l, 0, V(16 * u + r, n));
+        put(O::G_VX + u, l, 1, P(n, 16 * u + r));
+      }
+    }
   }
   return out;
 }
