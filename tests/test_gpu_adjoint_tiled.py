@@ -5,8 +5,9 @@ for the upwind flux, in the impedances (Zp, Zs), with point sources and
 receivers and a ragged last checkpoint interval, on the Kuhn mesh and on
 an odd element count (a ragged last element tile).  The FP64 path matches
 the oracle's discrete adjoint to 1e-10 (test_gpu_adjoint.py); the FP32 one
-must agree with it to 1e-3 (per-field relative L2), and two reverse sweeps
-of one forward run must give bit-identical gradients (no atomics)."""
+must agree with it to 1e-5 (per-field relative L2; measured 1e-7 to 7e-7
+over these cases), and two reverse sweeps of one forward run must give
+bit-identical gradients (no atomics)."""
 import numpy as np
 import pytest
 
@@ -84,10 +85,38 @@ def test_tiled_fp32_adjoint_matches_the_fp64_adjoint(n, N, flux, split):
     assert np.array_equal(g32, g32b) and np.array_equal(z32, z32b)
     eg = _rel(g32, g64)
     print("gradient m, FP32 tiled vs FP64, per field:", np.array2string(eg, precision=2))
-    assert eg.max() <= 1e-3
+    assert eg.max() <= 1e-5
     if flux == "upwind":
         ez = _rel(z32, z64)
         print("gradient z, FP32 tiled vs FP64, per field:", np.array2string(ez, precision=2))
-        assert np.linalg.norm(z64) > 0 and ez.max() <= 1e-3
+        assert np.linalg.norm(z64) > 0 and ez.max() <= 1e-5
+    else:
+        assert not z32.any()
+
+
+@pytest.mark.parametrize("flux", ["upwind", "central"])
+def test_generic_fp32_adjoint_order5_matches_the_fp64_adjoint(flux):
+    """FP32 contexts above order 4 keep the generic adjoint kernels: their
+    gradients against the FP64 adjoint of the same run, as above."""
+    print(f"case generic FP32 adjoint N=5 {flux}", flush=True)
+    n, N = 2, 5
+    vx = synth.kuhn_cube_vertices(n)
+    s64, m, zp = _solver(n, N, flux, "fp64", vx)
+    s32, _, _ = _solver(n, N, flux, "fp32", vx)
+    K, Np, _, _ = s64.sizes()
+    q0 = synth.random_state(K, Np, seed=19) * 0.1
+    dt, nsteps, every = 0.002, 7, 3
+    d = np.random.default_rng(17).standard_normal((nsteps, len(RECS), 3)) * 0.05
+    _, [(g64, z64)] = _grads(s64, m, zp, q0, dt, nsteps, every, d)
+    _, [(g32, z32)] = _grads(s32, m, zp, q0, dt, nsteps, every, d)
+    s64.close()
+    s32.close()
+    eg = _rel(g32, g64)
+    print("gradient m, FP32 generic vs FP64, per field:", np.array2string(eg, precision=2))
+    assert np.isfinite(g32).all() and eg.max() <= 1e-5
+    if flux == "upwind":
+        ez = _rel(z32, z64)
+        print("gradient z, FP32 generic vs FP64, per field:", np.array2string(ez, precision=2))
+        assert ez.max() <= 1e-5
     else:
         assert not z32.any()
