@@ -20,10 +20,11 @@
 //   stresses, shear stresses) from R y to nu and g; the material operator
 //   and the gradient terms then stay inside a wave except the stress sum of
 //   d/d mu, whose two partial sums meet in LDS.  Every product's B operand
-//   comes from LDS (y, fluxes, mu) or straight from the previous product's
-//   accumulators (the K orders of AOrd).  All waves compute the face fluxes
-//   (with RIN only the face jumps); wave 3 also adds the stress term of the
-//   gradient.
+//   comes from LDS (y, fluxes, mu) or from registers in the K order of AOrd:
+//   the previous product's accumulators, or l and R y loaded in that order
+//   (with RIN the nodes of a last node tile of at most four go in one packed
+//   step).  All waves compute the face fluxes (with RIN only the face
+//   jumps); wave 3 also adds the stress term of the gradient.
 //
 //   For the upwind flux it also keeps the velocity and traction jumps of
 //   every face node (the state the impedance gradient needs).
