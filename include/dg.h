@@ -280,7 +280,9 @@ dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const doubl
  * [nsteps][nrec][3], working precision).  Leaves the context at the end of
  * the run.  Needs receivers (DG_ESTATE).  Library-owned device memory:
  * ceil(nsteps/every) + 5 every + 6 states (FP32 at orders 1-4: 10 every + 6,
- * the replay also keeping R y of every stage input) plus face-node work arrays
+ * the replay also keeping R y of every stage input, or 20 every + 6 when
+ * that much fits, so that the replay of the next interval overlaps the
+ * reverse sweep of this one) plus face-node work arrays
  * ([K][4 Nfp][9], two of them on the generic adjoint kernels) and the FP64
  * gradient [3][K][Nq] (upwind: also [K][4 Nfp][4] impedance terms, [K][4
  * Nfp][8] face jumps on the tiled FP32 kernels of orders 1-4, and the FP64

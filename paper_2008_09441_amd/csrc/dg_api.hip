@@ -118,6 +118,8 @@ struct dg_ctx {
   DevBuf adj_frag;          // FP32 orders 1-4: fragments of the tiled adjoint kernel
   DevBuf adj_r;             // FP32 orders 1-4: R y of every stage input of a segment,
                             // [every][5][9][K][Np] (stored by the replay)
+  bool adj_ov = false;      // adj_seg and adj_r hold two segments: the replay of
+                            // the next segment overlaps the reverse sweep
   DevBuf adj_trace;         // [nsteps][nrec][3]
   bool adj_ready = false;
   double adj_t0 = 0.0, adj_dt = 0.0;
@@ -763,8 +765,141 @@ dg_status adj_stage_tiled(dg_ctx* c, const float* y, const float* r, float* lres
   return DG_OK;
 }
 
+// The tiled FP32 sweep (orders 1-4).  Per segment: the replay, whose FP32
+// stages store every stage input and its R y, then the reverse stages on the
+// tiled adjoint kernels.  With two segment buffers (adj_ov) the replay of
+// the next segment runs on a second stream while this one is reversed; the
+// results are the same bit for bit.
+dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
+  const int Np = c->re.Np, Nq = c->re.Nq;
+  const int64_t K = c->mesh.K, n = int64_t(9) * K * Np, KNp = K * Np;
+  const float* ck = static_cast<const float*>(c->adj_ck.p);
+  float* seg0 = static_cast<float*>(c->adj_seg.p);
+  float* rr0 = static_cast<float*>(c->adj_r.p);
+  float* v = static_cast<float*>(c->adj_v.p);
+  // res and res2 (a scratch output for a segment's last stage) are the
+  // replay's; ly, lres and nu the reverse sweep's
+  float *ly = v, *lres = v + n, *res2 = v + 2 * n, *nu = v + 3 * n, *res = v + 5 * n;
+  double* grad = static_cast<double*>(c->adj_grad.p);
+  double* gradz = static_cast<double*>(c->adj_gradz.p);
+  const double t0 = c->adj_t0, dt = c->adj_dt;
+  const int64_t nsteps = c->adj_nsteps, every = c->adj_every;
+  const int64_t nck = (nsteps + every - 1) / every;
+  const size_t segn = size_t(every) * 5 * size_t(n);
+  const hipStream_t st = c->stream;
+  dg_status s;
+  if ((s = fill_zero(c, ly, n)) != DG_OK) return s;
+  if ((s = fill_zero(c, lres, n)) != DG_OK) return s;
+  dgk::fill_kernel<double><<<nblocks(3 * K * Nq), 256, 0, st>>>(grad, 3 * K * Nq, 0.0);
+  DG_HIP(c, hipGetLastError());
+  if (c->opt.flux == DG_FLUX_UPWIND) {
+    dgk::fill_kernel<double><<<nblocks(2 * KNp), 256, 0, st>>>(gradz, 2 * KNp, 0.0);
+    DG_HIP(c, hipGetLastError());
+  }
+  // the replay of segment sg into buffer b, on the context's current stream
+  auto replay = [&](int64_t sg, int b) -> dg_status {
+    float* seg = seg0 + b * segn;
+    float* rr = rr0 + b * segn;
+    const int64_t n0 = sg * every, n1 = std::min(n0 + every, nsteps);
+    DG_HIP(c, hipMemcpyAsync(seg, ck + sg * n, n * sizeof(float), hipMemcpyDeviceToDevice,
+                             c->stream));
+    dg_status e;
+    for (int64_t i = n0; i < n1; ++i) {
+      float* y = seg + (i - n0) * 5 * n;
+      const double ti = t0 + double(i) * dt;
+      if ((e = fill_zero(c, res, n)) != DG_OK) return e;
+      for (int q = 0; q < 5; ++q) {
+        float* out = q < 4 ? y + (q + 1) * n : (i + 1 < n1 ? y + 5 * n : res2);
+        if ((e = stage_raw(c, y + q * n, out, res, rr + ((i - n0) * 5 + q) * n, kRkA[q], kRkB[q],
+                           dt)) != DG_OK)
+          return e;
+        if ((e = launch_sources(c, res, out, ti + kRkC[q] * dt, dt, kRkB[q] * dt)) != DG_OK)
+          return e;
+      }
+    }
+    return DG_OK;
+  };
+  // the reverse stages of segment sg from buffer b, on the context's stream
+  auto reverse = [&](int64_t sg, int b) -> dg_status {
+    const float* seg = seg0 + b * segn;
+    const float* rr = rr0 + b * segn;
+    const int64_t n0 = sg * every, n1 = std::min(n0 + every, nsteps);
+    dg_status e;
+    for (int64_t i = n1 - 1; i >= n0; --i) {
+      const float* ys = seg + (i - n0) * 5 * n;
+      // misfit sensitivity of the trace row of step i (state after step i)
+      if (c->nrec > 0) {
+        dga::receiver_adjoint<float><<<nblocks(3 * Np), 256, 0, st>>>(
+            ly, resid + i * c->nrec * 3, static_cast<const int64_t*>(c->rec_elem.p),
+            static_cast<const float*>(c->rec_w.p), c->nrec, Np, KNp);
+        DG_HIP(c, hipGetLastError());
+      }
+      const double ti = t0 + double(i) * dt;
+      // the residual scaling of the stage after (a_{q+1}; for q = 4 the a_0
+      // = 0 of the next step's first stage) is applied in the kernel
+      for (int q = 4; q >= 0; --q)
+        if ((e = adj_stage_tiled(c, ys + q * n, rr + ((i - n0) * 5 + q) * n, lres, ly, nu, grad,
+                                 gradz, float(kRkA[q == 4 ? 0 : q + 1]), float(kRkB[q]), dt,
+                                 ti + kRkC[q] * dt)) != DG_OK)
+          return e;
+    }
+    return DG_OK;
+  };
+  if (!c->adj_ov) {
+    for (int64_t sg = nck - 1; sg >= 0; --sg) {
+      if ((s = replay(sg, 0)) != DG_OK) return s;
+      if ((s = reverse(sg, 0)) != DG_OK) return s;
+    }
+    return DG_OK;
+  }
+  // overlapped: a second stream (default priority) for the replays; events
+  // order each reverse sweep after its replay, and each replay after the
+  // reverse sweep that last read its buffer.  The guard restores the
+  // context's stream and waits for the replay stream on every exit.
+  struct Side {
+    dg_ctx* c;
+    hipStream_t main, s2 = nullptr;
+    hipEvent_t ev0 = nullptr, rep[2] = {nullptr, nullptr}, rev[2] = {nullptr, nullptr};
+    ~Side() {
+      c->stream = main;
+      if (s2) {
+        (void)hipStreamSynchronize(s2);
+        (void)hipStreamDestroy(s2);
+      }
+      for (hipEvent_t e : {ev0, rep[0], rep[1], rev[0], rev[1]})
+        if (e) (void)hipEventDestroy(e);
+    }
+  } side{c, st};
+  DG_HIP(c, hipStreamCreateWithFlags(&side.s2, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&side.ev0, &side.rep[0], &side.rep[1], &side.rev[0], &side.rev[1]})
+    DG_HIP(c, hipEventCreateWithFlags(e, hipEventDisableTiming));
+  DG_HIP(c, hipEventRecord(side.ev0, st));   // the forward run and the fills above
+  DG_HIP(c, hipStreamWaitEvent(side.s2, side.ev0, 0));
+  c->stream = side.s2;
+  if ((s = replay(nck - 1, 0)) != DG_OK) return s;
+  DG_HIP(c, hipEventRecord(side.rep[0], side.s2));
+  c->stream = st;
+  for (int64_t sg = nck - 1; sg >= 0; --sg) {
+    const int b = int((nck - 1 - sg) & 1);
+    if (sg > 0) {
+      // buffer 1 - b was last read by the reverse sweep of segment sg + 1
+      if (sg + 1 <= nck - 1) DG_HIP(c, hipStreamWaitEvent(side.s2, side.rev[1 - b], 0));
+      c->stream = side.s2;
+      if ((s = replay(sg - 1, 1 - b)) != DG_OK) return s;
+      DG_HIP(c, hipEventRecord(side.rep[1 - b], side.s2));
+      c->stream = st;
+    }
+    DG_HIP(c, hipStreamWaitEvent(st, side.rep[b], 0));
+    if ((s = reverse(sg, b)) != DG_OK) return s;
+    DG_HIP(c, hipEventRecord(side.rev[b], st));
+  }
+  return DG_OK;
+}
+
 template <typename T>
 dg_status adj_backward_t(dg_ctx* c, const T* resid) {
+  if constexpr (std::is_same_v<T, float>)
+    if (adj_tiled(c)) return adj_backward_tiled(c, resid);
   const int Np = c->re.Np, NF4 = 4 * c->re.Nfp, Nq = c->re.Nq;
   const int64_t K = c->mesh.K, n = int64_t(9) * K * Np, KNp = K * Np;
   const dga::AdjArgs<T> A = adj_args<T>(c);
@@ -772,11 +907,6 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
   T* seg = static_cast<T*>(c->adj_seg.p);
   T* v = static_cast<T*>(c->adj_v.p);
   T *ly = v, *lres = v + n, *mu = v + 2 * n, *nu = v + 3 * n, *r = v + 4 * n, *res = v + 5 * n;
-  // tiled FP32 adjoint: R y of every stage input of a segment, and a
-  // scratch output for the segment's last stage (mu is not used there)
-  const bool tiled = adj_tiled(c);
-  T* rr = static_cast<T*>(c->adj_r.p);
-  T* res2 = mu;
   T* gb = static_cast<T*>(c->adj_gb.p);
   T* hb = static_cast<T*>(c->adj_hb.p);
   double* grad = static_cast<double*>(c->adj_grad.p);
@@ -813,15 +943,9 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
       T* y = seg + (i - n0) * 5 * n;
       const double ti = t0 + double(i) * dt;
       if ((s = fill_zero(c, res, n)) != DG_OK) return s;
-      // the tiled adjoint also takes R y of every stage input, which the
-      // replay's FP32 stage stores as it goes (all five stages then)
-      for (int q = 0; q < 5 && (q < 4 || i + 1 < n1 || tiled); ++q) {
-        T* out = q < 4 ? y + (q + 1) * n : (i + 1 < n1 ? y + 5 * n : res2);
-        if (tiled) {
-          if ((s = stage_raw(c, y + q * n, out, res, rr + ((i - n0) * 5 + q) * n, kRkA[q],
-                             kRkB[q], dt)) != DG_OK)
-            return s;
-        } else if ((s = stage(c, y + q * n, out, res, nullptr, kRkA[q], kRkB[q], dt, 1)) != DG_OK)
+      for (int q = 0; q < 5 && (q < 4 || i + 1 < n1); ++q) {
+        T* out = q < 4 ? y + (q + 1) * n : y + 5 * n;   // stage 5: the next step's y_0
+        if ((s = stage(c, y + q * n, out, res, nullptr, kRkA[q], kRkB[q], dt, 1)) != DG_OK)
           return s;
         if ((s = launch_sources(c, res, out, ti + kRkC[q] * dt, dt, kRkB[q] * dt)) != DG_OK)
           return s;
@@ -837,18 +961,6 @@ dg_status adj_backward_t(dg_ctx* c, const T* resid) {
         DG_HIP(c, hipGetLastError());
       }
       const double ti = t0 + double(i) * dt;
-      if constexpr (std::is_same_v<T, float>) {
-        if (adj_tiled(c)) {
-          // the residual scaling of the stage after (a_{q+1}; for q = 4 the
-          // a_0 = 0 of the next step's first stage) is applied here
-          for (int q = 4; q >= 0; --q)
-            if ((s = adj_stage_tiled(c, ys + q * n, rr + ((i - n0) * 5 + q) * n, lres, ly, nu,
-                                     grad, gradz, float(kRkA[q == 4 ? 0 : q + 1]),
-                                     float(kRkB[q]), dt, ti + kRkC[q] * dt)) != DG_OK)
-              return s;
-          continue;
-        }
-      }
       for (int q = 4; q >= 0; --q) {
         const double ts = ti + kRkC[q] * dt;
         dga::axpby<T><<<nblocks(n), 256, 0, st>>>(lres, ly, kRkB[q], 1.0, n);
@@ -1876,12 +1988,30 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
     const bool upwind = c->opt.flux == DG_FLUX_UPWIND, tiled = adj_tiled(c);
     DG_HIP(c, hipStreamSynchronize(c->stream));
     c->adj_ready = false;
+    // the tiled adjoint keeps two segments when the memory allows, so that
+    // the replay of one overlaps the reverse sweep of the other
+    const size_t segb = S * size_t(every) * 5;
+    c->adj_ov = false;
+    if (tiled && nck > 1) {
+      release(c, c->adj_seg);
+      release(c, c->adj_r);
+      if (alloc(c, c->adj_seg, 2 * segb) == DG_OK && alloc(c, c->adj_r, 2 * segb) == DG_OK) {
+        c->adj_ov = true;
+      } else {
+        // one segment then; the failed allocation is not an error
+        release(c, c->adj_seg);
+        release(c, c->adj_r);
+        c->err.clear();
+        (void)hipGetLastError();
+      }
+    }
+    const int nseg = c->adj_ov ? 2 : 1;
     struct Need {
       DevBuf* b;
       size_t bytes;
     } need[] = {{&c->adj_ck, S * nck},
-                {&c->adj_seg, S * size_t(every) * 5},
-                {&c->adj_r, tiled ? S * size_t(every) * 5 : 0},
+                {&c->adj_seg, segb * nseg},
+                {&c->adj_r, tiled ? segb * nseg : 0},
                 {&c->adj_v, S * 6},
                 {&c->adj_gb, size_t(K) * NF4 * 9 * c->elem},
                 {&c->adj_hb, tiled ? 0 : size_t(K) * NF4 * 9 * c->elem},
