@@ -803,11 +803,13 @@ dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
     const int64_t n0 = sg * every, n1 = std::min(n0 + every, nsteps);
     DG_HIP(c, hipMemcpyAsync(seg, ck + sg * n, n * sizeof(float), hipMemcpyDeviceToDevice,
                              c->stream));
+    // the residual is cleared once per segment: as in the forward run, the
+    // first stage's a_0 = 0 discards the previous step's (finite) residual
     dg_status e;
+    if ((e = fill_zero(c, res, n)) != DG_OK) return e;
     for (int64_t i = n0; i < n1; ++i) {
       float* y = seg + (i - n0) * 5 * n;
       const double ti = t0 + double(i) * dt;
-      if ((e = fill_zero(c, res, n)) != DG_OK) return e;
       for (int q = 0; q < 5; ++q) {
         float* out = q < 4 ? y + (q + 1) * n : (i + 1 < n1 ? y + 5 * n : res2);
         if ((e = stage_raw(c, y + q * n, out, res, rr + ((i - n0) * 5 + q) * n, kRkA[q], kRkB[q],
