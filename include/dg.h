@@ -286,7 +286,11 @@ dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const doubl
  * ([K][4 Nfp][9], two of them on the generic adjoint kernels) and the FP64
  * gradient [3][K][Nq] (upwind: also [K][4 Nfp][4] impedance terms, [K][4
  * Nfp][8] face jumps on the tiled FP32 kernels of orders 1-4, and the FP64
- * gradient [2][K][Np]), counted against the HBM budget. */
+ * gradient [2][K][Np]), counted against the HBM budget.  Upwind on those
+ * tiled kernels, the replay also keeps the [K][4 Nfp][8] face jumps of every
+ * stage input (5 every of them, 10 every with the overlap) when they fit
+ * after everything else; otherwise the reverse stage recomputes them from
+ * the stage input, with the same results up to rounding. */
 dg_status dg_adjoint_forward(dg_ctx* ctx, double t0, double dt, int64_t nsteps, int64_t every,
                              void* trace);
 

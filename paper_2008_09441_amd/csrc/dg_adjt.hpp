@@ -27,7 +27,9 @@
 //   jumps); wave 3 also adds the stress term of the gradient.
 //
 //   For the upwind flux it also keeps the velocity and traction jumps of
-//   every face node (the state the impedance gradient needs).
+//   every face node (the state the impedance gradient needs), unless they
+//   are given (the replay's stage kernel, dgb::stage_bx_r, stores them
+//   beside R y): then the tile reads no y at all.
 //
 // adj_nodes: one thread per volume node.  Adds the flux transposes of the
 //   face nodes on the node (its own side, plus the side of the neighbour's
@@ -73,6 +75,8 @@ struct TileArgs {
   float a, b;            // l = a lres + b ly
   double s;              // gradient scale
   int upwind;
+  int jumps;             // adj_tile<N, true>, upwind: 1 computes the face-node jumps
+                         // into jmp; 0 skips them (the replay's stage stored them)
 };
 
 constexpr int kThreads = 256;
@@ -523,8 +527,9 @@ __global__ __launch_bounds__(kThreads, 2) void adj_tile(TileArgs A) {
   float lv[3][O::RT][4];
   if constexpr (RIN) {
     // R y is given: only the upwind flux's face-node jumps are needed here,
-    // from the own and the neighbour's state gathered straight from HBM
-    if (A.upwind) {
+    // from the own and the neighbour's state gathered straight from HBM,
+    // unless the replay's stage kernel stored them too
+    if (A.upwind && A.jumps) {
       float qM[NT][9], qP[NT][9];
       f4 fg[NT];
 #pragma unroll

@@ -120,6 +120,9 @@ struct dg_ctx {
                             // [every][5][9][K][Np] (stored by the replay)
   bool adj_ov = false;      // adj_seg and adj_r hold two segments: the replay of
                             // the next segment overlaps the reverse sweep
+  DevBuf adj_j;             // FP32 orders 1-4, upwind, when it fits: the face-node
+                            // jumps of every stage input of a segment (as adj_r),
+                            // [every][5][K][4 Nfp][8], stored by the replay
   DevBuf adj_trace;         // [nsteps][nrec][3]
   bool adj_ready = false;
   double adj_t0 = 0.0, adj_dt = 0.0;
@@ -232,7 +235,7 @@ dg_status upload_raw(dg_ctx* c, DevBuf& b, const U* src, size_t n) {
 template <int N>
 hipError_t launch_mfma_d(const dg_ctx* c, const double* q_in, double* q_out, double* res,
                          double* rhs_out, double a, double b, double dt, int lsrk) {
-  dgb::BxArgsT<double> A;
+  dgb::BxArgsT<double> A{};
   A.q_in = q_in;
   A.q_out = q_out;
   A.res = res;
@@ -318,8 +321,9 @@ dg_status launch_stage(dg_ctx* c, const void* q_in, void* q_out, void* res, void
 
 template <int N, bool F32, bool RST = false>
 hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res, float* rhs_out,
-                         double a, double b, double dt, int lsrk, float* r_out = nullptr) {
-  dgb::BxArgs A;
+                         double a, double b, double dt, int lsrk, float* r_out = nullptr,
+                         float* j_out = nullptr) {
+  dgb::BxArgs A{};
   A.q_in = q_in;
   A.q_out = q_out;
   A.res = res;
@@ -343,6 +347,7 @@ hipError_t launch_mfma_n(dg_ctx* c, const float* q_in, float* q_out, float* res,
   const int64_t tiles = (c->mesh.K + dgb::kTile - 1) / dgb::kTile;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   A.r_out = r_out;
+  A.j_out = j_out;
   if constexpr (RST)
     dgb::stage_bx_r<N><<<dim3(unsigned(tiles)), dim3(dgb::kThreads), 0, c->stream>>>(A);
   else
@@ -683,27 +688,31 @@ void launch_adj_tile(dg_ctx* c, const dgt::TileArgs& A) {
 }
 
 // one FP32 stage of the replay (fused LSRK update) that also stores R q_in
-dg_status stage_raw(dg_ctx* c, const void* q_in, void* q_out, void* res, void* r_out, double a,
-                    double b, double dt) {
+// and, if j_out is not null, the jumps at its face nodes
+dg_status stage_raw(dg_ctx* c, const void* q_in, void* q_out, void* res, void* r_out,
+                    float* j_out, double a, double b, double dt) {
   const float* qi = static_cast<const float*>(q_in);
   float* qo = static_cast<float*>(q_out);
   float* rs = static_cast<float*>(res);
   float* ro = static_cast<float*>(r_out);
+  float* jo = j_out;
   hipError_t e;
   switch (c->re.N) {
-    case 1: e = launch_mfma_n<1, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro); break;
-    case 2: e = launch_mfma_n<2, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro); break;
-    case 3: e = launch_mfma_n<3, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro); break;
-    case 4: e = launch_mfma_n<4, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro); break;
+    case 1: e = launch_mfma_n<1, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro, jo); break;
+    case 2: e = launch_mfma_n<2, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro, jo); break;
+    case 3: e = launch_mfma_n<3, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro, jo); break;
+    case 4: e = launch_mfma_n<4, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro, jo); break;
     default: return fail(c, DG_EINVAL, "adjoint: no tiled kernel at this order");
   }
   if (e != hipSuccess) return fail(c, DG_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
   return DG_OK;
 }
 
-dg_status adj_stage_tiled(dg_ctx* c, const float* y, const float* r, float* lres, float* ly,
-                          float* nu, double* grad, double* gradz, float a, float b, double dt,
-                          double ts) {
+// jin: the stage input's face-node jumps as the replay stored them, or null
+// (the tile kernel then computes them from y into adj_zb)
+dg_status adj_stage_tiled(dg_ctx* c, const float* y, const float* r, const float* jin,
+                          float* lres, float* ly, float* nu, double* grad, double* gradz,
+                          float a, float b, double dt, double ts) {
   const int64_t K = c->mesh.K;
   const int Np = c->re.Np;
   dgt::TileArgs A{};
@@ -733,6 +742,7 @@ dg_status adj_stage_tiled(dg_ctx* c, const float* y, const float* r, float* lres
   A.b = b;
   A.s = dt;
   A.upwind = c->opt.flux == DG_FLUX_UPWIND ? 1 : 0;
+  A.jumps = jin ? 0 : 1;
   if (!A.nbn || !A.mat || !A.frags || !A.fmask || !A.r)
     return fail(c, DG_ESTATE, "adjoint: tiled kernel tables missing");
   switch (c->re.N) {
@@ -746,7 +756,7 @@ dg_status adj_stage_tiled(dg_ctx* c, const float* y, const float* r, float* lres
   dgt::NodeArgs B{};
   B.nu = nu;
   B.gf = A.gf;
-  B.jmp = A.jmp;
+  B.jmp = jin ? jin : A.jmp;
   B.ly = ly;
   B.gradz = gradz;
   B.fgeo = A.fgeo;
@@ -776,6 +786,7 @@ dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
   const float* ck = static_cast<const float*>(c->adj_ck.p);
   float* seg0 = static_cast<float*>(c->adj_seg.p);
   float* rr0 = static_cast<float*>(c->adj_r.p);
+  float* jj0 = c->adj_j.p ? static_cast<float*>(c->adj_j.p) : nullptr;
   float* v = static_cast<float*>(c->adj_v.p);
   // res and res2 (a scratch output for a segment's last stage) are the
   // replay's; ly, lres and nu the reverse sweep's
@@ -786,6 +797,7 @@ dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
   const int64_t nsteps = c->adj_nsteps, every = c->adj_every;
   const int64_t nck = (nsteps + every - 1) / every;
   const size_t segn = size_t(every) * 5 * size_t(n);
+  const size_t jn = size_t(K) * 4 * c->re.Nfp * 8, segj = size_t(every) * 5 * jn;
   const hipStream_t st = c->stream;
   dg_status s;
   if ((s = fill_zero(c, ly, n)) != DG_OK) return s;
@@ -800,6 +812,7 @@ dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
   auto replay = [&](int64_t sg, int b) -> dg_status {
     float* seg = seg0 + b * segn;
     float* rr = rr0 + b * segn;
+    float* jj = jj0 ? jj0 + b * segj : nullptr;
     const int64_t n0 = sg * every, n1 = std::min(n0 + every, nsteps);
     DG_HIP(c, hipMemcpyAsync(seg, ck + sg * n, n * sizeof(float), hipMemcpyDeviceToDevice,
                              c->stream));
@@ -812,8 +825,9 @@ dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
       const double ti = t0 + double(i) * dt;
       for (int q = 0; q < 5; ++q) {
         float* out = q < 4 ? y + (q + 1) * n : (i + 1 < n1 ? y + 5 * n : res2);
-        if ((e = stage_raw(c, y + q * n, out, res, rr + ((i - n0) * 5 + q) * n, kRkA[q], kRkB[q],
-                           dt)) != DG_OK)
+        const int64_t sl = (i - n0) * 5 + q;
+        if ((e = stage_raw(c, y + q * n, out, res, rr + sl * n, jj ? jj + sl * jn : nullptr,
+                           kRkA[q], kRkB[q], dt)) != DG_OK)
           return e;
         if ((e = launch_sources(c, res, out, ti + kRkC[q] * dt, dt, kRkB[q] * dt)) != DG_OK)
           return e;
@@ -825,6 +839,7 @@ dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
   auto reverse = [&](int64_t sg, int b) -> dg_status {
     const float* seg = seg0 + b * segn;
     const float* rr = rr0 + b * segn;
+    const float* jj = jj0 ? jj0 + b * segj : nullptr;
     const int64_t n0 = sg * every, n1 = std::min(n0 + every, nsteps);
     dg_status e;
     for (int64_t i = n1 - 1; i >= n0; --i) {
@@ -839,11 +854,13 @@ dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
       const double ti = t0 + double(i) * dt;
       // the residual scaling of the stage after (a_{q+1}; for q = 4 the a_0
       // = 0 of the next step's first stage) is applied in the kernel
-      for (int q = 4; q >= 0; --q)
-        if ((e = adj_stage_tiled(c, ys + q * n, rr + ((i - n0) * 5 + q) * n, lres, ly, nu, grad,
-                                 gradz, float(kRkA[q == 4 ? 0 : q + 1]), float(kRkB[q]), dt,
-                                 ti + kRkC[q] * dt)) != DG_OK)
+      for (int q = 4; q >= 0; --q) {
+        const int64_t sl = (i - n0) * 5 + q;
+        if ((e = adj_stage_tiled(c, ys + q * n, rr + sl * n, jj ? jj + sl * jn : nullptr, lres,
+                                 ly, nu, grad, gradz, float(kRkA[q == 4 ? 0 : q + 1]),
+                                 float(kRkB[q]), dt, ti + kRkC[q] * dt)) != DG_OK)
           return e;
+      }
     }
     return DG_OK;
   };
@@ -1309,7 +1326,7 @@ void dg_destroy(dg_ctx* c) {
                       &c->res, &c->frags, &c->matblk, &c->nbn, &c->torder, &c->src_elem, &c->src_w,
                       &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf, &c->src_wraw,
                       &c->adj_nbface, &c->adj_invf, &c->adj_ck, &c->adj_seg, &c->adj_r,
-                      &c->adj_v, &c->adj_gb, &c->adj_hb, &c->adj_grad, &c->adj_zb,
+                      &c->adj_j, &c->adj_v, &c->adj_gb, &c->adj_hb, &c->adj_grad, &c->adj_zb,
                       &c->adj_gradz, &c->adj_frag, &c->adj_trace})
       release(c, *b);
   }
@@ -1355,7 +1372,7 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
     drop_graphs(c);
     for (DevBuf* b : {&c->src_elem, &c->src_w, &c->src_par, &c->rec_elem, &c->rec_w, &c->rec_buf,
                       &c->trace, &c->src_wraw, &c->adj_nbface, &c->adj_invf, &c->adj_ck,
-                      &c->adj_seg, &c->adj_r, &c->adj_v, &c->adj_gb, &c->adj_hb,
+                      &c->adj_seg, &c->adj_r, &c->adj_j, &c->adj_v, &c->adj_gb, &c->adj_hb,
                       &c->adj_grad, &c->adj_zb, &c->adj_gradz, &c->adj_frag, &c->adj_trace})
       release(c, *b);
     c->adj_ready = false;
@@ -2023,6 +2040,16 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
                 {&c->adj_trace, tb}};
     for (auto& x : need)
       if (x.b->bytes != x.bytes && (s = alloc(c, *x.b, x.bytes)) != DG_OK) return s;
+    // tiled and upwind: the replay also stores the face-node jumps of every
+    // stage input when the memory holds them (else the tile kernel computes
+    // them from the stage input); the failed allocation is not an error
+    const size_t jb =
+        tiled && upwind ? size_t(K) * NF4 * 8 * sizeof(float) * size_t(every) * 5 * nseg : 0;
+    if (c->adj_j.bytes != jb && alloc(c, c->adj_j, jb) != DG_OK) {
+      release(c, c->adj_j);
+      c->err.clear();
+      (void)hipGetLastError();
+    }
     char* ck = static_cast<char*>(c->adj_ck.p);
     char* tr = static_cast<char*>(c->adj_trace.p);
     const size_t per = size_t(c->nrec) * 3 * c->elem;

@@ -85,6 +85,8 @@ struct BxArgsT {
   int lsrk;              // 0: write rhs_out; 1: fused LSRK update
   int upwind;            // 1 upwind, 0 central
   T* r_out;              // stage_bx_r: the raw right-hand side R q [9][K][Np]
+  T* j_out;              // stage_bx_r, if not null: velocity and traction jumps of
+                         // every face node, [K][4 Nfp][8] (jv, jt, 0, 0)
 };
 typedef BxArgsT<float> BxArgs;
 
@@ -810,6 +812,15 @@ __device__ __forceinline__ void stage_bx_run(const BxArgsT<T>& A, int64_t G, int
       const T jty = (P[8] - qM[8]) * nx + (P[4] - qM[4]) * ny + (P[6] - qM[6]) * nz;
       const T jtz = (P[7] - qM[7]) * nx + (P[6] - qM[6]) * ny + (P[5] - qM[5]) * nz;
       const T jvx = P[0] - qM[0], jvy = P[1] - qM[1], jvz = P[2] - qM[2];
+      if constexpr (RST) {
+        // the jumps the adjoint's impedance gradient reads (jt = t(P) - t(M),
+        // t = sigma n, the same expressions as the flux's)
+        if (A.j_out && ok[it]) {
+          V4* jo = reinterpret_cast<V4*>(A.j_out + ((e0 + e) * NF4 + jf) * 8);
+          jo[0] = V4{jvx, jvy, jvz, jtx};
+          jo[1] = V4{jty, jtz, T(0), T(0)};
+        }
+      }
       T dvx, dvy, dvz, dtx, dty, dtz;
       if (A.upwind) {
         const int lm = vM[it] * kES + e;
@@ -949,8 +960,10 @@ __global__ __launch_bounds__(kThreads, 2) void stage_bx(BxArgs A) {
 }
 
 // The FP32 stage that also stores the raw right-hand side R q of its input
-// (r_out): the replay of a checkpoint interval in the discrete adjoint,
-// whose reverse stage needs R y of every stage input
+// (r_out) and, for the upwind flux, the jumps at its face nodes (j_out): the
+// replay of a checkpoint interval in the discrete adjoint, whose reverse
+// stage needs R y of every stage input and, for the impedance gradient, its
+// face-node jumps
 template <int N>
 __global__ __launch_bounds__(kThreads, 2) void stage_bx_r(BxArgs A) {
   stage_bx_run<N, true, float, true>(A, gridDim.x, blockIdx.x);

@@ -4,10 +4,14 @@
 // emu_runtime.hpp).  Built with AddressSanitizer by the test, so any
 // out-of-bounds access of the kernel source shows up on the CPU.
 //
+// rin = 0: adj_tile<N, false> computes R y; 1: R y is read from the input
+// file and the tile computes the face-node jumps; 2: as the library's replay
+// and reverse stage, dgb::stage_bx_r<N> first runs a stage on y and stores R y
+// and (upwind) the jumps, which adj_tile<N, true> and adj_nodes then read.
+//
 // input file: int32 N, flux_upwind, rin; int64 K; float64 vxyz[K*12], period[3],
 // rho_q, cp_q, cs_q [K*Nq each], rho_n, cp_n, cs_n [K*Np each]; float32
-// y, lres, ly [9*K*Np each]; with rin, float32 R y [9*K*Np] (the kernel
-// variant that takes R y instead of computing it); float64 a, b, dt, ts;
+// y, lres, ly [9*K*Np each]; with rin = 1, float32 R y [9*K*Np]; float64 a, b, dt, ts;
 // int32 nsrc; per source
 // int64 element, float32 raw response [3*Np], float64 (f0, t0, amplitude).
 // output file: float64 lres (= a lres + b ly), ly, grad [3*K*Nq], gradz
@@ -20,6 +24,7 @@
 #include <vector>
 
 #include "dg_adjt.hpp"
+#include "dg_bx.hpp"
 #include "dg_host.hpp"
 #include "dg_mfma_host.hpp"
 
@@ -32,7 +37,7 @@ int main(int argc, char** argv) {
   int32_t hdr[3]; int64_t K;
   if (fread(hdr, 4, 3, f) != 3 || fread(&K, 8, 1, f) != 1) return 2;
   const int N = hdr[0], upwind = hdr[1], rin = hdr[2];
-  if (N < 1 || N > 4) return 3;
+  if (N < 1 || N > 4 || rin < 0 || rin > 2) return 3;
   const int Np = dgh::num_nodes(N), Nq = dgh::num_quad(N);
   auto rd = [&](size_t n) { std::vector<double> v(n); if (fread(v.data(), 8, n, f) != n) exit(2); return v; };
   auto rdf = [&](size_t n) { std::vector<float> v(n); if (fread(v.data(), 4, n, f) != n) exit(2); return v; };
@@ -41,7 +46,7 @@ int main(int argc, char** argv) {
   auto rn = rd(K * Np), pn = rd(K * Np), sn = rd(K * Np);
   const size_t n9 = size_t(9) * K * Np;
   auto y = rdf(n9), lres = rdf(n9), ly = rdf(n9);
-  std::vector<float> rraw = rin ? rdf(n9) : std::vector<float>();
+  std::vector<float> rraw = rin == 1 ? rdf(n9) : std::vector<float>();
   auto sc = rd(4);
   int32_t nsrc = 0;
   if (fread(&nsrc, 4, 1, f) != 1) return 2;
@@ -82,7 +87,7 @@ int main(int argc, char** argv) {
   std::vector<int32_t> fm(re.Fmask.begin(), re.Fmask.end());
 
   dgt::TileArgs A{};
-  A.y = yd; A.r = rin ? dup(rraw) : nullptr; A.lres = lr; A.ly = lyd; A.nu = nu; A.gf = gf; A.jmp = jmp; A.grad = grad;
+  A.y = yd; A.r = rin == 1 ? dup(rraw) : nullptr; A.lres = lr; A.ly = lyd; A.nu = nu; A.gf = gf; A.jmp = jmp; A.grad = grad;
   A.geo = dupf(m.geo); A.fgeo = dupf(m.fgeo);
   A.nbn = dup(dgh::neighbour_nodes(re, m));
   A.fmask = dup(fm);
@@ -94,7 +99,32 @@ int main(int argc, char** argv) {
   A.src_par = nsrc ? dup(spar) : nullptr;
   A.nsrc = nsrc; A.ts = sc[3];
   A.K = K; A.a = float(sc[0]); A.b = float(sc[1]); A.s = sc[2]; A.upwind = upwind;
+  A.jumps = 1;
   const int tiles = int((K + 15) / 16);
+  float* jst = nullptr;   // the jumps the replay's stage stores (rin = 2)
+  if (rin == 2) {
+    dgb::BxArgs S{};
+    S.q_in = yd;
+    S.q_out = alloc<float>(n9);
+    S.res = alloc<float>(n9);
+    for (size_t i = 0; i < n9; ++i) S.res[i] = 0.f;
+    S.geo = A.geo; S.fgeo = A.fgeo; S.nbn = A.nbn; S.fmask = A.fmask;
+    S.torder = dup(dgh::tile_order(m, dgb::kTile, 8));
+    S.mat = A.mat; S.zp = A.zp; S.zs = A.zs;
+    S.frags = reinterpret_cast<const dgb::u32x4*>(dup(dgh::mfma_fragments_f32(re)));
+    S.K = K; S.a = 0.f; S.b = 1.f; S.dt = 1.f; S.lsrk = 1; S.upwind = upwind;
+    S.r_out = alloc<float>(n9);
+    if (upwind) jst = S.j_out = alloc<float>(size_t(8) * K * NF4);
+    const int sg = int((K + dgb::kTile - 1) / dgb::kTile);
+    switch (N) {
+      case 1: run_grid(sg, [=]() { dgb::stage_bx_r<1>(S); }); break;
+      case 2: run_grid(sg, [=]() { dgb::stage_bx_r<2>(S); }); break;
+      case 3: run_grid(sg, [=]() { dgb::stage_bx_r<3>(S); }); break;
+      default: run_grid(sg, [=]() { dgb::stage_bx_r<4>(S); }); break;
+    }
+    A.r = S.r_out;
+    A.jumps = 0;
+  }
   if (rin) {
     switch (N) {
       case 1: run_grid(tiles, [=]() { dgt::adj_tile<1, true>(A); }); break;
@@ -111,7 +141,7 @@ int main(int argc, char** argv) {
     }
   }
   dgt::NodeArgs B{};
-  B.nu = nu; B.gf = gf; B.jmp = jmp; B.ly = lyd; B.gradz = gradz;
+  B.nu = nu; B.gf = gf; B.jmp = jst ? jst : jmp; B.ly = lyd; B.gradz = gradz;
   B.fgeo = A.fgeo; B.zp = A.zp; B.zs = A.zs; B.nbn = A.nbn;
   B.nbface = dup(nbface); B.invf = dup(invf);
   B.K = K; B.Np = Np; B.Nfp = re.Nfp; B.s = sc[2]; B.upwind = upwind;

@@ -1,6 +1,7 @@
 """CPU check of the tiled FP32 adjoint kernels (dgt::adj_tile<N> and
 dgt::adj_nodes, orders 1-4): one reverse stage runs on host threads
-(tests/emu/emu_adjoint.cpp) built with AddressSanitizer, so any
+(tests/emu/emu_adjoint.cpp, with the replay stage kernel that stores R y
+and the face-node jumps) built with AddressSanitizer, so any
 out-of-bounds index fails the test, and its results are compared with the
 oracle's discrete adjoint of the same stage (oracle/adjoint.py):
 
@@ -70,13 +71,13 @@ def _case(exe, tmp_path, n, N, flux, split=False, nsrc=0, rin=False):
     for i in range(nsrc):
         srcs.append(dict(k=int(rng.integers(K)), w=rng.standard_normal((3, Np)).astype(np.float32),
                          f0=float(rng.uniform(2, 6)), t0=0.15, amp=float(rng.uniform(0.5, 2))))
-    parts = [np.array([N, 1 if flux == "upwind" else 0, 1 if rin else 0], np.int32).tobytes(),
+    parts = [np.array([N, 1 if flux == "upwind" else 0, int(rin)], np.int32).tobytes(),
              np.array([K], np.int64).tobytes(), vx.astype(np.float64).tobytes(),
              np.ones(3).tobytes()]
     for arr in synth.fourier_media(op.mesh.xq) + synth.fourier_media(op.mesh.x):
         parts.append(np.ascontiguousarray(arr, np.float64).tobytes())
     parts += [y.tobytes(), lres.tobytes(), ly.tobytes()]
-    if rin:   # R y as the replay's FP32 stage would store it
+    if rin == 1:   # R y as the replay's FP32 stage would store it
         parts.append(op.rhs_raw(y.astype(np.float64)).astype(np.float32).tobytes())
     parts += [np.array([a, b, dt, ts]).tobytes(), np.array([nsrc], np.int32).tobytes()]
     for s in srcs:
@@ -122,16 +123,18 @@ def _check(errs):
     assert errs.get("gradz", 0.0) <= 1e-4
 
 
-@pytest.mark.parametrize("rin", [False, True])
+@pytest.mark.parametrize("rin", [0, 1, 2])
 @pytest.mark.parametrize("n,N,flux", [(1, 1, "upwind"), (2, 1, "central"), (2, 2, "upwind"),
                                       (1, 3, "central"), (1, 4, "upwind")])
 def test_adjoint_tile_kernels_in_bounds_and_match_the_oracle(emu_adj, tmp_path, n, N, flux, rin):
-    """Both variants: R y computed in the kernel, and R y given (the
-    library's, which the replay's forward stage stores)."""
+    """Three variants: R y computed in the kernel (rin 0); R y given, the
+    face-node jumps computed in the kernel (1); and as in the library, R y
+    and the jumps stored by the replay's stage kernel stage_bx_r<N> run on
+    the same stage input first (2)."""
     _check(_case(emu_adj, tmp_path, n, N, flux, rin=rin))
 
 
-@pytest.mark.parametrize("rin", [False, True])
+@pytest.mark.parametrize("rin", [0, 1, 2])
 @pytest.mark.parametrize("n,N,flux,nsrc", [(2, 3, "upwind", 2), (1, 4, "central", 1)])
 def test_adjoint_tile_kernels_odd_count_and_sources(emu_adj, tmp_path, n, N, flux, nsrc, rin):
     """An odd element count (one element split at its centroid, non-Kuhn
