@@ -695,7 +695,7 @@ dg_status stage_raw(dg_ctx* c, const void* q_in, void* q_out, void* res, void* r
   float* qo = static_cast<float*>(q_out);
   float* rs = static_cast<float*>(res);
   float* ro = static_cast<float*>(r_out);
-  float* jo = j_out;
+  float* jo = j_out;   // may be null
   hipError_t e;
   switch (c->re.N) {
     case 1: e = launch_mfma_n<1, true, true>(c, qi, qo, rs, nullptr, a, b, dt, 1, ro, jo); break;
@@ -786,7 +786,7 @@ dg_status adj_backward_tiled(dg_ctx* c, const float* resid) {
   const float* ck = static_cast<const float*>(c->adj_ck.p);
   float* seg0 = static_cast<float*>(c->adj_seg.p);
   float* rr0 = static_cast<float*>(c->adj_r.p);
-  float* jj0 = c->adj_j.p ? static_cast<float*>(c->adj_j.p) : nullptr;
+  float* jj0 = static_cast<float*>(c->adj_j.p);   // null: the replay keeps no jumps
   float* v = static_cast<float*>(c->adj_v.p);
   // res and res2 (a scratch output for a segment's last stage) are the
   // replay's; ly, lres and nu the reverse sweep's
