@@ -1,6 +1,8 @@
 """The tiled FP32 adjoint on the matrix cores (orders 1-4: dgt::adj_tile<N>
-and dgt::adj_nodes) against the FP64 generic adjoint kernels on the same
-run (run on an MI355X): gradients in the weights m = (1/rho, lam, mu) and,
+and dgt::adj_nodes, reading R y and, for the upwind flux, the face-node
+jumps that the replay's stage kernel stores) against the FP64 generic
+adjoint kernels on the same run (run on an MI355X): gradients in the
+weights m = (1/rho, lam, mu) and,
 for the upwind flux, in the impedances (Zp, Zs), with point sources and
 receivers and a ragged last checkpoint interval, on the Kuhn mesh and on
 an odd element count (a ragged last element tile).  The FP64 path matches
