@@ -90,6 +90,8 @@ def parse():
     p.add_argument("--no-order7", action="store_true",
                    help="skip the order-7 layered-media measurement")
     p.add_argument("--adjoint-steps", type=int, default=400)
+    p.add_argument("--adjoint-n", type=int, default=24,
+                   help="hexahedra per cube side of the adjoint workload")
     p.add_argument("--serving-requests", type=int, default=64)
     p.add_argument("--serving-rate", type=float, default=3.0, help="arrivals per second")
     p.add_argument("--serving-full", action="store_true",
@@ -398,7 +400,7 @@ def serving(args, precision="fp32", batched=False, rate=None):
 def adjoint(args):
     """Gradient of an L2 receiver misfit with respect to the material fields
     rho, lam, mu (at the quadrature points and at the nodes): order 4 on
-    24^3 x 6 tets, smooth random media, 4 Ricker forces, 64 receivers,
+    24^3 x 6 tets (--adjoint-n), smooth random media, 4 Ricker forces, 64 receivers,
     checkpoint every 20 steps, FP32, upwind.  libdg returns dJ/dm for the
     weight-adjusted weights m = (1/rho, lam, mu) and dJ/d(Zp, Zs) for the
     flux impedances; the field gradient follows by the chain rule.  Times
@@ -407,7 +409,7 @@ def adjoint(args):
     that perturbs the fields (weights and impedances recomputed)."""
     import synth
     from paper_2008_09441_amd import B, Solver
-    n, N, steps, every = 24, 4, args.adjoint_steps, 20
+    n, N, steps, every = args.adjoint_n, 4, args.adjoint_steps, 20
     s = Solver(N, precision="fp32", flux="upwind", device=0)
     s.upload_mesh(synth.kuhn_cube_vertices(n))
     xq, xn = s.quad_coords(), s.node_coords()

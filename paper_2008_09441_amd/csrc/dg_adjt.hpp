@@ -298,15 +298,29 @@ __device__ __forceinline__ void tile_group(const TileArgs& A, int64_t k0, float*
       fvt[t] = frag(O::G_VT + t);
     }
     f4 m0 = matv(W == 0 ? 0 : 2, 0), m1 = W == 1 ? matv(1, 0) : f4{0.f, 0.f, 0.f, 0.f};
+    // the gradient values of the quadrature tile after this one are read
+    // while this one's products run
+    double* gr = A.grad + (W == 2 ? 0 : W) * K * Nq + kc * Nq;
+    double gnext[4];
+    if (W < 2) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = 4 * g + j;
+        gnext[j] = gr[p < Nq ? p : Nq - 1];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < QT; ++u) {
-      double* gr = A.grad + (W == 2 ? 0 : W) * K * Nq + kc * Nq;
       double gold[4];
       if (W < 2) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int p = 16 * u + 4 * g + j;
-          gold[j] = gr[p < Nq ? p : Nq - 1];
+        for (int j = 0; j < 4; ++j) gold[j] = gnext[j];
+        if (u + 1 < QT) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int p = 16 * (u + 1) + 4 * g + j;
+            gnext[j] = gr[p < Nq ? p : Nq - 1];
+          }
         }
       }
       f4 w[3], p[3];

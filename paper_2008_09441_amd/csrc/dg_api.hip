@@ -123,6 +123,8 @@ struct dg_ctx {
   DevBuf adj_j;             // FP32 orders 1-4, upwind, when it fits: the face-node
                             // jumps of every stage input of a segment (as adj_r),
                             // [every][5][K][4 Nfp][8], stored by the replay
+  size_t adj_ov_failed = 0; // interval sizes (bytes of one segment, of the jumps) whose
+  size_t adj_j_failed = 0;  // optional buffers did not fit: not tried again for this mesh
   DevBuf adj_trace;         // [nsteps][nrec][3]
   bool adj_ready = false;
   double adj_t0 = 0.0, adj_dt = 0.0;
@@ -1376,6 +1378,7 @@ dg_status dg_mesh_upload(dg_ctx* c, int64_t K, const double* vxyz, const double*
                       &c->adj_grad, &c->adj_zb, &c->adj_gradz, &c->adj_frag, &c->adj_trace})
       release(c, *b);
     c->adj_ready = false;
+    c->adj_ov_failed = c->adj_j_failed = 0;
     c->trace_cap = 0;
     if (!c->clk.p) {
       if ((s = alloc(c, c->clk, 2 * sizeof(double))) != DG_OK) return s;
@@ -2012,16 +2015,21 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
     const size_t segb = S * size_t(every) * 5;
     c->adj_ov = false;
     if (tiled && nck > 1) {
-      release(c, c->adj_seg);
-      release(c, c->adj_r);
-      if (alloc(c, c->adj_seg, 2 * segb) == DG_OK && alloc(c, c->adj_r, 2 * segb) == DG_OK) {
-        c->adj_ov = true;
-      } else {
-        // one segment then; the failed allocation is not an error
+      if (c->adj_seg.bytes == 2 * segb && c->adj_r.bytes == 2 * segb) {
+        c->adj_ov = true;   // kept from the last run with this interval
+      } else if (c->adj_ov_failed != segb) {
         release(c, c->adj_seg);
         release(c, c->adj_r);
-        c->err.clear();
-        (void)hipGetLastError();
+        if (alloc(c, c->adj_seg, 2 * segb) == DG_OK && alloc(c, c->adj_r, 2 * segb) == DG_OK) {
+          c->adj_ov = true;
+        } else {
+          // one segment then; the failed allocation is not an error
+          release(c, c->adj_seg);
+          release(c, c->adj_r);
+          c->adj_ov_failed = segb;
+          c->err.clear();
+          (void)hipGetLastError();
+        }
       }
     }
     const int nseg = c->adj_ov ? 2 : 1;
@@ -2045,10 +2053,14 @@ dg_status dg_adjoint_forward(dg_ctx* c, double t0, double dt, int64_t nsteps, in
     // them from the stage input); the failed allocation is not an error
     const size_t jb =
         tiled && upwind ? size_t(K) * NF4 * 8 * sizeof(float) * size_t(every) * 5 * nseg : 0;
-    if (c->adj_j.bytes != jb && alloc(c, c->adj_j, jb) != DG_OK) {
+    if (c->adj_j.bytes != jb) {
       release(c, c->adj_j);
-      c->err.clear();
-      (void)hipGetLastError();
+      if (jb && jb != c->adj_j_failed && alloc(c, c->adj_j, jb) != DG_OK) {
+        release(c, c->adj_j);
+        c->adj_j_failed = jb;
+        c->err.clear();
+        (void)hipGetLastError();
+      }
     }
     char* ck = static_cast<char*>(c->adj_ck.p);
     char* tr = static_cast<char*>(c->adj_trace.p);
