@@ -290,7 +290,10 @@ dg_status dg_material_set_weights(dg_ctx* ctx, const double* irho_q, const doubl
  * tiled kernels, the replay also keeps the [K][4 Nfp][8] face jumps of every
  * stage input (5 every of them, 10 every with the overlap) when they fit
  * after everything else; otherwise the reverse stage recomputes them from
- * the stage input, with the same results up to rounding. */
+ * the stage input, with the same results up to rounding.  These buffers are
+ * kept from one call to the next; an optional one (the second interval, the
+ * jumps) that did not fit is not tried again for the same sizes until the
+ * next dg_mesh_upload. */
 dg_status dg_adjoint_forward(dg_ctx* ctx, double t0, double dt, int64_t nsteps, int64_t every,
                              void* trace);
 
